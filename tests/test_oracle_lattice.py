@@ -1,0 +1,194 @@
+"""Pins of the oracle's lattice-Boltzmann core against what the mathematics fixes.
+
+Section 2.2: Eqs. s2-density, s2-fv (moments), s2-eq (equilibrium), s2-ident3
+(viscosity), s2-coll / s2-trans (collide, stream).  None of these tests retypes
+the oracle's update: they check it against lattice isotropy, equilibrium
+moments, an independently derived spectral recursion, closed forms and the
+Navier-Stokes viscosity.
+"""
+import numpy as np
+import pytest
+
+
+def test_lattice_isotropy(oracle_mod):
+    # A lattice with c_s^2 = 1/3 needs sum w = 1, sum w e = 0,
+    # sum w e_i e_j = delta_ij / 3, odd moments zero and
+    # sum w e_i e_j e_k e_l = (d_ij d_kl + d_ik d_jl + d_il d_jk) / 9.
+    e, w = oracle_mod.lattice()
+    e = e.astype(float)
+    assert e.shape == (19, 3)
+    assert abs(w.sum() - 1.0) < 1e-15
+    assert np.allclose(np.einsum("a,ai->i", w, e), 0.0, atol=1e-16)
+    assert np.allclose(np.einsum("a,ai,aj->ij", w, e, e), np.eye(3) / 3.0, atol=1e-15)
+    assert np.allclose(np.einsum("a,ai,aj,ak->ijk", w, e, e, e), 0.0, atol=1e-16)
+    d = np.eye(3)
+    iso4 = (np.einsum("ij,kl->ijkl", d, d) + np.einsum("ik,jl->ijkl", d, d)
+            + np.einsum("il,jk->ijkl", d, d)) / 9.0
+    assert np.allclose(np.einsum("a,ai,aj,ak,al->ijkl", w, e, e, e, e), iso4, atol=1e-15)
+    # every velocity appears with its opposite, and all 19 are distinct
+    assert len({tuple(v) for v in e.astype(int)}) == 19
+    for v in e:
+        assert any(np.array_equal(-v, u) for u in e)
+
+
+def test_equilibrium_moments(oracle_mod):
+    # Eq. s2-eq must reproduce the density, the momentum and the Euler
+    # momentum flux rho/3 I + u u of the incompressible model.
+    e, _ = oracle_mod.lattice()
+    e = e.astype(float)
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        rho = 1.0 + 0.01 * rng.standard_normal()
+        u = 0.05 * rng.standard_normal(3)
+        feq = oracle_mod.equilibrium(rho, u)
+        assert abs(feq.sum() - rho) < 1e-15
+        assert np.allclose(e.T @ feq, u, atol=1e-16)
+        pi = np.einsum("a,ai,aj->ij", feq, e, e)
+        assert np.allclose(pi, rho / 3.0 * np.eye(3) + np.outer(u, u), atol=1e-15)
+
+
+def test_rest_state_stays_at_rest(oracle_mod):
+    # Fluid at rest with a particle at rest and no noise: u = 0 exactly, so the
+    # friction fit returns zero and nothing moves.
+    s = oracle_mod.Sim(8, 8, 8, 0.8)
+    f0 = s.populations()
+    r0 = np.array([[3.3, 4.2, 5.7]])
+    s.set_particles(r0, np.zeros((1, 3)), mass=10.0, gamma=1.0, kT=0.0)
+    s.step(300)
+    r, v = s.particles()
+    assert np.array_equal(v, np.zeros((1, 3)))
+    assert np.array_equal(r, r0)
+    assert np.max(np.abs(s.populations() - f0)) < 1e-15
+
+
+def _shear_recursion(e, w, L, tau, amp, nsteps):
+    """Spectral recursion for one Fourier mode exp(i k z) of the linearised
+    BGK update: f <- S [I - (I - E)/tau] f with E_ab = w_a (1 + 3 e_a.e_b)
+    (the linear part of the equilibrium) and S = diag(exp(-i k e_az))
+    (streaming).  Returns the complex amplitude of u_x for n = 0..nsteps."""
+    Q = len(w)
+    k = 2.0 * np.pi / L
+    Emat = np.array([[w[a] * (1.0 + 3.0 * np.dot(e[a], e[b])) for b in range(Q)] for a in range(Q)])
+    S = np.diag(np.exp(-1j * k * e[:, 2]))
+    M = S @ (np.eye(Q) - (np.eye(Q) - Emat) / tau)
+    f = (3.0 * amp * w * e[:, 0]).astype(complex)
+    out = []
+    for _ in range(nsteps + 1):
+        out.append(np.dot(e[:, 0], f))
+        f = M @ f
+    return np.array(out)
+
+
+@pytest.mark.parametrize("tau", [0.6, 0.8, 1.0])
+def test_shear_wave_matches_spectral_recursion(oracle_mod, tau):
+    # For a shear wave u_x(z) the quadratic equilibrium terms never reach the
+    # density or momentum of this lattice, so u_x follows the linear
+    # single-mode recursion exactly (up to rounding).
+    e, w = oracle_mod.lattice()
+    e = e.astype(float)
+    L, amp = 16, 1e-2
+    s = oracle_mod.Sim(4, 4, L, tau)
+    z = np.arange(L)
+    u = np.zeros((3, L, 4, 4))
+    u[0] = amp * np.sin(2 * np.pi * z / L)[:, None, None]
+    s.set_equilibrium(None, u)
+    rec = _shear_recursion(e, w, L, tau, amp, 60)
+    for n in range(61):
+        rho, uu = s.moments()
+        pred = np.imag(rec[n] * np.exp(2j * np.pi * z / L))
+        assert np.max(np.abs(uu[0][:, :, :] - pred[:, None, None])) < 1e-14
+        assert np.max(np.abs(uu[1:])) < 1e-15
+        assert np.max(np.abs(rho - 1.0)) < 1e-13
+        s.step(1)
+
+
+def test_shear_wave_tau1_closed_form(oracle_mod):
+    # tau = 1 relaxes fully each step, and the lattice then gives
+    # u(z) <- 2/3 u(z) + 1/6 [u(z-1) + u(z+1)]: a sine mode decays by exactly
+    # lambda = (2 + cos k)/3 per step, and -ln(lambda) -> nu k^2 with nu = 1/6.
+    L, amp = 32, 1e-3
+    s = oracle_mod.Sim(2, 2, L, 1.0)
+    z = np.arange(L)
+    k = 2 * np.pi / L
+    u = np.zeros((3, L, 2, 2))
+    u[0] = amp * np.sin(k * z)[:, None, None]
+    s.set_equilibrium(None, u)
+    lam = (2.0 + np.cos(k)) / 3.0
+    for n in range(0, 201, 20):
+        _, uu = s.moments()
+        assert np.max(np.abs(uu[0][:, 0, 0] - amp * lam**n * np.sin(k * z))) < 1e-15
+        s.step(20)
+    nu = 1.0 / 6.0
+    assert abs(-np.log(lam) / (nu * k * k) - 1.0) < 1e-5
+
+
+@pytest.mark.parametrize("tau", [0.6, 0.8, 1.0])
+def test_shear_wave_decay_rate_is_navier_stokes(oracle_mod, tau):
+    # Eq. s2-ident3: a long shear wave decays at nu k^2, nu = (tau - 1/2)/3.
+    L, amp = 64, 1e-3
+    s = oracle_mod.Sim(2, 2, L, tau)
+    z = np.arange(L)
+    k = 2 * np.pi / L
+    u = np.zeros((3, L, 2, 2))
+    u[0] = amp * np.sin(k * z)[:, None, None]
+    s.set_equilibrium(None, u)
+    s.step(200)
+    a1 = 2.0 / L * np.sum(s.moments()[1][0][:, 0, 0] * np.sin(k * z))
+    s.step(200)
+    a2 = 2.0 / L * np.sum(s.moments()[1][0][:, 0, 0] * np.sin(k * z))
+    nu = (tau - 0.5) / 3.0
+    rate = -np.log(a2 / a1) / 200.0
+    assert abs(rate / (nu * k * k) - 1.0) < 2e-3
+
+
+def test_mass_and_momentum_conserved_without_forcing(oracle_mod):
+    from paper_1909_13412_amd.inputs import perturbed_fields
+
+    s = oracle_mod.Sim(12, 10, 8, 0.7)
+    rho, u = perturbed_fields((8, 10, 12), seed=11, amp_rho=1e-2, amp_u=1e-2)
+    s.set_equilibrium(rho, u)
+    o0 = s.observables()
+    s.step(50)
+    o1 = s.observables()
+    assert abs(o1[0] - o0[0]) / o0[0] < 1e-13
+    assert np.max(np.abs(o1[1:4] - o0[1:4])) < 1e-13
+
+
+def test_regularised_stokeslet_far_field(oracle_mod):
+    # Steady Stokes flow (Eq. s2-ns without inertia) driven by a smooth point-like
+    # force F (Gaussian of width 2 with a uniform counter-force, so the periodic
+    # problem is solvable) against the spectral periodic Stokes solution
+    # u(k) = (I - k k / k^2) F(k) / (eta k^2).  The measured u = sum e f of the
+    # first-order forcing lags the fluid velocity by F/2 where the force acts.
+    L, tau, sig, F0 = 32, 1.0, 2.0, 1e-5
+    nu = (tau - 0.5) / 3.0
+    s = oracle_mod.Sim(L, L, L, tau)
+    z, y, x = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    c = 15.5
+    dx = (x - c + L / 2) % L - L / 2
+    dy = (y - c + L / 2) % L - L / 2
+    dz = (z - c + L / 2) % L - L / 2
+    g = np.exp(-(dx**2 + dy**2 + dz**2) / (2 * sig**2))
+    g /= g.sum()
+    F = np.zeros((3, L, L, L))
+    F[0] = F0 * (g - 1.0 / L**3)
+    s.set_body_force(F)
+    s.step(2500)
+    _, u = s.moments()
+    k = 2 * np.pi * np.fft.fftfreq(L)
+    KZ, KY, KX = np.meshgrid(k, k, k, indexing="ij")
+    K = np.stack([KX, KY, KZ])
+    K2 = (K**2).sum(0)
+    K2[0, 0, 0] = 1.0
+    Fh = np.fft.fftn(F, axes=(1, 2, 3))
+    uh = (Fh - K * (K * Fh).sum(0) / K2) / (nu * K2)
+    uh[:, 0, 0, 0] = 0.0
+    us = np.real(np.fft.ifftn(uh, axes=(1, 2, 3)))
+    r = np.sqrt(dx**2 + dy**2 + dz**2)
+    far = r >= 6
+    far_err = np.max(np.abs(u - us)[:, far]) / np.max(np.abs(us[:, far]))
+    all_err = np.max(np.abs(u + F / 2 - us)) / np.max(np.abs(us))
+    assert far_err < 0.01, far_err
+    assert all_err < 0.01, all_err
+    # transverse components and the density stay consistent with Stokes flow
+    assert abs(u[0].mean()) < 1e-12 * F0 * 1e6

@@ -1,0 +1,350 @@
+"""Pins of the oracle's particle side: friction fit (section 2.1, Eq. s2-slet-v),
+reaction force and spreading (first Eq. s2-force), Langevin update (Eqs.
+s2-langevin, s2-langevin2), random force (Eqs. s2-rf1, s2-rf2) and the
+hydrodynamic results the paper reports in section 3 (long-time tail of the
+velocity autocorrelation, momentum conservation).
+"""
+import itertools
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _corners(s):
+    c = np.floor(s)
+    return np.array([c + np.array([p & 1, (p >> 1) & 1, (p >> 2) & 1]) for p in range(8)])
+
+
+def _oseen_wake(R, U0, e, d):
+    """Velocity relative to a sphere held in a uniform stream U0 e, keeping the
+    Stokeslet part only: u = U0 e - G(d) F with the Oseen tensor
+    G = (I + d d / |d|^2) / (8 pi eta |d|) and Stokes' drag F = 6 pi eta R U0 e."""
+    r = np.linalg.norm(d)
+    G = (np.eye(3) + np.outer(d, d) / r**2) / (8 * np.pi * r)  # eta cancels
+    return U0 * e - G @ (6 * np.pi * R * U0 * e)
+
+
+def test_fit_recovers_stokeslet_stream_at_cell_centre(oracle_mod):
+    # With the particle at the centre of its cell the eight-node mean of the
+    # Stokeslet shape is parallel to the stream, so the least-squares fit
+    # returns the stream speed exactly: F_H = gamma U0 e.
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        R = rng.uniform(0.1, 0.9)
+        U0 = rng.uniform(1e-4, 1e-2)
+        e = rng.standard_normal(3)
+        e /= np.linalg.norm(e)
+        V = 1e-3 * rng.standard_normal(3)
+        s = np.floor(rng.uniform(0, 20, 3)) + 0.5
+        u8 = np.array([V + _oseen_wake(R, U0, e, x - s) for x in _corners(s)])
+        FH = oracle_mod.friction_force("stokeslet", R, 1.7, s, V, u8)
+        assert np.allclose(FH, 1.7 * U0 * e, rtol=1e-12, atol=1e-18)
+
+
+def test_fit_with_zero_radius_is_eight_node_mean(oracle_mod):
+    # R = 0 makes every shape vector equal e^N, so U^inf = |mean(w)| and
+    # F_H = gamma (mean_p u_p - V).
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        s = rng.uniform(0, 10, 3)
+        V = rng.standard_normal(3) * 1e-2
+        u8 = rng.standard_normal((8, 3)) * 1e-2
+        FH = oracle_mod.friction_force("stokeslet", 0.0, 0.9, s, V, u8)
+        assert np.allclose(FH, 0.9 * (u8.mean(0) - V), rtol=1e-13, atol=1e-19)
+
+
+def _cube_symmetries():
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product([1, -1], repeat=3):
+            P = np.zeros((3, 3))
+            for i, j in enumerate(perm):
+                P[i, j] = signs[i]
+            yield P
+
+
+def test_fit_is_covariant_under_cube_symmetries(oracle_mod):
+    # Rotating/reflecting the whole configuration by a lattice symmetry about
+    # the cell centre must rotate F_H the same way (checks every index, sign
+    # and corner ordering in the fit).
+    rng = np.random.default_rng(5)
+    for P in _cube_symmetries():
+        R = rng.uniform(0.2, 1.6)
+        t = rng.uniform(0.05, 0.95, 3)  # fractional position in the cell
+        base = np.array([4.0, 7.0, 2.0])
+        s = base + t
+        V = rng.standard_normal(3) * 1e-2
+        u8 = rng.standard_normal((8, 3)) * 1e-2
+        FH = oracle_mod.friction_force("stokeslet", R, 1.0, s, V, u8)
+        # transformed configuration
+        t2 = P @ (t - 0.5) + 0.5
+        s2 = base + t2
+        u82 = np.zeros((8, 3))
+        for p in range(8):
+            b = np.array([p & 1, (p >> 1) & 1, (p >> 2) & 1], dtype=float)
+            b2 = np.rint(P @ (b - 0.5) + 0.5).astype(int)
+            q = b2[0] + 2 * b2[1] + 4 * b2[2]
+            u82[q] = P @ u8[p]
+        FH2 = oracle_mod.friction_force("stokeslet", R, 1.0, s2, P @ V, u82)
+        assert np.allclose(FH2, P @ FH, rtol=1e-12, atol=1e-17)
+
+
+def test_fit_homogeneous_and_galilean(oracle_mod):
+    rng = np.random.default_rng(6)
+    s = np.array([3.21, 8.77, 0.43])
+    V = rng.standard_normal(3) * 1e-2
+    u8 = rng.standard_normal((8, 3)) * 1e-2
+    FH = oracle_mod.friction_force("stokeslet", 0.53, 1.0, s, V, u8)
+    for alpha in (3.0, -0.25):
+        FHa = oracle_mod.friction_force("stokeslet", 0.53, 1.0, s, alpha * V, alpha * u8)
+        assert np.allclose(FHa, alpha * FH, rtol=1e-13, atol=1e-18)
+    shift = np.array([0.3, -0.2, 0.1])
+    FHs = oracle_mod.friction_force("stokeslet", 0.53, 1.0, s, V + shift, u8 + shift)
+    assert np.allclose(FHs, FH, rtol=1e-10, atol=1e-15)
+    # degenerate: no relative flow -> no force
+    FH0 = oracle_mod.friction_force("stokeslet", 0.53, 1.0, s, V, np.tile(V, (8, 1)))
+    assert np.array_equal(FH0, np.zeros(3))
+
+
+def test_pointwise_and_bd_friction_closed_forms(oracle_mod):
+    rng = np.random.default_rng(8)
+    s = np.array([1.25, 2.5, 3.75])
+    V = rng.standard_normal(3)
+    u0 = rng.standard_normal(3)
+    # Eq. s2-dis1 in a uniform stream: the interpolated velocity is the stream
+    FH = oracle_mod.friction_force("pointwise", 0.5, 2.0, s, V, np.tile(u0, (8, 1)))
+    assert np.allclose(FH, -2.0 * (V - u0), rtol=1e-14)
+    # interpolation of a linear field is exact: u(x) = A x + b
+    A = rng.standard_normal((3, 3))
+    b = rng.standard_normal(3)
+    u8 = np.array([A @ x + b for x in _corners(s)])
+    FH = oracle_mod.friction_force("pointwise", 0.5, 2.0, s, V, u8)
+    assert np.allclose(FH, -2.0 * (V - (A @ s + b)), rtol=1e-13)
+    # Eq. s2-dis0
+    FH = oracle_mod.friction_force("bd", 0.5, 2.0, s, V, u8)
+    assert np.allclose(FH, -2.0 * V, rtol=0, atol=0)
+
+
+def test_first_step_spreading_moments(oracle_mod):
+    # From rest, one step later the momentum added at the nodes is exactly
+    # -F_H (weights sum to one) and its first moment is -F_H s (weights are
+    # centred on the particle): sum_x x_k u_j = -F_H,j s_k.
+    L = 16
+    s = oracle_mod.Sim(L, L, L, 0.8)
+    r0 = np.array([[7.3, 8.61, 6.15]])
+    v0 = np.array([[0.01, -0.004, 0.002]])
+    s.set_particles(r0, v0, mass=10.0, gamma=1.0)
+    s.step(1)
+    fh, fr = s.particle_forces()
+    assert np.array_equal(fr, np.zeros((1, 3)))
+    _, u = s.moments()
+    assert np.allclose(u.sum(axis=(1, 2, 3)), -fh[0], rtol=1e-13, atol=1e-18)
+    z, y, x = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    X = [x, y, z]
+    for j in range(3):
+        for k in range(3):
+            mom = np.sum(X[k] * u[j])
+            assert abs(mom - (-fh[0, j] * r0[0, k])) < 1e-13 * abs(fh[0]).max() * L
+    # and the particle velocity changed by F_H / M
+    _, v1 = s.particles()
+    assert np.allclose(v1, v0 + fh / 10.0, rtol=1e-15)
+
+
+def test_total_momentum_balance(oracle_mod):
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    L = 12
+    for kT in (0.0, 1e-4):
+        s = oracle_mod.Sim(L, L, L, 0.8)
+        r = particle_positions(6, L, seed=21)
+        v = particle_velocities(6, 1e-4, seed=21)
+        s.set_particles(r, v, mass=10.0, gamma=1.0, kT=kT, seed=99)
+        o = s.observables()
+        for _ in range(40):
+            s.step(1)
+            _, fr = s.particle_forces()
+            o1 = s.observables()
+            # fluid + particle momentum (about 3e-2 here) changes by exactly the
+            # random forces, up to the rounding of the 1728-node momentum sum
+            dp = (o1[1:4] + o1[4:7]) - (o[1:4] + o[4:7])
+            assert np.allclose(dp, fr.sum(0), rtol=0, atol=1e-14)
+            assert abs(o1[0] - o[0]) < 1e-11
+            o = o1
+
+
+def test_translation_by_lattice_vector_is_exact(oracle_mod):
+    # Shifting particles by a lattice vector (with positions beyond the box,
+    # which wrap) and rolling the fluid the same way reproduces the run, up to
+    # the rounding of the shifted coordinates.
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    L = 10
+    r = particle_positions(3, L, seed=31)
+    v = particle_velocities(3, 1e-4, seed=31)
+    a = oracle_mod.Sim(L, L, L, 0.7)
+    a.set_particles(r, v, kT=1e-4, seed=5)
+    a.step(25)
+    shift = np.array([3, -2, 12])
+    b = oracle_mod.Sim(L, L, L, 0.7)
+    b.set_particles(r + shift, v, kT=1e-4, seed=5)
+    b.step(25)
+    ra, va = a.particles()
+    rb, vb = b.particles()
+    assert np.allclose(va, vb, rtol=1e-11, atol=0)
+    assert np.allclose(rb - shift, ra, rtol=0, atol=1e-13)
+    fa = a.populations()
+    fb = np.roll(b.populations(), shift=(-shift[2], -shift[1], -shift[0]), axis=(1, 2, 3))
+    assert np.max(np.abs(fa - fb)) < 1e-15
+
+
+def test_brownian_dynamics_closed_form(oracle_mod):
+    # Eq. s2-dis0 without noise: V^n = V^0 (1 - gamma/M)^n and
+    # r^n = r^0 + sum_{k=1..n} V^k (the position uses the updated velocity).
+    s = oracle_mod.Sim(4, 4, 4, 0.8)
+    r0 = np.array([[1.2, 2.3, 3.4]])
+    v0 = np.array([[0.01, -0.02, 0.005]])
+    s.set_particles(r0, v0, mass=10.0, gamma=1.0, friction="bd")
+    s.step(50)
+    r, v = s.particles()
+    a = 1.0 - 1.0 / 10.0
+    assert np.allclose(v, v0 * a**50, rtol=1e-13)
+    assert np.allclose(r, r0 + v0 * a * (1 - a**50) / (1 - a), rtol=1e-13)
+    # the solvent is not touched
+    assert np.max(np.abs(s.observables()[1:4])) == 0.0
+
+
+@pytest.mark.slow
+def test_brownian_dynamics_stationary_statistics(oracle_mod):
+    # Discrete Langevin update with noise variance 2 gamma kT per step:
+    # V' = a V + xi / M with a = 1 - gamma/M has stationary variance
+    # (kT/M) / (1 - gamma/(2M)) and lag-1 correlation a.
+    n, M, g, kT = 4096, 10.0, 1.0, 1e-4
+    s = oracle_mod.Sim(2, 2, 2, 0.8)
+    s.set_particles(np.zeros((n, 3)), np.zeros((n, 3)), mass=M, gamma=g, kT=kT, seed=1234,
+                    friction="bd")
+    s.step(200)
+    samples, lag1 = [], []
+    for _ in range(60):
+        _, v = s.particles()
+        s.step(1)
+        _, v1 = s.particles()
+        samples.append(v.ravel().copy())
+        lag1.append((v * v1).ravel())
+        s.step(19)
+    x = np.concatenate(samples)
+    var = np.mean(x**2)
+    expect = (kT / M) / (1 - g / (2 * M))
+    se = expect * np.sqrt(2.0 / x.size)
+    assert abs(var - expect) < 4 * se, (var, expect, se)
+    assert abs(np.mean(x)) < 4 * np.sqrt(expect / x.size)
+    rho1 = np.mean(np.concatenate(lag1)) / var
+    assert abs(rho1 - (1 - g / M)) < 4 * np.sqrt(1.0 / x.size) * 1.5
+
+
+def test_philox_matches_library_engine(oracle_mod, tmp_path):
+    # Cross-check against PyTorch's header-only Philox4x32-10 engine, built
+    # from its source header (key = seed, counter = (offset, subsequence)).
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    import torch
+
+    inc = os.path.join(os.path.dirname(torch.__file__), "include")
+    if not os.path.exists(os.path.join(inc, "ATen", "core", "PhiloxRNGEngine.h")):
+        pytest.skip("PhiloxRNGEngine.h not shipped with this torch")
+    exe = str(tmp_path / "philox_check")
+    subprocess.run([gxx, "-O1", "-std=c++17", "-I", inc,
+                    os.path.join(ROOT, "tests", "philox_lib_check.cpp"), "-o", exe], check=True)
+    rng = np.random.default_rng(9)
+    cases = rng.integers(0, 2**32, size=(300, 6), dtype=np.uint64)
+    cases[0] = 0
+    cases[1] = 2**32 - 1
+    inp = "\n".join(" ".join(str(int(x)) for x in row) for row in cases) + "\n"
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    lib = np.array([[int(t) for t in line.split()] for line in out.strip().splitlines()], dtype=np.uint64)
+    mine = np.array([oracle_mod.philox4x32_10(row[:4], row[4:]) for row in cases], dtype=np.uint64)
+    assert np.array_equal(lib, mine)
+
+
+def test_gaussian_stream_moments(oracle_mod):
+    z = np.array([oracle_mod.gauss3(2002, n, i) for n in range(200) for i in range(100)]).ravel()
+    N = z.size
+    assert abs(z.mean()) < 4 / np.sqrt(N)
+    assert abs(z.var() - 1.0) < 4 * np.sqrt(2.0 / N)
+    assert abs(np.mean(z**4) - 3.0) < 4 * np.sqrt(96.0 / N)
+    # distinct counters give uncorrelated draws
+    a = np.array([oracle_mod.gauss3(7, n, 0)[0] for n in range(5000)])
+    b = np.array([oracle_mod.gauss3(7, n, 1)[0] for n in range(5000)])
+    assert abs(np.mean(a * b)) < 4 / np.sqrt(5000)
+
+
+def test_vacf_estimator_matches_trace(oracle_mod):
+    # Device-style accumulation (origins every K steps, lags <= Lmax) against a
+    # brute-force recomputation from the recorded velocity trace.
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    L, n, T, Lmax, K = 8, 5, 57, 13, 4
+    s = oracle_mod.Sim(L, L, L, 0.8)
+    s.set_particles(particle_positions(n, L, 41), particle_velocities(n, 1e-5, 41), kT=1e-4, seed=3)
+    s.vacf_config(Lmax, K)
+    trace = []
+    for _ in range(T):
+        trace.append(s.particles()[1].copy())
+        s.step(1)
+    trace = np.array(trace)
+    acc, cnt = s.vacf()
+    for lag in range(Lmax + 1):
+        origins = [t0 for t0 in range(0, T, K) if t0 + lag < T]
+        assert cnt[lag] == len(origins)
+        ref = sum(np.sum(trace[t0] * trace[t0 + lag], axis=1) for t0 in origins)
+        assert np.allclose(acc[:, lag], ref, rtol=1e-14, atol=1e-30)
+
+
+@pytest.mark.slow
+def test_velocity_relaxation_long_time_tail(oracle_mod):
+    # Section 3: the velocity of a kicked particle relaxes like the VACF and
+    # tends to B t^(-3/2) with B = M / [12 rho_f (pi nu)^(3/2)].  The next term
+    # of the long-time expansion is smaller by 1/t, so V(t) t^(3/2) / V(0) is
+    # fitted as B' (1 + a/t) on 60 <= t <= 150, before the sound wave crosses
+    # the 96^3 box (L / c_s = 166 steps).
+    L, tau, M = 96, 0.8, 10.0
+    nu = (tau - 0.5) / 3.0
+    s = oracle_mod.Sim(L, L, L, tau)
+    s.set_particles(np.array([[L / 2 + 0.5, L / 2 + 0.5, L / 2 + 0.5]]),
+                    np.array([[0.01, 0.0, 0.0]]), mass=M, gamma=1.0)
+    V = []
+    for _ in range(151):
+        V.append(s.particles()[1][0, 0])
+        s.step(1)
+    V = np.array(V) / 0.01
+    t = np.arange(151, dtype=float)
+    win = (t >= 60) & (t <= 150)
+    A = np.stack([np.ones(win.sum()), 1.0 / t[win]], axis=1)
+    coef, *_ = np.linalg.lstsq(A, V[win] * t[win] ** 1.5, rcond=None)
+    B = M / (12.0 * (np.pi * nu) ** 1.5)
+    assert abs(coef[0] / B - 1.0) < 0.05, coef[0] / B
+    # and the approach is from above, monotone, with no sign change
+    assert np.all(V[win] > B * t[win] ** -1.5)
+    assert np.all(np.diff(V[1:]) < 0)
+
+
+@pytest.mark.slow
+def test_finite_box_momentum_plateau(oracle_mod):
+    # In a periodic box the kicked particle and the fluid end up moving
+    # together: V(inf) = M V0 / (M + rho0 L^3).
+    L, M = 8, 10.0
+    s = oracle_mod.Sim(L, L, L, 1.0)
+    s.set_particles(np.array([[3.4, 4.1, 2.7]]), np.array([[0.01, 0.0, 0.0]]), mass=M, gamma=1.0)
+    s.step(1500)
+    _, v = s.particles()
+    vinf = M * 0.01 / (M + L**3)
+    # the residual (a few 1e-5) is the lattice dependence of the fit as the
+    # particle drifts through its cell, not a momentum leak
+    assert abs(v[0, 0] / vinf - 1.0) < 1e-4
+    assert np.max(np.abs(v[0, 1:])) < 1e-4 * vinf
+    o = s.observables()
+    assert abs((o[1] + o[4]) / (M * 0.01) - 1.0) < 1e-12
