@@ -1,0 +1,198 @@
+/*
+ * lbmbp -- lattice-Boltzmann fluid two-way coupled to Brownian point particles,
+ * hand-written HIP for gfx950 (MI355X).  C ABI.
+ *
+ * Method: Yoshida, Kinjo & Washizu, "Numerical simulation method for Brownian
+ * particles dispersed in incompressible fluids" (arXiv:1909.13412).
+ *   - fluid:    section 2.2, Eqs. s2-density, s2-fv (moments), s2-lbe, s2-collision,
+ *               s2-eq (BGK with the incompressible equilibrium), second Eq. s2-force
+ *               (forcing term G), s2-coll and s2-trans (collide, then stream);
+ *               nineteen-velocity cubic lattice, periodic box.
+ *   - coupling: section 2.1, Eq. s2-slet-v (Stokeslet-fitted far-field velocity
+ *               from the eight nodes around each particle), Eq. s2-dis1 with u
+ *               replaced by u^inf (friction), first Eq. s2-force (reaction force
+ *               spread back to the same eight nodes).
+ *   - particles: Eqs. s2-langevin, s2-langevin2 (Langevin update) with the random
+ *               force of Eqs. s2-rf1, s2-rf2 drawn from Philox4x32-10.
+ *   - analysis: section 2.1 / 3, C_v(t) = <V(0).V(t)>.
+ *
+ * Units: lattice units throughout, dx = dt = C = rho0 = 1.
+ *
+ * Conventions shared by every entry point
+ *   - All device pointers are caller-owned; the library never allocates or frees
+ *     device memory.  Buffers must stay alive until lbm_destroy (or until the
+ *     next particles_couple / lbm_vacf_config replaces them).
+ *   - Every kernel is enqueued on the caller's HIP stream given to lbm_init
+ *     (NULL = the null stream).  Only lbm_observables, lbm_vacf_counts (host
+ *     only) and the lbm_get_* queries of host values synchronise; everything
+ *     else is asynchronous.
+ *   - Velocity order (a = 0..18): 0 rest; 1..6 = +x,-x,+y,-y,+z,-z;
+ *     7..10 = (+1,+1,0),(-1,-1,0),(+1,-1,0),(-1,+1,0);
+ *     11..14 = (+1,0,+1),(-1,0,-1),(+1,0,-1),(-1,0,+1);
+ *     15..18 = (0,+1,+1),(0,-1,-1),(0,+1,-1),(0,-1,+1).
+ *     Weights 1/3 (rest), 1/18 (axis), 1/36 (diagonal).
+ *   - Host-visible FP64 field layouts (C order, x fastest):
+ *       populations f[19][nz][ny][nx], density rho[nz][ny][nx],
+ *       velocity u[3][nz][ny][nx], particles r[n][3], v[n][3].
+ *   - Validation happens before any launch.  On LBM_E_INVAL the context is left
+ *     untouched.  A context is not thread-safe; calls on one stream are ordered.
+ */
+#ifndef LBMBP_H
+#define LBMBP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_Q 19
+
+typedef enum lbm_status {
+    LBM_OK = 0,
+    LBM_E_INVAL = 1,       /* bad argument; nothing was enqueued */
+    LBM_E_DEVICE = 2,      /* a HIP call or kernel launch failed */
+    LBM_E_STATE = 3,       /* call not valid in the context's current state */
+    LBM_E_NONFINITE = 4,   /* a reduction found NaN/Inf, or a node force overflowed */
+    LBM_E_UNSUPPORTED = 5  /* valid request this build does not implement */
+} lbm_status;
+
+/* Population storage.  Every storage holds the shifted value g = f - w_a rho0
+ * (rest state = all zeros).  F64 computes in FP64; F32, BF16 and F16 compute in
+ * FP32.  BF16 rounds g to nearest-even; F16 stores round-to-nearest-even of
+ * g * 2^f16_scale_log2. */
+typedef enum lbm_storage {
+    LBM_STORE_F64 = 0,
+    LBM_STORE_F32 = 1,
+    LBM_STORE_BF16 = 2,
+    LBM_STORE_F16 = 3
+} lbm_storage;
+
+/* Friction model.  STOKESLET is the paper's method (Eq. s2-slet-v); POINTWISE is
+ * Eq. s2-dis1 with u(r) interpolated trilinearly from the eight nodes; BD is
+ * Eq. s2-dis0 (solvent at rest, no reaction force). */
+typedef enum lbm_friction {
+    LBM_FRICTION_STOKESLET = 0,
+    LBM_FRICTION_POINTWISE = 1,
+    LBM_FRICTION_BD = 2
+} lbm_friction;
+
+typedef struct lbm_grid_desc {
+    int32_t nx, ny, nz;      /* periodic box, each >= 2, nx*ny*nz < 2^31 */
+    double tau;              /* BGK relaxation time, > 1/2; nu = (tau - 1/2)/3 (Eq. s2-ident3) */
+    int32_t storage;         /* lbm_storage */
+    int32_t f16_scale_log2;  /* F16 only: 0..24 (16 recommended); ignored otherwise */
+} lbm_grid_desc;
+
+typedef struct lbm_particle_desc {
+    int32_t n;           /* number of particles, 0..2^24 */
+    int32_t friction;    /* lbm_friction */
+    double mass;         /* M > 0 (all particles identical) */
+    double gamma;        /* friction constant >= 0 */
+    double kT;           /* temperature >= 0; random force variance 2 gamma kT per component per step */
+    double radius;       /* R; <= 0 derives it from Stokes' law gamma = 6 pi rho0 nu R */
+    uint64_t seed;       /* Philox key */
+    uint32_t replica;    /* third Philox counter word (independent replicas) */
+    uint32_t reserved;   /* must be 0 */
+} lbm_particle_desc;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Bytes of ONE population lattice (the library uses two, A and B, swapped every
+ * step).  Planes may be padded; the caller only allocates this many bytes. */
+lbm_status lbm_lattice_bytes(const lbm_grid_desc *grid, size_t *bytes);
+
+/* Bytes of grid scratch (forced-node bitmasks, reduction partials, flags). */
+lbm_status lbm_grid_scratch_bytes(const lbm_grid_desc *grid, size_t *bytes);
+
+/* Bytes of particle scratch for n particles (forced-node hash tables, corner
+ * bookkeeping, last-step forces). */
+lbm_status lbm_particle_scratch_bytes(const lbm_grid_desc *grid, int32_t n, size_t *bytes);
+
+/* Bytes of the VACF origin store for n particles: (max_lag/stride + 1) * n * 3 doubles. */
+lbm_status lbm_vacf_origin_bytes(int32_t n, int32_t max_lag, int32_t stride, size_t *bytes);
+
+/* Create a context on the current HIP device.  pop_a, pop_b: device buffers of
+ * lbm_lattice_bytes each, 256-byte aligned.  grid_scratch: lbm_grid_scratch_bytes,
+ * 256-byte aligned.  stream: hipStream_t or NULL.  Enqueues the rest state
+ * f = w (rho = 1, u = 0) and clears the scratch.  *out receives the context. */
+lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *grid_scratch,
+                    void *stream, lbm_ctx **out);
+
+/* f = f^eq(rho, u) at every node (Eq. s2-eq).  rho: device FP64 [nz][ny][nx] or
+ * NULL for 1; u: device FP64 [3][nz][ny][nx] or NULL for 0. */
+lbm_status lbm_set_equilibrium(lbm_ctx *ctx, const double *rho, const double *u);
+
+/* Load the post-streaming populations f^n from device FP64 [19][nz][ny][nx]. */
+lbm_status lbm_set_populations(lbm_ctx *ctx, const double *f);
+
+/* Decode the post-streaming populations f^n into device FP64 [19][nz][ny][nx]. */
+lbm_status lbm_get_populations(lbm_ctx *ctx, double *f);
+
+/* Moments of f^n (Eqs. s2-density, s2-fv) into device FP64 rho [nz][ny][nx]
+ * (may be NULL) and u [3][nz][ny][nx] (may be NULL). */
+lbm_status lbm_get_moments(lbm_ctx *ctx, double *rho, double *u);
+
+/* Attach (or replace) the particle set.  r, v: device FP64 [n][3]; the library
+ * updates them in place every step (r is kept unwrapped).  particle_scratch:
+ * lbm_particle_scratch_bytes(grid, n), 256-byte aligned.  Clears forced-node
+ * state and detaches any VACF configuration.  n = 0 detaches all particles. */
+lbm_status particles_couple(lbm_ctx *ctx, const lbm_particle_desc *desc, double *r, double *v,
+                            void *particle_scratch);
+
+/* The radius the coupling uses (given or derived), or a negative value when no
+ * particles are attached. */
+double lbm_particle_radius(const lbm_ctx *ctx);
+
+/* Copy the friction F_H and random force F_R of the most recent step into
+ * device FP64 [n][3] buffers (either may be NULL). */
+lbm_status lbm_particle_forces(lbm_ctx *ctx, double *fh, double *fr);
+
+/* Start accumulating C_i(l) = sum over origins t0 of V_i(t0).V_i(t0 + l), for
+ * lags 0..max_lag, origins every `stride` steps counted from this call;
+ * V sampled before each step's update.  acc: device FP64 [n][max_lag+1],
+ * zeroed here.  origins: device buffer of lbm_vacf_origin_bytes.  Requires
+ * attached particles.  max_lag = -1 switches the accumulation off. */
+lbm_status lbm_vacf_config(lbm_ctx *ctx, int32_t max_lag, int32_t stride, double *acc,
+                           double *origins);
+
+/* Host array cnt[max_lag+1]: number of origins that contributed to each lag so
+ * far (the same for every particle). */
+lbm_status lbm_vacf_counts(const lbm_ctx *ctx, int64_t *cnt);
+
+/* Advance nsteps coupled steps (asynchronous).  Per step: VACF sample (if
+ * configured), particle coupling (gather, fit, random force, spreading,
+ * Langevin update), fused stream-collide with the forcing. */
+lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps);
+
+/* Synchronous FP64 sums over the current state: out[0] fluid mass sum rho~,
+ * out[1..3] fluid momentum sum u, out[4..6] particle momentum sum M V.
+ * Returns LBM_E_NONFINITE (after filling out) if any value is not finite or a
+ * node force left the fixed-point range since the last call. */
+lbm_status lbm_observables(lbm_ctx *ctx, double out[7]);
+
+/* Per-kernel GPU timing with HIP events recorded on the context's stream.
+ * enable = 1 brackets every particle-phase launch (VACF sample + particle
+ * coupling) and every stream-collide launch of lbm_step with start/stop
+ * events (host-side event objects only, no device memory); enable = 0 stops. */
+lbm_status lbm_profile_enable(lbm_ctx *ctx, int32_t enable);
+
+/* Synchronise the stream and return the accumulated timings, then reset them:
+ * out[0] summed stream-collide milliseconds, out[1] stream-collide launches,
+ * out[2] summed particle-phase milliseconds, out[3] particle-phase launches. */
+lbm_status lbm_profile_read(lbm_ctx *ctx, double out[4]);
+
+/* Number of steps taken since lbm_init. */
+lbm_status lbm_get_step(const lbm_ctx *ctx, int64_t *step);
+
+/* Release the context (host memory only; device buffers stay the caller's). */
+lbm_status lbm_destroy(lbm_ctx *ctx);
+
+/* Static string for a status code. */
+const char *lbm_status_string(lbm_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBMBP_H */

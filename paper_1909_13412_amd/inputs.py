@@ -12,8 +12,14 @@ nineteen-velocity lattice, particle mass 10 and friction constant 1:
   at a seeded off-lattice position, kT = 0, 1000 steps.
 * ``vacf128``       -- 128^3, tau 0.8, FP32, 64 particles, kT = 1e-4, 20000 steps.
 * ``suspension256`` -- 256^3, tau 0.6, 4096 particles, kT = 1e-4, 2000 steps,
-  FP32 / shifted BF16 / shifted FP16 storage.
+  FP32 / shifted BF16 / shifted FP16 storage, particle radius 0.5.
 * ``suspension512`` -- the same at 512^3.
+
+``radius`` 0 means "from Stokes' law" (gamma = 6 pi rho0 nu R).  At tau 0.6 that
+law would give R = 1.59, and the eight-node Stokeslet fit returns negative
+friction once R exceeds about 0.87 (the fitted gain for a particle at a cell
+centre in a uniform stream is 1 - 2R/sqrt(3)), so the coupled run diverges; the
+suspensions therefore keep the friction constant 1 and fix R = 0.5.
 
 They stand in for the paper's own runs (a 100^3 box of 500 particles), which
 use no external dataset.
@@ -24,13 +30,13 @@ import numpy as np
 
 WORKLOADS = {
     "relaxation32": dict(L=32, tau=1.0, storage="f64", n=1, mass=10.0, gamma=1.0, kT=0.0,
-                         steps=1000, seed=1001, kick=0.01),
+                         radius=0.0, steps=1000, seed=1001, kick=0.01),
     "vacf128": dict(L=128, tau=0.8, storage="f32", n=64, mass=10.0, gamma=1.0, kT=1e-4,
-                    steps=20000, seed=2002, max_lag=2000, stride=10),
+                    radius=0.0, steps=20000, seed=2002, max_lag=2000, stride=10),
     "suspension256": dict(L=256, tau=0.6, storage="f32", n=4096, mass=10.0, gamma=1.0, kT=1e-4,
-                          steps=2000, seed=3003, max_lag=500, stride=10),
+                          radius=0.5, steps=2000, seed=3003, max_lag=500, stride=10),
     "suspension512": dict(L=512, tau=0.6, storage="f32", n=4096, mass=10.0, gamma=1.0, kT=1e-4,
-                          steps=2000, seed=3004, max_lag=500, stride=10),
+                          radius=0.5, steps=2000, seed=3004, max_lag=500, stride=10),
 }
 
 

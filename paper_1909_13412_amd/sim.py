@@ -1,0 +1,185 @@
+"""Thin Python handle over the C ABI: torch provides device memory and the stream,
+every step of the method runs in the HIP kernels of liblbmbp.so."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _abi
+
+Q = _abi.LBM_Q
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _device_f64(a, device, shape=None):
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        t = a.to(device=device, dtype=torch.float64)
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+    t = t.contiguous()
+    if shape is not None:
+        t = t.reshape(shape)
+    return t
+
+
+def _alloc_bytes(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator hands out 512-byte aligned blocks
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class Lattice:
+    """One periodic box of nx*ny*nz nodes with two population lattices.
+
+    storage: "f64", "f32", "bf16" (shifted, round-to-nearest-even) or "f16"
+    (shifted, scaled by 2^f16_scale_log2).
+    """
+
+    def __init__(self, nx: int, ny: int, nz: int, tau: float, storage: str = "f32",
+                 f16_scale_log2: int = 16, device="cuda:0", stream: torch.cuda.Stream | None = None):
+        self.lib = _abi.load()
+        self.device = torch.device(device)
+        self.shape = (nz, ny, nx)
+        self.ncell = nx * ny * nz
+        self.tau = float(tau)
+        self.storage = storage
+        self.desc = _abi.GridDesc(nx, ny, nz, float(tau), _abi.STORAGE[storage], int(f16_scale_log2))
+        sz = ctypes.c_size_t()
+        _abi.check("lbm_lattice_bytes", self.lib.lbm_lattice_bytes(ctypes.byref(self.desc), ctypes.byref(sz)))
+        self.lattice_bytes = sz.value
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.pop_a = _alloc_bytes(self.lattice_bytes, self.device)
+            self.pop_b = _alloc_bytes(self.lattice_bytes, self.device)
+            _abi.check("lbm_grid_scratch_bytes",
+                       self.lib.lbm_grid_scratch_bytes(ctypes.byref(self.desc), ctypes.byref(sz)))
+            self.grid_scratch = _alloc_bytes(sz.value, self.device)
+            ctx = ctypes.c_void_p()
+            _abi.check("lbm_init", self.lib.lbm_init(ctypes.byref(self.desc), _ptr(self.pop_a),
+                                                     _ptr(self.pop_b), _ptr(self.grid_scratch),
+                                                     ctypes.c_void_p(self.stream.cuda_stream),
+                                                     ctypes.byref(ctx)))
+        self.ctx = ctx
+        self.n = 0
+        self.r = self.v = None
+        self._vacf = None
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.stream.synchronize()
+            self.lib.lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- fluid ------------------------------------------------------------
+    def set_equilibrium(self, rho=None, u=None):
+        self._rho_in = _device_f64(rho, self.device, (self.ncell,))
+        self._u_in = _device_f64(u, self.device, (3 * self.ncell,))
+        _abi.check("lbm_set_equilibrium",
+                   self.lib.lbm_set_equilibrium(self.ctx, _ptr(self._rho_in), _ptr(self._u_in)))
+
+    def set_populations(self, f):
+        self._f_in = _device_f64(f, self.device, (Q * self.ncell,))
+        _abi.check("lbm_set_populations", self.lib.lbm_set_populations(self.ctx, _ptr(self._f_in)))
+
+    def populations(self) -> torch.Tensor:
+        out = torch.empty((Q,) + self.shape, dtype=torch.float64, device=self.device)
+        _abi.check("lbm_get_populations", self.lib.lbm_get_populations(self.ctx, _ptr(out)))
+        return out
+
+    def moments(self):
+        rho = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        u = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        _abi.check("lbm_get_moments", self.lib.lbm_get_moments(self.ctx, _ptr(rho), _ptr(u)))
+        return rho, u
+
+    # -- particles --------------------------------------------------------
+    def particles_couple(self, r, v, mass=10.0, gamma=1.0, kT=0.0, radius=0.0, seed=0,
+                         replica=0, friction="stokeslet"):
+        r = _device_f64(r, self.device).reshape(-1, 3).clone()
+        v = _device_f64(v, self.device).reshape(-1, 3).clone()
+        n = r.shape[0]
+        if v.shape != r.shape:
+            raise ValueError("r and v must both be [n, 3]")
+        pd = _abi.ParticleDesc(n, _abi.FRICTION[friction], float(mass), float(gamma), float(kT),
+                               float(radius), int(seed), int(replica), 0)
+        sz = ctypes.c_size_t()
+        _abi.check("lbm_particle_scratch_bytes",
+                   self.lib.lbm_particle_scratch_bytes(ctypes.byref(self.desc), n, ctypes.byref(sz)))
+        scratch = _alloc_bytes(sz.value, self.device)
+        _abi.check("particles_couple", self.lib.particles_couple(self.ctx, ctypes.byref(pd), _ptr(r),
+                                                                 _ptr(v), _ptr(scratch)))
+        self.n, self.r, self.v, self.pdesc, self._pscratch = n, r, v, pd, scratch
+        self._vacf = None
+        self.fh = torch.zeros((n, 3), dtype=torch.float64, device=self.device)
+        self.fr = torch.zeros((n, 3), dtype=torch.float64, device=self.device)
+
+    @property
+    def radius(self) -> float:
+        return float(self.lib.lbm_particle_radius(self.ctx))
+
+    def particles(self):
+        """(r, v) device tensors [n, 3]; updated in place by every step."""
+        return self.r, self.v
+
+    def particle_forces(self):
+        _abi.check("lbm_particle_forces", self.lib.lbm_particle_forces(self.ctx, _ptr(self.fh), _ptr(self.fr)))
+        return self.fh, self.fr
+
+    # -- velocity autocorrelation ----------------------------------------
+    def vacf_config(self, max_lag: int, stride: int):
+        sz = ctypes.c_size_t()
+        _abi.check("lbm_vacf_origin_bytes",
+                   self.lib.lbm_vacf_origin_bytes(self.n, max_lag, stride, ctypes.byref(sz)))
+        acc = torch.empty((self.n, max_lag + 1), dtype=torch.float64, device=self.device)
+        origins = _alloc_bytes(sz.value, self.device)
+        _abi.check("lbm_vacf_config",
+                   self.lib.lbm_vacf_config(self.ctx, max_lag, stride, _ptr(acc), _ptr(origins)))
+        self._vacf = (acc, origins, max_lag)
+
+    def vacf(self):
+        """(acc [n, max_lag+1] device FP64, counts [max_lag+1] numpy int64)."""
+        acc, _, max_lag = self._vacf
+        cnt = np.zeros(max_lag + 1, dtype=np.int64)
+        _abi.check("lbm_vacf_counts", self.lib.lbm_vacf_counts(
+            self.ctx, cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return acc, cnt
+
+    # -- stepping and diagnostics ----------------------------------------
+    def step(self, nsteps: int = 1):
+        _abi.check("lbm_step", self.lib.lbm_step(self.ctx, int(nsteps)))
+
+    def observables(self, allow_nonfinite: bool = False) -> np.ndarray:
+        out = np.zeros(7)
+        code = self.lib.lbm_observables(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        _abi.check("lbm_observables", code, allow=(4,) if allow_nonfinite else ())
+        return out
+
+    def profile_enable(self, enable: bool = True):
+        _abi.check("lbm_profile_enable", self.lib.lbm_profile_enable(self.ctx, int(bool(enable))))
+
+    def profile_read(self) -> dict:
+        """Accumulated per-kernel event timings since the last read (then reset)."""
+        out = np.zeros(4)
+        _abi.check("lbm_profile_read",
+                   self.lib.lbm_profile_read(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return {"collide_ms": out[0], "collide_launches": int(out[1]),
+                "particle_ms": out[2], "particle_launches": int(out[3])}
+
+    @property
+    def step_count(self) -> int:
+        s = ctypes.c_int64()
+        _abi.check("lbm_get_step", self.lib.lbm_get_step(self.ctx, ctypes.byref(s)))
+        return s.value

@@ -1,0 +1,63 @@
+"""Shared helpers for the GPU parity tests: run the same seeded case through the
+HIP path (via the C ABI) and through the FP64 oracle, and compare."""
+import sys
+
+import numpy as np
+
+
+def nmax_err(x, ref) -> float:
+    """Normalised max error max|x - ref| / max|ref| (0/0 -> 0)."""
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.max(np.abs(ref))
+    diff = np.max(np.abs(x - ref)) if x.size else 0.0
+    if scale == 0.0:
+        return float(diff)
+    return float(diff / scale)
+
+
+def announce(msg: str):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_pair(oracle_mod, L, tau, storage, r, v, steps, *, mass=10.0, gamma=1.0, kT=0.0, seed=0,
+             friction="stokeslet", radius=0.0, rho=None, u=None, trace=False, vacf=None,
+             f16_scale_log2=16):
+    """Run the oracle and the GPU side by side.  L is (nx, ny, nz).
+    Returns dict with final fields/particles of both, and per-step traces."""
+    import torch
+
+    from paper_1909_13412_amd import Lattice
+
+    nx, ny, nz = L
+    gpu = Lattice(nx, ny, nz, tau, storage=storage, f16_scale_log2=f16_scale_log2)
+    ref = oracle_mod.Sim(nx, ny, nz, tau)
+    if rho is not None or u is not None:
+        gpu.set_equilibrium(rho, u)
+        ref.set_equilibrium(rho, u)
+    n = 0 if r is None else len(r)
+    if n:
+        kw = dict(mass=mass, gamma=gamma, kT=kT, radius=radius, seed=seed, friction=friction)
+        gpu.particles_couple(r, v, **kw)
+        ref.set_particles(r, v, **kw)
+        if vacf:
+            gpu.vacf_config(*vacf)
+            ref.vacf_config(*vacf)
+    out = {"gpu_trace_v": [], "ref_trace_v": [], "gpu_obs": [], "ref_obs": []}
+    if trace:
+        for _ in range(steps):
+            gpu.step(1)
+            ref.step(1)
+            if n:
+                out["gpu_trace_v"].append(gpu.v.cpu().numpy().copy())
+                out["ref_trace_v"].append(ref.particles()[1])
+            out["gpu_obs"].append(gpu.observables())
+            out["ref_obs"].append(ref.observables())
+    else:
+        gpu.step(steps)
+        ref.step(steps)
+    torch.cuda.synchronize()
+    out["gpu"] = gpu
+    out["ref"] = ref
+    return out

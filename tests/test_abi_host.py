@@ -1,0 +1,118 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point the
+header declares, sizes its buffers, and rejects bad arguments before touching a
+device.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1909_13412_amd import _abi
+
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.fail("liblbmbp.so is not built (run __graft_entry__.build())")
+    return _abi.load()
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "lbmbp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)))
+
+
+def test_header_and_binding_agree():
+    from paper_1909_13412_amd import _abi
+
+    assert sorted(_abi.EXPORTS) == _header_functions()
+    for name in ("lbm_init", "lbm_step", "particles_couple", "lbm_observables", "lbm_vacf_config"):
+        assert name in _abi.EXPORTS
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_header(lib):
+    from paper_1909_13412_amd import _abi
+
+    assert ctypes.sizeof(_abi.GridDesc) == 32
+    assert ctypes.sizeof(_abi.ParticleDesc) == 56
+
+
+def _grid(nx=16, ny=16, nz=16, tau=0.8, storage=1, s=16):
+    from paper_1909_13412_amd import _abi
+
+    return _abi.GridDesc(nx, ny, nz, tau, storage, s)
+
+
+def test_lattice_and_scratch_sizes(lib):
+    sz = ctypes.c_size_t()
+    for storage, elem in ((0, 8), (1, 4), (2, 2), (3, 2)):
+        g = _grid(nx=37, ny=23, nz=19, storage=storage)
+        assert lib.lbm_lattice_bytes(ctypes.byref(g), ctypes.byref(sz)) == 0
+        ncell = 37 * 23 * 19
+        assert sz.value >= 19 * ncell * elem
+        assert sz.value % 256 == 0
+        assert sz.value < 19 * (ncell + 256) * elem
+    g = _grid(nx=256, ny=256, nz=256)
+    assert lib.lbm_lattice_bytes(ctypes.byref(g), ctypes.byref(sz)) == 0
+    assert sz.value == 19 * 256**3 * 4
+    assert lib.lbm_grid_scratch_bytes(ctypes.byref(g), ctypes.byref(sz)) == 0
+    assert sz.value >= 2 * 256**3 // 8
+    assert lib.lbm_particle_scratch_bytes(ctypes.byref(g), 4096, ctypes.byref(sz)) == 0
+    assert sz.value > 0
+    assert lib.lbm_particle_scratch_bytes(ctypes.byref(g), 0, ctypes.byref(sz)) == 0
+    assert sz.value == 0
+    assert lib.lbm_vacf_origin_bytes(64, 2000, 10, ctypes.byref(sz)) == 0
+    assert sz.value == 201 * 64 * 3 * 8
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=1), dict(ny=0), dict(nz=-4), dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")),
+    dict(storage=7), dict(storage=3, s=40), dict(nx=2048, ny=2048, nz=1024),
+])
+def test_invalid_grids_rejected(lib, bad):
+    kw = dict(nx=8, ny=8, nz=8, tau=0.8, storage=1, s=16)
+    kw.update(bad)
+    g = _grid(**kw)
+    sz = ctypes.c_size_t()
+    assert lib.lbm_lattice_bytes(ctypes.byref(g), ctypes.byref(sz)) == 1
+    assert lib.lbm_grid_scratch_bytes(ctypes.byref(g), ctypes.byref(sz)) == 1
+    ctx = ctypes.c_void_p()
+    buf = ctypes.c_void_p(256)  # never dereferenced: validation fails first
+    assert lib.lbm_init(ctypes.byref(g), buf, ctypes.c_void_p(512), buf, None, ctypes.byref(ctx)) == 1
+
+
+def test_init_rejects_null_and_misaligned_buffers(lib):
+    g = _grid()
+    ctx = ctypes.c_void_p()
+    assert lib.lbm_init(ctypes.byref(g), None, ctypes.c_void_p(512), ctypes.c_void_p(1024), None,
+                        ctypes.byref(ctx)) == 1
+    assert lib.lbm_init(ctypes.byref(g), ctypes.c_void_p(260), ctypes.c_void_p(512),
+                        ctypes.c_void_p(1024), None, ctypes.byref(ctx)) == 1
+    assert lib.lbm_init(ctypes.byref(g), ctypes.c_void_p(512), ctypes.c_void_p(512),
+                        ctypes.c_void_p(1024), None, ctypes.byref(ctx)) == 1
+    assert lib.lbm_init(ctypes.byref(g), ctypes.c_void_p(512), ctypes.c_void_p(1024),
+                        ctypes.c_void_p(2048), None, None) == 1
+
+
+def test_null_context_rejected(lib):
+    out = (ctypes.c_double * 7)()
+    assert lib.lbm_step(None, 1) == 1
+    assert lib.lbm_observables(None, out) == 1
+    assert lib.lbm_destroy(None) == 1
+    assert lib.lbm_particle_radius(None) < 0
+
+
+def test_status_strings(lib):
+    for code in range(6):
+        s = lib.lbm_status_string(code)
+        assert isinstance(s, bytes) and len(s) > 0
+    assert lib.lbm_status_string(0) == b"ok"
+    assert lib.lbm_status_string(99) == b"unknown status"

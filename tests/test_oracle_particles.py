@@ -46,6 +46,25 @@ def test_fit_recovers_stokeslet_stream_at_cell_centre(oracle_mod):
         assert np.allclose(FH, 1.7 * U0 * e, rtol=1e-12, atol=1e-18)
 
 
+def test_fit_gain_in_uniform_stream_at_cell_centre(oracle_mod):
+    # Closed form for the particle at a cell centre in a uniform relative stream
+    # W along an axis: all corners sit at r = sqrt(3)/2 with (d.e)^2 = 1/4, so
+    # e.g_p = 1 - 2R/sqrt(3) and |g_p|^2 = (1 - 2R/sqrt(3))^2 + R^2/6, and
+    # F_H = gamma W (1 - 2R/sqrt(3)) / [(1 - 2R/sqrt(3))^2 + R^2/6].  The gain
+    # changes sign at R = sqrt(3)/2: beyond it the fit yields negative friction.
+    for R in (0.0, 0.2, 0.5, 0.8, np.sqrt(3) / 2, 1.0, 1.59):
+        for axis in range(3):
+            e = np.zeros(3)
+            e[axis] = 1.0
+            W = 2e-3
+            s = np.array([7.5, 3.5, 11.5])
+            V = np.array([1e-3, -2e-3, 5e-4])
+            FH = oracle_mod.friction_force("stokeslet", R, 0.7, s, V, np.tile(V + W * e, (8, 1)))
+            a = 1.0 - 2.0 * R / np.sqrt(3.0)
+            k = a / (a * a + R * R / 6.0)
+            assert np.allclose(FH, 0.7 * W * k * e, rtol=1e-12, atol=1e-17), (R, FH)
+
+
 def test_fit_with_zero_radius_is_eight_node_mean(oracle_mod):
     # R = 0 makes every shape vector equal e^N, so U^inf = |mean(w)| and
     # F_H = gamma (mean_p u_p - V).
