@@ -10,7 +10,9 @@ lags up to 500 and origins every 10 steps; synthetic seeded initial state.
 Prints ONE JSON line.  `value` is whole-step MLUPS (nodes x steps / s / 1e6) with
 FP32 population storage; `variants` repeats the timing for shifted BF16 and FP16
 storage; `roofline` prices the stream-collide kernel (the dominant one) against
-the 8 TB/s HBM peak from HIP-event timings taken inside the timed region;
+the 8 TB/s HBM peak from HIP-event timings of every launch in a second timed
+region (events add a few microseconds per step, so `value` comes from a region
+without them);
 `cpu_baseline` times the FP64 oracle on a few steps of the same workload.
 """
 from __future__ import annotations
@@ -28,6 +30,37 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 ELEM = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
 METRIC = "MLUPS & % HBM roofline, FP32 vs shifted-BF16 storage at stated VACF error"
+
+
+PMC_PROFILE = os.path.join(ROOT, "profiles", "k_stream_collide_suspension256.md")
+
+
+def kernel_source_hash() -> str:
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1909_13412_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_traffic(storage: str):
+    """HBM bytes per stream-collide launch from the committed FETCH_SIZE /
+    WRITE_SIZE profile (scaled by the copy-kernel calibration), or None when
+    the kernel sources changed since the counters were taken."""
+    try:
+        with open(PMC_PROFILE) as fh:
+            line = next(ln for ln in fh if ln.strip().startswith("PMC_TRAFFIC "))
+    except (OSError, StopIteration):
+        return None
+    rec = json.loads(line.strip()[len("PMC_TRAFFIC "):])
+    if rec.get("source_sha256") != kernel_source_hash() or not rec.get(storage):
+        return None
+    c = rec[storage]
+    return (c["fetch_kib"] * rec["fetch_scale"] + c["write_kib"] * rec["write_scale"]) * 1024.0
 
 
 def collide_bytes_per_node(storage: str) -> float:
@@ -49,41 +82,79 @@ def make_lattice(w, storage, device="cuda:0"):
     return lat
 
 
-def time_storage(w, storage, steps, warmup):
+def time_storage(w, storage, steps, warmup, prof_steps):
+    """Autotune the stream-collide launch shape, time `steps` whole steps with
+    nothing but the kernels on the stream (-> MLUPS), then time `prof_steps`
+    more with HIP events around every kernel launch (-> per-kernel durations;
+    the events themselves add a few microseconds per step, so they stay out
+    of the first region)."""
     import torch
 
     lat = make_lattice(w, storage)
     lat.step(warmup)
     torch.cuda.synchronize()
-    lat.profile_enable(True)
-    lat.profile_read()
+    shape, shape_ms = lat.autotune(20)
+    lat.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lat.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    lat.profile_enable(True)
+    lat.profile_read()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    lat.step(prof_steps)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
     prof = lat.profile_read()
     lat.profile_enable(False)
     obs = lat.observables()
     ncell = w["L"] ** 3
-    ms_step = (t1 - t0) * 1e3 / steps
-    mlups = ncell * steps / (t1 - t0) / 1e6
     coll_ms = prof["collide_ms"] / max(prof["collide_launches"], 1)
     part_ms = prof["particle_ms"] / max(prof["particle_launches"], 1)
     achieved = ncell * collide_bytes_per_node(storage) / (coll_ms * 1e-3) / 1e9
     res = {
         "storage": storage,
-        "mlups": mlups,
-        "ms_per_step": ms_step,
+        "mlups": ncell * steps / (t1 - t0) / 1e6,
+        "ms_per_step": (t1 - t0) * 1e3 / steps,
+        "profiled_ms_per_step": (t3 - t2) * 1e3 / prof_steps,
         "collide_ms": coll_ms,
         "particle_phase_ms": part_ms,
         "collide_GBs": achieved,
         "collide_frac": achieved / HBM_PEAK_GBS,
+        "collide_shape": shape,
+        "autotune_ms": [round(float(x), 5) for x in shape_ms],
         "mass": obs[0],
     }
     del lat
     torch.cuda.empty_cache()
     return res
+
+
+def copy_probe(nbytes, reps=20):
+    """Plain device copy of `nbytes` (one lattice's worth): the practical
+    read+write ceiling next to the stream-collide, and the reference kernel
+    for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    for _ in range(3):
+        dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "ms": round(ms, 5),
+            "GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
 def precision_study(w, steps, storages=("f32", "bf16", "f16")):
@@ -161,6 +232,8 @@ def main():
     ap.add_argument("--variants", default="bf16,f16")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps timed (0 = skip)")
     ap.add_argument("--precision-steps", type=int, default=2000, help="0 = skip the VACF error study")
+    ap.add_argument("--prof-steps", type=int, default=300, help="steps timed with per-kernel events")
+    ap.add_argument("--no-copy-probe", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -178,14 +251,19 @@ def main():
     w = dict(WORKLOADS[args.workload])
     w["name"] = args.workload
 
+    copy = None
+    if not args.no_copy_probe:
+        print("[bench] copy probe", file=sys.stderr, flush=True)
+        copy = copy_probe(19 * w["L"] ** 3 * ELEM[args.storage])
     print(f"[bench] timing {args.workload} storage={args.storage} steps={args.steps}", file=sys.stderr,
           flush=True)
-    main_res = time_storage(w, args.storage, args.steps, args.warmup)
+    main_res = time_storage(w, args.storage, args.steps, args.warmup, args.prof_steps)
     variants = {}
     for s in [v for v in args.variants.split(",") if v and v != args.storage]:
         print(f"[bench] timing storage={s}", file=sys.stderr, flush=True)
-        r = time_storage(w, s, args.steps, args.warmup)
+        r = time_storage(w, s, args.steps, args.warmup, args.prof_steps)
         r["speedup_vs_main"] = r["mlups"] / main_res["mlups"]
+        r["traffic"] = pmc_traffic(s)
         variants[s] = r
     precision = None
     if args.precision_steps > 0:
@@ -223,11 +301,18 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(main_res["collide_frac"], 4),
-            "traffic": None,
+            "traffic": pmc_traffic(args.storage),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, "
+                            "copy-calibrated; null if the kernels changed since)",
+            "algorithmic_bytes_per_launch": collide_bytes_per_node(args.storage) * ncell,
             "bytes_per_node": collide_bytes_per_node(args.storage),
             "avg_launch_ms": round(main_res["collide_ms"], 5),
+            "launch_shape": main_res["collide_shape"],
+            "autotune_ms": main_res["autotune_ms"],
         },
+        "profiled_ms_per_step": round(main_res["profiled_ms_per_step"], 5),
         "particle_phase_ms": round(main_res["particle_phase_ms"], 5),
+        "copy_probe": copy,
         "variants": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                      for k, v in variants.items()},
         "precision": precision,

@@ -103,11 +103,12 @@ typedef struct lbm_ctx lbm_ctx;
  * step).  Planes may be padded; the caller only allocates this many bytes. */
 lbm_status lbm_lattice_bytes(const lbm_grid_desc *grid, size_t *bytes);
 
-/* Bytes of grid scratch (forced-node bitmasks, reduction partials, flags). */
+/* Bytes of grid scratch: two node-force fields (24 bytes per node each) with
+ * their one-bit flags, reduction partials and flags. */
 lbm_status lbm_grid_scratch_bytes(const lbm_grid_desc *grid, size_t *bytes);
 
-/* Bytes of particle scratch for n particles (forced-node hash tables, corner
- * bookkeeping, last-step forces). */
+/* Bytes of particle scratch for n particles (corner bookkeeping, last-step
+ * forces). */
 lbm_status lbm_particle_scratch_bytes(const lbm_grid_desc *grid, int32_t n, size_t *bytes);
 
 /* Bytes of the VACF origin store for n particles: (max_lag/stride + 1) * n * 3 doubles. */
@@ -161,9 +162,9 @@ lbm_status lbm_vacf_config(lbm_ctx *ctx, int32_t max_lag, int32_t stride, double
  * far (the same for every particle). */
 lbm_status lbm_vacf_counts(const lbm_ctx *ctx, int64_t *cnt);
 
-/* Advance nsteps coupled steps (asynchronous).  Per step: VACF sample (if
- * configured), particle coupling (gather, fit, random force, spreading,
- * Langevin update), fused stream-collide with the forcing. */
+/* Advance nsteps coupled steps (asynchronous).  Per step: one particle kernel
+ * (VACF sample if configured, gather, fit, random force, spreading, Langevin
+ * update), then the fused stream-collide with the forcing. */
 lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps);
 
 /* Synchronous FP64 sums over the current state: out[0] fluid mass sum rho~,
@@ -182,6 +183,19 @@ lbm_status lbm_profile_enable(lbm_ctx *ctx, int32_t enable);
  * out[0] summed stream-collide milliseconds, out[1] stream-collide launches,
  * out[2] summed particle-phase milliseconds, out[3] particle-phase launches. */
 lbm_status lbm_profile_read(lbm_ctx *ctx, double out[4]);
+
+/* Stream-collide launch shapes: 0 = one node per lane, 512-lane blocks;
+ * 1 = one node, 256; 2 = two nodes (rows y and y + ny/2), 512; 3 = two
+ * nodes, 256 (shapes 2 and 3 need an even ny). */
+#define LBM_NUM_SHAPES 4
+
+/* Time every valid stream-collide shape on this context's lattice (iters
+ * launches each, reading the current populations and writing the spare
+ * lattice, so the simulation state is not changed) and keep the fastest for
+ * later lbm_step calls.  Synchronises the stream.  ms (host, LBM_NUM_SHAPES
+ * entries, may be NULL) receives the mean milliseconds per launch (-1 for a
+ * shape that does not apply); *chosen (may be NULL) the shape kept. */
+lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen);
 
 /* Number of steps taken since lbm_init. */
 lbm_status lbm_get_step(const lbm_ctx *ctx, int64_t *step);

@@ -19,8 +19,10 @@ EXPORTS = [
     "lbm_vacf_origin_bytes", "lbm_init", "lbm_set_equilibrium", "lbm_set_populations",
     "lbm_get_populations", "lbm_get_moments", "particles_couple", "lbm_particle_radius",
     "lbm_particle_forces", "lbm_vacf_config", "lbm_vacf_counts", "lbm_step", "lbm_observables",
-    "lbm_profile_enable", "lbm_profile_read", "lbm_get_step", "lbm_destroy", "lbm_status_string",
+    "lbm_profile_enable", "lbm_profile_read", "lbm_autotune", "lbm_get_step", "lbm_destroy",
+    "lbm_status_string",
 ]
+LBM_NUM_SHAPES = 4
 
 
 class GridDesc(ctypes.Structure):
@@ -74,6 +76,7 @@ def load() -> ctypes.CDLL:
         "lbm_observables": [vp, ctypes.POINTER(ctypes.c_double)],
         "lbm_profile_enable": [vp, i32],
         "lbm_profile_read": [vp, ctypes.POINTER(ctypes.c_double)],
+        "lbm_autotune": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],
         "lbm_get_step": [vp, ctypes.POINTER(i64)],
         "lbm_destroy": [vp],
     }

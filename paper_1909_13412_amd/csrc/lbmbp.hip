@@ -2,12 +2,12 @@
 // (Yoshida, Kinjo & Washizu, arXiv:1909.13412), hand-written HIP for gfx950.
 //
 // One coupled step n (section 2):
-//   [k_vacf]          C_i(l) += V_i(t0) . V_i(n)                    (section 2.1)
 //   k_particle        per particle, eight lanes = eight neighbour nodes:
+//                     VACF sample C_i(l) += V_i(t0).V_i(n) (section 2.1),
 //                     gather u^n at the nodes (Eq. s2-fv), Stokeslet fit
 //                     (Eq. s2-slet-v) -> F_H, Philox Brownian force
-//                     (Eqs. s2-rf1, s2-rf2), spread -F_H into the forced-node
-//                     table (first Eq. s2-force), Langevin update (Eqs.
+//                     (Eqs. s2-rf1, s2-rf2), spread -F_H into the node-force
+//                     field (first Eq. s2-force), Langevin update (Eqs.
 //                     s2-langevin, s2-langevin2)
 //   k_stream_collide  every node: pull f^n_a(x) = A_a(x - e_a) (Eq. s2-trans of
 //                     the previous step), moments (Eqs. s2-density, s2-fv),
@@ -15,9 +15,13 @@
 //                     Eq. s2-force) where the node is flagged, write B_a(x)
 //                     (Eq. s2-coll); A and B swap.
 //
-// Layout: structure of arrays, one plane of nx*ny*nz values per velocity,
-// x fastest.  Lattice A holds post-collision values at their source node, so
-// the post-streaming population is read by pulling from x - e_a.
+// Layout: for every lattice row (y, z) the 19 population rows are stored one
+// after another, x fastest: element (a, x, y, z) sits at
+// ((z*ny + y)*19 + a)*chunk + x, chunk = nx rounded up to a 128-byte line.  A
+// block streams whole rows, so each wave reads nine contiguous 19-row groups
+// and writes one; this beats one plane per velocity (38 far-apart streams).
+// Lattice A holds post-collision values at their source node, so the
+// post-streaming population is read by pulling from x - e_a.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -36,8 +40,9 @@
 namespace lbmbp {
 
 constexpr int kBlock = 256;
+constexpr int kParticleBlock = 64;  // eight particles per block: spread over every CU
 constexpr int kRedBlocks = 1024;
-constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 // Node forces are accumulated as 64-bit fixed point (2^-48 resolution) so that
 // the sum over particles sharing a node is exact and order independent: runs
 // are bitwise reproducible.  |contribution| must stay below 2^14.
@@ -49,20 +54,23 @@ constexpr uint32_t kErrFixRange = 1u;
 struct Grid {
     uint32_t nx, ny, nz;
     uint32_t ncell;
-    uint64_t pstride;  // elements between velocity planes
+    uint32_t chunk;  // elements per population row (nx padded to a 128-byte line)
 };
 
-struct ForceTable {
-    uint32_t *keys;    // [cap] node index or kEmpty
-    long long *vals;   // [cap][3] fixed-point force
-    uint32_t *mask;    // one bit per node: node carries a force this step
-    uint32_t capmask;  // cap - 1 (cap is a power of two)
-    uint32_t shift;    // 32 - log2(cap)
-};
-
-__device__ inline uint32_t hash_slot(uint32_t cell, uint32_t shift) {
-    return (cell * 2654435769u) >> shift;  // Fibonacci hashing
+// Storage index of population a at node (x, y, z).
+__device__ inline uint64_t pop_index(const Grid &g, uint32_t x, uint32_t y, uint32_t z, int a) {
+    return (uint64_t(z * g.ny + y) * D3Q19::Q + uint32_t(a)) * g.chunk + x;
 }
+
+// Node forces of one step: a dense fixed-point field, written only at the
+// (at most 8 per particle) nodes that receive a reaction force and read only
+// where the one-bit flag is set, so the stream-collide pays 1/8 byte per node.
+// Two of them alternate between steps; each is cleared node by node by the
+// particles that wrote it.
+struct ForceField {
+    long long *f;    // [ncell][3] fixed-point force
+    uint32_t *mask;  // one bit per node: node carries a force this step
+};
 
 // Source node of direction a for a pull at (x, y, z): x - e_a, periodic.
 struct Neighbours {
@@ -78,9 +86,15 @@ struct Neighbours {
         sz[1] = z;
         sz[2] = (z == 0) ? g.nz - 1 : z - 1;
     }
+    // linear node index of x - e_a (canonical [z][y][x] order)
     template <int a>
     __device__ inline uint32_t src(const Grid &g) const {
         return (sz[D3Q19::ez[a] + 1] * g.ny + sy[D3Q19::ey[a] + 1]) * g.nx + sx[D3Q19::ex[a] + 1];
+    }
+    // storage index of population a at x - e_a
+    template <int a>
+    __device__ inline uint64_t pop(const Grid &g) const {
+        return pop_index(g, sx[D3Q19::ex[a] + 1], sy[D3Q19::ey[a] + 1], sz[D3Q19::ez[a] + 1], a);
     }
 };
 
@@ -94,62 +108,89 @@ __device__ inline void static_for(F &&f) {
 
 // ---------------------------------------------------------------------------
 // Fused pull stream-collide with sparse forcing.
+//
+// Each lane updates CPT nodes with the same x in rows y, y + ny/CPT, ...: all
+// 19 x CPT population loads (and the forcing flags) are issued before any of
+// them is consumed, which keeps more bytes in flight per wave.  BS lanes per
+// block.  Lattice A -> B; F is the node-force field of this step.
 // ---------------------------------------------------------------------------
-template <class C, bool FORCED>
-__global__ __launch_bounds__(kBlock) void k_stream_collide(const typename C::T *__restrict__ A,
-                                                           typename C::T *__restrict__ B, Grid g,
-                                                           typename C::R omega,
-                                                           typename C::R enc_s,
-                                                           typename C::R dec_s, ForceTable ft) {
+template <class C, bool FORCED, int CPT, int BS>
+__global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__restrict__ A,
+                                                       typename C::T *__restrict__ B, Grid g,
+                                                       typename C::R omega, typename C::R enc_s,
+                                                       typename C::R dec_s, ForceField ff) {
     using T = typename C::T;
     using R = typename C::R;
-    const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
-    if (cell >= g.ncell) return;
-    const uint32_t x = cell % g.nx;
-    const uint32_t t = cell / g.nx;
-    const uint32_t y = t % g.ny;
-    const uint32_t z = t / g.ny;
-    const Neighbours nb(x, y, z, g);
+    const uint32_t lane_cell = blockIdx.x * BS + threadIdx.x;  // node index in the first row band
+    const uint32_t band = g.ncell / CPT;                         // nodes per band of ny/CPT rows
+    if (lane_cell >= band) return;
+    const uint32_t x = lane_cell % g.nx;
+    const uint32_t t = lane_cell / g.nx;
+    const uint32_t rows = g.ny / CPT;
+    const uint32_t y0 = t % rows;
+    const uint32_t z = t / rows;
 
-    R gv[D3Q19::Q];
-    static_for<0, D3Q19::Q>([&](auto ac) {
-        constexpr int a = decltype(ac)::value;
-        gv[a] = C::dec(A[a * g.pstride + nb.src<a>(g)], dec_s);
-    });
-    R drho = R(0), ux = R(0), uy = R(0), uz = R(0);
-    static_for<0, D3Q19::Q>([&](auto ac) {
-        constexpr int a = decltype(ac)::value;
-        drho += gv[a];
-        if constexpr (D3Q19::ex[a] != 0) ux += D3Q19::ex[a] > 0 ? gv[a] : -gv[a];
-        if constexpr (D3Q19::ey[a] != 0) uy += D3Q19::ey[a] > 0 ? gv[a] : -gv[a];
-        if constexpr (D3Q19::ez[a] != 0) uz += D3Q19::ez[a] > 0 ? gv[a] : -gv[a];
-    });
-    const R uu = ux * ux + uy * uy + uz * uz;
-    R Fx = R(0), Fy = R(0), Fz = R(0);
-    if constexpr (FORCED) {
-        const uint32_t word = ft.mask[cell >> 5];
-        if ((word >> (cell & 31)) & 1u) {
-            uint32_t slot = hash_slot(cell, ft.shift);
-            for (uint32_t probe = 0; probe <= ft.capmask; ++probe) {
-                if (ft.keys[slot] == cell) break;
-                slot = (slot + 1) & ft.capmask;
-            }
-            Fx = R(double(ft.vals[3 * slot + 0]) * kFixInv);
-            Fy = R(double(ft.vals[3 * slot + 1]) * kFixInv);
-            Fz = R(double(ft.vals[3 * slot + 2]) * kFixInv);
+    T raw[CPT][D3Q19::Q];
+    uint32_t flags[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const uint32_t y = y0 + uint32_t(c) * rows;
+        const Neighbours nb(x, y, z, g);
+        static_for<0, D3Q19::Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            raw[c][a] = A[nb.pop<a>(g)];
+        });
+        if constexpr (FORCED) {
+            const uint32_t cell = (z * g.ny + y) * g.nx + x;
+            flags[c] = (ff.mask[cell >> 5] >> (cell & 31)) & 1u;
         }
     }
-    static_for<0, D3Q19::Q>([&](auto ac) {
-        constexpr int a = decltype(ac)::value;
-        constexpr int cx = D3Q19::ex[a], cy = D3Q19::ey[a], cz = D3Q19::ez[a];
-        const R w = D3Q19::w<R>(a);
-        const R eu = R(cx) * ux + R(cy) * uy + R(cz) * uz;
-        const R geq = w * (drho + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
-        R gn = gv[a] + omega * (geq - gv[a]);
-        if constexpr (FORCED) gn += R(3) * w * (R(cx) * Fx + R(cy) * Fy + R(cz) * Fz);
-        B[a * g.pstride + cell] = C::enc(gn, enc_s);
-    });
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const uint32_t y = y0 + uint32_t(c) * rows;
+        R gv[D3Q19::Q];
+        static_for<0, D3Q19::Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            gv[a] = C::dec(raw[c][a], dec_s);
+        });
+        R drho = R(0), ux = R(0), uy = R(0), uz = R(0);
+        static_for<0, D3Q19::Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            drho += gv[a];
+            if constexpr (D3Q19::ex[a] != 0) ux += D3Q19::ex[a] > 0 ? gv[a] : -gv[a];
+            if constexpr (D3Q19::ey[a] != 0) uy += D3Q19::ey[a] > 0 ? gv[a] : -gv[a];
+            if constexpr (D3Q19::ez[a] != 0) uz += D3Q19::ez[a] > 0 ? gv[a] : -gv[a];
+        });
+        const R uu = ux * ux + uy * uy + uz * uz;
+        R Fx = R(0), Fy = R(0), Fz = R(0);
+        if constexpr (FORCED) {
+            if (flags[c]) {
+                const uint64_t cell = (z * g.ny + y) * g.nx + x;
+                Fx = R(double(ff.f[3 * cell + 0]) * kFixInv);
+                Fy = R(double(ff.f[3 * cell + 1]) * kFixInv);
+                Fz = R(double(ff.f[3 * cell + 2]) * kFixInv);
+            }
+        }
+        const uint64_t row_base = uint64_t(z * g.ny + y) * D3Q19::Q * g.chunk + x;
+        static_for<0, D3Q19::Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            constexpr int cx = D3Q19::ex[a], cy = D3Q19::ey[a], cz = D3Q19::ez[a];
+            const R w = D3Q19::w<R>(a);
+            const R eu = R(cx) * ux + R(cy) * uy + R(cz) * uz;
+            const R geq = w * (drho + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
+            R gn = gv[a] + omega * (geq - gv[a]);
+            if constexpr (FORCED) gn += R(3) * w * (R(cx) * Fx + R(cy) * Fy + R(cz) * Fz);
+            B[row_base + uint64_t(a) * g.chunk] = C::enc(gn, enc_s);
+        });
+    }
 }
+
+// Launch shapes of the stream-collide, chosen per context (lbm_autotune).
+struct CollideShape {
+    int cpt, bs;
+};
+constexpr CollideShape kShapes[] = {{1, 512}, {1, 256}, {2, 512}, {2, 256}};
+constexpr int kNumShapes = 4;
 
 // ---------------------------------------------------------------------------
 // Particle coupling: eight lanes per particle, lane p owns neighbour node
@@ -158,8 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide(const typename C::T *
 struct ParticleArgs {
     double *r, *v;
     double *fh, *fr;
-    int32_t *prev_slot;
-    uint32_t *prev_cell;
+    uint32_t *prev_cell;  // [n][8] node each lane spread to last step, or kNoNode
     uint32_t *err;
     int32_t n;
     int32_t friction;
@@ -167,6 +207,13 @@ struct ParticleArgs {
     uint64_t seed;
     uint32_t replica;
     uint32_t step;
+    // velocity autocorrelation (acc == nullptr: off).  Origins k*stride with
+    // k in [k_lo, k_hi] are active at sample time t; origin k lives in slot
+    // k % nslot.
+    double *acc;      // [n][max_lag+1]
+    double *origins;  // [nslot][n][3]
+    int64_t t, k_lo, k_hi;
+    int32_t nslot, stride, max_lag;
 };
 
 __device__ inline double sum8(double v) {
@@ -177,10 +224,11 @@ __device__ inline double sum8(double v) {
 }
 
 template <class C>
-__global__ __launch_bounds__(kBlock) void k_particle(const typename C::T *__restrict__ A, Grid g,
-                                                     typename C::R dec_s, ParticleArgs pa,
-                                                     ForceTable cur, ForceTable old) {
-    const uint32_t gt = blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kParticleBlock) void k_particle(const typename C::T *__restrict__ A,
+                                                             Grid g, typename C::R dec_s,
+                                                             ParticleArgs pa, ForceField cur,
+                                                             ForceField old) {
+    const uint32_t gt = blockIdx.x * kParticleBlock + threadIdx.x;
     const int32_t i = int32_t(gt >> 3);
     const int p = int(gt & 7u);
     const bool valid = i < pa.n;
@@ -200,32 +248,78 @@ __global__ __launch_bounds__(kBlock) void k_particle(const typename C::T *__rest
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double L = double(Ln[k]);
-        const double s = r[k] - L * floor(r[k] / L);  // wrapped position, in [0, L]
+        const double s = r[k] - L * floor(r[k] / L);  // wrapped position, in [-eps, L]
         const double c = floor(s);
         d[k] = (c + double(b[k])) - s;                // node minus particle, unwrapped
-        // c may equal L after rounding; the modulo also keeps a non-finite
-        // position (converted with saturation) inside the box
-        node[k] = (uint32_t(c) + uint32_t(b[k])) % Ln[k];
+        // Rounding can leave c at -1 or L; the periodic wrap handles both (a
+        // non-finite position converts with saturation and stays in the box).
+        int32_t ci = (int32_t(c) + b[k]) % int32_t(Ln[k]);
+        node[k] = uint32_t(ci < 0 ? ci + int32_t(Ln[k]) : ci);
         W *= 1.0 - fabs(d[k]);
     }
     const uint32_t cell = (node[2] * g.ny + node[1]) * g.nx + node[0];
+    const bool coupled = pa.friction != LBM_FRICTION_BD;
+
+    // Issue the gather of f^n at this lane's node (pull from node - e_a); the
+    // values are consumed only after the VACF sample and the Brownian force,
+    // which overlap the load latency.
+    typename C::T raw[D3Q19::Q];
+    if (coupled) {
+        const Neighbours nb(node[0], node[1], node[2], g);
+        static_for<1, D3Q19::Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            raw[a] = A[nb.pop<a>(g)];
+        });
+    }
+
+    // C_v(t) = <V(0).V(t)> (section 2.1): V^n against every active origin;
+    // lane p takes the origins k = k_lo + p, k_lo + p + 8, ...  The newest
+    // origin (lag 0) is stored by the lane that owns it.
+    if (valid && pa.acc) {
+        double *acc_i = pa.acc + int64_t(i) * (pa.max_lag + 1);
+        for (int64_t k = pa.k_lo + p; k <= pa.k_hi; k += 8) {
+            double *o = pa.origins + (int64_t(k % pa.nslot) * pa.n + i) * 3;
+            const int64_t lag = pa.t - k * pa.stride;
+            if (lag == 0) {
+                o[0] = V[0];
+                o[1] = V[1];
+                o[2] = V[2];
+                acc_i[0] += V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
+            } else {
+                acc_i[lag] += o[0] * V[0] + o[1] * V[1] + o[2] * V[2];
+            }
+        }
+    }
+
+    // Eqs. s2-rf1, s2-rf2: white noise of variance 2 gamma kT per step.  The
+    // three Box-Muller outputs are computed by lanes 0, 1, 2 of the group
+    // (one logarithm, square root and sine/cosine each) and gathered.
+    double FR[3] = {0.0, 0.0, 0.0};
+    if (pa.sig > 0.0) {
+        const Philox4x32 x = philox4x32_10(pa.step, uint32_t(i), pa.replica, 0u,
+                                           uint32_t(pa.seed), uint32_t(pa.seed >> 32));
+        const int q = p < 3 ? p : 0;
+        const uint32_t wa = q == 2 ? x.v[2] : x.v[0];
+        const uint32_t wb = q == 2 ? x.v[3] : x.v[1];
+        double zq;
+        box_muller_one(wa, wb, q == 1, &zq);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) FR[k] = pa.sig * __shfl(zq, k, 8);
+    }
 
     double FH[3] = {0.0, 0.0, 0.0};
-    if (pa.friction == LBM_FRICTION_BD) {
+    if (!coupled) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) FH[k] = -pa.gamma * V[k];
     } else {
         // u^n at this lane's node: u = sum_a e_a f_a = sum_a e_a g_a (Eq. s2-fv).
-        const Neighbours nb(node[0], node[1], node[2], g);
         double u[3] = {0.0, 0.0, 0.0};
-        static_for<0, D3Q19::Q>([&](auto ac) {
+        static_for<1, D3Q19::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            if constexpr (a != 0) {
-                const double gvl = double(C::dec(A[a * g.pstride + nb.src<a>(g)], dec_s));
-                if constexpr (D3Q19::ex[a] != 0) u[0] += D3Q19::ex[a] > 0 ? gvl : -gvl;
-                if constexpr (D3Q19::ey[a] != 0) u[1] += D3Q19::ey[a] > 0 ? gvl : -gvl;
-                if constexpr (D3Q19::ez[a] != 0) u[2] += D3Q19::ez[a] > 0 ? gvl : -gvl;
-            }
+            const double gvl = double(C::dec(raw[a], dec_s));
+            if constexpr (D3Q19::ex[a] != 0) u[0] += D3Q19::ex[a] > 0 ? gvl : -gvl;
+            if constexpr (D3Q19::ey[a] != 0) u[1] += D3Q19::ey[a] > 0 ? gvl : -gvl;
+            if constexpr (D3Q19::ez[a] != 0) u[2] += D3Q19::ez[a] > 0 ? gvl : -gvl;
         });
         if (pa.friction == LBM_FRICTION_POINTWISE) {
             // Eq. s2-dis1 with u(r) interpolated trilinearly.
@@ -269,20 +363,18 @@ __global__ __launch_bounds__(kBlock) void k_particle(const typename C::T *__rest
     }
     if (!valid) return;
 
-    // Release this lane's node from the table used one step ago (its entries
-    // were consumed by that step's stream-collide).
-    const int32_t ps = pa.prev_slot[8 * i + p];
-    if (ps >= 0) {
-        const uint32_t pc = pa.prev_cell[8 * i + p];
-        old.keys[ps] = kEmpty;
-        old.vals[3 * ps + 0] = 0;
-        old.vals[3 * ps + 1] = 0;
-        old.vals[3 * ps + 2] = 0;
+    // Release this lane's node from the field used one step ago (it was
+    // consumed by that step's stream-collide).
+    const uint32_t pc = pa.prev_cell[8 * i + p];
+    if (pc != kNoNode) {
+        old.f[3 * uint64_t(pc) + 0] = 0;
+        old.f[3 * uint64_t(pc) + 1] = 0;
+        old.f[3 * uint64_t(pc) + 2] = 0;
         atomicAnd(&old.mask[pc >> 5], ~(1u << (pc & 31)));
     }
     // First Eq. s2-force: the node receives -F_H W_p (unit cell volume).
-    int32_t my_slot = -1;
-    if (pa.friction != LBM_FRICTION_BD) {
+    uint32_t my_cell = kNoNode;
+    if (coupled) {
         long long q[3];
         bool ok = true;
 #pragma unroll
@@ -295,31 +387,16 @@ __global__ __launch_bounds__(kBlock) void k_particle(const typename C::T *__rest
             atomicOr(pa.err, kErrFixRange);
             q[0] = q[1] = q[2] = 0;
         }
-        uint32_t slot = hash_slot(cell, cur.shift);
-        for (uint32_t probe = 0; probe <= cur.capmask; ++probe) {
-            const uint32_t prev = atomicCAS(&cur.keys[slot], kEmpty, cell);
-            if (prev == kEmpty || prev == cell) break;
-            slot = (slot + 1) & cur.capmask;
-        }
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            atomicAdd(reinterpret_cast<unsigned long long *>(&cur.vals[3 * slot + k]),
+            atomicAdd(reinterpret_cast<unsigned long long *>(&cur.f[3 * uint64_t(cell) + k]),
                       static_cast<unsigned long long>(q[k]));
         atomicOr(&cur.mask[cell >> 5], 1u << (cell & 31));
-        my_slot = int32_t(slot);
+        my_cell = cell;
     }
-    pa.prev_slot[8 * i + p] = my_slot;
-    pa.prev_cell[8 * i + p] = cell;
+    pa.prev_cell[8 * i + p] = my_cell;
 
     if (p != 0) return;
-    // Eqs. s2-rf1, s2-rf2: white noise of variance 2 gamma kT per step.
-    double FR[3] = {0.0, 0.0, 0.0};
-    if (pa.sig > 0.0) {
-        double z[3];
-        gauss3(pa.seed, pa.step, uint32_t(i), pa.replica, 0u, z);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) FR[k] = pa.sig * z[k];
-    }
     // Eqs. s2-langevin, s2-langevin2 with dt = 1 (F_C = 0).
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -329,35 +406,6 @@ __global__ __launch_bounds__(kBlock) void k_particle(const typename C::T *__rest
         pa.fh[3 * i + k] = FH[k];
         pa.fr[3 * i + k] = FR[k];
     }
-}
-
-// ---------------------------------------------------------------------------
-// Velocity autocorrelation, one thread per (origin slot, particle).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_vacf(const double *__restrict__ v, int32_t n,
-                                                 int32_t nslot, int32_t stride, int32_t max_lag,
-                                                 int64_t t, double *__restrict__ origins,
-                                                 double *__restrict__ acc) {
-    const int64_t gt = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (gt >= int64_t(n) * nslot) return;
-    const int32_t i = int32_t(gt % n);
-    const int32_t s = int32_t(gt / n);
-    const double vx = v[3 * i], vy = v[3 * i + 1], vz = v[3 * i + 2];
-    const int64_t kn = t / stride;
-    double *o = origins + (int64_t(s) * n + i) * 3;
-    if (t % stride == 0 && s == int32_t(kn % nslot)) {
-        o[0] = vx;
-        o[1] = vy;
-        o[2] = vz;
-        acc[int64_t(i) * (max_lag + 1)] += vx * vx + vy * vy + vz * vz;
-        return;
-    }
-    const int64_t back = ((kn - s) % nslot + nslot) % nslot;
-    const int64_t k = kn - back;
-    if (k < 0) return;
-    const int64_t lag = t - k * stride;
-    if (lag > max_lag) return;
-    acc[int64_t(i) * (max_lag + 1) + lag] += o[0] * vx + o[1] * vy + o[2] * vz;
 }
 
 // ---------------------------------------------------------------------------
@@ -374,7 +422,7 @@ __global__ __launch_bounds__(kBlock) void k_get_populations(const typename C::T 
     static_for<0, D3Q19::Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         f[uint64_t(a) * g.ncell + cell] =
-            double(C::dec(A[a * g.pstride + nb.src<a>(g)], dec_s)) + D3Q19::w<double>(a);
+            double(C::dec(A[nb.pop<a>(g)], dec_s)) + D3Q19::w<double>(a);
     });
 }
 
@@ -390,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_get_moments(const typename C::T *__r
     double dr = 0.0, m[3] = {0.0, 0.0, 0.0};
     static_for<0, D3Q19::Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        const double gvl = double(C::dec(A[a * g.pstride + nb.src<a>(g)], dec_s));
+        const double gvl = double(C::dec(A[nb.pop<a>(g)], dec_s));
         dr += gvl;
         m[0] += D3Q19::ex[a] * gvl;
         m[1] += D3Q19::ey[a] * gvl;
@@ -418,7 +466,7 @@ __global__ __launch_bounds__(kBlock) void k_set_populations(const double *__rest
         constexpr int a = decltype(ac)::value;
         constexpr int o = (a == 0) ? 0 : ((a & 1) ? a + 1 : a - 1);
         const double gvl = f[uint64_t(a) * g.ncell + nb.src<o>(g)] - D3Q19::w<double>(a);
-        A[a * g.pstride + cell] = C::enc(typename C::R(gvl), enc_s);
+        A[pop_index(g, x, y, z, a)] = C::enc(typename C::R(gvl), enc_s);
     });
 }
 
@@ -445,7 +493,7 @@ __global__ __launch_bounds__(kBlock) void k_set_equilibrium(const double *__rest
         const double eu = D3Q19::ex[a] * uc[0] + D3Q19::ey[a] * uc[1] + D3Q19::ez[a] * uc[2];
         const double uu = uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2];
         const double geq = D3Q19::w<double>(a) * (dr + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-        A[a * g.pstride + cell] = C::enc(typename C::R(geq), enc_s);
+        A[pop_index(g, x, y, z, a)] = C::enc(typename C::R(geq), enc_s);
     });
 }
 
@@ -463,7 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_fluid_partials(const typename C::T *
         const Neighbours nb(x, y, z, g);
         static_for<0, D3Q19::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            const double gvl = double(C::dec(A[a * g.pstride + nb.src<a>(g)], dec_s));
+            const double gvl = double(C::dec(A[nb.pop<a>(g)], dec_s));
             acc[0] += gvl;
             acc[1] += D3Q19::ex[a] * gvl;
             acc[2] += D3Q19::ey[a] * gvl;
@@ -522,6 +570,7 @@ struct lbm_ctx {
     double enc_s, dec_s;
     // grid scratch
     uint32_t *mask[2];
+    long long *force[2];  // [ncell][3] fixed-point node forces, alternating steps
     uint32_t mask_words;
     double *partials;
     double *result;
@@ -531,10 +580,6 @@ struct lbm_ctx {
     lbm_particle_desc pdesc;
     double R;
     double *r, *v;
-    uint32_t *keys[2];
-    long long *vals[2];
-    uint32_t cap, shift;
-    int32_t *prev_slot;
     uint32_t *prev_cell;
     double *fh, *fr;
     // velocity autocorrelation
@@ -548,6 +593,7 @@ struct lbm_ctx {
     hipEvent_t *prof_ev;    // pairs: [2k] start, [2k+1] stop
     int32_t *prof_kind;     // per pair: 0 stream-collide, 1 particle phase
     int32_t prof_used, prof_cap;
+    int shape;  // index into kShapes
 };
 
 namespace {
@@ -581,37 +627,30 @@ uint64_t ncell_of(const lbm_grid_desc *g) {
     return uint64_t(g->nx) * uint64_t(g->ny) * uint64_t(g->nz);
 }
 
-// Elements between velocity planes: whole 256-byte lines.
-uint64_t plane_stride(const lbm_grid_desc *g) {
-    const uint64_t per_line = kAlign / elem_size(g->storage);
-    return align_up(ncell_of(g), per_line);
+// Elements per population row: nx rounded up to a 128-byte line.
+uint32_t row_chunk(const lbm_grid_desc *g) {
+    const uint32_t per_line = uint32_t(128 / elem_size(g->storage));
+    return uint32_t(align_up(uint32_t(g->nx), per_line));
 }
 
 uint32_t mask_words(uint64_t ncell) { return uint32_t(align_up((ncell + 31) / 32, 64)); }
+
+size_t force_field_bytes(const lbm_grid_desc *g) { return align_up(ncell_of(g) * 3 * 8, kAlign); }
 
 size_t grid_scratch_size(const lbm_grid_desc *g) {
     const size_t words = mask_words(ncell_of(g));
     size_t s = 0;
     s += 2 * align_up(words * 4, kAlign);            // two bitmasks
+    s += 2 * force_field_bytes(g);                   // two node-force fields
     s += align_up(size_t(kRedBlocks) * 4 * 8, kAlign);  // partials
     s += align_up(8 * 8, kAlign);                    // result
     s += kAlign;                                      // error flags
     return s;
 }
 
-uint32_t table_cap(int32_t n) {
-    uint32_t cap = 64;
-    while (cap < uint32_t(16) * uint32_t(n)) cap <<= 1;
-    return cap;
-}
-
 size_t particle_scratch_size(int32_t n) {
     if (n <= 0) return 0;
-    const size_t cap = table_cap(n);
     size_t s = 0;
-    s += 2 * align_up(cap * 4, kAlign);        // keys
-    s += 2 * align_up(cap * 3 * 8, kAlign);    // values
-    s += align_up(size_t(n) * 8 * 4, kAlign);  // prev slot
     s += align_up(size_t(n) * 8 * 4, kAlign);  // prev cell
     s += 2 * align_up(size_t(n) * 3 * 8, kAlign);  // fh, fr
     return s;
@@ -625,16 +664,28 @@ lbm_status launch_status() {
 }
 
 unsigned blocks_for(uint64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+bool shape_ok(const lbm_ctx *c, int k) { return c->g.ny % uint32_t(kShapes[k].cpt) == 0; }
 
-ForceTable table(lbm_ctx *c, int par) {
-    ForceTable t;
-    t.keys = c->np > 0 ? c->keys[par] : nullptr;
-    t.vals = c->np > 0 ? c->vals[par] : nullptr;
-    t.mask = c->mask[par];
-    t.capmask = c->np > 0 ? c->cap - 1 : 0;
-    t.shift = c->np > 0 ? c->shift : 31;
-    return t;
+template <class C, bool FORCED, int CPT, int BS>
+void launch_collide_shape(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff) {
+    using R = typename C::R;
+    const uint64_t band = c->g.ncell / CPT;
+    hipLaunchKernelGGL((k_stream_collide<C, FORCED, CPT, BS>), dim3(unsigned((band + BS - 1) / BS)),
+                       dim3(BS), 0, c->stream, A, B, c->g, R(c->omega), R(c->enc_s), R(c->dec_s),
+                       ff);
 }
+
+template <class C, bool FORCED>
+void launch_collide(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff, int shape) {
+    switch (shape) {
+        case 1: launch_collide_shape<C, FORCED, 1, 256>(c, A, B, ff); break;
+        case 2: launch_collide_shape<C, FORCED, 2, 512>(c, A, B, ff); break;
+        case 3: launch_collide_shape<C, FORCED, 2, 256>(c, A, B, ff); break;
+        default: launch_collide_shape<C, FORCED, 1, 512>(c, A, B, ff); break;
+    }
+}
+
+ForceField field(lbm_ctx *c, int par) { return ForceField{c->force[par], c->mask[par]}; }
 
 // Returns the start event of a new timing pair (or nullptr when profiling is
 // off); the caller records it before the launch and prof_stop after.
@@ -674,19 +725,30 @@ void launch_step(lbm_ctx *c) {
     const int par = int(c->step & 1);
     if (c->np > 0) {
         const int32_t pk = prof_start(c, 1);
+        ParticleArgs pa;
+        pa.acc = nullptr;
+        pa.origins = nullptr;
+        pa.t = pa.k_lo = 0;
+        pa.k_hi = -1;
+        pa.nslot = pa.stride = 1;
+        pa.max_lag = 0;
         if (c->vacf_on) {
-            const int64_t work = int64_t(c->np) * c->nslot;
-            hipLaunchKernelGGL(k_vacf, dim3(blocks_for(work)), dim3(kBlock), 0, c->stream, c->v,
-                               c->np, c->nslot, c->stride, c->max_lag, c->vacf_t, c->origins,
-                               c->acc);
+            // active origins k*stride with t - max_lag <= k*stride <= t
+            const int64_t t = c->vacf_t;
+            pa.acc = c->acc;
+            pa.origins = c->origins;
+            pa.t = t;
+            pa.k_hi = t / c->stride;
+            pa.k_lo = t > c->max_lag ? (t - c->max_lag + c->stride - 1) / c->stride : 0;
+            pa.nslot = c->nslot;
+            pa.stride = c->stride;
+            pa.max_lag = c->max_lag;
             c->vacf_t += 1;
         }
-        ParticleArgs pa;
         pa.r = c->r;
         pa.v = c->v;
         pa.fh = c->fh;
         pa.fr = c->fr;
-        pa.prev_slot = c->prev_slot;
         pa.prev_cell = c->prev_cell;
         pa.err = c->err;
         pa.n = c->np;
@@ -698,23 +760,56 @@ void launch_step(lbm_ctx *c) {
         pa.seed = c->pdesc.seed;
         pa.replica = c->pdesc.replica;
         pa.step = uint32_t(c->step);
-        hipLaunchKernelGGL(k_particle<C>, dim3(blocks_for(uint64_t(c->np) * 8)), dim3(kBlock), 0,
-                           c->stream, A, c->g, R(c->dec_s), pa, table(c, par), table(c, par ^ 1));
+        hipLaunchKernelGGL(k_particle<C>, dim3(unsigned((uint64_t(c->np) * 8 + kParticleBlock - 1) / kParticleBlock)), dim3(kParticleBlock), 0,
+                           c->stream, A, c->g, R(c->dec_s), pa, field(c, par), field(c, par ^ 1));
         prof_stop(c, pk);
         const int32_t ck = prof_start(c, 0);
-        hipLaunchKernelGGL((k_stream_collide<C, true>), dim3(blocks_for(c->g.ncell)), dim3(kBlock),
-                           0, c->stream, A, B, c->g, R(c->omega), R(c->enc_s), R(c->dec_s),
-                           table(c, par));
+        launch_collide<C, true>(c, A, B, field(c, par), c->shape);
         prof_stop(c, ck);
     } else {
         const int32_t ck = prof_start(c, 0);
-        hipLaunchKernelGGL((k_stream_collide<C, false>), dim3(blocks_for(c->g.ncell)),
-                           dim3(kBlock), 0, c->stream, A, B, c->g, R(c->omega), R(c->enc_s),
-                           R(c->dec_s), table(c, par));
+        launch_collide<C, false>(c, A, B, field(c, par), c->shape);
         prof_stop(c, ck);
     }
     c->cur ^= 1;
     c->step += 1;
+}
+
+// Times every valid stream-collide shape on A -> B without swapping (the
+// simulation state in A is untouched; B is the next step's output anyway).
+// With particles attached the forced variant is timed, reading the node
+// forces of the last step (still in place until the next particle kernel).
+template <class C>
+void time_shapes(lbm_ctx *c, int32_t iters, double *ms, hipError_t *err) {
+    using T = typename C::T;
+    const T *A = static_cast<const T *>(c->pop[c->cur]);
+    T *B = static_cast<T *>(c->pop[c->cur ^ 1]);
+    hipEvent_t e0, e1;
+    *err = hipEventCreate(&e0);
+    if (*err == hipSuccess) *err = hipEventCreate(&e1);
+    if (*err != hipSuccess) return;
+    const bool forced = c->np > 0;
+    const ForceField last = field(c, int((c->step + 1) & 1));
+    auto launch = [&](int k) {
+        if (forced)
+            launch_collide<C, true>(c, A, B, last, k);
+        else
+            launch_collide<C, false>(c, A, B, last, k);
+    };
+    for (int k = 0; k < kNumShapes && *err == hipSuccess; ++k) {
+        ms[k] = -1.0;
+        if (!shape_ok(c, k)) continue;
+        for (int w = 0; w < 2; ++w) launch(k);
+        hipEventRecord(e0, c->stream);
+        for (int it = 0; it < iters; ++it) launch(k);
+        hipEventRecord(e1, c->stream);
+        *err = hipEventSynchronize(e1);
+        float t = 0.0f;
+        if (*err == hipSuccess) *err = hipEventElapsedTime(&t, e0, e1);
+        ms[k] = double(t) / iters;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
 }
 
 template <class C>
@@ -768,7 +863,9 @@ extern "C" {
 
 lbm_status lbm_lattice_bytes(const lbm_grid_desc *grid, size_t *bytes) {
     if (!grid_ok(grid) || !bytes) return LBM_E_INVAL;
-    *bytes = size_t(plane_stride(grid)) * LBM_Q * elem_size(grid->storage);
+    *bytes = align_up(size_t(row_chunk(grid)) * LBM_Q * size_t(grid->ny) * size_t(grid->nz) *
+                          elem_size(grid->storage),
+                      kAlign);
     return LBM_OK;
 }
 
@@ -802,7 +899,7 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
     c->g.ny = uint32_t(grid->ny);
     c->g.nz = uint32_t(grid->nz);
     c->g.ncell = uint32_t(ncell_of(grid));
-    c->g.pstride = plane_stride(grid);
+    c->g.chunk = row_chunk(grid);
     c->elem = elem_size(grid->storage);
     c->pop[0] = pop_a;
     c->pop[1] = pop_b;
@@ -821,6 +918,10 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
     s += align_up(size_t(c->mask_words) * 4, kAlign);
     c->mask[1] = reinterpret_cast<uint32_t *>(s);
     s += align_up(size_t(c->mask_words) * 4, kAlign);
+    c->force[0] = reinterpret_cast<long long *>(s);
+    s += force_field_bytes(grid);
+    c->force[1] = reinterpret_cast<long long *>(s);
+    s += force_field_bytes(grid);
     c->partials = reinterpret_cast<double *>(s);
     s += align_up(size_t(kRedBlocks) * 4 * 8, kAlign);
     c->result = reinterpret_cast<double *>(s);
@@ -878,10 +979,14 @@ lbm_status particles_couple(lbm_ctx *ctx, const lbm_particle_desc *d, double *r,
         if (d->friction < LBM_FRICTION_STOKESLET || d->friction > LBM_FRICTION_BD)
             return LBM_E_INVAL;
     }
-    // Forced-node state from any previous particle set is cleared.
+    // Node forces left by any previous particle set are cleared.
     hipError_t e = hipMemsetAsync(ctx->mask[0], 0, size_t(ctx->mask_words) * 4, ctx->stream);
     if (e == hipSuccess)
         e = hipMemsetAsync(ctx->mask[1], 0, size_t(ctx->mask_words) * 4, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(ctx->force[0], 0, force_field_bytes(&ctx->desc), ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(ctx->force[1], 0, force_field_bytes(&ctx->desc), ctx->stream);
     if (e != hipSuccess) return LBM_E_DEVICE;
     ctx->vacf_on = 0;
     ctx->np = d->n;
@@ -895,36 +1000,16 @@ lbm_status particles_couple(lbm_ctx *ctx, const lbm_particle_desc *d, double *r,
     ctx->R = d->radius > 0.0 ? d->radius : d->gamma / (6.0 * M_PI * nu);
     ctx->r = r;
     ctx->v = v;
-    ctx->cap = table_cap(d->n);
-    int lg = 0;
-    while ((1u << lg) < ctx->cap) ++lg;
-    ctx->shift = uint32_t(32 - lg);
     char *s = static_cast<char *>(particle_scratch);
-    ctx->keys[0] = reinterpret_cast<uint32_t *>(s);
-    s += align_up(size_t(ctx->cap) * 4, kAlign);
-    ctx->keys[1] = reinterpret_cast<uint32_t *>(s);
-    s += align_up(size_t(ctx->cap) * 4, kAlign);
-    ctx->vals[0] = reinterpret_cast<long long *>(s);
-    s += align_up(size_t(ctx->cap) * 3 * 8, kAlign);
-    ctx->vals[1] = reinterpret_cast<long long *>(s);
-    s += align_up(size_t(ctx->cap) * 3 * 8, kAlign);
-    ctx->prev_slot = reinterpret_cast<int32_t *>(s);
-    s += align_up(size_t(d->n) * 8 * 4, kAlign);
     ctx->prev_cell = reinterpret_cast<uint32_t *>(s);
     s += align_up(size_t(d->n) * 8 * 4, kAlign);
     ctx->fh = reinterpret_cast<double *>(s);
     s += align_up(size_t(d->n) * 3 * 8, kAlign);
     ctx->fr = reinterpret_cast<double *>(s);
-    // keys -> kEmpty (all ones), prev_slot -> -1 (all ones), the rest zero.
-    e = hipMemsetAsync(ctx->keys[0], 0xFF, size_t(ctx->cap) * 4, ctx->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->keys[1], 0xFF, size_t(ctx->cap) * 4, ctx->stream);
-    if (e == hipSuccess)
-        e = hipMemsetAsync(ctx->vals[0], 0, size_t(ctx->cap) * 3 * 8, ctx->stream);
-    if (e == hipSuccess)
-        e = hipMemsetAsync(ctx->vals[1], 0, size_t(ctx->cap) * 3 * 8, ctx->stream);
-    if (e == hipSuccess)
-        e = hipMemsetAsync(ctx->prev_slot, 0xFF, size_t(d->n) * 8 * 4, ctx->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->fh, 0, size_t(d->n) * 3 * 8 * 2, ctx->stream);
+    // prev_cell -> kNoNode (all ones); forces zero.
+    e = hipMemsetAsync(ctx->prev_cell, 0xFF, size_t(d->n) * 8 * 4, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->fh, 0, size_t(d->n) * 3 * 8, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->fr, 0, size_t(d->n) * 3 * 8, ctx->stream);
     return e == hipSuccess ? LBM_OK : LBM_E_DEVICE;
 }
 
@@ -1024,6 +1109,27 @@ lbm_status lbm_profile_read(lbm_ctx *ctx, double out[4]) {
     }
     ctx->prof_used = 0;
     for (int k = 0; k < 4; ++k) out[k] = acc[k];
+    return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen) {
+    if (!ctx || iters < 1 || iters > 10000) return LBM_E_INVAL;
+    double t[kNumShapes];
+    hipError_t err = hipSuccess;
+    switch (ctx->desc.storage) {
+        case LBM_STORE_F64: time_shapes<CodecF64>(ctx, iters, t, &err); break;
+        case LBM_STORE_F32: time_shapes<CodecF32>(ctx, iters, t, &err); break;
+        case LBM_STORE_BF16: time_shapes<CodecBF16>(ctx, iters, t, &err); break;
+        case LBM_STORE_F16: time_shapes<CodecF16>(ctx, iters, t, &err); break;
+    }
+    if (err != hipSuccess || launch_status() != LBM_OK) return LBM_E_DEVICE;
+    int best = 0;
+    for (int k = 0; k < kNumShapes; ++k)
+        if (t[k] > 0.0 && (t[best] <= 0.0 || t[k] < t[best])) best = k;
+    ctx->shape = best;
+    if (ms)
+        for (int k = 0; k < kNumShapes; ++k) ms[k] = t[k];
+    if (chosen) *chosen = best;
     return LBM_OK;
 }
 

@@ -35,6 +35,21 @@ __device__ inline Philox4x32 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2
     return Philox4x32{{c0, c1, c2, c3}};
 }
 
+// Maps a 32-bit word to the open unit interval: (x + 1/2) 2^-32.
+__device__ inline double unit_open(uint32_t x) {
+    return (double(x) + 0.5) * 2.3283064365386962890625e-10;
+}
+
+// One Box-Muller output from two words: sqrt(-2 ln u_a) times cos(2 pi u_b)
+// (or sin when `sine`), the same numbers gauss3 produces.
+__device__ inline void box_muller_one(uint32_t wa, uint32_t wb, bool sine, double *z) {
+    constexpr double two_pi = 6.283185307179586476925286766559;
+    const double rad = sqrt(-2.0 * log(unit_open(wa)));
+    double sn, cs;
+    sincos(two_pi * unit_open(wb), &sn, &cs);
+    *z = rad * (sine ? sn : cs);
+}
+
 // Three standard normals for (step, particle, replica, stream) under `seed`.
 // Words map to the open unit interval as (x + 1/2) 2^-32; (u0, u1) give two
 // normals, (u2, u3) the third.

@@ -178,6 +178,15 @@ class Lattice:
         return {"collide_ms": out[0], "collide_launches": int(out[1]),
                 "particle_ms": out[2], "particle_launches": int(out[3])}
 
+    def autotune(self, iters: int = 20):
+        """Time the stream-collide launch shapes on this lattice (state unchanged)
+        and keep the fastest.  Returns (chosen shape, ms per launch of each)."""
+        ms = np.zeros(_abi.LBM_NUM_SHAPES)
+        chosen = ctypes.c_int32()
+        _abi.check("lbm_autotune", self.lib.lbm_autotune(
+            self.ctx, int(iters), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(chosen)))
+        return chosen.value, ms
+
     @property
     def step_count(self) -> int:
         s = ctypes.c_int64()

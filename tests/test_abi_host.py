@@ -59,7 +59,10 @@ def test_lattice_and_scratch_sizes(lib):
         ncell = 37 * 23 * 19
         assert sz.value >= 19 * ncell * elem
         assert sz.value % 256 == 0
-        assert sz.value < 19 * (ncell + 256) * elem
+        # population rows are padded to whole 128-byte lines
+        per_line = 128 // elem
+        chunk = -(-37 // per_line) * per_line
+        assert sz.value == -(-(19 * chunk * 23 * 19 * elem) // 256) * 256
     g = _grid(nx=256, ny=256, nz=256)
     assert lib.lbm_lattice_bytes(ctypes.byref(g), ctypes.byref(sz)) == 0
     assert sz.value == 19 * 256**3 * 4
