@@ -3,7 +3,8 @@
 
 A step is the whole hot path: VACF sample, particle coupling (gather at the eight
 neighbour nodes, Stokeslet fit, Philox Brownian force, reaction-force spreading,
-Langevin update) and the fused stream-collide with forcing.  Workload (default):
+Langevin update) and the fused stream-collide with forcing; every 10th step also
+records the FP64 mass and momentum sums (fused into the same kernels).  Workload (default):
 256^3 periodic box, tau 0.6, 4096 particles (M 10, gamma 1, R 0.5, kT 1e-4), VACF with
 lags up to 500 and origins every 10 steps; synthetic seeded initial state.
 
@@ -69,7 +70,10 @@ def collide_bytes_per_node(storage: str) -> float:
     return 2 * 19 * ELEM[storage] + 1.0 / 8.0
 
 
-def make_lattice(w, storage, device="cuda:0"):
+SERIES_EVERY = 10  # FP64 mass/momentum sums recorded inside the step kernels every 10 steps
+
+
+def make_lattice(w, storage, device="cuda:0", series_capacity=0):
     from paper_1909_13412_amd import Lattice
     from paper_1909_13412_amd.inputs import workload_particles
 
@@ -79,6 +83,8 @@ def make_lattice(w, storage, device="cuda:0"):
     lat.particles_couple(r, v, mass=w["mass"], gamma=w["gamma"], kT=w["kT"], radius=w["radius"],
                          seed=w["seed"])
     lat.vacf_config(w["max_lag"], w["stride"])
+    if series_capacity > 0:
+        lat.series_config(SERIES_EVERY, series_capacity)
     return lat
 
 
@@ -90,7 +96,7 @@ def time_storage(w, storage, steps, warmup, prof_steps):
     of the first region)."""
     import torch
 
-    lat = make_lattice(w, storage)
+    lat = make_lattice(w, storage, series_capacity=(2 * warmup + steps + prof_steps) // SERIES_EVERY + 2)
     lat.step(warmup)
     torch.cuda.synchronize()
     shape, shape_ms = lat.autotune(20)
@@ -293,6 +299,7 @@ def main():
                    "particles": w["n"], "kT": w["kT"], "gamma": w["gamma"], "radius": w["radius"],
                    "mass": w["mass"], "storage": args.storage,
                    "vacf": {"max_lag": w["max_lag"], "stride": w["stride"]},
+                   "fp64_sums_every": SERIES_EVERY,
                    "parallelism": "single GPU"},
         "roofline": {
             "kernel": "k_stream_collide",

@@ -167,6 +167,19 @@ lbm_status lbm_vacf_counts(const lbm_ctx *ctx, int64_t *cnt);
  * update), then the fused stream-collide with the forcing. */
 lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps);
 
+/* Record FP64 sums during lbm_step without extra passes over the lattice:
+ * every `every` steps, starting with the next step, series[8k .. 8k+7] =
+ * {step, fluid mass sum rho~, fluid momentum sum u (3), particle momentum
+ * sum M V (3)} of the state at the start of that step, for k < capacity
+ * (recording stops when full).  The fluid sums are taken inside the
+ * stream-collide and the particle sums inside the particle kernel, as
+ * per-block FP64 partials finished in a fixed order (deterministic).
+ * series: device FP64 [capacity][8], caller-owned.  every = 0 stops. */
+lbm_status lbm_series_config(lbm_ctx *ctx, int32_t every, double *series, int64_t capacity);
+
+/* Number of series entries recorded since lbm_series_config. */
+lbm_status lbm_series_count(const lbm_ctx *ctx, int64_t *count);
+
 /* Synchronous FP64 sums over the current state: out[0] fluid mass sum rho~,
  * out[1..3] fluid momentum sum u, out[4..6] particle momentum sum M V.
  * Returns LBM_E_NONFINITE (after filling out) if any value is not finite or a

@@ -18,7 +18,8 @@ EXPORTS = [
     "lbm_lattice_bytes", "lbm_grid_scratch_bytes", "lbm_particle_scratch_bytes",
     "lbm_vacf_origin_bytes", "lbm_init", "lbm_set_equilibrium", "lbm_set_populations",
     "lbm_get_populations", "lbm_get_moments", "particles_couple", "lbm_particle_radius",
-    "lbm_particle_forces", "lbm_vacf_config", "lbm_vacf_counts", "lbm_step", "lbm_observables",
+    "lbm_particle_forces", "lbm_vacf_config", "lbm_vacf_counts", "lbm_step", "lbm_series_config",
+    "lbm_series_count", "lbm_observables",
     "lbm_profile_enable", "lbm_profile_read", "lbm_autotune", "lbm_get_step", "lbm_destroy",
     "lbm_status_string",
 ]
@@ -73,6 +74,8 @@ def load() -> ctypes.CDLL:
         "lbm_vacf_config": [vp, i32, i32, dp, dp],
         "lbm_vacf_counts": [vp, ctypes.POINTER(i64)],
         "lbm_step": [vp, i32],
+        "lbm_series_config": [vp, i32, dp, i64],
+        "lbm_series_count": [vp, ctypes.POINTER(i64)],
         "lbm_observables": [vp, ctypes.POINTER(ctypes.c_double)],
         "lbm_profile_enable": [vp, i32],
         "lbm_profile_read": [vp, ctypes.POINTER(ctypes.c_double)],

@@ -114,16 +114,43 @@ __device__ inline void static_for(F &&f) {
 // them is consumed, which keeps more bytes in flight per wave.  BS lanes per
 // block.  Lattice A -> B; F is the node-force field of this step.
 // ---------------------------------------------------------------------------
-template <class C, bool FORCED, int CPT, int BS>
+// Deterministic block sum of N doubles (fixed butterfly and wave order);
+// thread k < N writes out[k].  Every thread of the block must call it.
+template <int N, int BS>
+__device__ inline void block_sum(double (&v)[N], double *__restrict__ out) {
+    __shared__ double sh[BS / 64][N];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) sh[threadIdx.x >> 6][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < N) {
+        double s = 0.0;
+        for (int w = 0; w < BS / 64; ++w) s += sh[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+template <class C, bool FORCED, bool MOMENTS, int CPT, int BS>
 __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__restrict__ A,
                                                        typename C::T *__restrict__ B, Grid g,
                                                        typename C::R omega, typename C::R enc_s,
-                                                       typename C::R dec_s, ForceField ff) {
+                                                       typename C::R dec_s, ForceField ff,
+                                                       double *__restrict__ mom) {
     using T = typename C::T;
     using R = typename C::R;
     const uint32_t lane_cell = blockIdx.x * BS + threadIdx.x;  // node index in the first row band
     const uint32_t band = g.ncell / CPT;                         // nodes per band of ny/CPT rows
-    if (lane_cell >= band) return;
+    const bool active = lane_cell < band;
+    if constexpr (!MOMENTS) {
+        if (!active) return;
+    }
+    // FP64 sums of (rho~ - 1, u) over this lane's nodes (MOMENTS only)
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (active) {
     const uint32_t x = lane_cell % g.nx;
     const uint32_t t = lane_cell / g.nx;
     const uint32_t rows = g.ny / CPT;
@@ -162,6 +189,12 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
             if constexpr (D3Q19::ez[a] != 0) uz += D3Q19::ez[a] > 0 ? gv[a] : -gv[a];
         });
         const R uu = ux * ux + uy * uy + uz * uz;
+        if constexpr (MOMENTS) {
+            acc[0] += double(drho);
+            acc[1] += double(ux);
+            acc[2] += double(uy);
+            acc[3] += double(uz);
+        }
         R Fx = R(0), Fy = R(0), Fz = R(0);
         if constexpr (FORCED) {
             if (flags[c]) {
@@ -183,6 +216,8 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
             B[row_base + uint64_t(a) * g.chunk] = C::enc(gn, enc_s);
         });
     }
+    }  // active
+    if constexpr (MOMENTS) block_sum<4, BS>(acc, mom + 4 * uint64_t(blockIdx.x));
 }
 
 // Launch shapes of the stream-collide, chosen per context (lbm_autotune).
@@ -214,6 +249,8 @@ struct ParticleArgs {
     double *origins;  // [nslot][n][3]
     int64_t t, k_lo, k_hi;
     int32_t nslot, stride, max_lag;
+    // per-block FP64 sums of M V^n (nullptr: off), [blocks][3]
+    double *pmom;
 };
 
 __device__ inline double sum8(double v) {
@@ -239,6 +276,13 @@ __global__ __launch_bounds__(kParticleBlock) void k_particle(const typename C::T
     for (int k = 0; k < 3; ++k) {
         r[k] = pa.r[3 * ii + k];
         V[k] = pa.v[3 * ii + k];
+    }
+    if (pa.pmom) {
+        // particle momentum M V^n of the state at the start of the step
+        double pm[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pm[k] = (valid && p == 0) ? pa.mass * V[k] : 0.0;
+        block_sum<3, kParticleBlock>(pm, pa.pmom + 3 * uint64_t(blockIdx.x));
     }
     const uint32_t Ln[3] = {g.nx, g.ny, g.nz};
     const int b[3] = {p & 1, (p >> 1) & 1, (p >> 2) & 1};
@@ -406,6 +450,38 @@ __global__ __launch_bounds__(kParticleBlock) void k_particle(const typename C::T
         pa.fh[3 * i + k] = FH[k];
         pa.fr[3 * i + k] = FR[k];
     }
+}
+
+// ---------------------------------------------------------------------------
+// Recorded observables: two fixed-order stages over the per-block partials
+// left by the stream-collide (rho~ - 1, u) and the particle kernel (M V).
+// ---------------------------------------------------------------------------
+constexpr int kSeriesBlocks = 64;
+
+__global__ __launch_bounds__(kBlock) void k_series_stage1(const double *__restrict__ fluid,
+                                                          int32_t nfluid,
+                                                          const double *__restrict__ part,
+                                                          int32_t npart,
+                                                          double *__restrict__ stage) {
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    const int32_t stride = kSeriesBlocks * kBlock;
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < nfluid; i += stride)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += fluid[4 * int64_t(i) + k];
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < npart; i += stride)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[4 + k] += part[3 * int64_t(i) + k];
+    block_sum<7, kBlock>(v, stage + 7 * blockIdx.x);
+}
+
+__global__ void k_series_stage2(const double *__restrict__ stage, double ncell, double step,
+                                double *__restrict__ out) {
+    if (threadIdx.x < 7) {
+        double s = 0.0;
+        for (int b = 0; b < kSeriesBlocks; ++b) s += stage[7 * b + threadIdx.x];
+        out[1 + threadIdx.x] = threadIdx.x == 0 ? ncell + s : s;
+    }
+    if (threadIdx.x == 0) out[0] = step;
 }
 
 // ---------------------------------------------------------------------------
@@ -594,6 +670,13 @@ struct lbm_ctx {
     int32_t *prof_kind;     // per pair: 0 stream-collide, 1 particle phase
     int32_t prof_used, prof_cap;
     int shape;  // index into kShapes
+    // recorded observables (lbm_series_config)
+    int32_t series_every;
+    double *series;
+    int64_t series_cap, series_count, series_t;
+    double *fluid_partials;  // grid scratch: [collide blocks][4]
+    double *series_stage;    // grid scratch: [kSeriesBlocks][7]
+    double *part_partials;   // particle scratch: [particle blocks][3]
 };
 
 namespace {
@@ -637,21 +720,32 @@ uint32_t mask_words(uint64_t ncell) { return uint32_t(align_up((ncell + 31) / 32
 
 size_t force_field_bytes(const lbm_grid_desc *g) { return align_up(ncell_of(g) * 3 * 8, kAlign); }
 
+// Per-block moment partials of the largest stream-collide grid (256-lane
+// blocks, one node per lane).
+size_t fluid_partials_bytes(const lbm_grid_desc *g) {
+    return align_up((ncell_of(g) / 256 + 1) * 4 * 8, kAlign);
+}
+
 size_t grid_scratch_size(const lbm_grid_desc *g) {
     const size_t words = mask_words(ncell_of(g));
     size_t s = 0;
     s += 2 * align_up(words * 4, kAlign);            // two bitmasks
     s += 2 * force_field_bytes(g);                   // two node-force fields
+    s += fluid_partials_bytes(g);                    // recorded-moment partials
+    s += align_up(size_t(kSeriesBlocks) * 7 * 8, kAlign);
     s += align_up(size_t(kRedBlocks) * 4 * 8, kAlign);  // partials
     s += align_up(8 * 8, kAlign);                    // result
     s += kAlign;                                      // error flags
     return s;
 }
 
+size_t particle_blocks(int32_t n) { return (size_t(n) * 8 + kParticleBlock - 1) / kParticleBlock; }
+
 size_t particle_scratch_size(int32_t n) {
     if (n <= 0) return 0;
     size_t s = 0;
     s += align_up(size_t(n) * 8 * 4, kAlign);  // prev cell
+    s += align_up(particle_blocks(n) * 3 * 8, kAlign);  // momentum partials
     s += 2 * align_up(size_t(n) * 3 * 8, kAlign);  // fh, fr
     return s;
 }
@@ -666,23 +760,38 @@ lbm_status launch_status() {
 unsigned blocks_for(uint64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 bool shape_ok(const lbm_ctx *c, int k) { return c->g.ny % uint32_t(kShapes[k].cpt) == 0; }
 
-template <class C, bool FORCED, int CPT, int BS>
-void launch_collide_shape(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff) {
-    using R = typename C::R;
-    const uint64_t band = c->g.ncell / CPT;
-    hipLaunchKernelGGL((k_stream_collide<C, FORCED, CPT, BS>), dim3(unsigned((band + BS - 1) / BS)),
-                       dim3(BS), 0, c->stream, A, B, c->g, R(c->omega), R(c->enc_s), R(c->dec_s),
-                       ff);
+uint32_t collide_grid(const lbm_ctx *c, int shape) {
+    const uint64_t band = c->g.ncell / uint32_t(kShapes[shape].cpt);
+    return uint32_t((band + kShapes[shape].bs - 1) / kShapes[shape].bs);
 }
 
+template <class C, bool FORCED, bool MOMENTS, int CPT, int BS>
+void launch_collide_shape(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff,
+                          double *mom, unsigned grid) {
+    using R = typename C::R;
+    hipLaunchKernelGGL((k_stream_collide<C, FORCED, MOMENTS, CPT, BS>), dim3(grid), dim3(BS), 0,
+                       c->stream, A, B, c->g, R(c->omega), R(c->enc_s), R(c->dec_s), ff, mom);
+}
+
+// mom != nullptr: also leave the per-block FP64 moment sums there.
 template <class C, bool FORCED>
-void launch_collide(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff, int shape) {
+void launch_collide(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff, int shape,
+                    double *mom = nullptr) {
+    const unsigned grid = collide_grid(c, shape);
+#define LBM_SHAPE(CPT, BS)                                                              \
+    do {                                                                               \
+        if (mom)                                                                       \
+            launch_collide_shape<C, FORCED, true, CPT, BS>(c, A, B, ff, mom, grid);    \
+        else                                                                           \
+            launch_collide_shape<C, FORCED, false, CPT, BS>(c, A, B, ff, mom, grid);   \
+    } while (0)
     switch (shape) {
-        case 1: launch_collide_shape<C, FORCED, 1, 256>(c, A, B, ff); break;
-        case 2: launch_collide_shape<C, FORCED, 2, 512>(c, A, B, ff); break;
-        case 3: launch_collide_shape<C, FORCED, 2, 256>(c, A, B, ff); break;
-        default: launch_collide_shape<C, FORCED, 1, 512>(c, A, B, ff); break;
+        case 1: LBM_SHAPE(1, 256); break;
+        case 2: LBM_SHAPE(2, 512); break;
+        case 3: LBM_SHAPE(2, 256); break;
+        default: LBM_SHAPE(1, 512); break;
     }
+#undef LBM_SHAPE
 }
 
 ForceField field(lbm_ctx *c, int par) { return ForceField{c->force[par], c->mask[par]}; }
@@ -723,9 +832,15 @@ void launch_step(lbm_ctx *c) {
     const T *A = static_cast<const T *>(c->pop[c->cur]);
     T *B = static_cast<T *>(c->pop[c->cur ^ 1]);
     const int par = int(c->step & 1);
+    // Record the observables of the state at the start of this step?
+    const bool sample = c->series_every > 0 && c->series_t % c->series_every == 0 &&
+                        c->series_count < c->series_cap;
+    if (c->series_every > 0) c->series_t += 1;
+    double *mom = sample ? c->fluid_partials : nullptr;
     if (c->np > 0) {
         const int32_t pk = prof_start(c, 1);
         ParticleArgs pa;
+        pa.pmom = sample ? c->part_partials : nullptr;
         pa.acc = nullptr;
         pa.origins = nullptr;
         pa.t = pa.k_lo = 0;
@@ -764,12 +879,21 @@ void launch_step(lbm_ctx *c) {
                            c->stream, A, c->g, R(c->dec_s), pa, field(c, par), field(c, par ^ 1));
         prof_stop(c, pk);
         const int32_t ck = prof_start(c, 0);
-        launch_collide<C, true>(c, A, B, field(c, par), c->shape);
+        launch_collide<C, true>(c, A, B, field(c, par), c->shape, mom);
         prof_stop(c, ck);
     } else {
         const int32_t ck = prof_start(c, 0);
-        launch_collide<C, false>(c, A, B, field(c, par), c->shape);
+        launch_collide<C, false>(c, A, B, field(c, par), c->shape, mom);
         prof_stop(c, ck);
+    }
+    if (sample) {
+        const int32_t np_blocks = c->np > 0 ? int32_t(particle_blocks(c->np)) : 0;
+        hipLaunchKernelGGL(k_series_stage1, dim3(kSeriesBlocks), dim3(kBlock), 0, c->stream,
+                           c->fluid_partials, int32_t(collide_grid(c, c->shape)), c->part_partials,
+                           np_blocks, c->series_stage);
+        hipLaunchKernelGGL(k_series_stage2, dim3(1), dim3(64), 0, c->stream, c->series_stage,
+                           double(c->g.ncell), double(c->step), c->series + 8 * c->series_count);
+        c->series_count += 1;
     }
     c->cur ^= 1;
     c->step += 1;
@@ -922,6 +1046,10 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
     s += force_field_bytes(grid);
     c->force[1] = reinterpret_cast<long long *>(s);
     s += force_field_bytes(grid);
+    c->fluid_partials = reinterpret_cast<double *>(s);
+    s += fluid_partials_bytes(grid);
+    c->series_stage = reinterpret_cast<double *>(s);
+    s += align_up(size_t(kSeriesBlocks) * 7 * 8, kAlign);
     c->partials = reinterpret_cast<double *>(s);
     s += align_up(size_t(kRedBlocks) * 4 * 8, kAlign);
     c->result = reinterpret_cast<double *>(s);
@@ -1003,6 +1131,8 @@ lbm_status particles_couple(lbm_ctx *ctx, const lbm_particle_desc *d, double *r,
     char *s = static_cast<char *>(particle_scratch);
     ctx->prev_cell = reinterpret_cast<uint32_t *>(s);
     s += align_up(size_t(d->n) * 8 * 4, kAlign);
+    ctx->part_partials = reinterpret_cast<double *>(s);
+    s += align_up(particle_blocks(d->n) * 3 * 8, kAlign);
     ctx->fh = reinterpret_cast<double *>(s);
     s += align_up(size_t(d->n) * 3 * 8, kAlign);
     ctx->fr = reinterpret_cast<double *>(s);
@@ -1130,6 +1260,23 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen
     if (ms)
         for (int k = 0; k < kNumShapes; ++k) ms[k] = t[k];
     if (chosen) *chosen = best;
+    return LBM_OK;
+}
+
+lbm_status lbm_series_config(lbm_ctx *ctx, int32_t every, double *series, int64_t capacity) {
+    if (!ctx || every < 0) return LBM_E_INVAL;
+    if (every > 0 && (!series || capacity < 1)) return LBM_E_INVAL;
+    ctx->series_every = every;
+    ctx->series = every > 0 ? series : nullptr;
+    ctx->series_cap = every > 0 ? capacity : 0;
+    ctx->series_count = 0;
+    ctx->series_t = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_series_count(const lbm_ctx *ctx, int64_t *count) {
+    if (!ctx || !count) return LBM_E_INVAL;
+    *count = ctx->series_count;
     return LBM_OK;
 }
 

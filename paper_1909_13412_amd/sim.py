@@ -157,6 +157,20 @@ class Lattice:
             self.ctx, cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
         return acc, cnt
 
+    # -- recorded observables --------------------------------------------
+    def series_config(self, every: int, capacity: int):
+        """Record {step, mass, fluid momentum, particle momentum} every `every`
+        steps (fused into the step kernels) into a device buffer."""
+        self._series = torch.zeros((max(int(capacity), 1), 8), dtype=torch.float64, device=self.device)
+        _abi.check("lbm_series_config", self.lib.lbm_series_config(
+            self.ctx, int(every), _ptr(self._series), int(capacity) if every > 0 else 0))
+
+    def series(self) -> np.ndarray:
+        """[count, 8] numpy array: step, mass, P_fluid (3), P_particle (3)."""
+        n = ctypes.c_int64()
+        _abi.check("lbm_series_count", self.lib.lbm_series_count(self.ctx, ctypes.byref(n)))
+        return self._series[: n.value].cpu().numpy()
+
     # -- stepping and diagnostics ----------------------------------------
     def step(self, nsteps: int = 1):
         _abi.check("lbm_step", self.lib.lbm_step(self.ctx, int(nsteps)))

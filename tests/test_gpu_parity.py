@@ -323,3 +323,44 @@ def test_reduced_precision_storage_error(oracle_mod, storage, tol):
     e_u = nmax_err(u_g.cpu().numpy(), u_r)
     announce(f"  {storage}: particle v {e_v:.2e}  u {e_u:.2e}")
     assert e_v < tol and e_u < 10 * tol
+
+
+@pytest.mark.parametrize("storage,every,steps", [("f64", 1, 150), ("f32", 3, 61)])
+def test_recorded_series_matches_oracle(oracle_mod, storage, every, steps):
+    # Observables recorded inside the step kernels (fused FP64 sums) against the
+    # oracle's per-step sums of the same state.
+    from paper_1909_13412_amd import Lattice
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    L = (37, 23, 19)
+    r = particle_positions(7, L, seed=12)
+    v = particle_velocities(7, 1e-5, seed=12)
+    gpu = Lattice(*L, 0.7, storage=storage)
+    gpu.particles_couple(r, v, kT=1e-4, seed=4242)
+    gpu.series_config(every, capacity=steps)
+    ref = oracle_mod.Sim(*L, 0.7)
+    ref.set_particles(r, v, kT=1e-4, seed=4242)
+    want = []
+    for n in range(steps):
+        if n % every == 0:
+            want.append(np.concatenate([[n], ref.observables()]))
+        ref.step(1)
+    gpu.step(steps)
+    got = gpu.series()
+    want = np.array(want)
+    assert got.shape == want.shape
+    assert np.array_equal(got[:, 0], want[:, 0])
+    tol = TOL[storage]
+    e_mass = np.max(np.abs(got[:, 1] - want[:, 1])) / want[0, 1]
+    e_pf = nmax_err(got[:, 2:5], want[:, 2:5])
+    e_pp = nmax_err(got[:, 5:8], want[:, 5:8])
+    announce(f"  series {storage}: mass {e_mass:.2e}  P_fluid {e_pf:.2e}  P_particle {e_pp:.2e}")
+    assert e_mass < tol * 1e-3 and e_pf < tol and e_pp < tol
+    # and against the separate reduction of the final state
+    gpu2 = Lattice(*L, 0.7, storage=storage)
+    gpu2.particles_couple(r, v, kT=1e-4, seed=4242)
+    gpu2.series_config(1, capacity=1)
+    obs = gpu2.observables()
+    gpu2.step(1)
+    s = gpu2.series()[0]
+    assert np.allclose(s[1:], obs, rtol=1e-12, atol=1e-15)
