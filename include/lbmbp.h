@@ -216,6 +216,71 @@ lbm_status lbm_get_step(const lbm_ctx *ctx, int64_t *step);
 /* Release the context (host memory only; device buffers stay the caller's). */
 lbm_status lbm_destroy(lbm_ctx *ctx);
 
+/* ---------------------------------------------------------------------------
+ * Ensembles: many independent periodic boxes of different sizes ("replicas"),
+ * e.g. for ensemble-averaged velocity autocorrelation, stepped together.  One
+ * particle launch and one stream-collide launch per step cover every replica
+ * (a block never straddles two boxes); steps are replayed from a captured
+ * two-step HIP graph.  Every replica computes exactly what a single-box
+ * context with the same box, tau, particles, seed and replica word computes.
+ * ------------------------------------------------------------------------- */
+typedef struct lbm_ensemble_desc {
+    int32_t nrep;            /* number of replicas, 1..65535 */
+    int32_t storage;         /* lbm_storage, shared */
+    int32_t f16_scale_log2;  /* F16 only */
+    int32_t friction;        /* lbm_friction, shared */
+    double mass, gamma, kT;  /* shared particle parameters (as lbm_particle_desc) */
+    double radius;           /* <= 0: from Stokes' law per replica (depends on its tau) */
+    int32_t reserved;        /* must be 0 */
+    int32_t pad;
+} lbm_ensemble_desc;
+
+typedef struct lbm_replica_desc {
+    int32_t nx, ny, nz;  /* its box, each >= 2 */
+    int32_t n;           /* its particles, >= 1 */
+    double tau;          /* its relaxation time, > 1/2 */
+    uint64_t seed;       /* its Philox key */
+    uint32_t replica;    /* its third Philox counter word */
+    uint32_t reserved;   /* must be 0 */
+} lbm_replica_desc;
+
+typedef struct lbm_ens lbm_ens;
+
+/* Bytes of ONE ensemble lattice (two are used) and of the ensemble scratch.
+ * Total nodes < 2^31, total particles < 2^24. */
+lbm_status lbm_ens_bytes(const lbm_ensemble_desc *desc, const lbm_replica_desc *reps,
+                         size_t *lattice_bytes, size_t *scratch_bytes);
+
+/* Create an ensemble on caller buffers (256-byte aligned): both lattices,
+ * scratch, and the particles r, v (device FP64 [sum n][3], replica after
+ * replica, updated in place).  Fluid starts at rest.  Synchronises. */
+lbm_status lbm_ens_init(const lbm_ensemble_desc *desc, const lbm_replica_desc *reps, void *pop_a,
+                        void *pop_b, void *scratch, double *r, double *v, void *stream,
+                        lbm_ens **out);
+
+/* 1 (default): lbm_ens_step replays a captured two-step graph; 0: plain launches. */
+lbm_status lbm_ens_use_graph(lbm_ens *ens, int32_t use);
+
+/* Per-particle VACF over all replicas (layouts as lbm_vacf_config with n = all
+ * particles).  Synchronises. */
+lbm_status lbm_ens_vacf_config(lbm_ens *ens, int32_t max_lag, int32_t stride, double *acc,
+                               double *origins);
+lbm_status lbm_ens_vacf_counts(const lbm_ens *ens, int64_t *cnt);
+
+/* Advance every replica nsteps steps (asynchronous). */
+lbm_status lbm_ens_step(lbm_ens *ens, int32_t nsteps);
+
+/* Time the stream-collide launch shapes on the ensemble (state unchanged) and
+ * keep the fastest; as lbm_autotune. */
+lbm_status lbm_ens_autotune(lbm_ens *ens, int32_t iters, double *ms, int32_t *chosen);
+
+/* Per-replica FP64 sums (as lbm_observables) and populations (as
+ * lbm_get_populations, the replica's own box). */
+lbm_status lbm_ens_observables(lbm_ens *ens, int32_t replica, double out[7]);
+lbm_status lbm_ens_get_populations(lbm_ens *ens, int32_t replica, double *f);
+lbm_status lbm_ens_get_step(const lbm_ens *ens, int64_t *step);
+lbm_status lbm_ens_destroy(lbm_ens *ens);
+
 /* Static string for a status code. */
 const char *lbm_status_string(lbm_status status);
 

@@ -10,8 +10,8 @@ from ._abi import EXPORTS, LIB_PATH, LbmError  # noqa: F401
 
 
 def __getattr__(name):
-    if name == "Lattice":
-        from .sim import Lattice
+    if name in ("Lattice", "Ensemble"):
+        from . import sim
 
-        return Lattice
+        return getattr(sim, name)
     raise AttributeError(name)

@@ -21,6 +21,9 @@ EXPORTS = [
     "lbm_particle_forces", "lbm_vacf_config", "lbm_vacf_counts", "lbm_step", "lbm_series_config",
     "lbm_series_count", "lbm_observables",
     "lbm_profile_enable", "lbm_profile_read", "lbm_autotune", "lbm_get_step", "lbm_destroy",
+    "lbm_ens_bytes", "lbm_ens_init", "lbm_ens_use_graph", "lbm_ens_vacf_config",
+    "lbm_ens_vacf_counts", "lbm_ens_step", "lbm_ens_autotune", "lbm_ens_observables",
+    "lbm_ens_get_populations", "lbm_ens_get_step", "lbm_ens_destroy",
     "lbm_status_string",
 ]
 LBM_NUM_SHAPES = 4
@@ -37,6 +40,19 @@ class ParticleDesc(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("kT", ctypes.c_double), ("radius", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("replica", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32)]
+
+
+class EnsembleDesc(ctypes.Structure):
+    _fields_ = [("nrep", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("f16_scale_log2", ctypes.c_int32), ("friction", ctypes.c_int32),
+                ("mass", ctypes.c_double), ("gamma", ctypes.c_double), ("kT", ctypes.c_double),
+                ("radius", ctypes.c_double), ("reserved", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class ReplicaDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("tau", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("replica", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class LbmError(RuntimeError):
@@ -82,6 +98,19 @@ def load() -> ctypes.CDLL:
         "lbm_autotune": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],
         "lbm_get_step": [vp, ctypes.POINTER(i64)],
         "lbm_destroy": [vp],
+        "lbm_ens_bytes": [ctypes.POINTER(EnsembleDesc), ctypes.POINTER(ReplicaDesc),
+                          ctypes.POINTER(sz), ctypes.POINTER(sz)],
+        "lbm_ens_init": [ctypes.POINTER(EnsembleDesc), ctypes.POINTER(ReplicaDesc), vp, vp, vp,
+                         dp, dp, vp, ctypes.POINTER(vp)],
+        "lbm_ens_use_graph": [vp, i32],
+        "lbm_ens_vacf_config": [vp, i32, i32, dp, dp],
+        "lbm_ens_vacf_counts": [vp, ctypes.POINTER(i64)],
+        "lbm_ens_step": [vp, i32],
+        "lbm_ens_autotune": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],
+        "lbm_ens_observables": [vp, i32, ctypes.POINTER(ctypes.c_double)],
+        "lbm_ens_get_populations": [vp, i32, dp],
+        "lbm_ens_get_step": [vp, ctypes.POINTER(i64)],
+        "lbm_ens_destroy": [vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

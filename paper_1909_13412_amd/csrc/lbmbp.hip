@@ -134,23 +134,16 @@ __device__ inline void block_sum(double (&v)[N], double *__restrict__ out) {
     }
 }
 
-template <class C, bool FORCED, bool MOMENTS, int CPT, int BS>
-__global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__restrict__ A,
-                                                       typename C::T *__restrict__ B, Grid g,
-                                                       typename C::R omega, typename C::R enc_s,
-                                                       typename C::R dec_s, ForceField ff,
-                                                       double *__restrict__ mom) {
+// The nodes of one lane: lane_cell < ncell / CPT indexes the first band of
+// ny/CPT rows; the lane also takes the same (x, z) in the CPT - 1 bands below.
+// With MOMENTS the FP64 sums of (rho~ - 1, u) over these nodes are added to acc.
+template <class C, bool FORCED, bool MOMENTS, int CPT>
+__device__ inline void collide_lane(const typename C::T *__restrict__ A,
+                                    typename C::T *__restrict__ B, const Grid &g,
+                                    typename C::R omega, typename C::R enc_s, typename C::R dec_s,
+                                    const ForceField &ff, uint32_t lane_cell, double (&acc)[4]) {
     using T = typename C::T;
     using R = typename C::R;
-    const uint32_t lane_cell = blockIdx.x * BS + threadIdx.x;  // node index in the first row band
-    const uint32_t band = g.ncell / CPT;                         // nodes per band of ny/CPT rows
-    const bool active = lane_cell < band;
-    if constexpr (!MOMENTS) {
-        if (!active) return;
-    }
-    // FP64 sums of (rho~ - 1, u) over this lane's nodes (MOMENTS only)
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (active) {
     const uint32_t x = lane_cell % g.nx;
     const uint32_t t = lane_cell / g.nx;
     const uint32_t rows = g.ny / CPT;
@@ -216,7 +209,21 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
             B[row_base + uint64_t(a) * g.chunk] = C::enc(gn, enc_s);
         });
     }
-    }  // active
+}
+
+template <class C, bool FORCED, bool MOMENTS, int CPT, int BS>
+__global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__restrict__ A,
+                                                       typename C::T *__restrict__ B, Grid g,
+                                                       typename C::R omega, typename C::R enc_s,
+                                                       typename C::R dec_s, ForceField ff,
+                                                       double *__restrict__ mom) {
+    const uint32_t lane_cell = blockIdx.x * BS + threadIdx.x;  // node index in the first row band
+    const bool active = lane_cell < g.ncell / CPT;
+    if constexpr (!MOMENTS) {
+        if (!active) return;
+    }
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (active) collide_lane<C, FORCED, MOMENTS, CPT>(A, B, g, omega, enc_s, dec_s, ff, lane_cell, acc);
     if constexpr (MOMENTS) block_sum<4, BS>(acc, mom + 4 * uint64_t(blockIdx.x));
 }
 
@@ -260,30 +267,30 @@ __device__ inline double sum8(double v) {
     return v;
 }
 
+// Where a particle lives: its box, lattice and node-force fields, and the
+// Philox key and counter words of its Brownian force.
 template <class C>
-__global__ __launch_bounds__(kParticleBlock) void k_particle(const typename C::T *__restrict__ A,
-                                                             Grid g, typename C::R dec_s,
-                                                             ParticleArgs pa, ForceField cur,
-                                                             ForceField old) {
-    const uint32_t gt = blockIdx.x * kParticleBlock + threadIdx.x;
-    const int32_t i = int32_t(gt >> 3);
-    const int p = int(gt & 7u);
-    const bool valid = i < pa.n;
-    const int32_t ii = valid ? i : pa.n - 1;  // whole 8-lane groups are valid or not
+struct ParticleSite {
+    const typename C::T *A;
+    Grid g;
+    ForceField cur, old;
+    uint64_t seed;
+    uint32_t replica;  // third counter word
+    uint32_t index;    // second counter word: particle index within its box
+    double R;          // particle radius used by the fit
+};
 
-    double r[3], V[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        r[k] = pa.r[3 * ii + k];
-        V[k] = pa.v[3 * ii + k];
-    }
-    if (pa.pmom) {
-        // particle momentum M V^n of the state at the start of the step
-        double pm[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) pm[k] = (valid && p == 0) ? pa.mass * V[k] : 0.0;
-        block_sum<3, kParticleBlock>(pm, pa.pmom + 3 * uint64_t(blockIdx.x));
-    }
+// One lane (node p of particle i) of the coupled particle update.  r, V are
+// the particle's position and velocity at the start of the step; the whole
+// 8-lane group must call this together (it shuffles within the group).
+template <class C>
+__device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R dec_s,
+                                     const ParticleArgs &pa, int32_t i, int p, bool valid,
+                                     const double (&r)[3], const double (&V)[3]) {
+    const typename C::T *__restrict__ A = site.A;
+    const Grid &g = site.g;
+    const ForceField &cur = site.cur;
+    const ForceField &old = site.old;
     const uint32_t Ln[3] = {g.nx, g.ny, g.nz};
     const int b[3] = {p & 1, (p >> 1) & 1, (p >> 2) & 1};
     double d[3];
@@ -340,8 +347,8 @@ __global__ __launch_bounds__(kParticleBlock) void k_particle(const typename C::T
     // (one logarithm, square root and sine/cosine each) and gathered.
     double FR[3] = {0.0, 0.0, 0.0};
     if (pa.sig > 0.0) {
-        const Philox4x32 x = philox4x32_10(pa.step, uint32_t(i), pa.replica, 0u,
-                                           uint32_t(pa.seed), uint32_t(pa.seed >> 32));
+        const Philox4x32 x = philox4x32_10(pa.step, site.index, site.replica, 0u,
+                                           uint32_t(site.seed), uint32_t(site.seed >> 32));
         const int q = p < 3 ? p : 0;
         const uint32_t wa = q == 2 ? x.v[2] : x.v[0];
         const uint32_t wb = q == 2 ? x.v[3] : x.v[1];
@@ -387,8 +394,8 @@ __global__ __launch_bounds__(kParticleBlock) void k_particle(const typename C::T
             double num = 0.0, den = 0.0;
             if (rp > 1e-12) {
                 const double de = d[0] * eN[0] + d[1] * eN[1] + d[2] * eN[2];
-                const double ca = 1.0 - 3.0 * pa.R / (4.0 * rp);
-                const double cb = 3.0 * pa.R * de / (4.0 * rp * rp * rp);
+                const double ca = 1.0 - 3.0 * site.R / (4.0 * rp);
+                const double cb = 3.0 * site.R * de / (4.0 * rp * rp * rp);
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     const double gk = ca * eN[k] - cb * d[k];
@@ -450,6 +457,121 @@ __global__ __launch_bounds__(kParticleBlock) void k_particle(const typename C::T
         pa.fh[3 * i + k] = FH[k];
         pa.fr[3 * i + k] = FR[k];
     }
+}
+
+template <class C>
+__global__ __launch_bounds__(kParticleBlock) void k_particle(const typename C::T *__restrict__ A,
+                                                             Grid g, typename C::R dec_s,
+                                                             ParticleArgs pa, ForceField cur,
+                                                             ForceField old) {
+    const uint32_t gt = blockIdx.x * kParticleBlock + threadIdx.x;
+    const int32_t i = int32_t(gt >> 3);
+    const int p = int(gt & 7u);
+    const bool valid = i < pa.n;
+    const int32_t ii = valid ? i : pa.n - 1;  // whole 8-lane groups are valid or not
+
+    double r[3], V[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        r[k] = pa.r[3 * ii + k];
+        V[k] = pa.v[3 * ii + k];
+    }
+    if (pa.pmom) {
+        // particle momentum M V^n of the state at the start of the step
+        double pm[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pm[k] = (valid && p == 0) ? pa.mass * V[k] : 0.0;
+        block_sum<3, kParticleBlock>(pm, pa.pmom + 3 * uint64_t(blockIdx.x));
+    }
+    const ParticleSite<C> site{A, g, cur, old, pa.seed, pa.replica, uint32_t(i), pa.R};
+    particle_lane<C>(site, dec_s, pa, i, p, valid, r, V);
+}
+
+// ---------------------------------------------------------------------------
+// Ensembles of independent boxes (replicas) of different sizes, stepped
+// together: one stream-collide launch covers every replica's nodes (a block
+// never straddles two replicas) and one particle launch covers every
+// particle.  Step-dependent values come from a device clock so that a
+// captured two-step graph can be replayed.
+// ---------------------------------------------------------------------------
+struct Replica {
+    Grid g;
+    uint64_t pop_off;              // first element of this box in the lattices
+    uint64_t cell_off;             // first node in the node-force fields
+    uint32_t mask_off;             // first word of its forcing flags
+    uint32_t first_block[4];       // first stream-collide block, per launch shape
+    uint32_t part_off, npart;      // its particles in the concatenated arrays
+    uint32_t replica_id;           // Philox third counter word
+    uint32_t pad;
+    uint64_t seed;                 // Philox key
+    double omega;                  // 1 / tau
+    double R;                      // particle radius
+};
+
+struct EnsClock {
+    int64_t step;    // Philox first counter word and field parity
+    int64_t vacf_t;  // VACF sample clock
+};
+
+template <class C, int CPT, int BS>
+__global__ __launch_bounds__(BS) void k_ens_collide(const typename C::T *__restrict__ A,
+                                                    typename C::T *__restrict__ B,
+                                                    const Replica *__restrict__ reps,
+                                                    const uint16_t *__restrict__ blk_rep,
+                                                    int shape, long long *force,
+                                                    uint32_t *mask, typename C::R enc_s,
+                                                    typename C::R dec_s, EnsClock *clock,
+                                                    int vacf_on) {
+    const uint32_t rid = blk_rep[blockIdx.x];
+    const Replica &rp = reps[rid];
+    const uint32_t lane_cell = (blockIdx.x - rp.first_block[shape]) * BS + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // the step's last reader of the clock has finished (previous kernel)
+        clock->step += 1;
+        if (vacf_on) clock->vacf_t += 1;
+    }
+    if (lane_cell >= rp.g.ncell / CPT) return;
+    const ForceField ff{force + 3 * rp.cell_off, mask + rp.mask_off};
+    double acc[4];
+    collide_lane<C, true, false, CPT>(A + rp.pop_off, B + rp.pop_off, rp.g,
+                                      typename C::R(rp.omega), enc_s, dec_s, ff, lane_cell, acc);
+}
+
+template <class C>
+__global__ __launch_bounds__(kParticleBlock) void k_ens_particle(
+    const typename C::T *__restrict__ A, const Replica *__restrict__ reps,
+    const uint16_t *__restrict__ part_rep, typename C::R dec_s, ParticleArgs pa,
+    const EnsClock *__restrict__ clock, long long *force_cur, uint32_t *mask_cur,
+    long long *force_old, uint32_t *mask_old) {
+    const uint32_t gt = blockIdx.x * kParticleBlock + threadIdx.x;
+    const int32_t i = int32_t(gt >> 3);
+    const int p = int(gt & 7u);
+    const bool valid = i < pa.n;
+    const int32_t ii = valid ? i : pa.n - 1;
+    // step-dependent values from the device clock
+    pa.step = uint32_t(clock->step);
+    if (pa.acc) {
+        const int64_t t = clock->vacf_t;
+        pa.t = t;
+        pa.k_hi = t / pa.stride;
+        pa.k_lo = t > pa.max_lag ? (t - pa.max_lag + pa.stride - 1) / pa.stride : 0;
+    }
+    double r[3], V[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        r[k] = pa.r[3 * ii + k];
+        V[k] = pa.v[3 * ii + k];
+    }
+    const Replica &rp = reps[part_rep[ii]];
+    const ParticleSite<C> site{A + rp.pop_off,
+                               rp.g,
+                               ForceField{force_cur + 3 * rp.cell_off, mask_cur + rp.mask_off},
+                               ForceField{force_old + 3 * rp.cell_off, mask_old + rp.mask_off},
+                               rp.seed,
+                               rp.replica_id,
+                               uint32_t(ii) - rp.part_off,
+                               rp.R};
+    particle_lane<C>(site, dec_s, pa, i, p, valid, r, V);
 }
 
 // ---------------------------------------------------------------------------
@@ -1305,6 +1427,571 @@ const char *lbm_status_string(lbm_status status) {
         case LBM_E_UNSUPPORTED: return "unsupported";
     }
     return "unknown status";
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Host side: ensembles of independent boxes.
+// ===========================================================================
+struct lbm_ens {
+    lbm_ensemble_desc desc;
+    int32_t nrep;
+    lbm_replica_desc *host_reps;  // copy of the caller's descriptors
+    Replica *host_table;          // device-side table, host copy
+    size_t elem;
+    void *pop[2];
+    int cur;
+    hipStream_t stream;
+    double enc_s, dec_s;
+    uint64_t total_cells, total_pop;
+    uint32_t total_blocks[kNumShapes];
+    int32_t n;  // particles in all replicas
+    // scratch
+    Replica *reps;
+    uint16_t *blk_rep[kNumShapes];
+    uint16_t *part_rep;
+    uint32_t *mask[2];
+    long long *force[2];
+    uint64_t total_mask_words;
+    uint32_t *prev_cell;
+    double *fh, *fr;
+    EnsClock *clock;
+    uint32_t *err;
+    double *partials, *result;
+    double *r, *v;
+    // velocity autocorrelation
+    int vacf_on;
+    int32_t max_lag, stride, nslot;
+    double *acc, *origins;
+    int64_t vacf_t;
+    int64_t step;
+    int shape;
+    // two-step graph
+    int use_graph;
+    hipGraphExec_t graph;
+    int graph_valid;
+};
+
+namespace {
+
+uint32_t ens_chunk(int storage, int32_t nx) {
+    const uint32_t per_line = uint32_t(128 / elem_size(storage));
+    return uint32_t(align_up(uint32_t(nx), per_line));
+}
+
+struct EnsLayout {
+    uint64_t total_cells = 0, total_pop = 0, total_mask_words = 0;
+    uint32_t total_blocks[kNumShapes] = {0, 0, 0, 0};
+    int32_t n = 0;
+    size_t lattice_bytes = 0, scratch_bytes = 0;
+    // scratch offsets
+    size_t o_reps, o_blk[kNumShapes], o_part, o_mask[2], o_force[2], o_prev, o_fh, o_fr, o_clock,
+        o_err, o_partials, o_result;
+};
+
+bool ens_desc_ok(const lbm_ensemble_desc *d, const lbm_replica_desc *reps) {
+    if (!d || !reps || d->nrep < 1 || d->nrep > 65535 || d->reserved != 0) return false;
+    if (elem_size(d->storage) == 0) return false;
+    if (d->storage == LBM_STORE_F16 && (d->f16_scale_log2 < 0 || d->f16_scale_log2 > 24)) return false;
+    if (!(d->mass > 0.0) || !isfinite(d->mass) || !(d->gamma >= 0.0) || !isfinite(d->gamma)) return false;
+    if (!(d->kT >= 0.0) || !isfinite(d->kT) || !isfinite(d->radius)) return false;
+    if (d->friction < LBM_FRICTION_STOKESLET || d->friction > LBM_FRICTION_BD) return false;
+    uint64_t cells = 0, n = 0;
+    for (int32_t k = 0; k < d->nrep; ++k) {
+        const lbm_replica_desc &r = reps[k];
+        if (r.nx < 2 || r.ny < 2 || r.nz < 2 || r.n < 1 || !(r.tau > 0.5) || !isfinite(r.tau))
+            return false;
+        if (r.reserved != 0) return false;
+        cells += uint64_t(r.nx) * uint64_t(r.ny) * uint64_t(r.nz);
+        n += uint64_t(r.n);
+    }
+    return cells < (uint64_t(1) << 31) && n < (uint64_t(1) << 24);
+}
+
+EnsLayout ens_layout(const lbm_ensemble_desc *d, const lbm_replica_desc *reps) {
+    EnsLayout L;
+    const size_t elem = elem_size(d->storage);
+    for (int32_t k = 0; k < d->nrep; ++k) {
+        const lbm_replica_desc &r = reps[k];
+        const uint64_t cells = uint64_t(r.nx) * r.ny * r.nz;
+        L.total_cells += cells;
+        L.total_pop += uint64_t(ens_chunk(d->storage, r.nx)) * D3Q19::Q * r.ny * r.nz;
+        L.total_mask_words += mask_words(cells);
+        for (int s = 0; s < kNumShapes; ++s) {
+            const uint64_t band = (r.ny % kShapes[s].cpt == 0) ? cells / kShapes[s].cpt : 0;
+            L.total_blocks[s] += uint32_t((band + kShapes[s].bs - 1) / kShapes[s].bs);
+        }
+        L.n += r.n;
+    }
+    L.lattice_bytes = align_up(L.total_pop * elem, kAlign);
+    size_t o = 0;
+    L.o_reps = o;
+    o += align_up(sizeof(Replica) * size_t(d->nrep), kAlign);
+    for (int s = 0; s < kNumShapes; ++s) {
+        L.o_blk[s] = o;
+        o += align_up(size_t(L.total_blocks[s]) * 2 + 2, kAlign);
+    }
+    L.o_part = o;
+    o += align_up(size_t(L.n) * 2, kAlign);
+    for (int k = 0; k < 2; ++k) {
+        L.o_mask[k] = o;
+        o += align_up(L.total_mask_words * 4, kAlign);
+    }
+    for (int k = 0; k < 2; ++k) {
+        L.o_force[k] = o;
+        o += align_up(L.total_cells * 3 * 8, kAlign);
+    }
+    L.o_prev = o;
+    o += align_up(size_t(L.n) * 8 * 4, kAlign);
+    L.o_fh = o;
+    o += align_up(size_t(L.n) * 3 * 8, kAlign);
+    L.o_fr = o;
+    o += align_up(size_t(L.n) * 3 * 8, kAlign);
+    L.o_clock = o;
+    o += kAlign;
+    L.o_err = o;
+    o += kAlign;
+    L.o_partials = o;
+    o += align_up(size_t(kRedBlocks) * 4 * 8, kAlign);
+    L.o_result = o;
+    o += kAlign;
+    L.scratch_bytes = o;
+    return L;
+}
+
+ParticleArgs ens_particle_args(lbm_ens *e) {
+    ParticleArgs pa;
+    memset(&pa, 0, sizeof(pa));
+    pa.r = e->r;
+    pa.v = e->v;
+    pa.fh = e->fh;
+    pa.fr = e->fr;
+    pa.prev_cell = e->prev_cell;
+    pa.err = e->err;
+    pa.n = e->n;
+    pa.friction = e->desc.friction;
+    pa.mass = e->desc.mass;
+    pa.gamma = e->desc.gamma;
+    pa.sig = e->desc.kT > 0.0 ? sqrt(2.0 * e->desc.gamma * e->desc.kT) : 0.0;
+    pa.acc = nullptr;
+    pa.origins = nullptr;
+    pa.k_hi = -1;
+    pa.nslot = pa.stride = 1;
+    pa.pmom = nullptr;
+    if (e->vacf_on) {
+        pa.acc = e->acc;
+        pa.origins = e->origins;
+        pa.nslot = e->nslot;
+        pa.stride = e->stride;
+        pa.max_lag = e->max_lag;
+    }
+    return pa;
+}
+
+template <class C, int CPT, int BS>
+void ens_collide_shape(lbm_ens *e, const typename C::T *A, typename C::T *B, int par) {
+    using R = typename C::R;
+    hipLaunchKernelGGL((k_ens_collide<C, CPT, BS>), dim3(e->total_blocks[e->shape]), dim3(BS), 0,
+                       e->stream, A, B, e->reps, e->blk_rep[e->shape], e->shape, e->force[par],
+                       e->mask[par], R(e->enc_s), R(e->dec_s), e->clock, e->vacf_on);
+}
+
+// One step of every replica; par = field parity of this step.
+template <class C>
+void ens_launch_step(lbm_ens *e, int cur, int par) {
+    using T = typename C::T;
+    using R = typename C::R;
+    const T *A = static_cast<const T *>(e->pop[cur]);
+    T *B = static_cast<T *>(e->pop[cur ^ 1]);
+    const ParticleArgs pa = ens_particle_args(e);
+    hipLaunchKernelGGL(k_ens_particle<C>,
+                       dim3(unsigned((uint64_t(e->n) * 8 + kParticleBlock - 1) / kParticleBlock)),
+                       dim3(kParticleBlock), 0, e->stream, A, e->reps, e->part_rep, R(e->dec_s), pa,
+                       e->clock, e->force[par], e->mask[par], e->force[par ^ 1], e->mask[par ^ 1]);
+    switch (e->shape) {
+        case 1: ens_collide_shape<C, 1, 256>(e, A, B, par); break;
+        case 2: ens_collide_shape<C, 2, 512>(e, A, B, par); break;
+        case 3: ens_collide_shape<C, 2, 256>(e, A, B, par); break;
+        default: ens_collide_shape<C, 1, 512>(e, A, B, par); break;
+    }
+}
+
+void ens_dispatch_step(lbm_ens *e, int cur, int par) {
+    switch (e->desc.storage) {
+        case LBM_STORE_F64: ens_launch_step<CodecF64>(e, cur, par); break;
+        case LBM_STORE_F32: ens_launch_step<CodecF32>(e, cur, par); break;
+        case LBM_STORE_BF16: ens_launch_step<CodecBF16>(e, cur, par); break;
+        case LBM_STORE_F16: ens_launch_step<CodecF16>(e, cur, par); break;
+    }
+}
+
+void ens_drop_graph(lbm_ens *e) {
+    if (e->graph_valid) hipGraphExecDestroy(e->graph);
+    e->graph_valid = 0;
+}
+
+// Capture steps with parity (0, 1) starting from lattice e->cur into a graph.
+lbm_status ens_capture(lbm_ens *e) {
+    ens_drop_graph(e);
+    hipGraph_t g;
+    if (hipStreamBeginCapture(e->stream, hipStreamCaptureModeRelaxed) != hipSuccess)
+        return LBM_E_DEVICE;
+    ens_dispatch_step(e, e->cur, 0);
+    ens_dispatch_step(e, e->cur ^ 1, 1);
+    if (hipStreamEndCapture(e->stream, &g) != hipSuccess) return LBM_E_DEVICE;
+    const hipError_t err = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (err != hipSuccess) return LBM_E_DEVICE;
+    e->graph_valid = 1;
+    return LBM_OK;
+}
+
+template <class C, int CPT, int BS>
+void ens_time_shape(lbm_ens *e, int k) {
+    // A -> B without swapping (the state in A is untouched); the caller
+    // restores the device clock the launches advance.
+    const int saved = e->shape;
+    e->shape = k;
+    ens_collide_shape<C, CPT, BS>(e, static_cast<const typename C::T *>(e->pop[e->cur]),
+                                  static_cast<typename C::T *>(e->pop[e->cur ^ 1]),
+                                  int((e->step + 1) & 1));  // last step's node forces
+    e->shape = saved;
+}
+
+template <class C>
+void ens_time_dispatch(lbm_ens *e, int k) {
+    switch (k) {
+        case 1: ens_time_shape<C, 1, 256>(e, k); break;
+        case 2: ens_time_shape<C, 2, 512>(e, k); break;
+        case 3: ens_time_shape<C, 2, 256>(e, k); break;
+        default: ens_time_shape<C, 1, 512>(e, k); break;
+    }
+}
+
+void ens_time_any(lbm_ens *e, int k) {
+    switch (e->desc.storage) {
+        case LBM_STORE_F64: ens_time_dispatch<CodecF64>(e, k); break;
+        case LBM_STORE_F32: ens_time_dispatch<CodecF32>(e, k); break;
+        case LBM_STORE_BF16: ens_time_dispatch<CodecBF16>(e, k); break;
+        case LBM_STORE_F16: ens_time_dispatch<CodecF16>(e, k); break;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_ens_bytes(const lbm_ensemble_desc *desc, const lbm_replica_desc *reps,
+                         size_t *lattice_bytes, size_t *scratch_bytes) {
+    if (!ens_desc_ok(desc, reps) || !lattice_bytes || !scratch_bytes) return LBM_E_INVAL;
+    const EnsLayout L = ens_layout(desc, reps);
+    *lattice_bytes = L.lattice_bytes;
+    *scratch_bytes = L.scratch_bytes;
+    return LBM_OK;
+}
+
+lbm_status lbm_ens_init(const lbm_ensemble_desc *desc, const lbm_replica_desc *reps, void *pop_a,
+                        void *pop_b, void *scratch, double *r, double *v, void *stream,
+                        lbm_ens **out) {
+    if (!ens_desc_ok(desc, reps) || !pop_a || !pop_b || !scratch || !r || !v || !out)
+        return LBM_E_INVAL;
+    if (!aligned(pop_a) || !aligned(pop_b) || !aligned(scratch) || pop_a == pop_b) return LBM_E_INVAL;
+    const EnsLayout L = ens_layout(desc, reps);
+    lbm_ens *e = static_cast<lbm_ens *>(calloc(1, sizeof(lbm_ens)));
+    if (!e) return LBM_E_DEVICE;
+    e->desc = *desc;
+    e->nrep = desc->nrep;
+    e->host_reps = static_cast<lbm_replica_desc *>(malloc(sizeof(lbm_replica_desc) * e->nrep));
+    e->host_table = static_cast<Replica *>(calloc(e->nrep, sizeof(Replica)));
+    uint16_t *blk[kNumShapes];
+    for (int s = 0; s < kNumShapes; ++s)
+        blk[s] = static_cast<uint16_t *>(malloc(size_t(L.total_blocks[s]) * 2 + 2));
+    uint16_t *prep = static_cast<uint16_t *>(malloc(size_t(L.n) * 2));
+    bool ok = e->host_reps && e->host_table && prep;
+    for (int s = 0; s < kNumShapes; ++s) ok = ok && blk[s];
+    if (!ok) {
+        for (int s = 0; s < kNumShapes; ++s) free(blk[s]);
+        free(prep);
+        free(e->host_reps);
+        free(e->host_table);
+        free(e);
+        return LBM_E_DEVICE;
+    }
+    memcpy(e->host_reps, reps, sizeof(lbm_replica_desc) * e->nrep);
+    e->elem = elem_size(desc->storage);
+    e->pop[0] = pop_a;
+    e->pop[1] = pop_b;
+    e->stream = static_cast<hipStream_t>(stream);
+    if (desc->storage == LBM_STORE_F16) {
+        e->enc_s = ldexp(1.0, desc->f16_scale_log2);
+        e->dec_s = ldexp(1.0, -desc->f16_scale_log2);
+    } else {
+        e->enc_s = e->dec_s = 1.0;
+    }
+    e->total_cells = L.total_cells;
+    e->total_pop = L.total_pop;
+    e->total_mask_words = L.total_mask_words;
+    for (int s = 0; s < kNumShapes; ++s) e->total_blocks[s] = L.total_blocks[s];
+    e->n = L.n;
+    char *base = static_cast<char *>(scratch);
+    e->reps = reinterpret_cast<Replica *>(base + L.o_reps);
+    for (int s = 0; s < kNumShapes; ++s) e->blk_rep[s] = reinterpret_cast<uint16_t *>(base + L.o_blk[s]);
+    e->part_rep = reinterpret_cast<uint16_t *>(base + L.o_part);
+    for (int k = 0; k < 2; ++k) {
+        e->mask[k] = reinterpret_cast<uint32_t *>(base + L.o_mask[k]);
+        e->force[k] = reinterpret_cast<long long *>(base + L.o_force[k]);
+    }
+    e->prev_cell = reinterpret_cast<uint32_t *>(base + L.o_prev);
+    e->fh = reinterpret_cast<double *>(base + L.o_fh);
+    e->fr = reinterpret_cast<double *>(base + L.o_fr);
+    e->clock = reinterpret_cast<EnsClock *>(base + L.o_clock);
+    e->err = reinterpret_cast<uint32_t *>(base + L.o_err);
+    e->partials = reinterpret_cast<double *>(base + L.o_partials);
+    e->result = reinterpret_cast<double *>(base + L.o_result);
+    e->r = r;
+    e->v = v;
+    e->use_graph = 1;
+    // replica table, block and particle maps
+    uint64_t pop_off = 0, cell_off = 0, mask_off = 0;
+    uint32_t first[kNumShapes] = {0, 0, 0, 0};
+    uint32_t part_off = 0;
+    for (int32_t k = 0; k < e->nrep; ++k) {
+        const lbm_replica_desc &rd = reps[k];
+        Replica &t = e->host_table[k];
+        t.g.nx = uint32_t(rd.nx);
+        t.g.ny = uint32_t(rd.ny);
+        t.g.nz = uint32_t(rd.nz);
+        t.g.ncell = uint32_t(uint64_t(rd.nx) * rd.ny * rd.nz);
+        t.g.chunk = ens_chunk(desc->storage, rd.nx);
+        t.pop_off = pop_off;
+        t.cell_off = cell_off;
+        t.mask_off = uint32_t(mask_off);
+        t.part_off = part_off;
+        t.npart = uint32_t(rd.n);
+        t.replica_id = rd.replica;
+        t.seed = rd.seed;
+        t.omega = 1.0 / rd.tau;
+        const double nu = (rd.tau - 0.5) / 3.0;
+        t.R = desc->radius > 0.0 ? desc->radius : desc->gamma / (6.0 * M_PI * nu);
+        for (int s = 0; s < kNumShapes; ++s) {
+            t.first_block[s] = first[s];
+            const uint64_t band = (rd.ny % kShapes[s].cpt == 0) ? t.g.ncell / kShapes[s].cpt : 0;
+            const uint32_t nb = uint32_t((band + kShapes[s].bs - 1) / kShapes[s].bs);
+            for (uint32_t b = 0; b < nb; ++b) blk[s][first[s] + b] = uint16_t(k);
+            first[s] += nb;
+        }
+        for (int32_t q = 0; q < rd.n; ++q) prep[part_off + q] = uint16_t(k);
+        pop_off += uint64_t(t.g.chunk) * D3Q19::Q * rd.ny * rd.nz;
+        cell_off += t.g.ncell;
+        mask_off += mask_words(t.g.ncell);
+        part_off += uint32_t(rd.n);
+    }
+    hipError_t err = hipMemsetAsync(pop_a, 0, L.lattice_bytes, e->stream);
+    if (err == hipSuccess) err = hipMemsetAsync(pop_b, 0, L.lattice_bytes, e->stream);
+    if (err == hipSuccess) err = hipMemsetAsync(scratch, 0, L.scratch_bytes, e->stream);
+    if (err == hipSuccess)
+        err = hipMemsetAsync(e->prev_cell, 0xFF, size_t(L.n) * 8 * 4, e->stream);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(e->reps, e->host_table, sizeof(Replica) * e->nrep,
+                             hipMemcpyHostToDevice, e->stream);
+    for (int s = 0; s < kNumShapes && err == hipSuccess; ++s)
+        if (L.total_blocks[s] > 0)
+            err = hipMemcpyAsync(e->blk_rep[s], blk[s], size_t(L.total_blocks[s]) * 2,
+                                 hipMemcpyHostToDevice, e->stream);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(e->part_rep, prep, size_t(L.n) * 2, hipMemcpyHostToDevice, e->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(e->stream);  // host staging is freed below
+    for (int s = 0; s < kNumShapes; ++s) free(blk[s]);
+    free(prep);
+    if (err != hipSuccess) {
+        free(e->host_reps);
+        free(e->host_table);
+        free(e);
+        return LBM_E_DEVICE;
+    }
+    *out = e;
+    return LBM_OK;
+}
+
+lbm_status lbm_ens_use_graph(lbm_ens *e, int32_t use) {
+    if (!e || (use != 0 && use != 1)) return LBM_E_INVAL;
+    e->use_graph = use;
+    if (!use) ens_drop_graph(e);
+    return LBM_OK;
+}
+
+lbm_status lbm_ens_vacf_config(lbm_ens *e, int32_t max_lag, int32_t stride, double *acc,
+                               double *origins) {
+    if (!e) return LBM_E_INVAL;
+    ens_drop_graph(e);
+    if (max_lag == -1) {
+        e->vacf_on = 0;
+        return LBM_OK;
+    }
+    if (max_lag < 0 || stride < 1 || !acc || !origins) return LBM_E_INVAL;
+    e->max_lag = max_lag;
+    e->stride = stride;
+    e->nslot = max_lag / stride + 1;
+    e->acc = acc;
+    e->origins = origins;
+    e->vacf_t = 0;
+    const EnsClock clk{e->step, 0};
+    hipError_t err = hipMemsetAsync(acc, 0, size_t(e->n) * size_t(max_lag + 1) * 8, e->stream);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(e->clock, &clk, sizeof(clk), hipMemcpyHostToDevice, e->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
+    if (err != hipSuccess) return LBM_E_DEVICE;
+    e->vacf_on = 1;
+    return LBM_OK;
+}
+
+lbm_status lbm_ens_vacf_counts(const lbm_ens *e, int64_t *cnt) {
+    if (!e || !cnt) return LBM_E_INVAL;
+    if (!e->vacf_on) return LBM_E_STATE;
+    const int64_t T = e->vacf_t;
+    for (int32_t l = 0; l <= e->max_lag; ++l)
+        cnt[l] = (T - 1 - l >= 0) ? (T - 1 - l) / e->stride + 1 : 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_ens_step(lbm_ens *e, int32_t nsteps) {
+    if (!e || nsteps < 0) return LBM_E_INVAL;
+    int32_t left = nsteps;
+    auto eager = [&]() {
+        ens_dispatch_step(e, e->cur, int(e->step & 1));
+        e->cur ^= 1;
+        e->step += 1;
+        if (e->vacf_on) e->vacf_t += 1;
+        --left;
+    };
+    if (e->use_graph) {
+        if (left > 0 && (e->step & 1)) eager();
+        if (left >= 2) {
+            if (!e->graph_valid) {
+                const lbm_status st = ens_capture(e);
+                if (st != LBM_OK) return st;
+            }
+            // the graph was captured from lattice parity cur at an even step;
+            // cur and the step parity change together, so they still match
+            while (left >= 2) {
+                if (hipGraphLaunch(e->graph, e->stream) != hipSuccess) return LBM_E_DEVICE;
+                e->step += 2;
+                if (e->vacf_on) e->vacf_t += 2;
+                left -= 2;
+            }
+        }
+    }
+    while (left > 0) eager();
+    return launch_status();
+}
+
+lbm_status lbm_ens_autotune(lbm_ens *e, int32_t iters, double *ms, int32_t *chosen) {
+    if (!e || iters < 1 || iters > 10000) return LBM_E_INVAL;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return LBM_E_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) return LBM_E_DEVICE;
+    // the timing launches advance the device clock; restore it afterwards
+    EnsClock saved;
+    hipError_t err = hipMemcpyAsync(&saved, e->clock, sizeof(saved), hipMemcpyDeviceToHost, e->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
+    double t[kNumShapes];
+    for (int k = 0; k < kNumShapes && err == hipSuccess; ++k) {
+        t[k] = -1.0;
+        if (e->total_blocks[k] == 0) continue;
+        bool all = true;
+        for (int32_t q = 0; q < e->nrep; ++q) all = all && (e->host_reps[q].ny % kShapes[k].cpt == 0);
+        if (!all) continue;
+        for (int w = 0; w < 2; ++w) ens_time_any(e, k);
+        hipEventRecord(e0, e->stream);
+        for (int32_t it = 0; it < iters; ++it) ens_time_any(e, k);
+        hipEventRecord(e1, e->stream);
+        err = hipEventSynchronize(e1);
+        float f = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&f, e0, e1);
+        t[k] = double(f) / iters;
+    }
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(e->clock, &saved, sizeof(saved), hipMemcpyHostToDevice, e->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (err != hipSuccess) return LBM_E_DEVICE;
+    int best = 0;
+    for (int k = 0; k < kNumShapes; ++k)
+        if (t[k] > 0.0 && (t[best] <= 0.0 || t[k] < t[best])) best = k;
+    if (best != e->shape) ens_drop_graph(e);
+    e->shape = best;
+    if (ms)
+        for (int k = 0; k < kNumShapes; ++k) ms[k] = t[k];
+    if (chosen) *chosen = best;
+    return LBM_OK;
+}
+
+lbm_status lbm_ens_observables(lbm_ens *e, int32_t replica, double out[7]) {
+    if (!e || !out || replica < 0 || replica >= e->nrep) return LBM_E_INVAL;
+    const Replica &t = e->host_table[replica];
+    const char *A = static_cast<const char *>(e->pop[e->cur]) + t.pop_off * e->elem;
+    switch (e->desc.storage) {
+#define LBM_ENS_PARTIALS(CODEC)                                                                 \
+    hipLaunchKernelGGL(k_fluid_partials<CODEC>, dim3(kRedBlocks), dim3(kBlock), 0, e->stream, \
+                       reinterpret_cast<const CODEC::T *>(A), t.g, CODEC::R(e->dec_s),          \
+                       e->partials)
+        case LBM_STORE_F64: LBM_ENS_PARTIALS(CodecF64); break;
+        case LBM_STORE_F32: LBM_ENS_PARTIALS(CodecF32); break;
+        case LBM_STORE_BF16: LBM_ENS_PARTIALS(CodecBF16); break;
+        case LBM_STORE_F16: LBM_ENS_PARTIALS(CodecF16); break;
+#undef LBM_ENS_PARTIALS
+    }
+    hipLaunchKernelGGL(k_final_sums, dim3(1), dim3(kBlock), 0, e->stream, e->partials, kRedBlocks,
+                       double(t.g.ncell), e->v + 3 * uint64_t(t.part_off), int32_t(t.npart),
+                       e->desc.mass, e->result);
+    if (launch_status() != LBM_OK) return LBM_E_DEVICE;
+    double host[7];
+    uint32_t flag = 0;
+    hipError_t err = hipMemcpyAsync(host, e->result, sizeof(host), hipMemcpyDeviceToHost, e->stream);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(&flag, e->err, sizeof(flag), hipMemcpyDeviceToHost, e->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
+    if (err != hipSuccess) return LBM_E_DEVICE;
+    bool finite = true;
+    for (int k = 0; k < 7; ++k) {
+        out[k] = host[k];
+        finite = finite && isfinite(host[k]);
+    }
+    return (finite && flag == 0) ? LBM_OK : LBM_E_NONFINITE;
+}
+
+lbm_status lbm_ens_get_populations(lbm_ens *e, int32_t replica, double *f) {
+    if (!e || !f || replica < 0 || replica >= e->nrep) return LBM_E_INVAL;
+    const Replica &t = e->host_table[replica];
+    const char *A = static_cast<const char *>(e->pop[e->cur]) + t.pop_off * e->elem;
+    switch (e->desc.storage) {
+#define LBM_ENS_POPS(CODEC)                                                                      \
+    hipLaunchKernelGGL(k_get_populations<CODEC>, dim3(blocks_for(t.g.ncell)), dim3(kBlock), 0, \
+                       e->stream, reinterpret_cast<const CODEC::T *>(A), t.g, CODEC::R(e->dec_s), f)
+        case LBM_STORE_F64: LBM_ENS_POPS(CodecF64); break;
+        case LBM_STORE_F32: LBM_ENS_POPS(CodecF32); break;
+        case LBM_STORE_BF16: LBM_ENS_POPS(CodecBF16); break;
+        case LBM_STORE_F16: LBM_ENS_POPS(CodecF16); break;
+#undef LBM_ENS_POPS
+    }
+    return launch_status();
+}
+
+lbm_status lbm_ens_get_step(const lbm_ens *e, int64_t *step) {
+    if (!e || !step) return LBM_E_INVAL;
+    *step = e->step;
+    return LBM_OK;
+}
+
+lbm_status lbm_ens_destroy(lbm_ens *e) {
+    if (!e) return LBM_E_INVAL;
+    ens_drop_graph(e);
+    free(e->host_reps);
+    free(e->host_table);
+    free(e);
+    return LBM_OK;
 }
 
 }  // extern "C"

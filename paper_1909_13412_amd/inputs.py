@@ -21,6 +21,9 @@ friction once R exceeds about 0.87 (the fitted gain for a particle at a cell
 centre in a uniform stream is 1 - 2R/sqrt(3)), so the coupled run diverges; the
 suspensions therefore keep the friction constant 1 and fix R = 0.5.
 
+* ``ENSEMBLE64``    -- 64 independent cubic boxes with edges drawn from
+  {48, 64, 80, 96}, tau 0.8, 8 particles each, kT = 1e-4, FP32.
+
 They stand in for the paper's own runs (a 100^3 box of 500 particles), which
 use no external dataset.
 """
@@ -38,6 +41,25 @@ WORKLOADS = {
     "suspension512": dict(L=512, tau=0.6, storage="f32", n=4096, mass=10.0, gamma=1.0, kT=1e-4,
                           radius=0.5, steps=2000, seed=3004, max_lag=500, stride=10),
 }
+
+
+ENSEMBLE64 = dict(replicas=64, sizes=(48, 64, 80, 96), tau=0.8, n=8, mass=10.0, gamma=1.0,
+                  kT=1e-4, seed=4000, steps=5000, max_lag=1000, stride=10, storage="f32")
+
+
+def ensemble_replicas(replicas: int = 64, sizes=(48, 64, 80, 96), n: int = 8, tau: float = 0.8,
+                      kT: float = 1e-4, mass: float = 10.0, seed: int = 4000):
+    """Replica list for an ensemble of cubic boxes with edges drawn uniformly
+    from `sizes`; replica k gets Philox key seed + k and counter word k."""
+    rng = np.random.default_rng([seed, 0x5EED, 4])
+    edges = rng.choice(np.asarray(sizes), size=replicas)
+    out = []
+    for k, L in enumerate(edges):
+        L = int(L)
+        out.append(dict(nx=L, ny=L, nz=L, tau=tau, seed=seed + k, replica=k,
+                        r=particle_positions(n, L, seed + k),
+                        v=particle_velocities(n, kT / mass, seed + k)))
+    return out
 
 
 def particle_positions(n: int, box, seed: int) -> np.ndarray:

@@ -206,3 +206,107 @@ class Lattice:
         s = ctypes.c_int64()
         _abi.check("lbm_get_step", self.lib.lbm_get_step(self.ctx, ctypes.byref(s)))
         return s.value
+
+
+class Ensemble:
+    """Many independent periodic boxes stepped together (one launch per kernel
+    per step, replayed from a captured two-step graph).
+
+    replicas: list of dicts with keys nx, ny, nz, r [n, 3], v [n, 3], tau, seed,
+    replica (Philox third counter word).  Shared: storage, mass, gamma, kT,
+    radius, friction."""
+
+    def __init__(self, replicas, storage="f32", mass=10.0, gamma=1.0, kT=0.0, radius=0.0,
+                 friction="stokeslet", f16_scale_log2=16, device="cuda:0", stream=None):
+        self.lib = _abi.load()
+        self.device = torch.device(device)
+        self.nrep = len(replicas)
+        self.desc = _abi.EnsembleDesc(self.nrep, _abi.STORAGE[storage], int(f16_scale_log2),
+                                      _abi.FRICTION[friction], float(mass), float(gamma),
+                                      float(kT), float(radius), 0, 0)
+        reps = (_abi.ReplicaDesc * self.nrep)()
+        rs, vs = [], []
+        for k, rd in enumerate(replicas):
+            r = np.asarray(rd["r"], dtype=np.float64).reshape(-1, 3)
+            v = np.asarray(rd["v"], dtype=np.float64).reshape(-1, 3)
+            reps[k] = _abi.ReplicaDesc(int(rd["nx"]), int(rd["ny"]), int(rd["nz"]), r.shape[0],
+                                       float(rd["tau"]), int(rd["seed"]), int(rd.get("replica", k)), 0)
+            rs.append(r)
+            vs.append(v)
+        self.reps = reps
+        self.shapes = [(int(rd["nz"]), int(rd["ny"]), int(rd["nx"])) for rd in replicas]
+        self.offsets = np.concatenate([[0], np.cumsum([len(r) for r in rs])])
+        self.n = int(self.offsets[-1])
+        lat, scr = ctypes.c_size_t(), ctypes.c_size_t()
+        _abi.check("lbm_ens_bytes", self.lib.lbm_ens_bytes(ctypes.byref(self.desc), reps,
+                                                           ctypes.byref(lat), ctypes.byref(scr)))
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.pop_a = _alloc_bytes(lat.value, self.device)
+            self.pop_b = _alloc_bytes(lat.value, self.device)
+            self.scratch = _alloc_bytes(scr.value, self.device)
+            self.r = _device_f64(np.concatenate(rs), self.device).clone()
+            self.v = _device_f64(np.concatenate(vs), self.device).clone()
+            ctx = ctypes.c_void_p()
+            _abi.check("lbm_ens_init", self.lib.lbm_ens_init(
+                ctypes.byref(self.desc), reps, _ptr(self.pop_a), _ptr(self.pop_b), _ptr(self.scratch),
+                _ptr(self.r), _ptr(self.v), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+        self.ctx = ctx
+        self._vacf = None
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.stream.synchronize()
+            self.lib.lbm_ens_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def use_graph(self, use: bool = True):
+        _abi.check("lbm_ens_use_graph", self.lib.lbm_ens_use_graph(self.ctx, int(bool(use))))
+
+    def step(self, nsteps: int = 1):
+        _abi.check("lbm_ens_step", self.lib.lbm_ens_step(self.ctx, int(nsteps)))
+
+    def autotune(self, iters: int = 10):
+        ms = np.zeros(_abi.LBM_NUM_SHAPES)
+        chosen = ctypes.c_int32()
+        _abi.check("lbm_ens_autotune", self.lib.lbm_ens_autotune(
+            self.ctx, int(iters), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(chosen)))
+        return chosen.value, ms
+
+    def vacf_config(self, max_lag: int, stride: int):
+        sz = ctypes.c_size_t()
+        _abi.check("lbm_vacf_origin_bytes",
+                   self.lib.lbm_vacf_origin_bytes(self.n, max_lag, stride, ctypes.byref(sz)))
+        acc = torch.empty((self.n, max_lag + 1), dtype=torch.float64, device=self.device)
+        origins = _alloc_bytes(sz.value, self.device)
+        _abi.check("lbm_ens_vacf_config",
+                   self.lib.lbm_ens_vacf_config(self.ctx, max_lag, stride, _ptr(acc), _ptr(origins)))
+        self._vacf = (acc, origins, max_lag)
+
+    def vacf(self):
+        acc, _, max_lag = self._vacf
+        cnt = np.zeros(max_lag + 1, dtype=np.int64)
+        _abi.check("lbm_ens_vacf_counts", self.lib.lbm_ens_vacf_counts(
+            self.ctx, cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return acc, cnt
+
+    def particles(self, k: int):
+        a, b = int(self.offsets[k]), int(self.offsets[k + 1])
+        return self.r[a:b], self.v[a:b]
+
+    def populations(self, k: int) -> torch.Tensor:
+        out = torch.empty((Q,) + self.shapes[k], dtype=torch.float64, device=self.device)
+        _abi.check("lbm_ens_get_populations", self.lib.lbm_ens_get_populations(self.ctx, int(k), _ptr(out)))
+        return out
+
+    def observables(self, k: int) -> np.ndarray:
+        out = np.zeros(7)
+        _abi.check("lbm_ens_observables", self.lib.lbm_ens_observables(
+            self.ctx, int(k), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out

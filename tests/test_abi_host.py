@@ -43,6 +43,8 @@ def test_struct_layouts_match_header(lib):
 
     assert ctypes.sizeof(_abi.GridDesc) == 32
     assert ctypes.sizeof(_abi.ParticleDesc) == 56
+    assert ctypes.sizeof(_abi.EnsembleDesc) == 56
+    assert ctypes.sizeof(_abi.ReplicaDesc) == 40
 
 
 def _grid(nx=16, ny=16, nz=16, tau=0.8, storage=1, s=16):
@@ -119,3 +121,30 @@ def test_status_strings(lib):
         assert isinstance(s, bytes) and len(s) > 0
     assert lib.lbm_status_string(0) == b"ok"
     assert lib.lbm_status_string(99) == b"unknown status"
+
+
+def test_ensemble_sizes_and_validation(lib):
+    from paper_1909_13412_amd import _abi
+
+    d = _abi.EnsembleDesc(3, 1, 16, 0, 10.0, 1.0, 1e-4, 0.0, 0, 0)
+    reps = (_abi.ReplicaDesc * 3)(_abi.ReplicaDesc(48, 48, 48, 8, 0.8, 1, 0, 0),
+                                  _abi.ReplicaDesc(37, 20, 11, 3, 0.7, 2, 1, 0),
+                                  _abi.ReplicaDesc(96, 96, 96, 8, 0.8, 3, 2, 0))
+    lat, scr = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.lbm_ens_bytes(ctypes.byref(d), reps, ctypes.byref(lat), ctypes.byref(scr)) == 0
+    chunk = lambda nx: -(-nx // 32) * 32
+    want = 19 * 4 * (chunk(48) * 48 * 48 + chunk(37) * 20 * 11 + chunk(96) * 96 * 96)
+    assert lat.value == -(-want // 256) * 256
+    cells = 48**3 + 37 * 20 * 11 + 96**3
+    assert scr.value > 2 * 24 * cells
+    bad = (_abi.ReplicaDesc * 3)(*reps)
+    bad[1].tau = 0.5
+    assert lib.lbm_ens_bytes(ctypes.byref(d), bad, ctypes.byref(lat), ctypes.byref(scr)) == 1
+    bad[1].tau = 0.7
+    bad[2].n = 0
+    assert lib.lbm_ens_bytes(ctypes.byref(d), bad, ctypes.byref(lat), ctypes.byref(scr)) == 1
+    d.nrep = 0
+    assert lib.lbm_ens_bytes(ctypes.byref(d), reps, ctypes.byref(lat), ctypes.byref(scr)) == 1
+    out = ctypes.c_void_p()
+    assert lib.lbm_ens_init(None, reps, None, None, None, None, None, None, ctypes.byref(out)) == 1
+    assert lib.lbm_ens_step(None, 1) == 1

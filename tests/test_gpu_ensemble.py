@@ -1,0 +1,134 @@
+"""GPU parity of the ensemble path (many boxes in one launch per kernel, steps
+replayed from a captured graph): every replica against the FP64 oracle and
+against a single-box run with the same inputs."""
+import numpy as np
+import pytest
+
+from helpers import announce, nmax_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+
+
+def _small_replicas(kT=1e-4):
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    boxes = [((12, 10, 8), 0.7, 4), ((9, 9, 9), 0.8, 3), ((16, 6, 10), 0.9, 5), ((7, 13, 11), 0.75, 2)]
+    reps = []
+    for k, (L, tau, n) in enumerate(boxes):
+        reps.append(dict(nx=L[0], ny=L[1], nz=L[2], tau=tau, seed=900 + k, replica=k,
+                         r=particle_positions(n, L, 60 + k), v=particle_velocities(n, kT / 10.0, 60 + k)))
+    return reps
+
+
+def test_ensemble_replicas_match_oracle(oracle_mod):
+    from paper_1909_13412_amd import Ensemble
+
+    reps = _small_replicas()
+    ens = Ensemble(reps, storage="f64", kT=1e-4)
+    ens.vacf_config(9, 4)
+    ens.step(31)  # odd: one plain step, then fifteen two-step graph replays
+    for k, rd in enumerate(reps):
+        ref = oracle_mod.Sim(rd["nx"], rd["ny"], rd["nz"], rd["tau"])
+        ref.set_particles(rd["r"], rd["v"], kT=1e-4, seed=rd["seed"], replica=rd["replica"])
+        ref.vacf_config(9, 4)
+        ref.step(31)
+        rr, vr = ref.particles()
+        rg, vg = ens.particles(k)
+        e_v = nmax_err(vg.cpu().numpy(), vr)
+        e_r = np.max(np.abs(rg.cpu().numpy() - rr))
+        w = oracle_mod.lattice()[1][:, None, None, None]
+        e_g = nmax_err(ens.populations(k).cpu().numpy() - w, ref.populations() - w)
+        acc_g, cnt_g = ens.vacf()
+        a, b = int(ens.offsets[k]), int(ens.offsets[k + 1])
+        acc_r, cnt_r = ref.vacf()
+        e_acc = nmax_err(acc_g.cpu().numpy()[a:b], acc_r)
+        o_g = ens.observables(k)
+        o_r = ref.observables()
+        announce(f"  replica {k}: v {e_v:.2e} r {e_r:.2e} g {e_g:.2e} vacf {e_acc:.2e}")
+        assert e_v < 1e-10 and e_r < 1e-10 and e_g < 1e-10 and e_acc < 1e-10
+        assert np.array_equal(cnt_g, cnt_r)
+        assert abs(o_g[0] - o_r[0]) < 1e-10 * o_r[0]
+        assert nmax_err(o_g[1:], o_r[1:]) < 1e-10
+
+
+def test_ensemble_equals_single_box_runs():
+    from paper_1909_13412_amd import Ensemble, Lattice
+
+    reps = _small_replicas()
+    ens = Ensemble(reps, storage="f32", kT=1e-4)
+    ens.step(24)
+    bitwise = True
+    for k, rd in enumerate(reps):
+        one = Lattice(rd["nx"], rd["ny"], rd["nz"], rd["tau"], storage="f32")
+        one.particles_couple(rd["r"], rd["v"], kT=1e-4, seed=rd["seed"], replica=rd["replica"])
+        one.step(24)
+        fe, fo = ens.populations(k).cpu().numpy(), one.populations().cpu().numpy()
+        ve, vo = ens.particles(k)[1].cpu().numpy(), one.v.cpu().numpy()
+        bitwise = bitwise and np.array_equal(fe, fo) and np.array_equal(ve, vo)
+        assert np.allclose(fe, fo, rtol=0, atol=1e-12) and nmax_err(ve, vo) < 1e-12
+    announce(f"  ensemble vs single-box runs bit-identical: {bitwise}")
+
+
+def test_graph_replays_match_plain_launches():
+    # Replays of the captured two-step graph, with eager work and
+    # synchronisation between them, against the same ensemble stepped with
+    # plain launches: every replay compared.
+    import torch
+
+    from paper_1909_13412_amd import Ensemble
+
+    reps = _small_replicas()
+    g = Ensemble(reps, storage="f32", kT=1e-4)
+    e = Ensemble(reps, storage="f32", kT=1e-4)
+    e.use_graph(False)
+    g.vacf_config(6, 3)
+    e.vacf_config(6, 3)
+    for rep in range(6):
+        g.step(2)
+        e.step(2)
+        torch.cuda.synchronize()
+        for k in range(len(reps)):
+            assert np.array_equal(g.populations(k).cpu().numpy(), e.populations(k).cpu().numpy()), (rep, k)
+            assert np.array_equal(g.particles(k)[1].cpu().numpy(), e.particles(k)[1].cpu().numpy())
+        g.observables(rep % len(reps))
+        _ = torch.ones(1000, device="cuda").sum().item()
+    assert np.array_equal(g.vacf()[0].cpu().numpy(), e.vacf()[0].cpu().numpy())
+
+
+def test_ensemble64_workload():
+    # The 64-replica workload (edges 48..96), checked replica by replica for
+    # the smallest and largest boxes against single-box runs.
+    from paper_1909_13412_amd import Ensemble, Lattice
+    from paper_1909_13412_amd.inputs import ENSEMBLE64, ensemble_replicas
+
+    w = ENSEMBLE64
+    reps = ensemble_replicas(w["replicas"], w["sizes"], w["n"], w["tau"], w["kT"], w["mass"], w["seed"])
+    announce(f"ensemble64: edges {sorted(set(r['nx'] for r in reps))}, "
+             f"{sum(r['nx'] ** 3 for r in reps)} nodes")
+    ens = Ensemble(reps, storage="f32", kT=w["kT"], mass=w["mass"], gamma=w["gamma"])
+    ens.vacf_config(50, 10)
+    chosen, ms = ens.autotune(5)
+    announce(f"  autotune shape {chosen} ms {np.round(ms, 4)}")
+    ens.step(20)
+    edges = [r["nx"] for r in reps]
+    for k in (int(np.argmin(edges)), int(np.argmax(edges))):
+        rd = reps[k]
+        one = Lattice(rd["nx"], rd["ny"], rd["nz"], rd["tau"], storage="f32")
+        one.particles_couple(rd["r"], rd["v"], mass=w["mass"], gamma=w["gamma"], kT=w["kT"],
+                             seed=rd["seed"], replica=rd["replica"])
+        one.step(20)
+        assert np.allclose(ens.populations(k).cpu().numpy(), one.populations().cpu().numpy(),
+                           rtol=0, atol=1e-12)
+        assert nmax_err(ens.particles(k)[1].cpu().numpy(), one.v.cpu().numpy()) < 1e-12
+    for k in range(len(reps)):
+        o = ens.observables(k)
+        assert abs(o[0] - reps[k]["nx"] ** 3) < 1e-6 * reps[k]["nx"] ** 3
