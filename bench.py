@@ -203,6 +203,48 @@ def precision_study(w, steps, storages=("f32", "bf16", "f16")):
     return out
 
 
+def time_ensemble(steps, warmup):
+    """The 64-replica ensemble (edges 48..96, tau 0.8, 8 particles each, FP32,
+    VACF on): whole-ensemble MLUPS with graph-replayed steps and with plain
+    launches."""
+    import numpy as np
+    import torch
+
+    from paper_1909_13412_amd import Ensemble
+    from paper_1909_13412_amd.inputs import ENSEMBLE64, ensemble_replicas
+
+    w = ENSEMBLE64
+    reps = ensemble_replicas(w["replicas"], w["sizes"], w["n"], w["tau"], w["kT"], w["mass"], w["seed"])
+    nodes = sum(r["nx"] * r["ny"] * r["nz"] for r in reps)
+    out = {"workload": "ensemble64", "replicas": len(reps), "nodes": nodes,
+           "particles": sum(len(r["r"]) for r in reps), "storage": w["storage"], "steps": steps}
+    for use_graph in (True, False):
+        ens = Ensemble(reps, storage=w["storage"], mass=w["mass"], gamma=w["gamma"], kT=w["kT"])
+        ens.vacf_config(w["max_lag"], w["stride"])
+        ens.use_graph(use_graph)
+        ens.step(warmup)
+        torch.cuda.synchronize()
+        shape, _ = ens.autotune(10)
+        ens.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ens.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        key = "graph" if use_graph else "plain"
+        out[f"mlups_{key}"] = round(nodes * steps / dt / 1e6, 1)
+        out[f"ms_per_step_{key}"] = round(dt * 1e3 / steps, 5)
+        out["launch_shape"] = shape
+        if use_graph:
+            out["graph_replays"] = ens.graph_replays
+            acc, cnt = ens.vacf()
+            c = acc.sum(0).cpu().numpy() / (acc.shape[0] * np.maximum(cnt, 1))
+            out["vacf_norm_lag"] = {str(l): round(float(c[l] / c[0]), 5) for l in (0, 10, 50, 100)}
+        del ens
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, steps):
     import oracle
     from paper_1909_13412_amd.inputs import workload_particles
@@ -240,6 +282,7 @@ def main():
     ap.add_argument("--precision-steps", type=int, default=2000, help="0 = skip the VACF error study")
     ap.add_argument("--prof-steps", type=int, default=300, help="steps timed with per-kernel events")
     ap.add_argument("--no-copy-probe", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=1000, help="0 = skip the ensemble timing")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -271,6 +314,10 @@ def main():
         r["speedup_vs_main"] = r["mlups"] / main_res["mlups"]
         r["traffic"] = pmc_traffic(s)
         variants[s] = r
+    ensemble = None
+    if args.ensemble_steps > 0:
+        print(f"[bench] ensemble ({args.ensemble_steps} steps)", file=sys.stderr, flush=True)
+        ensemble = time_ensemble(args.ensemble_steps, args.warmup)
     precision = None
     if args.precision_steps > 0:
         print(f"[bench] precision study ({args.precision_steps} steps per storage)", file=sys.stderr,
@@ -322,6 +369,7 @@ def main():
         "copy_probe": copy,
         "variants": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                      for k, v in variants.items()},
+        "ensemble": ensemble,
         "precision": precision,
         "cpu_baseline": cpu,
     }

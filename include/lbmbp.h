@@ -258,7 +258,9 @@ lbm_status lbm_ens_init(const lbm_ensemble_desc *desc, const lbm_replica_desc *r
                         void *pop_b, void *scratch, double *r, double *v, void *stream,
                         lbm_ens **out);
 
-/* 1 (default): lbm_ens_step replays a captured two-step graph; 0: plain launches. */
+/* 1 (default): lbm_ens_step replays a captured two-step graph (captured on a
+ * private stream, replayed on the context's stream; plain launches are used
+ * if capture is not possible); 0: plain launches. */
 lbm_status lbm_ens_use_graph(lbm_ens *ens, int32_t use);
 
 /* Per-particle VACF over all replicas (layouts as lbm_vacf_config with n = all
@@ -279,6 +281,8 @@ lbm_status lbm_ens_autotune(lbm_ens *ens, int32_t iters, double *ms, int32_t *ch
 lbm_status lbm_ens_observables(lbm_ens *ens, int32_t replica, double out[7]);
 lbm_status lbm_ens_get_populations(lbm_ens *ens, int32_t replica, double *f);
 lbm_status lbm_ens_get_step(const lbm_ens *ens, int64_t *step);
+/* Number of two-step graph launches made so far (0 when stepping eagerly). */
+lbm_status lbm_ens_graph_replays(const lbm_ens *ens, int64_t *replays);
 lbm_status lbm_ens_destroy(lbm_ens *ens);
 
 /* Static string for a status code. */

@@ -23,7 +23,7 @@ EXPORTS = [
     "lbm_profile_enable", "lbm_profile_read", "lbm_autotune", "lbm_get_step", "lbm_destroy",
     "lbm_ens_bytes", "lbm_ens_init", "lbm_ens_use_graph", "lbm_ens_vacf_config",
     "lbm_ens_vacf_counts", "lbm_ens_step", "lbm_ens_autotune", "lbm_ens_observables",
-    "lbm_ens_get_populations", "lbm_ens_get_step", "lbm_ens_destroy",
+    "lbm_ens_get_populations", "lbm_ens_get_step", "lbm_ens_graph_replays", "lbm_ens_destroy",
     "lbm_status_string",
 ]
 LBM_NUM_SHAPES = 4
@@ -110,6 +110,7 @@ def load() -> ctypes.CDLL:
         "lbm_ens_observables": [vp, i32, ctypes.POINTER(ctypes.c_double)],
         "lbm_ens_get_populations": [vp, i32, dp],
         "lbm_ens_get_step": [vp, ctypes.POINTER(i64)],
+        "lbm_ens_graph_replays": [vp, ctypes.POINTER(i64)],
         "lbm_ens_destroy": [vp],
     }
     for name, args in sig.items():

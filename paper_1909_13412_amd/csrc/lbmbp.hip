@@ -1467,10 +1467,12 @@ struct lbm_ens {
     int64_t vacf_t;
     int64_t step;
     int shape;
-    // two-step graph
+    // two-step graph, captured on a private stream and replayed on `stream`
     int use_graph;
     hipGraphExec_t graph;
     int graph_valid;
+    hipStream_t cap_stream;
+    int graph_replays;  // number of graph launches so far
 };
 
 namespace {
@@ -1632,19 +1634,36 @@ void ens_drop_graph(lbm_ens *e) {
 }
 
 // Capture steps with parity (0, 1) starting from lattice e->cur into a graph.
-lbm_status ens_capture(lbm_ens *e) {
+// Capture runs on a private non-blocking stream (the caller's stream may be
+// the null stream, which cannot be captured); the graph is then launched on
+// the caller's stream.  Returns false when no graph could be made.
+bool ens_capture(lbm_ens *e) {
     ens_drop_graph(e);
-    hipGraph_t g;
-    if (hipStreamBeginCapture(e->stream, hipStreamCaptureModeRelaxed) != hipSuccess)
-        return LBM_E_DEVICE;
+    if (!e->cap_stream && hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        e->cap_stream = nullptr;
+        return false;
+    }
+    hipStream_t user = e->stream;
+    if (hipStreamBeginCapture(e->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return false;
+    e->stream = e->cap_stream;
     ens_dispatch_step(e, e->cur, 0);
     ens_dispatch_step(e, e->cur ^ 1, 1);
-    if (hipStreamEndCapture(e->stream, &g) != hipSuccess) return LBM_E_DEVICE;
+    e->stream = user;
+    hipGraph_t g = nullptr;
+    const hipError_t end = hipStreamEndCapture(e->cap_stream, &g);
+    if (end != hipSuccess || !g) {
+        hipGetLastError();
+        return false;
+    }
     const hipError_t err = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
-    if (err != hipSuccess) return LBM_E_DEVICE;
+    if (err != hipSuccess) {
+        hipGetLastError();
+        return false;
+    }
     e->graph_valid = 1;
-    return LBM_OK;
+    return true;
 }
 
 template <class C, int CPT, int BS>
@@ -1867,15 +1886,13 @@ lbm_status lbm_ens_step(lbm_ens *e, int32_t nsteps) {
     };
     if (e->use_graph) {
         if (left > 0 && (e->step & 1)) eager();
-        if (left >= 2) {
-            if (!e->graph_valid) {
-                const lbm_status st = ens_capture(e);
-                if (st != LBM_OK) return st;
-            }
+        if (left >= 2 && !e->graph_valid && !ens_capture(e)) e->use_graph = 0;  // plain launches
+        if (left >= 2 && e->graph_valid) {
             // the graph was captured from lattice parity cur at an even step;
             // cur and the step parity change together, so they still match
             while (left >= 2) {
                 if (hipGraphLaunch(e->graph, e->stream) != hipSuccess) return LBM_E_DEVICE;
+                e->graph_replays += 1;
                 e->step += 2;
                 if (e->vacf_on) e->vacf_t += 2;
                 left -= 2;
@@ -1985,9 +2002,16 @@ lbm_status lbm_ens_get_step(const lbm_ens *e, int64_t *step) {
     return LBM_OK;
 }
 
+lbm_status lbm_ens_graph_replays(const lbm_ens *e, int64_t *replays) {
+    if (!e || !replays) return LBM_E_INVAL;
+    *replays = e->graph_replays;
+    return LBM_OK;
+}
+
 lbm_status lbm_ens_destroy(lbm_ens *e) {
     if (!e) return LBM_E_INVAL;
     ens_drop_graph(e);
+    if (e->cap_stream) hipStreamDestroy(e->cap_stream);
     free(e->host_reps);
     free(e->host_table);
     free(e);

@@ -272,6 +272,12 @@ class Ensemble:
     def step(self, nsteps: int = 1):
         _abi.check("lbm_ens_step", self.lib.lbm_ens_step(self.ctx, int(nsteps)))
 
+    @property
+    def graph_replays(self) -> int:
+        n = ctypes.c_int64()
+        _abi.check("lbm_ens_graph_replays", self.lib.lbm_ens_graph_replays(self.ctx, ctypes.byref(n)))
+        return n.value
+
     def autotune(self, iters: int = 10):
         ms = np.zeros(_abi.LBM_NUM_SHAPES)
         chosen = ctypes.c_int32()

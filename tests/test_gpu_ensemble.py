@@ -35,7 +35,8 @@ def test_ensemble_replicas_match_oracle(oracle_mod):
     reps = _small_replicas()
     ens = Ensemble(reps, storage="f64", kT=1e-4)
     ens.vacf_config(9, 4)
-    ens.step(31)  # odd: one plain step, then fifteen two-step graph replays
+    ens.step(31)  # odd: fifteen two-step graph replays and one plain step
+    assert ens.graph_replays == 15
     for k, rd in enumerate(reps):
         ref = oracle_mod.Sim(rd["nx"], rd["ny"], rd["nz"], rd["tau"])
         ref.set_particles(rd["r"], rd["v"], kT=1e-4, seed=rd["seed"], replica=rd["replica"])
@@ -95,6 +96,7 @@ def test_graph_replays_match_plain_launches():
     for rep in range(6):
         g.step(2)
         e.step(2)
+        assert g.graph_replays == rep + 1 and e.graph_replays == 0
         torch.cuda.synchronize()
         for k in range(len(reps)):
             assert np.array_equal(g.populations(k).cpu().numpy(), e.populations(k).cpu().numpy()), (rep, k)
