@@ -37,14 +37,19 @@ PMC_PROFILE = os.path.join(ROOT, "profiles", "k_stream_collide_suspension256.md"
 
 
 def kernel_source_hash() -> str:
-    import glob
+    """SHA-256 over the sources the stream-collide kernel is compiled from (its
+    header, the codecs, the lattice constants) and the hipcc flags: the PMC
+    traffic figure is reported only while this matches the profiled build."""
     import hashlib
 
+    from paper_1909_13412_amd import build as hip_build
+
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1909_13412_amd", "csrc", "*"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for name in ("collide.hpp", "codec.hpp", "d3q19.hpp"):
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_1909_13412_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(hip_build.HIPCC_FLAGS).encode())
     return h.hexdigest()
 
 

@@ -1,0 +1,216 @@
+// Fused pull stream-collide of the D3Q19 BGK lattice with sparse node forcing
+// (section 2.2: Eqs. s2-lbe, s2-collision, s2-eq, s2-coll, s2-trans and the
+// second Eq. s2-force), and the data layout it streams.
+//
+// Layout: for every lattice row (y, z) the 19 population rows are stored one
+// after another, x fastest: element (a, x, y, z) sits at
+// ((z*ny + y)*19 + a)*chunk + x, chunk = nx rounded up to a 128-byte line.  A
+// block streams whole rows, so each wave reads nine contiguous 19-row groups
+// and writes one; this beats one plane per velocity (38 far-apart streams).
+// Lattice A holds post-collision values at their source node, so the
+// post-streaming population is read by pulling from x - e_a.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "codec.hpp"
+#include "d3q19.hpp"
+
+namespace lbmbp {
+
+constexpr int kBlock = 256;
+// Node forces are accumulated as 64-bit fixed point (2^-48 resolution) so that
+// the sum over particles sharing a node is exact and order independent: runs
+// are bitwise reproducible.  |contribution| must stay below 2^14.
+constexpr double kFixScale = 281474976710656.0;        // 2^48
+constexpr double kFixInv = 1.0 / 281474976710656.0;
+constexpr double kFixLimit = 16384.0;
+constexpr uint32_t kErrFixRange = 1u;
+
+struct Grid {
+    uint32_t nx, ny, nz;
+    uint32_t ncell;
+    uint32_t chunk;  // elements per population row (nx padded to a 128-byte line)
+};
+
+// Storage index of population a at node (x, y, z).
+__device__ inline uint64_t pop_index(const Grid &g, uint32_t x, uint32_t y, uint32_t z, int a) {
+    return (uint64_t(z * g.ny + y) * D3Q19::Q + uint32_t(a)) * g.chunk + x;
+}
+
+// Node forces of one step: a dense fixed-point field, written only at the
+// (at most 8 per particle) nodes that receive a reaction force and read only
+// where the one-bit flag is set, so the stream-collide pays 1/8 byte per node.
+// Two of them alternate between steps; each is cleared node by node by the
+// particles that wrote it.
+struct ForceField {
+    long long *f;    // [ncell][3] fixed-point force
+    uint32_t *mask;  // one bit per node: node carries a force this step
+};
+
+// Source node of direction a for a pull at (x, y, z): x - e_a, periodic.
+struct Neighbours {
+    uint32_t sx[3], sy[3], sz[3];  // index [e + 1]: coordinate - e
+    __device__ inline Neighbours(uint32_t x, uint32_t y, uint32_t z, const Grid &g) {
+        sx[0] = (x + 1 == g.nx) ? 0 : x + 1;
+        sx[1] = x;
+        sx[2] = (x == 0) ? g.nx - 1 : x - 1;
+        sy[0] = (y + 1 == g.ny) ? 0 : y + 1;
+        sy[1] = y;
+        sy[2] = (y == 0) ? g.ny - 1 : y - 1;
+        sz[0] = (z + 1 == g.nz) ? 0 : z + 1;
+        sz[1] = z;
+        sz[2] = (z == 0) ? g.nz - 1 : z - 1;
+    }
+    // linear node index of x - e_a (canonical [z][y][x] order)
+    template <int a>
+    __device__ inline uint32_t src(const Grid &g) const {
+        return (sz[D3Q19::ez[a] + 1] * g.ny + sy[D3Q19::ey[a] + 1]) * g.nx + sx[D3Q19::ex[a] + 1];
+    }
+    // storage index of population a at x - e_a
+    template <int a>
+    __device__ inline uint64_t pop(const Grid &g) const {
+        return pop_index(g, sx[D3Q19::ex[a] + 1], sy[D3Q19::ey[a] + 1], sz[D3Q19::ez[a] + 1], a);
+    }
+};
+
+template <int a, int Q, typename F>
+__device__ inline void static_for(F &&f) {
+    if constexpr (a < Q) {
+        f(std::integral_constant<int, a>{});
+        static_for<a + 1, Q>(f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused pull stream-collide with sparse forcing.
+//
+// Each lane updates CPT nodes with the same x in rows y, y + ny/CPT, ...: all
+// 19 x CPT population loads (and the forcing flags) are issued before any of
+// them is consumed, which keeps more bytes in flight per wave.  BS lanes per
+// block.  Lattice A -> B; F is the node-force field of this step.
+// ---------------------------------------------------------------------------
+// Deterministic block sum of N doubles (fixed butterfly and wave order);
+// thread k < N writes out[k].  Every thread of the block must call it.
+template <int N, int BS>
+__device__ inline void block_sum(double (&v)[N], double *__restrict__ out) {
+    __shared__ double sh[BS / 64][N];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) sh[threadIdx.x >> 6][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < N) {
+        double s = 0.0;
+        for (int w = 0; w < BS / 64; ++w) s += sh[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// The nodes of one lane: lane_cell < ncell / CPT indexes the first band of
+// ny/CPT rows; the lane also takes the same (x, z) in the CPT - 1 bands below.
+// With MOMENTS the FP64 sums of (rho~ - 1, u) over these nodes are added to acc.
+template <class C, bool FORCED, bool MOMENTS, int CPT>
+__device__ inline void collide_lane(const typename C::T *__restrict__ A,
+                                    typename C::T *__restrict__ B, const Grid &g,
+                                    typename C::R omega, typename C::R enc_s, typename C::R dec_s,
+                                    const ForceField &ff, uint32_t lane_cell, double (&acc)[4]) {
+    using T = typename C::T;
+    using R = typename C::R;
+    const uint32_t x = lane_cell % g.nx;
+    const uint32_t t = lane_cell / g.nx;
+    const uint32_t rows = g.ny / CPT;
+    const uint32_t y0 = t % rows;
+    const uint32_t z = t / rows;
+
+    T raw[CPT][D3Q19::Q];
+    uint32_t flags[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const uint32_t y = y0 + uint32_t(c) * rows;
+        const Neighbours nb(x, y, z, g);
+        static_for<0, D3Q19::Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            raw[c][a] = A[nb.pop<a>(g)];
+        });
+        if constexpr (FORCED) {
+            const uint32_t cell = (z * g.ny + y) * g.nx + x;
+            flags[c] = (ff.mask[cell >> 5] >> (cell & 31)) & 1u;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const uint32_t y = y0 + uint32_t(c) * rows;
+        R gv[D3Q19::Q];
+        static_for<0, D3Q19::Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            gv[a] = C::dec(raw[c][a], dec_s);
+        });
+        R drho = R(0), ux = R(0), uy = R(0), uz = R(0);
+        static_for<0, D3Q19::Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            drho += gv[a];
+            if constexpr (D3Q19::ex[a] != 0) ux += D3Q19::ex[a] > 0 ? gv[a] : -gv[a];
+            if constexpr (D3Q19::ey[a] != 0) uy += D3Q19::ey[a] > 0 ? gv[a] : -gv[a];
+            if constexpr (D3Q19::ez[a] != 0) uz += D3Q19::ez[a] > 0 ? gv[a] : -gv[a];
+        });
+        const R uu = ux * ux + uy * uy + uz * uz;
+        if constexpr (MOMENTS) {
+            acc[0] += double(drho);
+            acc[1] += double(ux);
+            acc[2] += double(uy);
+            acc[3] += double(uz);
+        }
+        R Fx = R(0), Fy = R(0), Fz = R(0);
+        if constexpr (FORCED) {
+            if (flags[c]) {
+                const uint64_t cell = (z * g.ny + y) * g.nx + x;
+                Fx = R(double(ff.f[3 * cell + 0]) * kFixInv);
+                Fy = R(double(ff.f[3 * cell + 1]) * kFixInv);
+                Fz = R(double(ff.f[3 * cell + 2]) * kFixInv);
+            }
+        }
+        const uint64_t row_base = uint64_t(z * g.ny + y) * D3Q19::Q * g.chunk + x;
+        static_for<0, D3Q19::Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            constexpr int cx = D3Q19::ex[a], cy = D3Q19::ey[a], cz = D3Q19::ez[a];
+            const R w = D3Q19::w<R>(a);
+            const R eu = R(cx) * ux + R(cy) * uy + R(cz) * uz;
+            const R geq = w * (drho + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
+            R gn = gv[a] + omega * (geq - gv[a]);
+            if constexpr (FORCED) gn += R(3) * w * (R(cx) * Fx + R(cy) * Fy + R(cz) * Fz);
+            B[row_base + uint64_t(a) * g.chunk] = C::enc(gn, enc_s);
+        });
+    }
+}
+
+template <class C, bool FORCED, bool MOMENTS, int CPT, int BS>
+__global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__restrict__ A,
+                                                       typename C::T *__restrict__ B, Grid g,
+                                                       typename C::R omega, typename C::R enc_s,
+                                                       typename C::R dec_s, ForceField ff,
+                                                       double *__restrict__ mom) {
+    const uint32_t lane_cell = blockIdx.x * BS + threadIdx.x;  // node index in the first row band
+    const bool active = lane_cell < g.ncell / CPT;
+    if constexpr (!MOMENTS) {
+        if (!active) return;
+    }
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (active) collide_lane<C, FORCED, MOMENTS, CPT>(A, B, g, omega, enc_s, dec_s, ff, lane_cell, acc);
+    if constexpr (MOMENTS) block_sum<4, BS>(acc, mom + 4 * uint64_t(blockIdx.x));
+}
+
+// Launch shapes of the stream-collide, chosen per context (lbm_autotune).
+struct CollideShape {
+    int cpt, bs;
+};
+constexpr CollideShape kShapes[] = {{1, 512}, {1, 256}, {2, 512}, {2, 256}};
+constexpr int kNumShapes = 4;
+
+}  // namespace lbmbp
