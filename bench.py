@@ -250,6 +250,49 @@ def time_ensemble(steps, warmup):
     return out
 
 
+def time_adjoint(steps, warmup):
+    """Reverse mode on the 64^3 / 16-particle workload: the recorded forward
+    (checkpoint every 100 steps) and the adjoint sweep (segment recompute plus
+    the reverse step kernels), against plain forward steps."""
+    import torch
+
+    from paper_1909_13412_amd import Lattice
+    from paper_1909_13412_amd.inputs import ADJOINT64, particle_positions, particle_velocities
+
+    w = ADJOINT64
+    L, n, every = w["L"], w["n"], w["every"]
+    lat = Lattice(L, L, L, w["tau"], storage=w["storage"])
+    r = particle_positions(n, L, w["seed"])
+    v = particle_velocities(n, w["kT"] / w["mass"], w["seed"])
+    lat.particles_couple(r, v, mass=w["mass"], gamma=w["gamma"], kT=w["kT"], seed=w["seed"])
+    cv = torch.ones((n, 3), dtype=torch.float64, device=lat.device)
+    tape = lat.record(2 * every, every)
+    lat.adjoint(tape, None, None, cv)
+    lat.step(warmup)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = fn()
+        torch.cuda.synchronize()
+        return res, time.perf_counter() - t0
+
+    _, t_fwd = timed(lambda: lat.step(steps))
+    tape, t_rec = timed(lambda: lat.record(steps, every))
+    g, t_adj = timed(lambda: lat.adjoint(tape, None, None, cv))
+    work = lat._adj_keep[4].numel()
+    return {"workload": "adjoint64", "box": [L] * 3, "tau": w["tau"], "particles": n,
+            "storage": w["storage"], "steps": steps, "checkpoint_every": every,
+            "loss": "sum of final particle velocities",
+            "tape_MB": round(tape.buf.numel() / 2**20, 1), "work_MB": round(work / 2**20, 1),
+            "forward_ms_per_step": round(t_fwd * 1e3 / steps, 5),
+            "record_ms_per_step": round(t_rec * 1e3 / steps, 5),
+            "adjoint_ms_per_step": round(t_adj * 1e3 / steps, 5),
+            "adjoint_over_forward": round(t_adj / t_fwd, 3),
+            "grad_gamma_tau_M_kT": [float(x) for x in g["params"].cpu().tolist()]}
+
+
 def cpu_baseline(w, steps):
     import oracle
     from paper_1909_13412_amd.inputs import workload_particles
@@ -288,6 +331,7 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=300, help="steps timed with per-kernel events")
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=1000, help="0 = skip the ensemble timing")
+    ap.add_argument("--adjoint-steps", type=int, default=2000, help="0 = skip the reverse-mode timing")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -323,6 +367,10 @@ def main():
     if args.ensemble_steps > 0:
         print(f"[bench] ensemble ({args.ensemble_steps} steps)", file=sys.stderr, flush=True)
         ensemble = time_ensemble(args.ensemble_steps, args.warmup)
+    adjoint = None
+    if args.adjoint_steps > 0:
+        print(f"[bench] reverse mode ({args.adjoint_steps} steps)", file=sys.stderr, flush=True)
+        adjoint = time_adjoint(args.adjoint_steps, args.warmup)
     precision = None
     if args.precision_steps > 0:
         print(f"[bench] precision study ({args.precision_steps} steps per storage)", file=sys.stderr,
@@ -375,6 +423,7 @@ def main():
         "variants": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                      for k, v in variants.items()},
         "ensemble": ensemble,
+        "adjoint": adjoint,
         "precision": precision,
         "cpu_baseline": cpu,
     }

@@ -217,6 +217,57 @@ lbm_status lbm_get_step(const lbm_ctx *ctx, int64_t *step);
 lbm_status lbm_destroy(lbm_ctx *ctx);
 
 /* ---------------------------------------------------------------------------
+ * Reverse mode (gradients).  The coupled step of section 2 is a differentiable
+ * map S: (f^n, r^n, V^n; gamma, tau, M, kT) -> (f^{n+1}, r^{n+1}, V^{n+1}),
+ * f the post-streaming populations (Eq. s2-trans), the friction from Eq.
+ * s2-slet-v (or Eqs. s2-dis1 / s2-dis0), the Brownian force sqrt(2 gamma kT) xi
+ * with the drawn normals xi held fixed (Eqs. s2-rf1, s2-rf2), and the radius
+ * either given or R = gamma / (6 pi eta(tau)) by Stokes' law.  lbm_record runs
+ * N steps like lbm_step and keeps a checkpoint every `every` steps;
+ * lbm_adjoint then returns the gradient of J = <fb, f^N> + <rb, r^N> +
+ * <vb, V^N> with respect to the state at the start of the recording and to
+ * (gamma, tau, M, kT): the vector-Jacobian product of S^N, the derivative of
+ * the exact-arithmetic map taken along the stored trajectory, evaluated in
+ * FP64.  The corner cell floor(s) and the fit's degenerate-case branches are
+ * piecewise constant (zero derivative).  Supported for FP64 and FP32 storage
+ * (LBM_E_UNSUPPORTED otherwise). */
+
+/* Bytes of the checkpoint buffer for recording nsteps >= 1 with a checkpoint
+ * every `every` >= 1 steps: ceil(nsteps/every) checkpoints of one lattice plus
+ * the particle positions and velocities of the context as it is now. */
+lbm_status lbm_tape_bytes(const lbm_ctx *ctx, int32_t nsteps, int32_t every, size_t *bytes);
+
+/* Take nsteps coupled steps exactly as lbm_step does (VACF and series
+ * recording included) and store the state at the start of every `every`-th
+ * step in `tape` (device, lbm_tape_bytes, 256-byte aligned, caller-owned).
+ * Replaces any earlier recording of this context.  Asynchronous. */
+lbm_status lbm_record(lbm_ctx *ctx, int32_t nsteps, int32_t every, void *tape);
+
+/* Bytes of the work buffer lbm_adjoint needs for the current recording:
+ * `every` lattice states plus particle states for recomputing one segment
+ * forward, two FP64 adjoint lattices, the node fields and per-particle
+ * sums.  LBM_E_STATE if nothing was recorded. */
+lbm_status lbm_adjoint_work_bytes(const lbm_ctx *ctx, size_t *bytes);
+
+/* Gradient of the recorded run (asynchronous; the context's own state is not
+ * touched and may have moved on).  Segments are recomputed forward from their
+ * checkpoints with the same kernels (bit-identical states), then swept in
+ * reverse.  All arrays are device memory:
+ *   tape       the buffer of the last lbm_record on this context;
+ *   work       lbm_adjoint_work_bytes, 256-byte aligned;
+ *   adj_pop    in: dJ/df^N, canonical FP64 [19][nz][ny][nx] (the layout of
+ *              lbm_get_populations); out: dJ/df at the start of the recording;
+ *   adj_r, adj_v  in: dJ/dr^N, dJ/dV^N, FP64 [n][3]; out: the gradients at
+ *              the start (NULL allowed without particles);
+ *   adj_param  out: FP64 [4] dJ/d(gamma, tau, M, kT).  dJ/dkT is reported
+ *              only for kT > 0 (0 otherwise: sqrt(kT) has no derivative at 0).
+ * Node contributions of particles that share a node are added with FP64
+ * atomics, so repeated runs agree to rounding rather than bitwise when two
+ * particles touch the same node in a step. */
+lbm_status lbm_adjoint(lbm_ctx *ctx, const void *tape, void *work, double *adj_pop,
+                       double *adj_r, double *adj_v, double *adj_param);
+
+/* ---------------------------------------------------------------------------
  * Ensembles: many independent periodic boxes of different sizes ("replicas"),
  * e.g. for ensemble-averaged velocity autocorrelation, stepped together.  One
  * particle launch and one stream-collide launch per step cover every replica

@@ -21,6 +21,7 @@ EXPORTS = [
     "lbm_particle_forces", "lbm_vacf_config", "lbm_vacf_counts", "lbm_step", "lbm_series_config",
     "lbm_series_count", "lbm_observables",
     "lbm_profile_enable", "lbm_profile_read", "lbm_autotune", "lbm_get_step", "lbm_destroy",
+    "lbm_tape_bytes", "lbm_record", "lbm_adjoint_work_bytes", "lbm_adjoint",
     "lbm_ens_bytes", "lbm_ens_init", "lbm_ens_use_graph", "lbm_ens_vacf_config",
     "lbm_ens_vacf_counts", "lbm_ens_step", "lbm_ens_autotune", "lbm_ens_observables",
     "lbm_ens_get_populations", "lbm_ens_get_step", "lbm_ens_graph_replays", "lbm_ens_destroy",
@@ -98,6 +99,10 @@ def load() -> ctypes.CDLL:
         "lbm_autotune": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],
         "lbm_get_step": [vp, ctypes.POINTER(i64)],
         "lbm_destroy": [vp],
+        "lbm_tape_bytes": [vp, i32, i32, ctypes.POINTER(sz)],
+        "lbm_record": [vp, i32, i32, vp],
+        "lbm_adjoint_work_bytes": [vp, ctypes.POINTER(sz)],
+        "lbm_adjoint": [vp, vp, vp, dp, dp, dp, dp],
         "lbm_ens_bytes": [ctypes.POINTER(EnsembleDesc), ctypes.POINTER(ReplicaDesc),
                           ctypes.POINTER(sz), ctypes.POINTER(sz)],
         "lbm_ens_init": [ctypes.POINTER(EnsembleDesc), ctypes.POINTER(ReplicaDesc), vp, vp, vp,

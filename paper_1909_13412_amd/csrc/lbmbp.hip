@@ -27,269 +27,16 @@
 #include <type_traits>
 
 #include "lbmbp.h"
+#include "adjoint.hpp"
 #include "codec.hpp"
 #include "collide.hpp"
 #include "d3q19.hpp"
+#include "particle.hpp"
 #include "philox.hpp"
 
 namespace lbmbp {
 
-constexpr int kParticleBlock = 64;  // eight particles per block: spread over every CU
 constexpr int kRedBlocks = 1024;
-constexpr uint32_t kNoNode = 0xFFFFFFFFu;
-
-// ---------------------------------------------------------------------------
-// Particle coupling: eight lanes per particle, lane p owns neighbour node
-// floor(s) + (p & 1, p >> 1 & 1, p >> 2 & 1).
-// ---------------------------------------------------------------------------
-struct ParticleArgs {
-    double *r, *v;
-    double *fh, *fr;
-    uint32_t *prev_cell;  // [n][8] node each lane spread to last step, or kNoNode
-    uint32_t *err;
-    int32_t n;
-    int32_t friction;
-    double mass, gamma, sig, R;
-    uint64_t seed;
-    uint32_t replica;
-    uint32_t step;
-    // velocity autocorrelation (acc == nullptr: off).  Origins k*stride with
-    // k in [k_lo, k_hi] are active at sample time t; origin k lives in slot
-    // k % nslot.
-    double *acc;      // [n][max_lag+1]
-    double *origins;  // [nslot][n][3]
-    int64_t t, k_lo, k_hi;
-    int32_t nslot, stride, max_lag;
-    // per-block FP64 sums of M V^n (nullptr: off), [blocks][3]
-    double *pmom;
-};
-
-__device__ inline double sum8(double v) {
-    v += __shfl_xor(v, 1, 8);
-    v += __shfl_xor(v, 2, 8);
-    v += __shfl_xor(v, 4, 8);
-    return v;
-}
-
-// Where a particle lives: its box, lattice and node-force fields, and the
-// Philox key and counter words of its Brownian force.
-template <class C>
-struct ParticleSite {
-    const typename C::T *A;
-    Grid g;
-    ForceField cur, old;
-    uint64_t seed;
-    uint32_t replica;  // third counter word
-    uint32_t index;    // second counter word: particle index within its box
-    double R;          // particle radius used by the fit
-};
-
-// One lane (node p of particle i) of the coupled particle update.  r, V are
-// the particle's position and velocity at the start of the step; the whole
-// 8-lane group must call this together (it shuffles within the group).
-template <class C>
-__device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R dec_s,
-                                     const ParticleArgs &pa, int32_t i, int p, bool valid,
-                                     const double (&r)[3], const double (&V)[3]) {
-    const typename C::T *__restrict__ A = site.A;
-    const Grid &g = site.g;
-    const ForceField &cur = site.cur;
-    const ForceField &old = site.old;
-    const uint32_t Ln[3] = {g.nx, g.ny, g.nz};
-    const int b[3] = {p & 1, (p >> 1) & 1, (p >> 2) & 1};
-    double d[3];
-    uint32_t node[3];
-    double W = 1.0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double L = double(Ln[k]);
-        const double s = r[k] - L * floor(r[k] / L);  // wrapped position, in [-eps, L]
-        const double c = floor(s);
-        d[k] = (c + double(b[k])) - s;                // node minus particle, unwrapped
-        // Rounding can leave c at -1 or L; the periodic wrap handles both (a
-        // non-finite position converts with saturation and stays in the box).
-        int32_t ci = (int32_t(c) + b[k]) % int32_t(Ln[k]);
-        node[k] = uint32_t(ci < 0 ? ci + int32_t(Ln[k]) : ci);
-        W *= 1.0 - fabs(d[k]);
-    }
-    const uint32_t cell = (node[2] * g.ny + node[1]) * g.nx + node[0];
-    const bool coupled = pa.friction != LBM_FRICTION_BD;
-
-    // Issue the gather of f^n at this lane's node (pull from node - e_a); the
-    // values are consumed only after the VACF sample and the Brownian force,
-    // which overlap the load latency.
-    typename C::T raw[D3Q19::Q];
-    if (coupled) {
-        const Neighbours nb(node[0], node[1], node[2], g);
-        static_for<1, D3Q19::Q>([&](auto ac) {
-            constexpr int a = decltype(ac)::value;
-            raw[a] = A[nb.pop<a>(g)];
-        });
-    }
-
-    // C_v(t) = <V(0).V(t)> (section 2.1): V^n against every active origin;
-    // lane p takes the origins k = k_lo + p, k_lo + p + 8, ...  The newest
-    // origin (lag 0) is stored by the lane that owns it.
-    if (valid && pa.acc) {
-        double *acc_i = pa.acc + int64_t(i) * (pa.max_lag + 1);
-        for (int64_t k = pa.k_lo + p; k <= pa.k_hi; k += 8) {
-            double *o = pa.origins + (int64_t(k % pa.nslot) * pa.n + i) * 3;
-            const int64_t lag = pa.t - k * pa.stride;
-            if (lag == 0) {
-                o[0] = V[0];
-                o[1] = V[1];
-                o[2] = V[2];
-                acc_i[0] += V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
-            } else {
-                acc_i[lag] += o[0] * V[0] + o[1] * V[1] + o[2] * V[2];
-            }
-        }
-    }
-
-    // Eqs. s2-rf1, s2-rf2: white noise of variance 2 gamma kT per step.  The
-    // three Box-Muller outputs are computed by lanes 0, 1, 2 of the group
-    // (one logarithm, square root and sine/cosine each) and gathered.
-    double FR[3] = {0.0, 0.0, 0.0};
-    if (pa.sig > 0.0) {
-        const Philox4x32 x = philox4x32_10(pa.step, site.index, site.replica, 0u,
-                                           uint32_t(site.seed), uint32_t(site.seed >> 32));
-        const int q = p < 3 ? p : 0;
-        const uint32_t wa = q == 2 ? x.v[2] : x.v[0];
-        const uint32_t wb = q == 2 ? x.v[3] : x.v[1];
-        double zq;
-        box_muller_one(wa, wb, q == 1, &zq);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) FR[k] = pa.sig * __shfl(zq, k, 8);
-    }
-
-    double FH[3] = {0.0, 0.0, 0.0};
-    if (!coupled) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) FH[k] = -pa.gamma * V[k];
-    } else {
-        // u^n at this lane's node: u = sum_a e_a f_a = sum_a e_a g_a (Eq. s2-fv).
-        double u[3] = {0.0, 0.0, 0.0};
-        static_for<1, D3Q19::Q>([&](auto ac) {
-            constexpr int a = decltype(ac)::value;
-            const double gvl = double(C::dec(raw[a], dec_s));
-            if constexpr (D3Q19::ex[a] != 0) u[0] += D3Q19::ex[a] > 0 ? gvl : -gvl;
-            if constexpr (D3Q19::ey[a] != 0) u[1] += D3Q19::ey[a] > 0 ? gvl : -gvl;
-            if constexpr (D3Q19::ez[a] != 0) u[2] += D3Q19::ez[a] > 0 ? gvl : -gvl;
-        });
-        if (pa.friction == LBM_FRICTION_POINTWISE) {
-            // Eq. s2-dis1 with u(r) interpolated trilinearly.
-#pragma unroll
-            for (int k = 0; k < 3; ++k) FH[k] = -pa.gamma * (V[k] - sum8(W * u[k]));
-        } else {
-            // Eq. s2-slet-v: e^N from the mean relative velocity, least-squares
-            // amplitude of the Stokeslet shape, F_H = gamma U^inf e^N.
-            double w[3], m[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                w[k] = u[k] - V[k];
-                m[k] = sum8(w[k]) / 8.0;
-            }
-            const double mn = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
-            const bool has_dir = mn > 0.0;
-            double eN[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) eN[k] = has_dir ? m[k] / mn : 0.0;
-            const double rp = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            double num = 0.0, den = 0.0;
-            if (rp > 1e-12) {
-                const double de = d[0] * eN[0] + d[1] * eN[1] + d[2] * eN[2];
-                const double ca = 1.0 - 3.0 * site.R / (4.0 * rp);
-                const double cb = 3.0 * site.R * de / (4.0 * rp * rp * rp);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const double gk = ca * eN[k] - cb * d[k];
-                    num += w[k] * gk;
-                    den += gk * gk;
-                }
-            }
-            num = sum8(num);
-            den = sum8(den);
-            if (has_dir && den != 0.0) {
-                const double Uinf = num / den;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) FH[k] = pa.gamma * Uinf * eN[k];
-            }
-        }
-    }
-    if (!valid) return;
-
-    // Release this lane's node from the field used one step ago (it was
-    // consumed by that step's stream-collide).
-    const uint32_t pc = pa.prev_cell[8 * i + p];
-    if (pc != kNoNode) {
-        old.f[3 * uint64_t(pc) + 0] = 0;
-        old.f[3 * uint64_t(pc) + 1] = 0;
-        old.f[3 * uint64_t(pc) + 2] = 0;
-        atomicAnd(&old.mask[pc >> 5], ~(1u << (pc & 31)));
-    }
-    // First Eq. s2-force: the node receives -F_H W_p (unit cell volume).
-    uint32_t my_cell = kNoNode;
-    if (coupled) {
-        long long q[3];
-        bool ok = true;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const double c = -FH[k] * W;
-            ok = ok && (fabs(c) < kFixLimit);
-            q[k] = __double2ll_rn(c * kFixScale);
-        }
-        if (!ok) {
-            atomicOr(pa.err, kErrFixRange);
-            q[0] = q[1] = q[2] = 0;
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            atomicAdd(reinterpret_cast<unsigned long long *>(&cur.f[3 * uint64_t(cell) + k]),
-                      static_cast<unsigned long long>(q[k]));
-        atomicOr(&cur.mask[cell >> 5], 1u << (cell & 31));
-        my_cell = cell;
-    }
-    pa.prev_cell[8 * i + p] = my_cell;
-
-    if (p != 0) return;
-    // Eqs. s2-langevin, s2-langevin2 with dt = 1 (F_C = 0).
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double vn = V[k] + (FH[k] + FR[k]) / pa.mass;
-        pa.v[3 * i + k] = vn;
-        pa.r[3 * i + k] = r[k] + vn;
-        pa.fh[3 * i + k] = FH[k];
-        pa.fr[3 * i + k] = FR[k];
-    }
-}
-
-template <class C>
-__global__ __launch_bounds__(kParticleBlock) void k_particle(const typename C::T *__restrict__ A,
-                                                             Grid g, typename C::R dec_s,
-                                                             ParticleArgs pa, ForceField cur,
-                                                             ForceField old) {
-    const uint32_t gt = blockIdx.x * kParticleBlock + threadIdx.x;
-    const int32_t i = int32_t(gt >> 3);
-    const int p = int(gt & 7u);
-    const bool valid = i < pa.n;
-    const int32_t ii = valid ? i : pa.n - 1;  // whole 8-lane groups are valid or not
-
-    double r[3], V[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        r[k] = pa.r[3 * ii + k];
-        V[k] = pa.v[3 * ii + k];
-    }
-    if (pa.pmom) {
-        // particle momentum M V^n of the state at the start of the step
-        double pm[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) pm[k] = (valid && p == 0) ? pa.mass * V[k] : 0.0;
-        block_sum<3, kParticleBlock>(pm, pa.pmom + 3 * uint64_t(blockIdx.x));
-    }
-    const ParticleSite<C> site{A, g, cur, old, pa.seed, pa.replica, uint32_t(i), pa.R};
-    particle_lane<C>(site, dec_s, pa, i, p, valid, r, V);
-}
 
 // ---------------------------------------------------------------------------
 // Ensembles of independent boxes (replicas) of different sizes, stepped
@@ -603,6 +350,12 @@ struct lbm_ctx {
     double *fluid_partials;  // grid scratch: [collide blocks][4]
     double *series_stage;    // grid scratch: [kSeriesBlocks][7]
     double *part_partials;   // particle scratch: [particle blocks][3]
+    // forward run kept for the adjoint (lbm_record)
+    void *rec_tape;
+    int64_t rec_n0;
+    int32_t rec_nsteps, rec_every, rec_np;
+    lbm_particle_desc rec_pdesc;
+    double rec_R;
 };
 
 namespace {
@@ -1820,6 +1573,317 @@ lbm_status lbm_ens_destroy(lbm_ens *e) {
     free(e->host_table);
     free(e);
     return LBM_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Reverse mode: recorded forward runs and their adjoint.
+// ===========================================================================
+namespace {
+
+// One checkpoint: the lattice as stored (post-collision values at their
+// source node) and the particle state r[n][3], v[n][3].
+struct TapeLayout {
+    size_t lat, part, slot;
+};
+
+TapeLayout tape_layout(const lbm_ctx *c, int32_t np) {
+    TapeLayout t;
+    lbm_lattice_bytes(&c->desc, &t.lat);
+    t.part = align_up(size_t(np) * 6 * 8, kAlign);
+    t.slot = t.lat + t.part;
+    return t;
+}
+
+// The FP64 adjoint lattice: interleaved rows of 128-byte-aligned doubles.
+Grid adj_grid(const lbm_ctx *c) {
+    Grid gd = c->g;
+    gd.chunk = uint32_t(align_up(c->g.nx, 16));
+    return gd;
+}
+
+size_t adj_lattice_bytes(const lbm_ctx *c) {
+    const Grid gd = adj_grid(c);
+    return align_up(size_t(gd.chunk) * D3Q19::Q * gd.ny * gd.nz * 8, kAlign);
+}
+
+struct AdjLayout {
+    size_t seg_lat, seg_part;  // `every` lattice / particle states of one segment
+    size_t abar[2];            // adjoint lattices
+    size_t uf[2], um[2];       // adjoint node fields and their flags
+    size_t ff[2], fm[2];       // node-force fields of the forward recompute
+    size_t prev_fwd, prev_adj, fh, fr, pgrad, wacc;
+    size_t total;
+};
+
+AdjLayout adj_layout(const lbm_ctx *c, int32_t np, int32_t every) {
+    AdjLayout L;
+    const TapeLayout t = tape_layout(c, np);
+    const size_t field = force_field_bytes(&c->desc);
+    const size_t mask = align_up(size_t(c->mask_words) * 4, kAlign);
+    const size_t pcell = align_up(size_t(np) * 8 * 4, kAlign);
+    size_t o = 0;
+    L.seg_lat = o;
+    o += size_t(every) * t.lat;
+    L.seg_part = o;
+    o += size_t(every) * t.part;
+    for (int k = 0; k < 2; ++k) {
+        L.abar[k] = o;
+        o += adj_lattice_bytes(c);
+    }
+    for (int k = 0; k < 2; ++k) {
+        L.uf[k] = o;
+        o += field;
+        L.um[k] = o;
+        o += mask;
+    }
+    for (int k = 0; k < 2; ++k) {
+        L.ff[k] = o;
+        o += field;
+        L.fm[k] = o;
+        o += mask;
+    }
+    L.prev_fwd = o;
+    o += pcell;
+    L.prev_adj = o;
+    o += pcell;
+    L.fh = o;
+    o += align_up(size_t(np) * 3 * 8, kAlign);
+    L.fr = o;
+    o += align_up(size_t(np) * 3 * 8, kAlign);
+    L.pgrad = o;
+    o += align_up(size_t(np) * 4 * 8, kAlign);
+    L.wacc = o;
+    o += align_up(size_t(blocks_for(c->g.ncell)) * 8, kAlign);
+    L.total = o;
+    return L;
+}
+
+bool adjoint_storage(const lbm_ctx *c) {
+    return c->desc.storage == LBM_STORE_F64 || c->desc.storage == LBM_STORE_F32;
+}
+
+template <class C>
+hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, double *adj_r,
+                       double *adj_v, double *adj_param) {
+    using T = typename C::T;
+    using R = typename C::R;
+    const int32_t np = c->rec_np, N = c->rec_nsteps, K = c->rec_every;
+    const lbm_particle_desc &pd = c->rec_pdesc;
+    const TapeLayout t = tape_layout(c, np);
+    const AdjLayout L = adj_layout(c, np, K);
+    const Grid gd = adj_grid(c);
+    hipStream_t st = c->stream;
+    const size_t field = force_field_bytes(&c->desc);
+    const size_t mask = size_t(c->mask_words) * 4;
+    const size_t pbytes = size_t(np) * 3 * 8;
+    auto at = [&](size_t off) { return work + off; };
+    auto seg = [&](int32_t k) { return reinterpret_cast<T *>(at(L.seg_lat + size_t(k) * t.lat)); };
+    auto seg_r = [&](int32_t k) { return reinterpret_cast<double *>(at(L.seg_part + size_t(k) * t.part)); };
+    auto seg_v = [&](int32_t k) { return seg_r(k) + 3 * size_t(np); };
+    double *abar[2] = {reinterpret_cast<double *>(at(L.abar[0])),
+                       reinterpret_cast<double *>(at(L.abar[1]))};
+    AdjField uf[2], ff_unused{nullptr, nullptr};
+    ForceField ff[2];
+    for (int k = 0; k < 2; ++k) {
+        uf[k] = AdjField{reinterpret_cast<double *>(at(L.uf[k])), reinterpret_cast<uint32_t *>(at(L.um[k]))};
+        ff[k] = ForceField{reinterpret_cast<long long *>(at(L.ff[k])), reinterpret_cast<uint32_t *>(at(L.fm[k]))};
+    }
+    double *pgrad = reinterpret_cast<double *>(at(L.pgrad));
+    double *wacc = reinterpret_cast<double *>(at(L.wacc));
+    uint32_t *prev_fwd = reinterpret_cast<uint32_t *>(at(L.prev_fwd));
+    uint32_t *prev_adj = reinterpret_cast<uint32_t *>(at(L.prev_adj));
+
+    hipError_t e = hipSuccess;
+    auto memset_ = [&](void *p, int v, size_t n) {
+        if (e == hipSuccess && n) e = hipMemsetAsync(p, v, n, st);
+    };
+    auto copy_ = [&](void *dst, const void *src, size_t n) {
+        if (e == hipSuccess && n) e = hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, st);
+    };
+    for (int k = 0; k < 2; ++k) {
+        memset_(uf[k].u, 0, field);
+        memset_(uf[k].mask, 0, mask);
+    }
+    memset_(prev_adj, 0xFF, size_t(np) * 8 * 4);
+    memset_(pgrad, 0, size_t(np) * 4 * 8);
+    memset_(wacc, 0, size_t(blocks_for(c->g.ncell)) * 8);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_import, dim3(blocks_for(c->g.ncell)), dim3(kBlock), 0, st, adj_pop,
+                       abar[0], gd);
+
+    // Forward recompute: the particle kernel without VACF or sums.
+    ParticleArgs pa{};
+    pa.fh = reinterpret_cast<double *>(at(L.fh));
+    pa.fr = reinterpret_cast<double *>(at(L.fr));
+    pa.prev_cell = prev_fwd;
+    pa.err = c->err;
+    pa.n = np;
+    pa.friction = pd.friction;
+    pa.mass = pd.mass;
+    pa.gamma = pd.gamma;
+    pa.sig = pd.kT > 0.0 ? sqrt(2.0 * pd.gamma * pd.kT) : 0.0;
+    pa.R = c->rec_R;
+    pa.seed = pd.seed;
+    pa.replica = pd.replica;
+    pa.acc = nullptr;
+    pa.origins = nullptr;
+    pa.pmom = nullptr;
+    pa.k_hi = -1;
+    pa.nslot = pa.stride = 1;
+
+    AdjParticleArgs ap{};
+    ap.rbar = adj_r;
+    ap.vbar = adj_v;
+    ap.pgrad = pgrad;
+    ap.prev_cell = prev_adj;
+    ap.n = np;
+    ap.friction = pd.friction;
+    ap.mass = pd.mass;
+    ap.gamma = pd.gamma;
+    ap.kT = pd.kT;
+    ap.sig = pa.sig;
+    ap.R = c->rec_R;
+    if (pd.radius > 0.0) {
+        ap.dR_dgamma = ap.dR_dtau = 0.0;
+    } else {
+        const double nu = (c->desc.tau - 0.5) / 3.0;
+        ap.dR_dgamma = 1.0 / (6.0 * M_PI * nu);
+        ap.dR_dtau = -c->rec_R / (3.0 * nu);
+    }
+    ap.seed = pd.seed;
+    ap.replica = pd.replica;
+    const unsigned pgrid = np > 0 ? unsigned(particle_blocks(np)) : 0;
+    const unsigned cgrid = blocks_for(c->g.ncell);
+
+    int cur = 0;
+    const int32_t nseg = (N + K - 1) / K;
+    for (int32_t j = nseg - 1; j >= 0 && e == hipSuccess; --j) {
+        const int32_t len = (N - j * K) < K ? (N - j * K) : K;
+        const char *slot = tape + size_t(j) * t.slot;
+        copy_(seg(0), slot, t.lat);
+        copy_(seg_r(0), slot + t.lat, 2 * pbytes);
+        if (np > 0 && len > 1) {
+            for (int k = 0; k < 2; ++k) {
+                memset_(ff[k].f, 0, field);
+                memset_(ff[k].mask, 0, mask);
+            }
+            memset_(prev_fwd, 0xFF, size_t(np) * 8 * 4);
+        }
+        for (int32_t k = 0; k + 1 < len && e == hipSuccess; ++k) {
+            const int64_t n = c->rec_n0 + int64_t(j) * K + k;
+            const int par = int(n & 1);
+            if (np > 0) {
+                copy_(seg_r(k + 1), seg_r(k), 2 * pbytes);
+                pa.r = seg_r(k + 1);
+                pa.v = seg_v(k + 1);
+                pa.step = uint32_t(n);
+                hipLaunchKernelGGL(k_particle<C>, dim3(pgrid), dim3(kParticleBlock), 0, st, seg(k),
+                                   c->g, R(c->dec_s), pa, ff[par], ff[par ^ 1]);
+                launch_collide<C, true>(c, seg(k), seg(k + 1), ff[par], c->shape);
+            } else {
+                launch_collide<C, false>(c, seg(k), seg(k + 1), ff[0], c->shape);
+            }
+        }
+        for (int32_t k = len - 1; k >= 0 && e == hipSuccess; --k) {
+            const int64_t n = c->rec_n0 + int64_t(j) * K + k;
+            const int par = int(n & 1);
+            if (np > 0) {
+                ap.r = seg_r(k);
+                ap.v = seg_v(k);
+                ap.step = uint32_t(n);
+                hipLaunchKernelGGL(k_adj_particle<C>, dim3(pgrid), dim3(kParticleBlock), 0, st,
+                                   seg(k), c->g, R(c->dec_s), abar[cur], gd, ap, uf[par],
+                                   uf[par ^ 1]);
+                hipLaunchKernelGGL((k_adj_collide<C, true>), dim3(cgrid), dim3(kBlock), 0, st,
+                                   seg(k), c->g, R(c->dec_s), abar[cur], abar[cur ^ 1], gd,
+                                   1.0 / c->desc.tau, uf[par], wacc);
+            } else {
+                hipLaunchKernelGGL((k_adj_collide<C, false>), dim3(cgrid), dim3(kBlock), 0, st,
+                                   seg(k), c->g, R(c->dec_s), abar[cur], abar[cur ^ 1], gd,
+                                   1.0 / c->desc.tau, ff_unused, wacc);
+            }
+            cur ^= 1;
+            const hipError_t le = hipGetLastError();
+            if (le != hipSuccess) e = le;
+        }
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_export, dim3(cgrid), dim3(kBlock), 0, st, abar[cur], adj_pop, gd);
+    hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(kBlock), 0, st, pgrad, np, wacc,
+                       int32_t(cgrid), c->desc.tau, adj_param);
+    return hipGetLastError();
+}
+
+template <class C>
+void adjoint_dispatch(lbm_ctx *c, char *tape, char *work, double *adj_pop, double *adj_r,
+                      double *adj_v, double *adj_param, hipError_t *e) {
+    *e = adjoint_run<C>(c, tape, work, adj_pop, adj_r, adj_v, adj_param);
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_tape_bytes(const lbm_ctx *ctx, int32_t nsteps, int32_t every, size_t *bytes) {
+    if (!ctx || !bytes || nsteps < 1 || every < 1) return LBM_E_INVAL;
+    const TapeLayout t = tape_layout(ctx, ctx->np);
+    *bytes = size_t((nsteps + every - 1) / every) * t.slot;
+    return LBM_OK;
+}
+
+lbm_status lbm_record(lbm_ctx *ctx, int32_t nsteps, int32_t every, void *tape) {
+    if (!ctx || nsteps < 1 || every < 1 || !tape || !aligned(tape)) return LBM_E_INVAL;
+    if (!adjoint_storage(ctx)) return LBM_E_UNSUPPORTED;
+    const TapeLayout t = tape_layout(ctx, ctx->np);
+    ctx->rec_tape = tape;
+    ctx->rec_n0 = ctx->step;
+    ctx->rec_nsteps = nsteps;
+    ctx->rec_every = every;
+    ctx->rec_np = ctx->np;
+    ctx->rec_pdesc = ctx->pdesc;
+    ctx->rec_R = ctx->R;
+    const size_t pbytes = size_t(ctx->np) * 3 * 8;
+    char *tp = static_cast<char *>(tape);
+    for (int32_t s = 0; s < nsteps; ++s) {
+        if (s % every == 0) {
+            char *slot = tp + size_t(s / every) * t.slot;
+            hipError_t e = hipMemcpyAsync(slot, ctx->pop[ctx->cur], t.lat,
+                                          hipMemcpyDeviceToDevice, ctx->stream);
+            if (e == hipSuccess && pbytes)
+                e = hipMemcpyAsync(slot + t.lat, ctx->r, pbytes, hipMemcpyDeviceToDevice,
+                                   ctx->stream);
+            if (e == hipSuccess && pbytes)
+                e = hipMemcpyAsync(slot + t.lat + pbytes, ctx->v, pbytes,
+                                   hipMemcpyDeviceToDevice, ctx->stream);
+            if (e != hipSuccess) {
+                ctx->rec_tape = nullptr;
+                return LBM_E_DEVICE;
+            }
+        }
+        LBM_DISPATCH(ctx, launch_step);
+    }
+    return launch_status();
+}
+
+lbm_status lbm_adjoint_work_bytes(const lbm_ctx *ctx, size_t *bytes) {
+    if (!ctx || !bytes) return LBM_E_INVAL;
+    if (!ctx->rec_tape) return LBM_E_STATE;
+    *bytes = adj_layout(ctx, ctx->rec_np, ctx->rec_every).total;
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint(lbm_ctx *ctx, const void *tape, void *work, double *adj_pop,
+                       double *adj_r, double *adj_v, double *adj_param) {
+    if (!ctx || !tape || !work || !aligned(work) || !adj_pop || !adj_param) return LBM_E_INVAL;
+    if (!adjoint_storage(ctx)) return LBM_E_UNSUPPORTED;
+    if (!ctx->rec_tape || tape != ctx->rec_tape) return LBM_E_STATE;
+    if (ctx->rec_np > 0 && (!adj_r || !adj_v)) return LBM_E_INVAL;
+    hipError_t e = hipSuccess;
+    LBM_DISPATCH(ctx, adjoint_dispatch, static_cast<char *>(const_cast<void *>(tape)),
+                 static_cast<char *>(work), adj_pop, adj_r, adj_v, adj_param, &e);
+    return e == hipSuccess ? LBM_OK : LBM_E_DEVICE;
 }
 
 }  // extern "C"

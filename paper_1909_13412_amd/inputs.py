@@ -46,6 +46,11 @@ WORKLOADS = {
 ENSEMBLE64 = dict(replicas=64, sizes=(48, 64, 80, 96), tau=0.8, n=8, mass=10.0, gamma=1.0,
                   kT=1e-4, seed=4000, steps=5000, max_lag=1000, stride=10, storage="f32")
 
+# Reverse-mode workload: 64^3, tau 0.8, FP32, 16 particles, gradients over
+# 2000 steps with a checkpoint every 100.
+ADJOINT64 = dict(L=64, tau=0.8, storage="f32", n=16, mass=10.0, gamma=1.0, kT=1e-4, steps=2000,
+                 every=100, seed=2024)
+
 
 def ensemble_replicas(replicas: int = 64, sizes=(48, 64, 80, 96), n: int = 8, tau: float = 0.8,
                       kT: float = 1e-4, mass: float = 10.0, seed: int = 4000):

@@ -34,6 +34,13 @@ def _alloc_bytes(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
+class Tape:
+    """Checkpoints of a recorded run (device buffer owned here)."""
+
+    def __init__(self, buf: torch.Tensor, nsteps: int, every: int, n: int):
+        self.buf, self.nsteps, self.every, self.n = buf, nsteps, every, n
+
+
 class Lattice:
     """One periodic box of nx*ny*nz nodes with two population lattices.
 
@@ -206,6 +213,48 @@ class Lattice:
         s = ctypes.c_int64()
         _abi.check("lbm_get_step", self.lib.lbm_get_step(self.ctx, ctypes.byref(s)))
         return s.value
+
+    # -- reverse mode -----------------------------------------------------
+    def record(self, nsteps: int, every: int = 100) -> "Tape":
+        """Take nsteps steps (exactly as step()) keeping a checkpoint every
+        `every` steps, for a later adjoint()."""
+        sz = ctypes.c_size_t()
+        _abi.check("lbm_tape_bytes", self.lib.lbm_tape_bytes(self.ctx, int(nsteps), int(every),
+                                                             ctypes.byref(sz)))
+        tape = Tape(_alloc_bytes(sz.value, self.device), int(nsteps), int(every), self.n)
+        _abi.check("lbm_record", self.lib.lbm_record(self.ctx, int(nsteps), int(every),
+                                                     _ptr(tape.buf)))
+        self._tape = tape
+        return tape
+
+    def adjoint(self, tape: "Tape", adj_pop=None, adj_r=None, adj_v=None) -> dict:
+        """Gradient of J = <adj_pop, f^N> + <adj_r, r^N> + <adj_v, V^N> of the
+        recorded run with respect to its initial populations ("pop", canonical
+        [19, nz, ny, nx]), particle positions and velocities ("r", "v", [n, 3])
+        and the parameters ("params": gamma, tau, M, kT).  Missing cotangents
+        are zero."""
+        if tape is not getattr(self, "_tape", None):
+            raise ValueError("adjoint() needs the tape of this lattice's last record()")
+        pop = torch.zeros((Q,) + self.shape, dtype=torch.float64, device=self.device)
+        if adj_pop is not None:
+            pop.copy_(_device_f64(adj_pop, self.device).reshape(pop.shape))
+        n = tape.n
+        r = torch.zeros((n, 3), dtype=torch.float64, device=self.device)
+        v = torch.zeros((n, 3), dtype=torch.float64, device=self.device)
+        if adj_r is not None:
+            r.copy_(_device_f64(adj_r, self.device).reshape(n, 3))
+        if adj_v is not None:
+            v.copy_(_device_f64(adj_v, self.device).reshape(n, 3))
+        params = torch.zeros(4, dtype=torch.float64, device=self.device)
+        sz = ctypes.c_size_t()
+        _abi.check("lbm_adjoint_work_bytes",
+                   self.lib.lbm_adjoint_work_bytes(self.ctx, ctypes.byref(sz)))
+        work = _alloc_bytes(sz.value, self.device)
+        _abi.check("lbm_adjoint", self.lib.lbm_adjoint(
+            self.ctx, _ptr(tape.buf), _ptr(work), _ptr(pop), _ptr(r if n else None),
+            _ptr(v if n else None), _ptr(params)))
+        self._adj_keep = (pop, r, v, params, work)  # alive until the stream reaches them
+        return {"pop": pop, "r": r, "v": v, "params": params}
 
 
 class Ensemble:
