@@ -66,6 +66,7 @@ def _load():
                                              ctypes.c_double, ctypes.c_double, u64, u32, i32]),
         "ora_get_particles": (None, [vp, dp, dp]),
         "ora_get_particle_forces": (None, [vp, dp, dp]),
+        "ora_set_particle_force": (None, [vp, dp]),
         "ora_radius": (ctypes.c_double, [vp]),
         "ora_vacf_config": (ctypes.c_int, [vp, i32, i32]),
         "ora_vacf_get": (None, [vp, dp, ctypes.POINTER(i64)]),
@@ -206,6 +207,11 @@ class Sim:
         if rc != 0:
             raise ValueError("oracle: invalid particle parameters")
         self.np = r.shape[0]
+
+    def set_particle_force(self, F=None):
+        """Constant force F_C on each particle, [n, 3] (None: none)."""
+        self._fc = None if F is None else _f64(F, (self.np, 3))
+        self._lib.ora_set_particle_force(self._h, _dp(self._fc))
 
     def particles(self):
         r = np.zeros((self.np, 3))

@@ -107,11 +107,12 @@ def corners(r, shape):
     return c, node
 
 
-def particle_update(f8, V, r, theta, xi, c, shape, friction: int, radius: float):
+def particle_update(f8, V, r, theta, xi, c, shape, friction: int, radius: float, fc=None):
     """One particle's step as a function of the populations at its eight
     corner nodes.  Batch axes lead: f8 [B, 8, 19], V, r [B, 3], theta [B, 4],
-    xi [3]; c [3] is the corner cell (fixed).  Returns (V', r', spread [B, 8, 3])
-    where spread is the force the eight nodes receive."""
+    xi [3]; c [3] is the corner cell (fixed); fc [3] a given force F_C on the
+    particle (None: zero).  Returns (V', r', spread [B, 8, 3]) where spread is
+    the force the eight nodes receive."""
     nz, ny, nx = shape
     Lv = np.array([nx, ny, nz], dtype=np.float64)
     gamma, tau, M, kT = (theta[:, k] for k in range(4))
@@ -155,13 +156,15 @@ def particle_update(f8, V, r, theta, xi, c, shape, friction: int, radius: float)
         spread = np.zeros(Wt.shape + (3,), dtype=np.result_type(FH, Wt))
     else:
         spread = -FH[:, None, :] * Wt[..., None]
-    Vn = V + (FH + FR) / M[:, None]
+    Fsum = FH + FR if fc is None else fc[None, :] + FH + FR
+    Vn = V + Fsum / M[:, None]
     rn = r + Vn
     return Vn, rn, spread
 
 
-def step(f, r, V, theta, xi_k, friction: int, radius: float):
-    """One coupled step; returns (f', r', V', F) with F the node-force field."""
+def step(f, r, V, theta, xi_k, friction: int, radius: float, fc=None):
+    """One coupled step; returns (f', r', V', F) with F the node-force field.
+    fc: given force on each particle [n, 3] or None."""
     shape = f.shape[1:]
     ncell = int(np.prod(shape))
     dtype = np.result_type(f, r, V, theta)
@@ -175,7 +178,7 @@ def step(f, r, V, theta, xi_k, friction: int, radius: float):
         for i in range(n):
             f8 = fl[:, node[i]].T[None]                   # [1, 8, 19]
             v1, r1, sp = particle_update(f8, V[i][None], r[i][None], theta[None], xi_k[i], c[i],
-                                         shape, friction, radius)
+                                         shape, friction, radius, None if fc is None else fc[i])
             Vn[i], rn[i] = v1[0], r1[0]
             for p in range(8):
                 F[:, node[i, p]] += sp[0, p]
@@ -184,7 +187,7 @@ def step(f, r, V, theta, xi_k, friction: int, radius: float):
     return stream(fs), rn, Vn, Fg
 
 
-def run(f0, r0, V0, theta, xi, friction="stokeslet", radius=0.0, keep=False):
+def run(f0, r0, V0, theta, xi, friction="stokeslet", radius=0.0, keep=False, fc=None):
     """N = len(xi) steps from (f0, r0, V0) with parameters theta (gamma, tau,
     M, kT).  Returns (f, r, V) at the end, plus the per-step states (f^n, r^n,
     V^n, F^n) when keep."""
@@ -193,26 +196,26 @@ def run(f0, r0, V0, theta, xi, friction="stokeslet", radius=0.0, keep=False):
     theta = np.asarray(theta)
     traj = []
     for k in range(len(xi)):
-        fn, rn, Vn, F = step(f, r, V, theta, xi[k], friction, radius)
+        fn, rn, Vn, F = step(f, r, V, theta, xi[k], friction, radius, fc)
         if keep:
             traj.append((f, r, V, F))
         f, r, V = fn, rn, Vn
     return (f, r, V, traj) if keep else (f, r, V)
 
 
-def jvp(f0, r0, V0, theta, xi, df, dr, dV, dtheta, friction="stokeslet", radius=0.0):
+def jvp(f0, r0, V0, theta, xi, df, dr, dV, dtheta, friction="stokeslet", radius=0.0, fc=None):
     """Directional derivative of S_N along (df, dr, dV, dtheta), complex step."""
     f, r, V = run(f0 + 1j * H * df, r0 + 1j * H * dr, V0 + 1j * H * dV,
-                  np.asarray(theta) + 1j * H * np.asarray(dtheta), xi, friction, radius)
+                  np.asarray(theta) + 1j * H * np.asarray(dtheta), xi, friction, radius, fc=fc)
     return np.imag(f) / H, np.imag(r) / H, np.imag(V) / H
 
 
-def vjp(f0, r0, V0, theta, xi, cf, cr, cV, friction="stokeslet", radius=0.0):
+def vjp(f0, r0, V0, theta, xi, cf, cr, cV, friction="stokeslet", radius=0.0, fc=None):
     """Gradient of J = <cf, f^N> + <cr, r^N> + <cV, V^N> with respect to f0, r0,
     V0 and theta, by a reverse sweep with complex-step local Jacobians."""
     fr_mode = FRICTION[friction] if isinstance(friction, str) else int(friction)
     theta = np.asarray(theta, dtype=np.float64)
-    _, _, _, traj = run(f0, r0, V0, theta, xi, fr_mode, radius, keep=True)
+    _, _, _, traj = run(f0, r0, V0, theta, xi, fr_mode, radius, keep=True, fc=fc)
     shape = f0.shape[1:]
     ncell = int(np.prod(shape))
     gf = np.array(cf, dtype=np.float64)
@@ -257,7 +260,7 @@ def vjp(f0, r0, V0, theta, xi, cf, cr, cV, friction="stokeslet", radius=0.0):
                 X = np.tile(base, (nin, 1)) + 1j * H * np.eye(nin)
                 v1, r1, sp = particle_update(X[:, :152].reshape(nin, 8, 19), X[:, 152:155],
                                              X[:, 155:158], X[:, 158:162], xi[k][i], c[i], shape,
-                                             fr_mode, radius)
+                                             fr_mode, radius, None if fc is None else fc[i])
                 jv, jr, jsp = np.imag(v1) / H, np.imag(r1) / H, np.imag(sp) / H
                 ybar_sp = gFl[:, node[i]].T                # [8, 3] gradient of each node force
                 xbar = jv @ gV[i] + jr @ gr[i] + np.einsum("bpk,pk->b", jsp, ybar_sp)

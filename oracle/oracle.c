@@ -58,6 +58,7 @@ struct ora_sim {
     uint32_t replica;
     int32_t friction;
     double *r, *v, *fh, *fr; /* [np][3] */
+    double *fc;              /* optional force F_C on each particle, [np][3] */
     int64_t step;
     /* velocity autocorrelation */
     int32_t vacf_on, max_lag, stride, nslot;
@@ -243,7 +244,7 @@ void ora_destroy(ora_sim *o)
 {
     if (!o) return;
     free(o->f); free(o->fnew); free(o->rho); free(o->u); free(o->F); free(o->body);
-    free(o->r); free(o->v); free(o->fh); free(o->fr);
+    free(o->r); free(o->v); free(o->fh); free(o->fr); free(o->fc);
     free(o->orig); free(o->orig_t); free(o->acc); free(o->cnt);
     free(o);
 }
@@ -313,8 +314,8 @@ int ora_set_particles(ora_sim *o, int32_t n, const double *r, const double *v,
                       uint64_t seed, uint32_t replica, int32_t friction)
 {
     if (n < 0 || !(mass > 0.0) || !(gamma >= 0.0) || !(kT >= 0.0)) return -1;
-    free(o->r); free(o->v); free(o->fh); free(o->fr);
-    o->r = o->v = o->fh = o->fr = NULL;
+    free(o->r); free(o->v); free(o->fh); free(o->fr); free(o->fc);
+    o->r = o->v = o->fh = o->fr = o->fc = NULL;
     o->np = n;
     o->mass = mass; o->gamma = gamma; o->kT = kT;
     /* Stokes' law gamma = 6 pi eta R with eta = rho0 nu and nu = (tau - 1/2)/3
@@ -331,6 +332,15 @@ int ora_set_particles(ora_sim *o, int32_t n, const double *r, const double *v,
         memcpy(o->v, v, sizeof(double) * 3 * (size_t)n);
     }
     return 0;
+}
+
+void ora_set_particle_force(ora_sim *o, const double *F)
+{
+    free(o->fc);
+    o->fc = NULL;
+    if (!F || o->np == 0) return;
+    o->fc = (double *)malloc(sizeof(double) * 3 * (size_t)o->np);
+    memcpy(o->fc, F, sizeof(double) * 3 * (size_t)o->np);
 }
 
 void ora_get_particles(const ora_sim *o, double *r, double *v)
@@ -487,13 +497,14 @@ static void collide_stream(ora_sim *o)
 }
 
 /* Langevin update (Eqs. s2-langevin, s2-langevin2) with the lattice time step:
- * V^{n+1} = V^n + (F_C + F_H + F_R)/M, r^{n+1} = r^n + V^{n+1}.  No
- * inter-particle force is used (F_C = 0). */
+ * V^{n+1} = V^n + (F_C + F_H + F_R)/M, r^{n+1} = r^n + V^{n+1}.  F_C is a
+ * given force per particle (zero unless set); no inter-particle force. */
 static void advance_particles(ora_sim *o)
 {
     for (int i = 0; i < o->np; ++i)
         for (int k = 0; k < 3; ++k) {
-            o->v[3 * i + k] += (o->fh[3 * i + k] + o->fr[3 * i + k]) / o->mass;
+            double fc = o->fc ? o->fc[3 * i + k] : 0.0;
+            o->v[3 * i + k] += (fc + o->fh[3 * i + k] + o->fr[3 * i + k]) / o->mass;
             o->r[3 * i + k] += o->v[3 * i + k];
         }
 }

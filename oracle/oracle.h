@@ -68,6 +68,9 @@ int ora_set_particles(ora_sim *o, int32_t n, const double *r, const double *v,
 void ora_get_particles(const ora_sim *o, double *r, double *v);
 /* F_H and F_R used in the most recent step, [n][3] each. */
 void ora_get_particle_forces(const ora_sim *o, double *fh, double *fr);
+/* Constant force F_C of Eq. s2-langevin on each particle, [n][3] (NULL: none);
+ * cleared by ora_set_particles. */
+void ora_set_particle_force(ora_sim *o, const double *F);
 double ora_radius(const ora_sim *o);
 
 /* Velocity autocorrelation: origins every `stride` steps, lags 0..max_lag. */

@@ -31,26 +31,31 @@ def _setup(L=8, n=3, seed=1, tau=0.8, amp=0.02):
     return rng, f0, r0, v0
 
 
-def _oracle_run(f0, r0, v0, theta, nsteps, friction, radius=0.0, seed=5):
+def _oracle_run(f0, r0, v0, theta, nsteps, friction, radius=0.0, seed=5, fc=None):
     gamma, tau, M, kT = theta
     L = f0.shape[1]
     o = oracle.Sim(L, L, L, tau)
     o.set_populations(f0)
     o.set_particles(r0, v0, mass=M, gamma=gamma, kT=kT, radius=radius, seed=seed,
                     friction=friction)
+    if fc is not None:
+        o.set_particle_force(fc)
     o.step(nsteps)
     r, v = o.particles()
     return o.populations(), r, v
 
 
-@pytest.mark.parametrize("friction,kT,radius", [("stokeslet", 1e-4, 0.0), ("stokeslet", 0.0, 0.4),
-                                                ("pointwise", 1e-4, 0.0), ("bd", 1e-4, 0.0)])
-def test_forward_matches_c_oracle(friction, kT, radius):
+@pytest.mark.parametrize("friction,kT,radius,force", [("stokeslet", 1e-4, 0.0, False),
+                                                      ("stokeslet", 0.0, 0.4, True),
+                                                      ("pointwise", 1e-4, 0.0, False),
+                                                      ("bd", 1e-4, 0.0, True)])
+def test_forward_matches_c_oracle(friction, kT, radius, force):
     _, f0, r0, v0 = _setup()
     theta = np.array([1.0, 0.8, 10.0, kT])
     N = 8
-    fr, rr, vr = _oracle_run(f0, r0, v0, theta, N, friction, radius)
-    f, r, v = A.run(f0, r0, v0, theta, A.noise(3, N, 5), friction, radius)
+    fc = np.array([[1e-3, 0.0, -5e-4], [0.0, 2e-3, 0.0], [1e-4, 1e-4, 1e-4]]) if force else None
+    fr, rr, vr = _oracle_run(f0, r0, v0, theta, N, friction, radius, fc=fc)
+    f, r, v = A.run(f0, r0, v0, theta, A.noise(3, N, 5), friction, radius, fc=fc)
     assert np.max(np.abs(f - fr)) < 1e-14
     assert np.max(np.abs(r - rr)) < 1e-13
     assert np.max(np.abs(v - vr)) < 1e-15
@@ -85,9 +90,11 @@ def test_complex_step_matches_finite_differences_of_c_oracle(friction):
     assert abs(dj2 - dj) > 1e-4 * abs(dj)
 
 
-@pytest.mark.parametrize("friction,kT,radius", [("stokeslet", 1e-4, 0.0), ("stokeslet", 0.0, 0.4),
-                                                ("pointwise", 1e-4, 0.0), ("bd", 1e-4, 0.0)])
-def test_reverse_sweep_is_the_transpose_of_the_complex_step(friction, kT, radius):
+@pytest.mark.parametrize("friction,kT,radius,force", [("stokeslet", 1e-4, 0.0, False),
+                                                      ("stokeslet", 0.0, 0.4, True),
+                                                      ("pointwise", 1e-4, 0.0, False),
+                                                      ("bd", 1e-4, 0.0, True)])
+def test_reverse_sweep_is_the_transpose_of_the_complex_step(friction, kT, radius, force):
     rng, f0, r0, v0 = _setup(seed=3)
     theta = np.array([1.0, 0.8, 10.0, kT])
     N = 7
@@ -95,7 +102,8 @@ def test_reverse_sweep_is_the_transpose_of_the_complex_step(friction, kT, radius
     cf = rng.standard_normal(f0.shape)
     cr = rng.standard_normal(r0.shape)
     cv = rng.standard_normal(v0.shape)
-    gf, gr, gv, gth = A.vjp(f0, r0, v0, theta, xi, cf, cr, cv, friction, radius)
+    fc = 1e-3 * rng.standard_normal(r0.shape) if force else None
+    gf, gr, gv, gth = A.vjp(f0, r0, v0, theta, xi, cf, cr, cv, friction, radius, fc=fc)
     for trial in range(2):
         df = rng.standard_normal(f0.shape)
         dr = rng.standard_normal(r0.shape)
@@ -103,7 +111,7 @@ def test_reverse_sweep_is_the_transpose_of_the_complex_step(friction, kT, radius
         dth = rng.standard_normal(4)
         if kT == 0.0:
             dth[3] = 0.0
-        jf, jr, jv = A.jvp(f0, r0, v0, theta, xi, df, dr, dv, dth, friction, radius)
+        jf, jr, jv = A.jvp(f0, r0, v0, theta, xi, df, dr, dv, dth, friction, radius, fc=fc)
         lhs = (gf * df).sum() + (gr * dr).sum() + (gv * dv).sum() + (gth * dth).sum()
         rhs = (cf * jf).sum() + (cr * jr).sum() + (cv * jv).sum()
         assert abs(lhs - rhs) < 1e-11 * (abs(rhs) + 1.0)

@@ -154,6 +154,21 @@ def test_mass_and_momentum_conserved_without_forcing(oracle_mod):
     assert np.max(np.abs(o1[1:4] - o0[1:4])) < 1e-13
 
 
+def test_uniform_body_force_adds_momentum_exactly(oracle_mod):
+    # The forcing term 3 w_a e_a.G carries momentum G and no mass (sum w e = 0,
+    # sum w e e = I/3): a uniform G on a uniform fluid keeps it uniform, with
+    # u^n = n G at every node and total momentum n G per node.
+    s = oracle_mod.Sim(6, 5, 4, 0.9)
+    G = np.array([1e-5, -2e-5, 3e-6])
+    s.set_body_force(np.broadcast_to(G.reshape(3, 1, 1, 1), (3, 4, 5, 6)).copy())
+    s.step(37)
+    rho, u = s.moments()
+    assert np.max(np.abs(rho - 1.0)) < 1e-13  # rounding of unshifted FP64 populations
+    assert np.max(np.abs(u - 37 * G.reshape(3, 1, 1, 1))) < 1e-13
+    o = s.observables()
+    assert np.allclose(o[1:4], 37 * G * 120, rtol=1e-10, atol=0)
+
+
 def test_regularised_stokeslet_far_field(oracle_mod):
     # Steady Stokes flow (Eq. s2-ns without inertia) driven by a smooth point-like
     # force F (Gaussian of width 2 with a uniform counter-force, so the periodic

@@ -236,6 +236,24 @@ def test_brownian_dynamics_closed_form(oracle_mod):
     assert np.max(np.abs(s.observables()[1:4])) == 0.0
 
 
+def test_given_particle_force_terminal_velocity(oracle_mod):
+    # Eq. s2-langevin with F_C and Eq. s2-dis0, no noise: V^{n+1} = a V^n + F_C/M
+    # with a = 1 - gamma/M, so V^n = a^n V^0 + (1 - a^n) F_C / gamma.
+    s = oracle_mod.Sim(4, 4, 4, 0.8)
+    v0 = np.array([[0.01, -0.02, 0.005], [0.0, 0.0, 0.0]])
+    s.set_particles(np.array([[1.2, 2.3, 3.4], [0.5, 0.5, 0.5]]), v0, mass=10.0, gamma=2.0,
+                    friction="bd")
+    F = np.array([[1e-3, 0.0, -2e-3], [0.0, 5e-4, 0.0]])
+    s.set_particle_force(F)
+    s.step(40)
+    a = 1.0 - 2.0 / 10.0
+    _, v = s.particles()
+    assert np.allclose(v, a**40 * v0 + (1 - a**40) * F / 2.0, rtol=1e-13, atol=1e-18)
+    s.set_particle_force(None)
+    s.step(1)
+    assert np.allclose(s.particles()[1], a * v, rtol=1e-14)
+
+
 @pytest.mark.slow
 def test_brownian_dynamics_stationary_statistics(oracle_mod):
     # Discrete Langevin update with noise variance 2 gamma kT per step:
