@@ -128,6 +128,13 @@ lbm_status lbm_set_equilibrium(lbm_ctx *ctx, const double *rho, const double *u)
 /* Load the post-streaming populations f^n from device FP64 [19][nz][ny][nx]. */
 lbm_status lbm_set_populations(lbm_ctx *ctx, const double *f);
 
+/* Uniform body force G (host array of 3 doubles, force per node in lattice
+ * units; NULL = zero) acting on every node from the next step on: it enters
+ * the collision through the same forcing term 3 w_a e_a.F as the particles'
+ * reaction forces (second Eq. s2-force), F = G + reaction force.  The total
+ * fluid momentum grows by G per node per step. */
+lbm_status lbm_set_body_force(lbm_ctx *ctx, const double *g);
+
 /* Decode the post-streaming populations f^n into device FP64 [19][nz][ny][nx]. */
 lbm_status lbm_get_populations(lbm_ctx *ctx, double *f);
 
@@ -141,6 +148,14 @@ lbm_status lbm_get_moments(lbm_ctx *ctx, double *rho, double *u);
  * state and detaches any VACF configuration.  n = 0 detaches all particles. */
 lbm_status particles_couple(lbm_ctx *ctx, const lbm_particle_desc *desc, double *r, double *v,
                             void *particle_scratch);
+
+/* A given force F_C on each particle (Eq. s2-langevin), e.g. an applied
+ * pulling force: device FP64 [n][3], caller-owned, read every step from the
+ * next step on (keep it alive and unchanged while it is attached, and until
+ * lbm_adjoint of a run recorded with it); NULL detaches it.  The fluid feels it
+ * only through the friction.  LBM_E_STATE without particles; particles_couple
+ * detaches it. */
+lbm_status lbm_set_particle_force(lbm_ctx *ctx, const double *f);
 
 /* The radius the coupling uses (given or derived), or a negative value when no
  * particles are attached. */

@@ -162,13 +162,16 @@ def particle_update(f8, V, r, theta, xi, c, shape, friction: int, radius: float,
     return Vn, rn, spread
 
 
-def step(f, r, V, theta, xi_k, friction: int, radius: float, fc=None):
+def step(f, r, V, theta, xi_k, friction: int, radius: float, fc=None, body=None):
     """One coupled step; returns (f', r', V', F) with F the node-force field.
-    fc: given force on each particle [n, 3] or None."""
+    fc: given force on each particle [n, 3] or None; body: uniform body force
+    [3] on every node or None."""
     shape = f.shape[1:]
     ncell = int(np.prod(shape))
     dtype = np.result_type(f, r, V, theta)
     F = np.zeros((3, ncell), dtype=dtype)
+    if body is not None:
+        F += np.asarray(body, dtype=np.float64).reshape(3, 1)
     n = r.shape[0]
     Vn = np.empty_like(V, dtype=dtype)
     rn = np.empty_like(r, dtype=dtype)
@@ -187,7 +190,7 @@ def step(f, r, V, theta, xi_k, friction: int, radius: float, fc=None):
     return stream(fs), rn, Vn, Fg
 
 
-def run(f0, r0, V0, theta, xi, friction="stokeslet", radius=0.0, keep=False, fc=None):
+def run(f0, r0, V0, theta, xi, friction="stokeslet", radius=0.0, keep=False, fc=None, body=None):
     """N = len(xi) steps from (f0, r0, V0) with parameters theta (gamma, tau,
     M, kT).  Returns (f, r, V) at the end, plus the per-step states (f^n, r^n,
     V^n, F^n) when keep."""
@@ -196,26 +199,28 @@ def run(f0, r0, V0, theta, xi, friction="stokeslet", radius=0.0, keep=False, fc=
     theta = np.asarray(theta)
     traj = []
     for k in range(len(xi)):
-        fn, rn, Vn, F = step(f, r, V, theta, xi[k], friction, radius, fc)
+        fn, rn, Vn, F = step(f, r, V, theta, xi[k], friction, radius, fc, body)
         if keep:
             traj.append((f, r, V, F))
         f, r, V = fn, rn, Vn
     return (f, r, V, traj) if keep else (f, r, V)
 
 
-def jvp(f0, r0, V0, theta, xi, df, dr, dV, dtheta, friction="stokeslet", radius=0.0, fc=None):
+def jvp(f0, r0, V0, theta, xi, df, dr, dV, dtheta, friction="stokeslet", radius=0.0, fc=None,
+        body=None):
     """Directional derivative of S_N along (df, dr, dV, dtheta), complex step."""
     f, r, V = run(f0 + 1j * H * df, r0 + 1j * H * dr, V0 + 1j * H * dV,
-                  np.asarray(theta) + 1j * H * np.asarray(dtheta), xi, friction, radius, fc=fc)
+                  np.asarray(theta) + 1j * H * np.asarray(dtheta), xi, friction, radius, fc=fc,
+                  body=body)
     return np.imag(f) / H, np.imag(r) / H, np.imag(V) / H
 
 
-def vjp(f0, r0, V0, theta, xi, cf, cr, cV, friction="stokeslet", radius=0.0, fc=None):
+def vjp(f0, r0, V0, theta, xi, cf, cr, cV, friction="stokeslet", radius=0.0, fc=None, body=None):
     """Gradient of J = <cf, f^N> + <cr, r^N> + <cV, V^N> with respect to f0, r0,
     V0 and theta, by a reverse sweep with complex-step local Jacobians."""
     fr_mode = FRICTION[friction] if isinstance(friction, str) else int(friction)
     theta = np.asarray(theta, dtype=np.float64)
-    _, _, _, traj = run(f0, r0, V0, theta, xi, fr_mode, radius, keep=True, fc=fc)
+    _, _, _, traj = run(f0, r0, V0, theta, xi, fr_mode, radius, keep=True, fc=fc, body=body)
     shape = f0.shape[1:]
     ncell = int(np.prod(shape))
     gf = np.array(cf, dtype=np.float64)

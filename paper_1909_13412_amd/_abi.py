@@ -17,7 +17,7 @@ FRICTION = {"stokeslet": 0, "pointwise": 1, "bd": 2}
 EXPORTS = [
     "lbm_lattice_bytes", "lbm_grid_scratch_bytes", "lbm_particle_scratch_bytes",
     "lbm_vacf_origin_bytes", "lbm_init", "lbm_set_equilibrium", "lbm_set_populations",
-    "lbm_get_populations", "lbm_get_moments", "particles_couple", "lbm_particle_radius",
+    "lbm_set_body_force", "lbm_get_populations", "lbm_get_moments", "particles_couple", "lbm_set_particle_force", "lbm_particle_radius",
     "lbm_particle_forces", "lbm_vacf_config", "lbm_vacf_counts", "lbm_step", "lbm_series_config",
     "lbm_series_count", "lbm_observables",
     "lbm_profile_enable", "lbm_profile_read", "lbm_autotune", "lbm_get_step", "lbm_destroy",
@@ -84,10 +84,12 @@ def load() -> ctypes.CDLL:
         "lbm_init": [gd, vp, vp, vp, vp, ctypes.POINTER(vp)],
         "lbm_set_equilibrium": [vp, dp, dp],
         "lbm_set_populations": [vp, dp],
+        "lbm_set_body_force": [vp, ctypes.POINTER(ctypes.c_double)],
         "lbm_get_populations": [vp, dp],
         "lbm_get_moments": [vp, dp, dp],
         "particles_couple": [vp, pd, dp, dp, vp],
         "lbm_particle_forces": [vp, dp, dp],
+        "lbm_set_particle_force": [vp, dp],
         "lbm_vacf_config": [vp, i32, i32, dp, dp],
         "lbm_vacf_counts": [vp, ctypes.POINTER(i64)],
         "lbm_step": [vp, i32],

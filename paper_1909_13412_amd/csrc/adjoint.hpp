@@ -4,8 +4,9 @@
 // s2-slet-v / s2-dis1 / s2-dis0, s2-rf1, s2-rf2, first and second Eq.
 // s2-force, s2-collision, s2-eq, s2-coll, s2-trans, s2-langevin,
 // s2-langevin2).  Derivatives are those of the exact-arithmetic map taken at
-// the stored forward trajectory; the corner cell floor(s) and the fit's branch
-// tests are piecewise constant.  Adjoint arithmetic is FP64 throughout.
+// the stored forward trajectory; a given particle force F_C is a constant, and
+// the corner cell floor(s) and the fit's branch tests are piecewise constant.
+// Adjoint arithmetic is FP64 throughout.
 //
 // Adjoint populations fb^n_a(x) = dJ/df^n_a(x) (post-streaming populations at
 // node x) live in an FP64 lattice of the interleaved-row layout, at their own
@@ -50,6 +51,7 @@ struct AdjParticleArgs {
     const double *r, *v;   // state at step n, [n][3]
     double *rbar, *vbar;   // in: dJ/dr^{n+1}, dJ/dV^{n+1}; out: dJ/dr^n, dJ/dV^n
     double *pgrad;         // [n][4] running dJ/d(gamma, tau, M, kT)
+    const double *fext;    // given force F_C on each particle, [n][3] (nullptr: none)
     uint32_t *prev_cell;   // [n][8] node each lane wrote one reverse step ago
     int32_t n;
     int32_t friction;
@@ -147,7 +149,7 @@ __global__ __launch_bounds__(kParticleBlock) void k_adj_particle(
     FitTrace tr;
     friction_lanes(pa.friction, pa.gamma, pa.R, W, u, V, d, FH, tr);
 
-    // Langevin update: V' = V + (F_H + F_R)/M, r' = r + V'.
+    // Langevin update: V' = V + (F_C + F_H + F_R)/M, r' = r + V'.
     double Vt[3], FHb[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -270,7 +272,8 @@ __global__ __launch_bounds__(kParticleBlock) void k_adj_particle(
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         FRb_xi += (Vt[k] / pa.mass) * xi[k];
-        dM -= Vt[k] * (FH[k] + pa.sig * xi[k]) / (pa.mass * pa.mass);
+        const double fc = pa.fext ? pa.fext[3 * i + k] : 0.0;
+        dM -= Vt[k] * (fc + FH[k] + pa.sig * xi[k]) / (pa.mass * pa.mass);
     }
     double *pg = pa.pgrad + 4 * int64_t(i);
     pg[0] += gam_b + R_b * pa.dR_dgamma + (pa.sig > 0.0 ? FRb_xi * pa.kT / pa.sig : 0.0);

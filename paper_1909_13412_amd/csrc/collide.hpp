@@ -116,11 +116,14 @@ __device__ inline void block_sum(double (&v)[N], double *__restrict__ out) {
 // The nodes of one lane: lane_cell < ncell / CPT indexes the first band of
 // ny/CPT rows; the lane also takes the same (x, z) in the CPT - 1 bands below.
 // With MOMENTS the FP64 sums of (rho~ - 1, u) over these nodes are added to acc.
+// The force at a node is the uniform body force G plus, where the node is
+// flagged (FORCED), the particles' reaction force.
 template <class C, bool FORCED, bool MOMENTS, int CPT>
 __device__ inline void collide_lane(const typename C::T *__restrict__ A,
                                     typename C::T *__restrict__ B, const Grid &g,
                                     typename C::R omega, typename C::R enc_s, typename C::R dec_s,
-                                    const ForceField &ff, uint32_t lane_cell, double (&acc)[4]) {
+                                    const ForceField &ff, typename C::R Gx, typename C::R Gy,
+                                    typename C::R Gz, uint32_t lane_cell, double (&acc)[4]) {
     using T = typename C::T;
     using R = typename C::R;
     const uint32_t x = lane_cell % g.nx;
@@ -167,13 +170,13 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
             acc[2] += double(uy);
             acc[3] += double(uz);
         }
-        R Fx = R(0), Fy = R(0), Fz = R(0);
+        R Fx = Gx, Fy = Gy, Fz = Gz;
         if constexpr (FORCED) {
             if (flags[c]) {
                 const uint64_t cell = (z * g.ny + y) * g.nx + x;
-                Fx = R(double(ff.f[3 * cell + 0]) * kFixInv);
-                Fy = R(double(ff.f[3 * cell + 1]) * kFixInv);
-                Fz = R(double(ff.f[3 * cell + 2]) * kFixInv);
+                Fx += R(double(ff.f[3 * cell + 0]) * kFixInv);
+                Fy += R(double(ff.f[3 * cell + 1]) * kFixInv);
+                Fz += R(double(ff.f[3 * cell + 2]) * kFixInv);
             }
         }
         const uint64_t row_base = uint64_t(z * g.ny + y) * D3Q19::Q * g.chunk + x;
@@ -184,7 +187,11 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
             const R eu = R(cx) * ux + R(cy) * uy + R(cz) * uz;
             const R geq = w * (drho + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
             R gn = gv[a] + omega * (geq - gv[a]);
-            if constexpr (FORCED) gn += R(3) * w * (R(cx) * Fx + R(cy) * Fy + R(cz) * Fz);
+            R eF = R(0);
+            if constexpr (cx != 0) eF += cx > 0 ? Fx : -Fx;
+            if constexpr (cy != 0) eF += cy > 0 ? Fy : -Fy;
+            if constexpr (cz != 0) eF += cz > 0 ? Fz : -Fz;
+            if constexpr (a != 0) gn += R(3) * w * eF;
             B[row_base + uint64_t(a) * g.chunk] = C::enc(gn, enc_s);
         });
     }
@@ -195,14 +202,17 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
                                                        typename C::T *__restrict__ B, Grid g,
                                                        typename C::R omega, typename C::R enc_s,
                                                        typename C::R dec_s, ForceField ff,
-                                                       double *__restrict__ mom) {
+                                                       typename C::R Gx, typename C::R Gy,
+                                                       typename C::R Gz, double *__restrict__ mom) {
     const uint32_t lane_cell = blockIdx.x * BS + threadIdx.x;  // node index in the first row band
     const bool active = lane_cell < g.ncell / CPT;
     if constexpr (!MOMENTS) {
         if (!active) return;
     }
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (active) collide_lane<C, FORCED, MOMENTS, CPT>(A, B, g, omega, enc_s, dec_s, ff, lane_cell, acc);
+    if (active)
+        collide_lane<C, FORCED, MOMENTS, CPT>(A, B, g, omega, enc_s, dec_s, ff, Gx, Gy, Gz,
+                                              lane_cell, acc);
     if constexpr (MOMENTS) block_sum<4, BS>(acc, mom + 4 * uint64_t(blockIdx.x));
 }
 

@@ -84,8 +84,9 @@ __global__ __launch_bounds__(BS) void k_ens_collide(const typename C::T *__restr
     if (lane_cell >= rp.g.ncell / CPT) return;
     const ForceField ff{force + 3 * rp.cell_off, mask + rp.mask_off};
     double acc[4];
-    collide_lane<C, true, false, CPT>(A + rp.pop_off, B + rp.pop_off, rp.g,
-                                      typename C::R(rp.omega), enc_s, dec_s, ff, lane_cell, acc);
+    using R = typename C::R;
+    collide_lane<C, true, false, CPT>(A + rp.pop_off, B + rp.pop_off, rp.g, R(rp.omega), enc_s,
+                                      dec_s, ff, R(0), R(0), R(0), lane_cell, acc);
 }
 
 template <class C>
@@ -317,6 +318,7 @@ struct lbm_ctx {
     hipStream_t stream;
     double omega;
     double enc_s, dec_s;
+    double body[3];  // uniform body force on every node (lbm_set_body_force)
     // grid scratch
     uint32_t *mask[2];
     long long *force[2];  // [ncell][3] fixed-point node forces, alternating steps
@@ -331,6 +333,7 @@ struct lbm_ctx {
     double *r, *v;
     uint32_t *prev_cell;
     double *fh, *fr;
+    const double *fext;  // given force on each particle (lbm_set_particle_force) or null
     // velocity autocorrelation
     int vacf_on;
     int32_t max_lag, stride, nslot;
@@ -356,6 +359,7 @@ struct lbm_ctx {
     int32_t rec_nsteps, rec_every, rec_np;
     lbm_particle_desc rec_pdesc;
     double rec_R;
+    const double *rec_fext;
 };
 
 namespace {
@@ -449,7 +453,8 @@ void launch_collide_shape(lbm_ctx *c, const typename C::T *A, typename C::T *B, 
                           double *mom, unsigned grid) {
     using R = typename C::R;
     hipLaunchKernelGGL((k_stream_collide<C, FORCED, MOMENTS, CPT, BS>), dim3(grid), dim3(BS), 0,
-                       c->stream, A, B, c->g, R(c->omega), R(c->enc_s), R(c->dec_s), ff, mom);
+                       c->stream, A, B, c->g, R(c->omega), R(c->enc_s), R(c->dec_s), ff,
+                       R(c->body[0]), R(c->body[1]), R(c->body[2]), mom);
 }
 
 // mom != nullptr: also leave the per-block FP64 moment sums there.
@@ -554,6 +559,7 @@ void launch_step(lbm_ctx *c) {
         pa.seed = c->pdesc.seed;
         pa.replica = c->pdesc.replica;
         pa.step = uint32_t(c->step);
+        pa.fext = c->fext;
         hipLaunchKernelGGL(k_particle<C>, dim3(unsigned((uint64_t(c->np) * 8 + kParticleBlock - 1) / kParticleBlock)), dim3(kParticleBlock), 0,
                            c->stream, A, c->g, R(c->dec_s), pa, field(c, par), field(c, par ^ 1));
         prof_stop(c, pk);
@@ -761,6 +767,19 @@ lbm_status lbm_set_populations(lbm_ctx *ctx, const double *f) {
     return launch_status();
 }
 
+lbm_status lbm_set_body_force(lbm_ctx *ctx, const double *g) {
+    if (!ctx) return LBM_E_INVAL;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (g) {
+        for (int k = 0; k < 3; ++k) {
+            if (!isfinite(g[k])) return LBM_E_INVAL;
+            v[k] = g[k];
+        }
+    }
+    for (int k = 0; k < 3; ++k) ctx->body[k] = v[k];
+    return LBM_OK;
+}
+
 lbm_status lbm_get_populations(lbm_ctx *ctx, double *f) {
     if (!ctx || !f) return LBM_E_INVAL;
     LBM_DISPATCH(ctx, launch_get_populations, f);
@@ -796,6 +815,7 @@ lbm_status particles_couple(lbm_ctx *ctx, const lbm_particle_desc *d, double *r,
         e = hipMemsetAsync(ctx->force[1], 0, force_field_bytes(&ctx->desc), ctx->stream);
     if (e != hipSuccess) return LBM_E_DEVICE;
     ctx->vacf_on = 0;
+    ctx->fext = nullptr;
     ctx->np = d->n;
     ctx->pdesc = *d;
     if (d->n == 0) {
@@ -820,6 +840,13 @@ lbm_status particles_couple(lbm_ctx *ctx, const lbm_particle_desc *d, double *r,
     if (e == hipSuccess) e = hipMemsetAsync(ctx->fh, 0, size_t(d->n) * 3 * 8, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->fr, 0, size_t(d->n) * 3 * 8, ctx->stream);
     return e == hipSuccess ? LBM_OK : LBM_E_DEVICE;
+}
+
+lbm_status lbm_set_particle_force(lbm_ctx *ctx, const double *f) {
+    if (!ctx) return LBM_E_INVAL;
+    if (f && ctx->np == 0) return LBM_E_STATE;
+    ctx->fext = f;
+    return LBM_OK;
 }
 
 double lbm_particle_radius(const lbm_ctx *ctx) { return (ctx && ctx->np > 0) ? ctx->R : -1.0; }
@@ -1730,6 +1757,7 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
     pa.acc = nullptr;
     pa.origins = nullptr;
     pa.pmom = nullptr;
+    pa.fext = c->rec_fext;
     pa.k_hi = -1;
     pa.nslot = pa.stride = 1;
 
@@ -1737,6 +1765,7 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
     ap.rbar = adj_r;
     ap.vbar = adj_v;
     ap.pgrad = pgrad;
+    ap.fext = c->rec_fext;
     ap.prev_cell = prev_adj;
     ap.n = np;
     ap.friction = pd.friction;
@@ -1844,6 +1873,7 @@ lbm_status lbm_record(lbm_ctx *ctx, int32_t nsteps, int32_t every, void *tape) {
     ctx->rec_np = ctx->np;
     ctx->rec_pdesc = ctx->pdesc;
     ctx->rec_R = ctx->R;
+    ctx->rec_fext = ctx->fext;
     const size_t pbytes = size_t(ctx->np) * 3 * 8;
     char *tp = static_cast<char *>(tape);
     for (int32_t s = 0; s < nsteps; ++s) {

@@ -44,6 +44,8 @@ struct ParticleArgs {
     int32_t nslot, stride, max_lag;
     // per-block FP64 sums of M V^n (nullptr: off), [blocks][3]
     double *pmom;
+    // given force F_C on each particle, [n][3] (nullptr: none)
+    const double *fext;
 };
 
 __device__ inline double sum8(double v) {
@@ -264,10 +266,11 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
     pa.prev_cell[8 * i + p] = my_cell;
 
     if (p != 0) return;
-    // Eqs. s2-langevin, s2-langevin2 with dt = 1 (F_C = 0).
+    // Eqs. s2-langevin, s2-langevin2 with dt = 1; F_C is the given force (or 0).
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double vn = V[k] + (FH[k] + FR[k]) / pa.mass;
+        const double fc = pa.fext ? pa.fext[3 * i + k] : 0.0;
+        const double vn = V[k] + (fc + FH[k] + FR[k]) / pa.mass;
         pa.v[3 * i + k] = vn;
         pa.r[3 * i + k] = r[k] + vn;
         pa.fh[3 * i + k] = FH[k];

@@ -101,6 +101,11 @@ class Lattice:
         self._f_in = _device_f64(f, self.device, (Q * self.ncell,))
         _abi.check("lbm_set_populations", self.lib.lbm_set_populations(self.ctx, _ptr(self._f_in)))
 
+    def set_body_force(self, g=None):
+        """Uniform body force (gx, gy, gz) on every node from the next step on."""
+        arr = None if g is None else (ctypes.c_double * 3)(*[float(x) for x in g])
+        _abi.check("lbm_set_body_force", self.lib.lbm_set_body_force(self.ctx, arr))
+
     def populations(self) -> torch.Tensor:
         out = torch.empty((Q,) + self.shape, dtype=torch.float64, device=self.device)
         _abi.check("lbm_get_populations", self.lib.lbm_get_populations(self.ctx, _ptr(out)))
@@ -132,6 +137,11 @@ class Lattice:
         self._vacf = None
         self.fh = torch.zeros((n, 3), dtype=torch.float64, device=self.device)
         self.fr = torch.zeros((n, 3), dtype=torch.float64, device=self.device)
+
+    def set_particle_force(self, F=None):
+        """Constant force F_C on each particle ([n, 3]; None detaches it)."""
+        self._fext = None if F is None else _device_f64(F, self.device).reshape(self.n, 3).contiguous()
+        _abi.check("lbm_set_particle_force", self.lib.lbm_set_particle_force(self.ctx, _ptr(self._fext)))
 
     @property
     def radius(self) -> float:

@@ -251,3 +251,109 @@ def test_adjoint_finite_differences_64(oracle_mod):
     fd = (J(h)[0] - J(-h)[0]) / (2 * h)
     announce(f"  adjoint {dj:.10e}  central difference {fd:.10e}")
     assert abs(fd - dj) < 1e-5 * abs(dj)
+
+
+def test_adjoint_with_body_force_and_particle_force(oracle_mod):
+    """The recorded forward and the segment recompute include a body force and
+    a given particle force; both are constants of the map (F_C enters the M
+    derivative)."""
+    from oracle import adjoint as A
+    from paper_1909_13412_amd import Lattice
+
+    f0, r0, v0, cf, cr, cv = _case(oracle_mod, 16)
+    theta = (1.0, 0.8, 10.0, 1e-4)
+    N, every, seed = 17, 6, 12
+    G = np.array([3e-6, 0.0, -2e-6])
+    fc = np.random.default_rng(16).standard_normal(r0.shape) * 1e-3
+    nx, ny, nz = BOX
+    lat = Lattice(nx, ny, nz, theta[1], storage="f64")
+    lat.set_populations(f0)
+    lat.particles_couple(r0, v0, mass=theta[2], gamma=theta[0], kT=theta[3], seed=seed)
+    lat.set_body_force(G)
+    lat.set_particle_force(fc)
+    tape = lat.record(N, every)
+    g = {k: t.cpu().numpy() for k, t in lat.adjoint(tape, cf, cr, cv).items()}
+    gf, gr, gv, gth = A.vjp(f0, r0, v0, np.array(theta), A.noise(len(r0), N, seed), cf, cr, cv,
+                            fc=fc, body=G)
+    errs = (nmax_err(g["pop"], gf), nmax_err(g["r"], gr), nmax_err(g["v"], gv),
+            nmax_err(g["params"], gth))
+    announce(f"adjoint with body force and F_C: {errs}")
+    assert max(errs) < 1e-10
+
+
+# ---- the 64^3 workload's own loss: mean squared displacement after 2000 steps ----
+
+def _msd_run(storage, friction, gamma, tau, vshift, grad):
+    from paper_1909_13412_amd import Lattice
+    from paper_1909_13412_amd.inputs import ADJOINT64, particle_positions, particle_velocities
+
+    w = ADJOINT64
+    L, n = w["L"], w["n"]
+    r0 = particle_positions(n, L, w["seed"])
+    v0 = particle_velocities(n, w["kT"] / w["mass"], w["seed"])
+    lat = Lattice(L, L, L, tau, storage=storage)
+    lat.particles_couple(r0, v0 + vshift, mass=w["mass"], gamma=gamma, kT=w["kT"], seed=w["seed"],
+                         friction=friction)
+    if grad:
+        tape = lat.record(w["steps"], w["every"])
+    else:
+        lat.step(w["steps"])
+    rN = lat.r.cpu().numpy()
+    J = float(np.mean(np.sum((rN - r0) ** 2, axis=1)))
+    if not grad:
+        return J, None
+    g = lat.adjoint(tape, None, 2.0 * (rN - r0) / n, None)
+    return J, (g["params"].cpu().numpy(), g["v"].cpu().numpy())
+
+
+def _msd_fd(storage, friction, h, dv):
+    from paper_1909_13412_amd.inputs import ADJOINT64 as w
+
+    def J(dg=0.0, dt=0.0, s=0.0):
+        return _msd_run(storage, friction, w["gamma"] + dg, w["tau"] + dt, s * dv, False)[0]
+
+    return ((J(dg=h) - J(dg=-h)) / (2 * h), (J(dt=h) - J(dt=-h)) / (2 * h),
+            (J(s=h) - J(s=-h)) / (2 * h))
+
+
+def _dv():
+    from paper_1909_13412_amd.inputs import ADJOINT64 as w
+
+    return np.random.default_rng(1).standard_normal((w["n"], 3)) * np.sqrt(w["kT"] / w["mass"])
+
+
+def test_msd_gradient_fp64_finite_differences_64():
+    """Loss = mean |r^N - r^0|^2 of the 16 particles after 2000 steps.  The
+    Stokeslet fit changes its node set when a particle crosses a cell face, so
+    the loss is only piecewise smooth; h = 1e-6 keeps every crossing on the
+    same step on both sides (measured: FD converges there and is off by tens
+    of percent at h >= 1e-5 for tau)."""
+    dv = _dv()
+    _, (gp, gv) = _msd_run("f64", "stokeslet", 1.0, 0.8, 0.0, True)
+    adj = (gp[0], gp[1], float(np.sum(gv * dv)))
+    fd = _msd_fd("f64", "stokeslet", 1e-6, dv)
+    announce(f"MSD 64^3 f64: adjoint {adj} fd(h=1e-6) {fd}")
+    for a, f in zip(adj, fd):
+        assert abs(f - a) < 1e-4 * abs(a)
+
+
+def test_msd_gradient_fp32_equals_fp64_adjoint_64():
+    dv = _dv()
+    _, (g64, v64) = _msd_run("f64", "stokeslet", 1.0, 0.8, 0.0, True)
+    _, (g32, v32) = _msd_run("f32", "stokeslet", 1.0, 0.8, 0.0, True)
+    announce(f"MSD 64^3 adjoint f32 {g32[:2]} {np.sum(v32 * dv):.6e} vs f64 {g64[:2]} {np.sum(v64 * dv):.6e}")
+    assert np.max(np.abs(g32 - g64)) < 1e-3 * np.max(np.abs(g64))
+    assert nmax_err(v32, v64) < 1e-3
+
+
+def test_msd_gradient_fp32_pointwise_h1e3_64():
+    """With the pointwise friction (trilinear interpolation, continuous across
+    cell faces) the map is smooth and central differences with h = 1e-3 on the
+    FP32 run agree with the adjoint."""
+    dv = _dv()
+    _, (gp, gv) = _msd_run("f32", "pointwise", 1.0, 0.8, 0.0, True)
+    adj = (gp[0], gp[1], float(np.sum(gv * dv)))
+    fd = _msd_fd("f32", "pointwise", 1e-3, dv)
+    announce(f"MSD 64^3 f32 pointwise: adjoint {adj} fd(h=1e-3) {fd}")
+    for a, f in zip(adj, fd):
+        assert abs(f - a) < 2e-2 * abs(a)

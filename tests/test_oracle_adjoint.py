@@ -61,6 +61,21 @@ def test_forward_matches_c_oracle(friction, kT, radius, force):
     assert np.max(np.abs(v - vr)) < 1e-15
 
 
+def test_forward_with_body_force_matches_c_oracle():
+    _, f0, r0, v0 = _setup(seed=7)
+    theta = np.array([1.0, 0.8, 10.0, 1e-4])
+    G = np.array([2e-5, -1e-5, 4e-6])
+    L = f0.shape[1]
+    o = oracle.Sim(L, L, L, theta[1])
+    o.set_populations(f0)
+    o.set_particles(r0, v0, mass=10.0, gamma=1.0, kT=1e-4, seed=5)
+    o.set_body_force(np.broadcast_to(G.reshape(3, 1, 1, 1), (3, L, L, L)).copy())
+    o.step(6)
+    f, r, v = A.run(f0, r0, v0, theta, A.noise(3, 6, 5), body=G)
+    assert np.max(np.abs(f - o.populations())) < 1e-14
+    assert np.max(np.abs(v - o.particles()[1])) < 1e-15
+
+
 @pytest.mark.parametrize("friction", ["stokeslet", "pointwise", "bd"])
 def test_complex_step_matches_finite_differences_of_c_oracle(friction):
     rng, f0, r0, v0 = _setup(seed=2)
