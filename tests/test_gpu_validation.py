@@ -1,0 +1,199 @@
+"""The paper's validation experiments (section 3), run on the GPU path.
+
+Fig. 1 -- drag on a sphere held at rest in a uniform flow U, present method
+(Stokeslet fit, Eq. s2-slet-v) against the pointwise friction (Eq. s2-dis1) and
+Stokes' law F = 6 pi eta R U.  In a periodic box the fluid starts at the
+uniform velocity U and a uniform body force G = 6 pi eta R U / L^3 keeps its
+mean velocity U near that value; U is the mean fluid velocity when the drag is
+read.  The reference is Stokes' law
+with Hasimoto's correction for a simple cubic array of spheres (J. Fluid Mech.
+5, 1959): F = 6 pi eta R U / (1 - 1.7601 c^(1/3) + c - 1.5593 c^2), c the
+volume fraction 4 pi R^3 / (3 L^3).  The paper's conditions are used: lattice
+viscosity nu = 0.89e-6 m^2/s x 0.5 ps / (5 nm)^2 (tau = 0.5534) and
+U = 1 m/s x 0.5 ps / 5 nm = 1e-4; the box is 64 nodes (the paper: 100).
+
+Fig. 3 -- response V_R (velocity after an instantaneous kick) against
+relaxation A_R (acceleration after a steady pulling force is released), both
+normalised at t = 0, and the thermal C_v.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from helpers import announce
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+
+
+L1, TAU1, U1 = 64, 0.5534, 1e-4
+POSITIONS = {"cell centre": (0.5, 0.5, 0.5), "node": (0.0, 0.0, 0.0),
+             "generic": (0.31, 0.72, 0.15)}
+
+
+def hasimoto(R, L):
+    c = 4.0 * math.pi / 3.0 * (R / L) ** 3
+    return 1.0 / (1.0 - 1.7601 * c ** (1.0 / 3.0) + c - 1.5593 * c * c)
+
+
+def drag_ratio(R, friction, offset, steps=60000, hold_u=True):
+    """F_H / (6 pi eta R U) for a particle held at rest (M = 1e30) in a fluid
+    started at the uniform velocity U1 and driven by the body force that
+    balances Stokes' drag, G = 6 pi eta R U1 / L^3, so that the mean velocity U
+    stays near U1 (it drifts by the small mismatch between F_H and G L^3).  The
+    wake builds up in a few times the decay time L^2 / (4 pi^2 nu) ~ 5800 steps
+    of the slowest mode; the ratio is read after ten of them and must have
+    stopped moving."""
+    from paper_1909_13412_amd import Lattice
+
+    nu = (TAU1 - 0.5) / 3.0
+    gamma = 6.0 * math.pi * nu * R  # Stokes' law: the coupling's radius is R
+    lat = Lattice(L1, L1, L1, TAU1, storage="f64")
+    u0 = np.zeros((3, L1, L1, L1))
+    u0[0] = U1
+    lat.set_equilibrium(None, u0)
+    pos = np.array([[L1 / 2 + offset[0], L1 / 2 + offset[1], L1 / 2 + offset[2]]])
+    lat.particles_couple(pos, np.zeros((1, 3)), mass=1e30, gamma=gamma, kT=0.0, friction=friction)
+    assert abs(lat.radius - R) < 1e-12
+    lat.set_body_force([gamma * U1 / L1**3, 0.0, 0.0])
+
+    def ratio():
+        U = lat.observables()[1] / L1**3
+        fh = lat.particle_forces()[0].cpu().numpy()[0]
+        return fh[0] / (6.0 * math.pi * nu * R * U), U
+
+    lat.step(steps - 10000)
+    K1, _ = ratio()
+    lat.step(10000)
+    K, U = ratio()
+    assert abs(K - K1) < 5e-3 * abs(K), (K1, K)
+    if hold_u:  # a negative drag accelerates the fluid instead
+        assert abs(U / U1 - 1.0) < 0.05
+    return K
+
+
+@pytest.mark.parametrize("where", list(POSITIONS))
+def test_fig1_present_method_follows_stokes_law_for_small_radius(where):
+    for R in (0.2, 0.4):
+        K = drag_ratio(R, "stokeslet", POSITIONS[where])
+        KH = hasimoto(R, L1)
+        announce(f"Fig. 1 stokeslet {where}: R={R} K={K:.4f} Hasimoto {KH:.4f}")
+        assert abs(K / KH - 1.0) < 0.12
+
+
+def test_fig1_pointwise_friction_underestimates_drag():
+    """Eq. s2-dis1 reads u at the particle, which its own reaction force slows:
+    F = gamma U / (1 + gamma mu_self), so 1/K = 1 + R / a_eff is affine in R."""
+    off = POSITIONS["cell centre"]
+    Rs = (0.2, 0.6, 1.0)
+    inv = [1.0 / drag_ratio(R, "pointwise", off) for R in Rs]
+    announce(f"Fig. 1 pointwise cell centre: 1/K = {inv} for R = {Rs}")
+    s1 = (inv[1] - inv[0]) / (Rs[1] - Rs[0])
+    s2 = (inv[2] - inv[1]) / (Rs[2] - Rs[1])
+    assert all(1.0 / k < hasimoto(R, L1) * 0.9 for k, R in zip(inv, Rs))
+    assert abs(s1 / s2 - 1.0) < 0.02
+    announce(f"  effective radius a_eff = {1.0 / s2:.3f}")
+
+
+def test_fig1_present_method_changes_sign_above_sqrt3_over_2():
+    """At a cell centre the fit's gain is a/(a^2 + R^2/6) with a = 1 - 2R/sqrt(3)
+    (pinned in the oracle): it is negative for R > sqrt(3)/2, and so is the
+    steady drag."""
+    off = POSITIONS["cell centre"]
+    K06 = drag_ratio(0.6, "stokeslet", off)
+    K10 = drag_ratio(1.0, "stokeslet", off, hold_u=False)
+    announce(f"Fig. 1 stokeslet cell centre: K(0.6) = {K06:.4f}, K(1.0) = {K10:.4f}")
+    assert K06 > 0.9 and K10 < 0.0
+
+
+# ---- Fig. 3 ----------------------------------------------------------------------
+
+L3, TAU3, M3, GAMMA3 = 64, 0.8, 10.0, 1.0
+POS3 = np.array([[20.3, 31.7, 40.2]])
+
+
+def _velocity_response(lags):
+    from paper_1909_13412_amd import Lattice
+
+    lat = Lattice(L3, L3, L3, TAU3, storage="f64")
+    lat.particles_couple(POS3, np.array([[1e-3, 0.0, 0.0]]), mass=M3, gamma=GAMMA3)
+    V = [1e-3]
+    for _ in range(lags):
+        lat.step(1)
+        V.append(lat.v[0, 0].item())
+    return np.array(V) / 1e-3
+
+
+def _release_acceleration(lags, F=1e-4, t_on=20000):
+    """Pull with F (the fluid carries -F/L^3 per node so the total momentum
+    stays zero) until steady, release both at t = 0, record dV/dt."""
+    from paper_1909_13412_amd import Lattice
+
+    lat = Lattice(L3, L3, L3, TAU3, storage="f64")
+    lat.particles_couple(POS3, np.zeros((1, 3)), mass=M3, gamma=GAMMA3)
+    lat.set_particle_force(np.array([[F, 0.0, 0.0]]))
+    lat.set_body_force([-F / L3**3, 0.0, 0.0])
+    lat.step(t_on)
+    V = [lat.v[0, 0].item()]
+    lat.set_particle_force(None)
+    lat.set_body_force(None)
+    for _ in range(lags + 1):
+        lat.step(1)
+        V.append(lat.v[0, 0].item())
+    A = np.diff(np.array(V))
+    return A / A[0]
+
+
+def test_fig3_response_equals_relaxation():
+    """For a linear response R(k), the kick gives V(k) = R(k) and the release
+    gives dV/dt(k) = -(F/M) R(k): normalised, they coincide.  The fit's e^N
+    normalisation makes the method only positively homogeneous, so the match
+    measures how linear it is in practice."""
+    lags = 200
+    VR = _velocity_response(lags)
+    AR = _release_acceleration(lags)
+    diff = np.abs(VR[: lags + 1] - AR[: lags + 1])
+    announce("Fig. 3 lag: V_R, -A_R: " + ", ".join(f"{k}: {VR[k]:.5f} {AR[k]:.5f}"
+                                                    for k in (1, 5, 10, 20, 50, 100, 200)))
+    assert np.max(diff) < 1e-3
+    # long-time tail t^-3/2 (section 3): local exponent between lags 50 and 200
+    slope = math.log(VR[200] / VR[50]) / math.log(4.0)
+    announce(f"  V_R local exponent over lags 50..200: {slope:.3f}")
+    assert -2.0 < slope < -1.3
+
+
+def test_fig3_thermal_vacf_against_response():
+    """C_v of 64 particles at kT = 1e-4 (noise on the particles only, Eqs.
+    s2-rf1, s2-rf2) against V_R of the same box.  Measured, not matched: with
+    no fluctuations in the fluid the stationary VACF decays more slowly than
+    the response (the particle's own wake co-moves with it); the test records
+    the two curves and checks C_v's own properties."""
+    from paper_1909_13412_amd import Lattice
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    n, kT, lags = 64, 1e-4, 100
+    lat = Lattice(L3, L3, L3, TAU3, storage="f32")
+    lat.particles_couple(particle_positions(n, L3, 5), particle_velocities(n, kT / M3, 5),
+                         mass=M3, gamma=GAMMA3, kT=kT, seed=5)
+    lat.step(2000)
+    lat.vacf_config(lags, 5)
+    lat.step(20000)
+    acc, cnt = lat.vacf()
+    C = acc.sum(0).cpu().numpy() / (n * np.maximum(cnt, 1))
+    C = C / C[0]
+    VR = _velocity_response(lags)
+    announce("Fig. 3 lag: C_v, V_R: " + ", ".join(f"{k}: {C[k]:.4f} {VR[k]:.4f}"
+                                                   for k in (1, 2, 5, 10, 20, 50, 100)))
+    coarse = C[[0, 1, 2, 5, 10, 20, 30, 50]]
+    assert np.all(np.diff(coarse) < 0.0) and C[50] > 0.0
+    # slower than Brownian dynamics without hydrodynamics, (1 - gamma/M)^k
+    assert C[20] > (1.0 - GAMMA3 / M3) ** 20
