@@ -107,12 +107,31 @@ def corners(r, shape):
     return c, node
 
 
-def particle_update(f8, V, r, theta, xi, c, shape, friction: int, radius: float, fc=None):
+def fit_corners(r, shape):
+    """Corners of the (2 dx)^3 fitting cube: per axis c0 and c0 + 2 with
+    c0 = floor(s + 1/2) - 1.  Returns c0 [n, 3] and node [n, 8]."""
+    nz, ny, nx = shape
+    Lv = np.array([nx, ny, nz], dtype=np.float64)
+    rr = np.real(r)
+    s = rr - Lv * np.floor(rr / Lv)
+    c0 = np.floor(s + 0.5) - 1.0
+    ci = c0.astype(np.int64)
+    node = np.zeros((r.shape[0], 8), dtype=np.int64)
+    for p in range(8):
+        q = (ci + 2 * _BITS[p]) % np.array([nx, ny, nz])
+        node[:, p] = (q[:, 2] * ny + q[:, 1]) * nx + q[:, 0]
+    return c0, node
+
+
+def particle_update(f8, V, r, theta, xi, c, shape, friction: int, radius: float, fc=None,
+                    cfit=None):
     """One particle's step as a function of the populations at its eight
-    corner nodes.  Batch axes lead: f8 [B, 8, 19], V, r [B, 3], theta [B, 4],
-    xi [3]; c [3] is the corner cell (fixed); fc [3] a given force F_C on the
-    particle (None: zero).  Returns (V', r', spread [B, 8, 3]) where spread is
-    the force the eight nodes receive."""
+    fitting nodes.  Batch axes lead: f8 [B, 8, 19], V, r [B, 3], theta [B, 4],
+    xi [3]; c [3] is the corner cell (fixed, the spreading nodes); cfit [3] the
+    (2 dx)^3 cube's first corner for the wide Stokeslet fit (f8 then holds
+    those corners); fc [3] a given force F_C on the particle (None: zero).
+    Returns (V', r', spread [B, 8, 3]) where spread is the force the eight
+    corner-cell nodes receive."""
     nz, ny, nx = shape
     Lv = np.array([nx, ny, nz], dtype=np.float64)
     gamma, tau, M, kT = (theta[:, k] for k in range(4))
@@ -121,6 +140,8 @@ def particle_update(f8, V, r, theta, xi, c, shape, friction: int, radius: float,
     t = np.where(_BITS[None] == 0, 1.0 + d, 1.0 - d)  # 1 - |d| inside the cell
     Wt = t[..., 0] * t[..., 1] * t[..., 2]            # [B, 8]
     u8 = np.einsum("bpa,ak->bpk", f8, _E)              # velocity moment at each node
+    if friction == FRICTION["stokeslet2dx"]:
+        d = (cfit + 2 * _BITS)[None, :, :] - s[:, None, :]
     if friction == FRICTION["bd"]:
         FH = -gamma[:, None] * V
     elif friction == FRICTION["pointwise"]:
@@ -177,11 +198,13 @@ def step(f, r, V, theta, xi_k, friction: int, radius: float, fc=None, body=None)
     rn = np.empty_like(r, dtype=dtype)
     if n:
         c, node = corners(r, shape)
+        cfit, nfit = fit_corners(r, shape) if friction == FRICTION["stokeslet2dx"] else (c, node)
         fl = f.reshape(19, ncell)
         for i in range(n):
-            f8 = fl[:, node[i]].T[None]                   # [1, 8, 19]
+            f8 = fl[:, nfit[i]].T[None]                   # [1, 8, 19]
             v1, r1, sp = particle_update(f8, V[i][None], r[i][None], theta[None], xi_k[i], c[i],
-                                         shape, friction, radius, None if fc is None else fc[i])
+                                         shape, friction, radius, None if fc is None else fc[i],
+                                         cfit[i])
             Vn[i], rn[i] = v1[0], r1[0]
             for p in range(8):
                 F[:, node[i, p]] += sp[0, p]
@@ -253,25 +276,28 @@ def vjp(f0, r0, V0, theta, xi, cf, cr, cV, friction="stokeslet", radius=0.0, fc=
         n = r.shape[0]
         if n:
             c, node = corners(r, shape)
+            wide = fr_mode == FRICTION["stokeslet2dx"]
+            cfit, nfit = fit_corners(r, shape) if wide else (c, node)
             fl = f.reshape(19, ncell)
             gFl = gF.reshape(3, ncell)
             gfl = gfn.reshape(19, ncell)
             new_gr = np.zeros_like(gr)
             new_gV = np.zeros_like(gV)
             for i in range(n):
-                f8 = fl[:, node[i]].T                      # [8, 19]
+                f8 = fl[:, nfit[i]].T                      # [8, 19]
                 nin = 8 * 19 + 3 + 3 + 4
                 base = np.concatenate([f8.ravel(), V[i], r[i], theta]).astype(complex)
                 X = np.tile(base, (nin, 1)) + 1j * H * np.eye(nin)
                 v1, r1, sp = particle_update(X[:, :152].reshape(nin, 8, 19), X[:, 152:155],
                                              X[:, 155:158], X[:, 158:162], xi[k][i], c[i], shape,
-                                             fr_mode, radius, None if fc is None else fc[i])
+                                             fr_mode, radius, None if fc is None else fc[i],
+                                             cfit[i])
                 jv, jr, jsp = np.imag(v1) / H, np.imag(r1) / H, np.imag(sp) / H
                 ybar_sp = gFl[:, node[i]].T                # [8, 3] gradient of each node force
                 xbar = jv @ gV[i] + jr @ gr[i] + np.einsum("bpk,pk->b", jsp, ybar_sp)
                 g8 = xbar[:152].reshape(8, 19)
                 for p in range(8):
-                    gfl[:, node[i, p]] += g8[p]
+                    gfl[:, nfit[i, p]] += g8[p]
                 new_gV[i] = xbar[152:155]
                 new_gr[i] = xbar[155:158]
                 gth += xbar[158:162]

@@ -161,17 +161,23 @@ void ora_gauss3(uint64_t seed, uint32_t step, uint32_t particle, uint32_t replic
  * gives F_H = 0.
  * mode POINTWISE (Eq. s2-dis1): F_H = -gamma (V - u(r)), u(r) interpolated
  *   trilinearly from the same eight nodes.
- * mode BD (Eq. s2-dis0): F_H = -gamma V. */
+ * mode BD (Eq. s2-dis0): F_H = -gamma V.
+ * mode STOKESLET_2DX: the same fit on the eight corners of a cube of edge
+ *   2 dx around the particle (the remedy section 2.2 suggests for large R):
+ *   per axis the corners are c0 and c0 + 2 with c0 = floor(s + 1/2) - 1, so
+ *   the particle lies in the middle half of the cube; u8 then holds the
+ *   velocities at those corners (p -> c0 + 2 (p&1, p>>1&1, p>>2&1)). */
 void ora_friction_force(int mode, double R, double gamma, const double s[3],
                         const double V[3], const double u8[8][3], double FH[3])
 {
     double c[3], d[8][3], wgt[8];
-    for (int k = 0; k < 3; ++k) c[k] = floor(s[k]);
+    const int wide = mode == ORA_FRICTION_STOKESLET_2DX;
+    for (int k = 0; k < 3; ++k) c[k] = wide ? floor(s[k] + 0.5) - 1.0 : floor(s[k]);
     for (int p = 0; p < 8; ++p) {
         int b[3] = {p & 1, (p >> 1) & 1, (p >> 2) & 1};
         wgt[p] = 1.0;
         for (int k = 0; k < 3; ++k) {
-            d[p][k] = (c[k] + b[k]) - s[k];
+            d[p][k] = (c[k] + (wide ? 2 * b[k] : b[k])) - s[k];
             wgt[p] *= 1.0 - fabs(d[p][k]);
         }
     }
@@ -440,6 +446,16 @@ static void couple_particles(ora_sim *o)
                 wgt[p] *= 1.0 - fabs(d);
             }
             for (int k = 0; k < 3; ++k) u8[p][k] = o->u[k * n + node[p]];
+        }
+        if (o->friction == ORA_FRICTION_STOKESLET_2DX) {
+            /* the fit reads the corners of the (2 dx)^3 cube instead */
+            for (int p = 0; p < 8; ++p) {
+                int64_t q[3];
+                for (int k = 0; k < 3; ++k)
+                    q[k] = (int64_t)floor(s[k] + 0.5) - 1 + 2 * ((p >> k) & 1);
+                int64_t nd = cell_index(o, wrap(q[0], L[0]), wrap(q[1], L[1]), wrap(q[2], L[2]));
+                for (int k = 0; k < 3; ++k) u8[p][k] = o->u[k * n + nd];
+            }
         }
         double FH[3];
         ora_friction_force(o->friction, o->R, o->gamma, s, Vi, u8, FH);

@@ -27,7 +27,8 @@ extern "C" {
 
 #define ORA_Q 19
 
-enum { ORA_FRICTION_STOKESLET = 0, ORA_FRICTION_POINTWISE = 1, ORA_FRICTION_BD = 2 };
+enum { ORA_FRICTION_STOKESLET = 0, ORA_FRICTION_POINTWISE = 1, ORA_FRICTION_BD = 2,
+       ORA_FRICTION_STOKESLET_2DX = 3 };
 
 typedef struct ora_sim ora_sim;
 

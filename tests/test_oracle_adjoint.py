@@ -48,7 +48,8 @@ def _oracle_run(f0, r0, v0, theta, nsteps, friction, radius=0.0, seed=5, fc=None
 @pytest.mark.parametrize("friction,kT,radius,force", [("stokeslet", 1e-4, 0.0, False),
                                                       ("stokeslet", 0.0, 0.4, True),
                                                       ("pointwise", 1e-4, 0.0, False),
-                                                      ("bd", 1e-4, 0.0, True)])
+                                                      ("bd", 1e-4, 0.0, True),
+                                                      ("stokeslet2dx", 1e-4, 1.2, False)])
 def test_forward_matches_c_oracle(friction, kT, radius, force):
     _, f0, r0, v0 = _setup()
     theta = np.array([1.0, 0.8, 10.0, kT])
@@ -76,7 +77,7 @@ def test_forward_with_body_force_matches_c_oracle():
     assert np.max(np.abs(v - o.particles()[1])) < 1e-15
 
 
-@pytest.mark.parametrize("friction", ["stokeslet", "pointwise", "bd"])
+@pytest.mark.parametrize("friction", ["stokeslet", "pointwise", "bd", "stokeslet2dx"])
 def test_complex_step_matches_finite_differences_of_c_oracle(friction):
     rng, f0, r0, v0 = _setup(seed=2)
     theta = np.array([1.0, 0.8, 10.0, 1e-4])
@@ -108,7 +109,8 @@ def test_complex_step_matches_finite_differences_of_c_oracle(friction):
 @pytest.mark.parametrize("friction,kT,radius,force", [("stokeslet", 1e-4, 0.0, False),
                                                       ("stokeslet", 0.0, 0.4, True),
                                                       ("pointwise", 1e-4, 0.0, False),
-                                                      ("bd", 1e-4, 0.0, True)])
+                                                      ("bd", 1e-4, 0.0, True),
+                                                      ("stokeslet2dx", 1e-4, 1.2, True)])
 def test_reverse_sweep_is_the_transpose_of_the_complex_step(friction, kT, radius, force):
     rng, f0, r0, v0 = _setup(seed=3)
     theta = np.array([1.0, 0.8, 10.0, kT])

@@ -65,6 +65,71 @@ def test_fit_gain_in_uniform_stream_at_cell_centre(oracle_mod):
             assert np.allclose(FH, 0.7 * W * k * e, rtol=1e-12, atol=1e-17), (R, FH)
 
 
+def _wide_corners(s):
+    c0 = np.floor(s + 0.5) - 1.0
+    return [c0 + 2 * np.array([p & 1, (p >> 1) & 1, (p >> 2) & 1]) for p in range(8)]
+
+
+def test_wide_fit_recovers_stokeslet_stream_at_cube_centre(oracle_mod):
+    # The (2 dx)^3 variant: the particle at a node (the centre of its fitting
+    # cube, corners at +-1 per axis) in the Stokeslet stream is fitted exactly,
+    # for radii up to the cube's own bound.
+    rng = np.random.default_rng(13)
+    for _ in range(20):
+        R = rng.uniform(0.1, 1.6)
+        U0 = rng.uniform(1e-4, 1e-2)
+        e = rng.standard_normal(3)
+        e /= np.linalg.norm(e)
+        V = 1e-3 * rng.standard_normal(3)
+        s = np.floor(rng.uniform(2, 20, 3))
+        u8 = np.array([V + _oseen_wake(R, U0, e, x - s) for x in _wide_corners(s)])
+        FH = oracle_mod.friction_force("stokeslet2dx", R, 1.7, s, V, u8)
+        assert np.allclose(FH, 1.7 * U0 * e, rtol=1e-12, atol=1e-18)
+
+
+def test_wide_fit_gain_is_the_unit_fit_at_half_radius(oracle_mod):
+    # Doubling every node offset scales the shape vectors as R -> R/2, so at a
+    # cube centre in a uniform stream the gain is a/(a^2 + R^2/24) with
+    # a = 1 - R/sqrt(3): it changes sign only at R = sqrt(3).
+    for R in (0.0, 0.5, 1.0, 1.5, 1.7, 2.0):
+        e = np.array([0.0, 1.0, 0.0])
+        W = 2e-3
+        s = np.array([7.0, 3.0, 11.0])
+        V = np.array([1e-3, -2e-3, 5e-4])
+        FH = oracle_mod.friction_force("stokeslet2dx", R, 0.7, s, V, np.tile(V + W * e, (8, 1)))
+        a = 1.0 - R / np.sqrt(3.0)
+        k = a / (a * a + R * R / 24.0)
+        assert np.allclose(FH, 0.7 * W * k * e, rtol=1e-12, atol=1e-17), (R, FH)
+        # and it equals the unit-cell fit with R/2 at a cell centre
+        FH1 = oracle_mod.friction_force("stokeslet", R / 2, 0.7, s + 0.5, V,
+                                        np.tile(V + W * e, (8, 1)))
+        assert np.allclose(FH, FH1, rtol=1e-12, atol=1e-17)
+
+
+def test_wide_fit_reads_the_cube_nodes_in_a_run(oracle_mod):
+    # In a coupled step the wide fit takes u at c0 + 2b (c0 = floor(s + 1/2) - 1):
+    # with a linear velocity field u(x) = A x + b0 set up as equilibrium, the
+    # fitted relative velocity at R = 0 is the mean over those eight nodes,
+    # A (c0 + 1) + b0, which differs from the unit cell's mean A (c + 1/2) + b0.
+    L = 12
+    A = np.array([[1e-4, 2e-4, 0.0], [0.0, -1e-4, 3e-4], [2e-4, 0.0, 1e-4]])
+    b0 = np.array([1e-3, -5e-4, 2e-4])
+    z, y, x = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    X = np.stack([x, y, z]).astype(float)  # [3, z, y, x]
+    u = np.einsum("ij,jzyx->izyx", A, X) + b0.reshape(3, 1, 1, 1)
+    r = np.array([[4.7, 5.2, 6.9]])
+    sim = oracle_mod.Sim(L, L, L, 0.8)
+    sim.set_equilibrium(None, u)
+    sim.set_particles(r, np.zeros((1, 3)), mass=10.0, gamma=1.0, radius=1e-30,
+                      friction="stokeslet2dx")
+    sim.step(1)
+    fh, _ = sim.particle_forces()
+    c0 = np.floor(r[0] + 0.5) - 1.0
+    assert np.allclose(fh[0], A @ (c0 + 1.0) + b0, rtol=1e-10, atol=1e-18)
+    c = np.floor(r[0])
+    assert not np.allclose(fh[0], A @ (c + 0.5) + b0, rtol=1e-3)
+
+
 def test_fit_with_zero_radius_is_eight_node_mean(oracle_mod):
     # R = 0 makes every shape vector equal e^N, so U^inf = |mean(w)| and
     # F_H = gamma (mean_p u_p - V).
