@@ -71,11 +71,16 @@ typedef enum lbm_storage {
 
 /* Friction model.  STOKESLET is the paper's method (Eq. s2-slet-v); POINTWISE is
  * Eq. s2-dis1 with u(r) interpolated trilinearly from the eight nodes; BD is
- * Eq. s2-dis0 (solvent at rest, no reaction force). */
+ * Eq. s2-dis0 (solvent at rest, no reaction force).  STOKESLET_2DX is the
+ * remedy section 2.2 names for large radii: the same fit on the eight corners
+ * of a cube of edge 2 dx around the particle (per axis c0 and c0 + 2,
+ * c0 = floor(s + 1/2) - 1); the reaction force is still spread to the corners
+ * of the unit cell. */
 typedef enum lbm_friction {
     LBM_FRICTION_STOKESLET = 0,
     LBM_FRICTION_POINTWISE = 1,
-    LBM_FRICTION_BD = 2
+    LBM_FRICTION_BD = 2,
+    LBM_FRICTION_STOKESLET_2DX = 3
 } lbm_friction;
 
 typedef struct lbm_grid_desc {

@@ -104,17 +104,23 @@ __global__ __launch_bounds__(kParticleBlock) void k_adj_particle(
         tf[k] = 1.0 - fabs(d[k]);
         W *= tf[k];
     }
-    const uint32_t cell = (node[2] * g.ny + node[1]) * g.nx + node[0];
     const bool coupled = pa.friction != LBM_FRICTION_BD;
+    // Fitting node: the same, or the corner of the (2 dx)^3 cube.
+    uint32_t fnode[3] = {node[0], node[1], node[2]};
+    double dfit[3] = {d[0], d[1], d[2]};
+    if (pa.friction == LBM_FRICTION_STOKESLET_2DX) wide_corner(r, Ln, b, fnode, dfit);
+    const uint32_t fcell = (fnode[2] * g.ny + fnode[1]) * g.nx + fnode[0];
 
-    // Nodal velocity u^n and the node-force adjoint Fb = 3 sum_a w_a e_a fs_a.
+    // Nodal velocity u^n at the fitting node and the node-force adjoint
+    // Fb = 3 sum_a w_a e_a fs_a at the spreading node.
     double u[3] = {0.0, 0.0, 0.0};
     double Fb[3] = {0.0, 0.0, 0.0};
     if (coupled) {
+        const Neighbours nf(fnode[0], fnode[1], fnode[2], g);
         const Neighbours nb(node[0], node[1], node[2], g);
         static_for<1, D3Q19::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            const double gvl = double(C::dec(A[nb.pop<a>(g)], dec_s));
+            const double gvl = double(C::dec(A[nf.pop<a>(g)], dec_s));
             const double fs = Abar[push_index<a>(nb, gd)];
             const double w3 = 3.0 * D3Q19::w<double>(a);
             if constexpr (D3Q19::ex[a] != 0) {
@@ -147,7 +153,7 @@ __global__ __launch_bounds__(kParticleBlock) void k_adj_particle(
     }
     double FH[3];
     FitTrace tr;
-    friction_lanes(pa.friction, pa.gamma, pa.R, W, u, V, d, FH, tr);
+    friction_lanes(pa.friction, pa.gamma, pa.R, W, u, V, dfit, FH, tr);
 
     // Langevin update: V' = V + (F_C + F_H + F_R)/M, r' = r + V'.
     double Vt[3], FHb[3];
@@ -169,7 +175,7 @@ __global__ __launch_bounds__(kParticleBlock) void k_adj_particle(
     // Back through the friction.
     double ub[3] = {0.0, 0.0, 0.0};  // this lane's node velocity
     double Vbf[3] = {0.0, 0.0, 0.0}; // particle velocity, whole-particle value
-    double db[3] = {0.0, 0.0, 0.0};  // this lane's offset d_p
+    double db[3] = {0.0, 0.0, 0.0};  // this lane's fitting offset
     double gam_b = 0.0, R_b = 0.0;   // whole-particle values
     if (pa.friction == LBM_FRICTION_BD) {
 #pragma unroll
@@ -205,7 +211,7 @@ __global__ __launch_bounds__(kParticleBlock) void k_adj_particle(
                 wb[k] = numb * tr.g[k];
                 gb[k] = numb * tr.w[k] + 2.0 * denb * tr.g[k];
                 cab += gb[k] * tr.eN[k];
-                cbb -= gb[k] * d[k];
+                cbb -= gb[k] * dfit[k];
             }
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -218,8 +224,8 @@ __global__ __launch_bounds__(kParticleBlock) void k_adj_particle(
             const double rpb = -cbb * 3.0 * tr.cb / rp + cab * 3.0 * pa.R / (4.0 * rp * rp);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                db[k] += deb * tr.eN[k] + rpb * d[k] / rp;
-                eNb[k] += deb * d[k];
+                db[k] += deb * tr.eN[k] + rpb * dfit[k] / rp;
+                eNb[k] += deb * dfit[k];
             }
         }
         // e^N = m / |m| with m the mean of w over the eight nodes.
@@ -238,8 +244,9 @@ __global__ __launch_bounds__(kParticleBlock) void k_adj_particle(
         }
         R_b = sum8(Rb);
     }
-    // Wrapped position s = r - L floor(r/L) (slope 1); d = c + b - s and the
-    // weight factors 1 + d (b = 0) or 1 - d (b = 1) inside the corner cell.
+    // Wrapped position s = r - L floor(r/L) (slope 1); both offsets are a
+    // fixed node minus s, and the weight factors are 1 + d (b = 0) or 1 - d
+    // (b = 1) inside the corner cell.
     double sb[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -259,9 +266,9 @@ __global__ __launch_bounds__(kParticleBlock) void k_adj_particle(
     uint32_t my_cell = kNoNode;
     if (coupled) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) atomicAdd(&cur.u[3 * uint64_t(cell) + k], ub[k]);
-        atomicOr(&cur.mask[cell >> 5], 1u << (cell & 31));
-        my_cell = cell;
+        for (int k = 0; k < 3; ++k) atomicAdd(&cur.u[3 * uint64_t(fcell) + k], ub[k]);
+        atomicOr(&cur.mask[fcell >> 5], 1u << (fcell & 31));
+        my_cell = fcell;
     }
     pa.prev_cell[8 * i + p] = my_cell;
 

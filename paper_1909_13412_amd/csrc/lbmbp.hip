@@ -501,12 +501,12 @@ int32_t prof_start(lbm_ctx *c, int32_t kind) {
     if (c->prof_used == c->prof_cap && !prof_grow(c)) return -1;
     const int32_t k = c->prof_used++;
     c->prof_kind[k] = kind;
-    hipEventRecord(c->prof_ev[2 * k], c->stream);
+    (void)hipEventRecord(c->prof_ev[2 * k], c->stream);
     return k;
 }
 
 void prof_stop(lbm_ctx *c, int32_t k) {
-    if (k >= 0) hipEventRecord(c->prof_ev[2 * k + 1], c->stream);
+    if (k >= 0) (void)hipEventRecord(c->prof_ev[2 * k + 1], c->stream);
 }
 
 template <class C>
@@ -609,16 +609,16 @@ void time_shapes(lbm_ctx *c, int32_t iters, double *ms, hipError_t *err) {
         ms[k] = -1.0;
         if (!shape_ok(c, k)) continue;
         for (int w = 0; w < 2; ++w) launch(k);
-        hipEventRecord(e0, c->stream);
+        (void)hipEventRecord(e0, c->stream);
         for (int it = 0; it < iters; ++it) launch(k);
-        hipEventRecord(e1, c->stream);
+        (void)hipEventRecord(e1, c->stream);
         *err = hipEventSynchronize(e1);
         float t = 0.0f;
         if (*err == hipSuccess) *err = hipEventElapsedTime(&t, e0, e1);
         ms[k] = double(t) / iters;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
 }
 
 template <class C>
@@ -802,7 +802,7 @@ lbm_status particles_couple(lbm_ctx *ctx, const lbm_particle_desc *d, double *r,
         if (!(d->gamma >= 0.0) || !isfinite(d->gamma)) return LBM_E_INVAL;
         if (!(d->kT >= 0.0) || !isfinite(d->kT)) return LBM_E_INVAL;
         if (!isfinite(d->radius)) return LBM_E_INVAL;
-        if (d->friction < LBM_FRICTION_STOKESLET || d->friction > LBM_FRICTION_BD)
+        if (d->friction < LBM_FRICTION_STOKESLET || d->friction > LBM_FRICTION_STOKESLET_2DX)
             return LBM_E_INVAL;
     }
     // Node forces left by any previous particle set are cleared.
@@ -994,7 +994,7 @@ lbm_status lbm_get_step(const lbm_ctx *ctx, int64_t *step) {
 
 lbm_status lbm_destroy(lbm_ctx *ctx) {
     if (!ctx) return LBM_E_INVAL;
-    for (int32_t k = 0; k < 2 * ctx->prof_cap; ++k) hipEventDestroy(ctx->prof_ev[k]);
+    for (int32_t k = 0; k < 2 * ctx->prof_cap; ++k) (void)hipEventDestroy(ctx->prof_ev[k]);
     free(ctx->prof_ev);
     free(ctx->prof_kind);
     free(ctx);
@@ -1082,7 +1082,7 @@ bool ens_desc_ok(const lbm_ensemble_desc *d, const lbm_replica_desc *reps) {
     if (d->storage == LBM_STORE_F16 && (d->f16_scale_log2 < 0 || d->f16_scale_log2 > 24)) return false;
     if (!(d->mass > 0.0) || !isfinite(d->mass) || !(d->gamma >= 0.0) || !isfinite(d->gamma)) return false;
     if (!(d->kT >= 0.0) || !isfinite(d->kT) || !isfinite(d->radius)) return false;
-    if (d->friction < LBM_FRICTION_STOKESLET || d->friction > LBM_FRICTION_BD) return false;
+    if (d->friction < LBM_FRICTION_STOKESLET || d->friction > LBM_FRICTION_STOKESLET_2DX) return false;
     uint64_t cells = 0, n = 0;
     for (int32_t k = 0; k < d->nrep; ++k) {
         const lbm_replica_desc &r = reps[k];
@@ -1213,7 +1213,7 @@ void ens_dispatch_step(lbm_ens *e, int cur, int par) {
 }
 
 void ens_drop_graph(lbm_ens *e) {
-    if (e->graph_valid) hipGraphExecDestroy(e->graph);
+    if (e->graph_valid) (void)hipGraphExecDestroy(e->graph);
     e->graph_valid = 0;
 }
 
@@ -1237,13 +1237,13 @@ bool ens_capture(lbm_ens *e) {
     hipGraph_t g = nullptr;
     const hipError_t end = hipStreamEndCapture(e->cap_stream, &g);
     if (end != hipSuccess || !g) {
-        hipGetLastError();
+        (void)hipGetLastError();
         return false;
     }
     const hipError_t err = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (err != hipSuccess) {
-        hipGetLastError();
+        (void)hipGetLastError();
         return false;
     }
     e->graph_valid = 1;
@@ -1504,9 +1504,9 @@ lbm_status lbm_ens_autotune(lbm_ens *e, int32_t iters, double *ms, int32_t *chos
         for (int32_t q = 0; q < e->nrep; ++q) all = all && (e->host_reps[q].ny % kShapes[k].cpt == 0);
         if (!all) continue;
         for (int w = 0; w < 2; ++w) ens_time_any(e, k);
-        hipEventRecord(e0, e->stream);
+        (void)hipEventRecord(e0, e->stream);
         for (int32_t it = 0; it < iters; ++it) ens_time_any(e, k);
-        hipEventRecord(e1, e->stream);
+        (void)hipEventRecord(e1, e->stream);
         err = hipEventSynchronize(e1);
         float f = 0.0f;
         if (err == hipSuccess) err = hipEventElapsedTime(&f, e0, e1);
@@ -1515,8 +1515,8 @@ lbm_status lbm_ens_autotune(lbm_ens *e, int32_t iters, double *ms, int32_t *chos
     if (err == hipSuccess)
         err = hipMemcpyAsync(e->clock, &saved, sizeof(saved), hipMemcpyHostToDevice, e->stream);
     if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (err != hipSuccess) return LBM_E_DEVICE;
     int best = 0;
     for (int k = 0; k < kNumShapes; ++k)
@@ -1595,7 +1595,7 @@ lbm_status lbm_ens_graph_replays(const lbm_ens *e, int64_t *replays) {
 lbm_status lbm_ens_destroy(lbm_ens *e) {
     if (!e) return LBM_E_INVAL;
     ens_drop_graph(e);
-    if (e->cap_stream) hipStreamDestroy(e->cap_stream);
+    if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
     free(e->host_reps);
     free(e->host_table);
     free(e);

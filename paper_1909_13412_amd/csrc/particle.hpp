@@ -71,7 +71,8 @@ struct FitTrace {
 // the group calls it and receives the same F_H.
 //   LBM_FRICTION_STOKESLET (Eq. s2-slet-v): e^N from the mean relative
 //     velocity, least-squares amplitude U^inf of the Stokeslet shape g_p,
-//     F_H = gamma U^inf e^N;
+//     F_H = gamma U^inf e^N; LBM_FRICTION_STOKESLET_2DX is the same fit with
+//     u and d taken at the corners of the (2 dx)^3 cube;
 //   LBM_FRICTION_POINTWISE (Eq. s2-dis1): F_H = -gamma (V - u(r)) with u(r)
 //     interpolated trilinearly;
 //   LBM_FRICTION_BD (Eq. s2-dis0): F_H = -gamma V.
@@ -125,6 +126,23 @@ __device__ inline void friction_lanes(int32_t mode, double gamma, double R, doub
     }
 }
 
+// Node p of the (2 dx)^3 fitting cube of the wide Stokeslet fit: per axis the
+// corners c0 and c0 + 2 with c0 = floor(s + 1/2) - 1, s the wrapped position,
+// so that the particle sits in the middle half of the cube.  q: the node
+// (periodic), dq: node minus particle (unwrapped).
+__device__ inline void wide_corner(const double (&r)[3], const uint32_t (&Ln)[3], const int (&b)[3],
+                                   uint32_t (&q)[3], double (&dq)[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double L = double(Ln[k]);
+        const double s = r[k] - L * floor(r[k] / L);
+        const double c0 = floor(s + 0.5) - 1.0;
+        dq[k] = (c0 + 2.0 * double(b[k])) - s;
+        int32_t ci = (int32_t(c0) + 2 * b[k]) % int32_t(Ln[k]);
+        q[k] = uint32_t(ci < 0 ? ci + int32_t(Ln[k]) : ci);
+    }
+}
+
 // Where a particle lives: its box, lattice and node-force fields, and the
 // Philox key and counter words of its Brownian force.
 template <class C>
@@ -168,13 +186,17 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
     }
     const uint32_t cell = (node[2] * g.ny + node[1]) * g.nx + node[0];
     const bool coupled = pa.friction != LBM_FRICTION_BD;
+    // The fit reads the same eight nodes, or those of the (2 dx)^3 cube.
+    uint32_t fnode[3] = {node[0], node[1], node[2]};
+    double dfit[3] = {d[0], d[1], d[2]};
+    if (pa.friction == LBM_FRICTION_STOKESLET_2DX) wide_corner(r, Ln, b, fnode, dfit);
 
-    // Issue the gather of f^n at this lane's node (pull from node - e_a); the
-    // values are consumed only after the VACF sample and the Brownian force,
-    // which overlap the load latency.
+    // Issue the gather of f^n at this lane's fitting node (pull from node -
+    // e_a); the values are consumed only after the VACF sample and the
+    // Brownian force, which overlap the load latency.
     typename C::T raw[D3Q19::Q];
     if (coupled) {
-        const Neighbours nb(node[0], node[1], node[2], g);
+        const Neighbours nb(fnode[0], fnode[1], fnode[2], g);
         static_for<1, D3Q19::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
             raw[a] = A[nb.pop<a>(g)];
@@ -229,7 +251,7 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
         });
     }
     FitTrace tr;
-    friction_lanes(pa.friction, pa.gamma, site.R, W, u, V, d, FH, tr);
+    friction_lanes(pa.friction, pa.gamma, site.R, W, u, V, dfit, FH, tr);
     if (!valid) return;
 
     // Release this lane's node from the field used one step ago (it was

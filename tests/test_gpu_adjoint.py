@@ -59,7 +59,7 @@ def _gpu_grad(storage, f0, r0, v0, theta, cf, cr, cv, nsteps, every, friction, r
 
 
 CASES = [("stokeslet", 1e-4, 0.0), ("stokeslet", 0.0, 0.4), ("pointwise", 1e-4, 0.0),
-         ("bd", 1e-4, 0.0)]
+         ("bd", 1e-4, 0.0), ("stokeslet2dx", 1e-4, 1.2)]
 
 
 @pytest.mark.parametrize("friction,kT,radius", CASES)

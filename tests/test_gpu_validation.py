@@ -115,6 +115,18 @@ def test_fig1_present_method_changes_sign_above_sqrt3_over_2():
     assert K06 > 0.9 and K10 < 0.0
 
 
+@pytest.mark.parametrize("where", list(POSITIONS))
+def test_fig1_wide_fit_extends_stokes_law_to_larger_radius(where):
+    """The remedy of section 2.2 for large radii, the fit on the corners of a
+    (2 dx)^3 cube: Stokes' law within 10% up to R = 1 wherever the particle
+    sits (the unit-cell fit leaves that band above R = 0.4)."""
+    for R in (0.6, 0.8, 1.0):
+        K = drag_ratio(R, "stokeslet2dx", POSITIONS[where])
+        KH = hasimoto(R, L1)
+        announce(f"Fig. 1 wide fit {where}: R={R} K={K:.4f} Hasimoto {KH:.4f}")
+        assert abs(K / KH - 1.0) < 0.10
+
+
 # ---- Fig. 3 ----------------------------------------------------------------------
 
 L3, TAU3, M3, GAMMA3 = 64, 0.8, 10.0, 1.0
