@@ -51,11 +51,14 @@ def _load():
     vp = ctypes.c_void_p
     sig = {
         "ora_lattice": (None, [vp, dp]),
+        "ora_lattice_q": (None, [i32, vp, dp]),
         "ora_equilibrium": (None, [ctypes.c_double, dp, dp]),
+        "ora_equilibrium_q": (None, [i32, ctypes.c_double, dp, dp]),
         "ora_philox4x32_10": (None, [vp, vp, vp]),
         "ora_gauss3": (None, [u64, u32, u32, u32, u32, dp]),
         "ora_friction_force": (None, [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]),
         "ora_create": (vp, [i32, i32, i32, ctypes.c_double]),
+        "ora_create_q": (vp, [i32, i32, i32, ctypes.c_double, i32]),
         "ora_destroy": (None, [vp]),
         "ora_set_equilibrium": (None, [vp, dp, dp]),
         "ora_set_populations": (None, [vp, dp]),
@@ -96,20 +99,20 @@ def _f64(a, shape=None):
     return a
 
 
-def lattice():
-    """(e[19,3] int, w[19]) of the oracle's velocity set."""
+def lattice(q: int = Q):
+    """(e[q,3] int, w[q]) of the oracle's velocity set with q = 19 or 15."""
     lib = _load()
-    e = np.zeros((Q, 3), dtype=np.int32)
-    w = np.zeros(Q, dtype=np.float64)
-    lib.ora_lattice(e.ctypes.data_as(ctypes.c_void_p), _dp(w))
+    e = np.zeros((q, 3), dtype=np.int32)
+    w = np.zeros(q, dtype=np.float64)
+    lib.ora_lattice_q(int(q), e.ctypes.data_as(ctypes.c_void_p), _dp(w))
     return e, w
 
 
-def equilibrium(rho: float, u) -> np.ndarray:
+def equilibrium(rho: float, u, q: int = Q) -> np.ndarray:
     lib = _load()
     u = _f64(u, (3,))
-    out = np.zeros(Q)
-    lib.ora_equilibrium(float(rho), _dp(u), _dp(out))
+    out = np.zeros(q)
+    lib.ora_equilibrium_q(int(q), float(rho), _dp(u), _dp(out))
     return out
 
 
@@ -147,14 +150,16 @@ def num_threads() -> int:
 
 class Sim:
     """One periodic box.  Arrays follow the oracle's layouts:
-    populations [19, nz, ny, nx], velocity [3, nz, ny, nx], particles [n, 3]."""
+    populations [q, nz, ny, nx], velocity [3, nz, ny, nx], particles [n, 3];
+    q = 19 or 15 velocities."""
 
-    def __init__(self, nx: int, ny: int, nz: int, tau: float):
+    def __init__(self, nx: int, ny: int, nz: int, tau: float, q: int = Q):
         self._lib = _load()
         self.shape = (nz, ny, nx)
         self.ncell = nx * ny * nz
         self.tau = tau
-        self._h = self._lib.ora_create(nx, ny, nz, float(tau))
+        self.q = int(q)
+        self._h = self._lib.ora_create_q(nx, ny, nz, float(tau), self.q)
         if not self._h:
             raise ValueError("oracle: invalid grid or tau")
         self.np = 0
@@ -176,11 +181,11 @@ class Sim:
         self._lib.ora_set_equilibrium(self._h, _dp(rho), _dp(u))
 
     def set_populations(self, f):
-        f = _f64(f, (Q * self.ncell,))
+        f = _f64(f, (self.q * self.ncell,))
         self._lib.ora_set_populations(self._h, _dp(f))
 
     def populations(self) -> np.ndarray:
-        f = np.zeros((Q,) + self.shape)
+        f = np.zeros((self.q,) + self.shape)
         self._lib.ora_get_populations(self._h, _dp(f))
         return f
 

@@ -24,25 +24,40 @@
 #include <omp.h>
 #endif
 
-/* Nineteen-velocity cubic set (the paper uses the fifteen-velocity member of the
- * same family, section 2.2; weights give c_s^2 = 1/3 as Eqs. s2-eq and s2-ident3
- * require).  Opposite pairs are adjacent: 1<->2, 3<->4, ... 17<->18. */
-static const int E[ORA_Q][3] = {
+/* Nineteen-velocity cubic set and the fifteen-velocity set the paper uses
+ * (section 2.2); both weight sets give c_s^2 = 1/3 as Eqs. s2-eq and s2-ident3
+ * require.  Opposite pairs are adjacent: 1<->2, 3<->4, ... */
+static const int E19[19][3] = {
     {0, 0, 0},
     {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},   {0, -1, 0},  {0, 0, 1},   {0, 0, -1},
     {1, 1, 0},   {-1, -1, 0}, {1, -1, 0},  {-1, 1, 0},
     {1, 0, 1},   {-1, 0, -1}, {1, 0, -1},  {-1, 0, 1},
     {0, 1, 1},   {0, -1, -1}, {0, 1, -1},  {0, -1, 1},
 };
-static const double W[ORA_Q] = {
+static const double W19[19] = {
     1.0 / 3.0,
     1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
 };
+/* rest, the six axis neighbours, the eight cube corners */
+static const int E15[15][3] = {
+    {0, 0, 0},
+    {1, 0, 0},   {-1, 0, 0},   {0, 1, 0},   {0, -1, 0},  {0, 0, 1},   {0, 0, -1},
+    {1, 1, 1},   {-1, -1, -1}, {1, 1, -1},  {-1, -1, 1}, {1, -1, 1},  {-1, 1, -1},
+    {-1, 1, 1},  {1, -1, -1},
+};
+static const double W15[15] = {
+    2.0 / 9.0,
+    1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+    1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0,
+};
 
 struct ora_sim {
     int32_t nx, ny, nz;
+    int q;               /* 19 or 15 velocities */
+    const int (*E)[3];   /* velocity table of this box */
+    const double *W;     /* weights */
     int64_t ncell;
     double tau;
     double *f;    /* post-streaming populations f^n, [a][cell] */
@@ -82,23 +97,34 @@ static int64_t wrap(int64_t i, int64_t n)
     return m < 0 ? m + n : m;
 }
 
-void ora_lattice(int32_t e[ORA_Q][3], double w[ORA_Q])
+void ora_lattice_q(int32_t q, int32_t e[][3], double w[])
 {
-    for (int a = 0; a < ORA_Q; ++a) {
+    const int (*E)[3] = q == 15 ? E15 : E19;
+    const double *W = q == 15 ? W15 : W19;
+    for (int a = 0; a < (q == 15 ? 15 : 19); ++a) {
         for (int k = 0; k < 3; ++k) e[a][k] = E[a][k];
         w[a] = W[a];
     }
 }
 
+void ora_lattice(int32_t e[ORA_Q][3], double w[ORA_Q]) { ora_lattice_q(19, e, w); }
+
 /* Eq. (s2-eq): f^eq_a = w_a [rho~ + 3 e_a.u + (9/2)(e_a.u)^2 - (3/2) u.u], the
  * incompressible form in which rho~ appears only in the zeroth-order term. */
-void ora_equilibrium(double rho, const double u[3], double feq[ORA_Q])
+void ora_equilibrium_q(int32_t q, double rho, const double u[3], double feq[])
 {
+    const int (*E)[3] = q == 15 ? E15 : E19;
+    const double *W = q == 15 ? W15 : W19;
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    for (int a = 0; a < ORA_Q; ++a) {
+    for (int a = 0; a < (q == 15 ? 15 : 19); ++a) {
         double eu = E[a][0] * u[0] + E[a][1] * u[1] + E[a][2] * u[2];
         feq[a] = W[a] * (rho + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
     }
+}
+
+void ora_equilibrium(double rho, const double u[3], double feq[ORA_Q])
+{
+    ora_equilibrium_q(19, rho, u, feq);
 }
 
 /* ---- Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) ------------------ */
@@ -224,17 +250,20 @@ void ora_friction_force(int mode, double R, double gamma, const double s[3],
 }
 
 /* ---- simulation state ------------------------------------------------------ */
-ora_sim *ora_create(int32_t nx, int32_t ny, int32_t nz, double tau)
+ora_sim *ora_create_q(int32_t nx, int32_t ny, int32_t nz, double tau, int32_t q)
 {
-    if (nx < 2 || ny < 2 || nz < 2 || !(tau > 0.5)) return NULL;
+    if (nx < 2 || ny < 2 || nz < 2 || !(tau > 0.5) || (q != 15 && q != 19)) return NULL;
     ora_sim *o = (ora_sim *)calloc(1, sizeof(ora_sim));
     if (!o) return NULL;
     o->nx = nx; o->ny = ny; o->nz = nz;
+    o->q = q;
+    o->E = q == 15 ? E15 : E19;
+    o->W = q == 15 ? W15 : W19;
     o->ncell = (int64_t)nx * ny * nz;
     o->tau = tau;
     size_t nc = (size_t)o->ncell;
-    o->f = (double *)malloc(sizeof(double) * ORA_Q * nc);
-    o->fnew = (double *)malloc(sizeof(double) * ORA_Q * nc);
+    o->f = (double *)malloc(sizeof(double) * (size_t)q * nc);
+    o->fnew = (double *)malloc(sizeof(double) * (size_t)q * nc);
     o->rho = (double *)malloc(sizeof(double) * nc);
     o->u = (double *)malloc(sizeof(double) * 3 * nc);
     o->F = (double *)malloc(sizeof(double) * 3 * nc);
@@ -244,6 +273,11 @@ ora_sim *ora_create(int32_t nx, int32_t ny, int32_t nz, double tau)
     }
     ora_set_equilibrium(o, NULL, NULL);
     return o;
+}
+
+ora_sim *ora_create(int32_t nx, int32_t ny, int32_t nz, double tau)
+{
+    return ora_create_q(nx, ny, nz, tau, 19);
 }
 
 void ora_destroy(ora_sim *o)
@@ -266,12 +300,12 @@ static void compute_moments(const ora_sim *o, const double *f, double *rho, doub
             for (int64_t x = 0; x < o->nx; ++x) {
                 int64_t c = cell_index(o, x, y, z);
                 double r = 0.0, ux = 0.0, uy = 0.0, uz = 0.0;
-                for (int a = 0; a < ORA_Q; ++a) {
+                for (int a = 0; a < o->q; ++a) {
                     double fa = f[a * n + c];
                     r += fa;
-                    ux += E[a][0] * fa;
-                    uy += E[a][1] * fa;
-                    uz += E[a][2] * fa;
+                    ux += o->E[a][0] * fa;
+                    uy += o->E[a][1] * fa;
+                    uz += o->E[a][2] * fa;
                 }
                 rho[c] = r;
                 u[c] = ux;
@@ -286,19 +320,19 @@ void ora_set_equilibrium(ora_sim *o, const double *rho, const double *u)
     for (int64_t c = 0; c < n; ++c) {
         double uc[3] = {u ? u[c] : 0.0, u ? u[n + c] : 0.0, u ? u[2 * n + c] : 0.0};
         double feq[ORA_Q];
-        ora_equilibrium(rho ? rho[c] : 1.0, uc, feq);
-        for (int a = 0; a < ORA_Q; ++a) o->f[a * n + c] = feq[a];
+        ora_equilibrium_q(o->q, rho ? rho[c] : 1.0, uc, feq);
+        for (int a = 0; a < o->q; ++a) o->f[a * n + c] = feq[a];
     }
 }
 
 void ora_set_populations(ora_sim *o, const double *f)
 {
-    memcpy(o->f, f, sizeof(double) * ORA_Q * (size_t)o->ncell);
+    memcpy(o->f, f, sizeof(double) * (size_t)o->q * (size_t)o->ncell);
 }
 
 void ora_get_populations(const ora_sim *o, double *f)
 {
-    memcpy(f, o->f, sizeof(double) * ORA_Q * (size_t)o->ncell);
+    memcpy(f, o->f, sizeof(double) * (size_t)o->q * (size_t)o->ncell);
 }
 
 void ora_get_moments(const ora_sim *o, double *rho, double *u)
@@ -497,13 +531,14 @@ static void collide_stream(ora_sim *o)
                 double uc[3] = {o->u[c], o->u[n + c], o->u[2 * n + c]};
                 double Fc[3] = {o->F[c], o->F[n + c], o->F[2 * n + c]};
                 double feq[ORA_Q];
-                ora_equilibrium(o->rho[c], uc, feq);
-                for (int a = 0; a < ORA_Q; ++a) {
+                ora_equilibrium_q(o->q, o->rho[c], uc, feq);
+                for (int a = 0; a < o->q; ++a) {
+                    const int *e = o->E[a];
                     double fa = o->f[a * n + c];
-                    double eF = E[a][0] * Fc[0] + E[a][1] * Fc[1] + E[a][2] * Fc[2];
-                    double fhat = fa + (feq[a] - fa) / tau + W[a] * 3.0 * eF;
-                    int64_t d = cell_index(o, wrap(x + E[a][0], o->nx), wrap(y + E[a][1], o->ny),
-                                           wrap(z + E[a][2], o->nz));
+                    double eF = e[0] * Fc[0] + e[1] * Fc[1] + e[2] * Fc[2];
+                    double fhat = fa + (feq[a] - fa) / tau + o->W[a] * 3.0 * eF;
+                    int64_t d = cell_index(o, wrap(x + e[0], o->nx), wrap(y + e[1], o->ny),
+                                           wrap(z + e[2], o->nz));
                     o->fnew[a * n + d] = fhat;
                 }
             }

@@ -25,18 +25,21 @@
 extern "C" {
 #endif
 
-#define ORA_Q 19
+#define ORA_Q 19  /* the largest velocity set */
 
 enum { ORA_FRICTION_STOKESLET = 0, ORA_FRICTION_POINTWISE = 1, ORA_FRICTION_BD = 2,
        ORA_FRICTION_STOKESLET_2DX = 3 };
 
 typedef struct ora_sim ora_sim;
 
-/* Lattice tables (velocity e[a][3], weight w[a]). */
+/* Lattice tables (velocity e[a][3], weight w[a]) of the nineteen-velocity set,
+ * or of the set with q = 19 or 15 velocities. */
 void ora_lattice(int32_t e[ORA_Q][3], double w[ORA_Q]);
+void ora_lattice_q(int32_t q, int32_t e[][3], double w[]);
 
-/* Equilibrium of Eq. (s2-eq) for one node. */
+/* Equilibrium of Eq. (s2-eq) for one node (nineteen or q velocities). */
 void ora_equilibrium(double rho, const double u[3], double feq[ORA_Q]);
+void ora_equilibrium_q(int32_t q, double rho, const double u[3], double feq[]);
 
 /* Philox4x32-10 (Salmon et al., SC'11) and the Box-Muller Gaussian triple. */
 void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -51,6 +54,8 @@ void ora_friction_force(int mode, double R, double gamma, const double s[3],
                         const double V[3], const double u8[8][3], double FH[3]);
 
 ora_sim *ora_create(int32_t nx, int32_t ny, int32_t nz, double tau);
+/* Same with the velocity set chosen: q = 19 or 15. */
+ora_sim *ora_create_q(int32_t nx, int32_t ny, int32_t nz, double tau, int32_t q);
 void ora_destroy(ora_sim *o);
 
 /* rho == NULL -> 1 everywhere; u == NULL -> 0 everywhere. */

@@ -238,12 +238,13 @@ def test_first_step_spreading_moments(oracle_mod):
     assert np.allclose(v1, v0 + fh / 10.0, rtol=1e-15)
 
 
-def test_total_momentum_balance(oracle_mod):
+@pytest.mark.parametrize("q", [19, 15])
+def test_total_momentum_balance(oracle_mod, q):
     from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
 
     L = 12
     for kT in (0.0, 1e-4):
-        s = oracle_mod.Sim(L, L, L, 0.8)
+        s = oracle_mod.Sim(L, L, L, 0.8, q=q)
         r = particle_positions(6, L, seed=21)
         v = particle_velocities(6, 1e-4, seed=21)
         s.set_particles(r, v, mass=10.0, gamma=1.0, kT=kT, seed=99)
