@@ -45,7 +45,7 @@ def kernel_source_hash() -> str:
     from paper_1909_13412_amd import build as hip_build
 
     h = hashlib.sha256()
-    for name in ("collide.hpp", "codec.hpp", "d3q19.hpp"):
+    for name in ("collide.hpp", "codec.hpp", "velocities.hpp"):
         h.update(name.encode())
         with open(os.path.join(ROOT, "paper_1909_13412_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())

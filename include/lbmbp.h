@@ -26,11 +26,15 @@
  *     (NULL = the null stream).  Only lbm_observables, lbm_vacf_counts (host
  *     only) and the lbm_get_* queries of host values synchronise; everything
  *     else is asynchronous.
- *   - Velocity order (a = 0..18): 0 rest; 1..6 = +x,-x,+y,-y,+z,-z;
+ *   - Velocity order, D3Q19 (a = 0..18): 0 rest; 1..6 = +x,-x,+y,-y,+z,-z;
  *     7..10 = (+1,+1,0),(-1,-1,0),(+1,-1,0),(-1,+1,0);
  *     11..14 = (+1,0,+1),(-1,0,-1),(+1,0,-1),(-1,0,+1);
  *     15..18 = (0,+1,+1),(0,-1,-1),(0,+1,-1),(0,-1,+1).
  *     Weights 1/3 (rest), 1/18 (axis), 1/36 (diagonal).
+ *     D3Q15 (a = 0..14): 0 rest; 1..6 as above; 7..14 = (+1,+1,+1),(-1,-1,-1),
+ *     (+1,+1,-1),(-1,-1,+1),(+1,-1,+1),(-1,+1,-1),(-1,+1,+1),(+1,-1,-1).
+ *     Weights 2/9 (rest), 1/9 (axis), 1/72 (body diagonal).
+ *     Population arrays hold Q = 19 or 15 planes accordingly.
  *   - Host-visible FP64 field layouts (C order, x fastest):
  *       populations f[19][nz][ny][nx], density rho[nz][ny][nx],
  *       velocity u[3][nz][ny][nx], particles r[n][3], v[n][3].
@@ -47,7 +51,8 @@
 extern "C" {
 #endif
 
-#define LBM_Q 19
+#define LBM_Q 19     /* populations per node of the default set */
+#define LBM_Q15 15   /* populations per node of the fifteen-velocity set */
 
 typedef enum lbm_status {
     LBM_OK = 0,
@@ -88,6 +93,8 @@ typedef struct lbm_grid_desc {
     double tau;              /* BGK relaxation time, > 1/2; nu = (tau - 1/2)/3 (Eq. s2-ident3) */
     int32_t storage;         /* lbm_storage */
     int32_t f16_scale_log2;  /* F16 only: 0..24 (16 recommended); ignored otherwise */
+    int32_t velocities;      /* velocity set: 19 (or 0) = D3Q19, 15 = D3Q15 (section 2.2) */
+    int32_t reserved;        /* must be 0 */
 } lbm_grid_desc;
 
 typedef struct lbm_particle_desc {
@@ -130,7 +137,7 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
  * NULL for 1; u: device FP64 [3][nz][ny][nx] or NULL for 0. */
 lbm_status lbm_set_equilibrium(lbm_ctx *ctx, const double *rho, const double *u);
 
-/* Load the post-streaming populations f^n from device FP64 [19][nz][ny][nx]. */
+/* Load the post-streaming populations f^n from device FP64 [Q][nz][ny][nx]. */
 lbm_status lbm_set_populations(lbm_ctx *ctx, const double *f);
 
 /* Uniform body force G (host array of 3 doubles, force per node in lattice
@@ -140,7 +147,7 @@ lbm_status lbm_set_populations(lbm_ctx *ctx, const double *f);
  * fluid momentum grows by G per node per step. */
 lbm_status lbm_set_body_force(lbm_ctx *ctx, const double *g);
 
-/* Decode the post-streaming populations f^n into device FP64 [19][nz][ny][nx]. */
+/* Decode the post-streaming populations f^n into device FP64 [Q][nz][ny][nx]. */
 lbm_status lbm_get_populations(lbm_ctx *ctx, double *f);
 
 /* Moments of f^n (Eqs. s2-density, s2-fv) into device FP64 rho [nz][ny][nx]

@@ -44,8 +44,15 @@ from . import FRICTION, gauss3, lattice
 
 H = 1e-30  # complex-step size
 
-_E, _W = lattice()
-_E = _E.astype(np.float64)
+_TABLES = {}
+
+
+def _tables(q: int):
+    """(e [q, 3] float, w [q]) of the velocity set with q = 19 or 15."""
+    if q not in _TABLES:
+        e, w = lattice(q)
+        _TABLES[q] = (e.astype(np.float64), w)
+    return _TABLES[q]
 _BITS = np.array([[p & 1, (p >> 1) & 1, (p >> 2) & 1] for p in range(8)], dtype=np.int64)
 
 
@@ -69,23 +76,25 @@ def radius_of(theta, radius: float):
 
 def collide(f, F, tau):
     """Post-collision populations of every node, f + (f^eq - f)/tau + 3 w e.F
-    (Eqs. s2-collision, s2-eq, second Eq. s2-force): f [19, *nodes],
+    (Eqs. s2-collision, s2-eq, second Eq. s2-force): f [q, *nodes],
     F [3, *nodes]."""
+    E, W = _tables(f.shape[0])
     rho = f.sum(axis=0)
-    u = np.tensordot(_E.T, f, axes=(1, 0))           # (3, *nodes)
+    u = np.tensordot(E.T, f, axes=(1, 0))            # (3, *nodes)
     uu = (u * u).sum(axis=0)
-    eu = np.tensordot(_E, u, axes=(1, 0))            # (19, *nodes)
-    wb = _W.reshape((19,) + (1,) * (f.ndim - 1))
+    eu = np.tensordot(E, u, axes=(1, 0))             # (q, *nodes)
+    wb = W.reshape((len(W),) + (1,) * (f.ndim - 1))
     feq = wb * (rho + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu)
-    eF = np.tensordot(_E, F, axes=(1, 0))
+    eF = np.tensordot(E, F, axes=(1, 0))
     return f + (feq - f) / tau + 3.0 * wb * eF
 
 
 def stream(fs):
-    """f_a(x + e_a) <- fs_a(x), periodic: fs [19, nz, ny, nx]."""
+    """f_a(x + e_a) <- fs_a(x), periodic: fs [q, nz, ny, nx]."""
+    E, _ = _tables(fs.shape[0])
     out = np.empty_like(fs)
-    for a in range(19):
-        ex, ey, ez = (int(v) for v in _E[a])
+    for a in range(fs.shape[0]):
+        ex, ey, ez = (int(v) for v in E[a])
         out[a] = np.roll(fs[a], shift=(ez, ey, ex), axis=(0, 1, 2))
     return out
 
@@ -126,7 +135,7 @@ def fit_corners(r, shape):
 def particle_update(f8, V, r, theta, xi, c, shape, friction: int, radius: float, fc=None,
                     cfit=None):
     """One particle's step as a function of the populations at its eight
-    fitting nodes.  Batch axes lead: f8 [B, 8, 19], V, r [B, 3], theta [B, 4],
+    fitting nodes.  Batch axes lead: f8 [B, 8, q], V, r [B, 3], theta [B, 4],
     xi [3]; c [3] is the corner cell (fixed, the spreading nodes); cfit [3] the
     (2 dx)^3 cube's first corner for the wide Stokeslet fit (f8 then holds
     those corners); fc [3] a given force F_C on the particle (None: zero).
@@ -139,7 +148,7 @@ def particle_update(f8, V, r, theta, xi, c, shape, friction: int, radius: float,
     d = (c + _BITS)[None, :, :] - s[:, None, :]       # [B, 8, 3] node minus particle
     t = np.where(_BITS[None] == 0, 1.0 + d, 1.0 - d)  # 1 - |d| inside the cell
     Wt = t[..., 0] * t[..., 1] * t[..., 2]            # [B, 8]
-    u8 = np.einsum("bpa,ak->bpk", f8, _E)              # velocity moment at each node
+    u8 = np.einsum("bpa,ak->bpk", f8, _tables(f8.shape[-1])[0])  # velocity at each node
     if friction == FRICTION["stokeslet2dx"]:
         d = (cfit + 2 * _BITS)[None, :, :] - s[:, None, :]
     if friction == FRICTION["bd"]:
@@ -199,9 +208,9 @@ def step(f, r, V, theta, xi_k, friction: int, radius: float, fc=None, body=None)
     if n:
         c, node = corners(r, shape)
         cfit, nfit = fit_corners(r, shape) if friction == FRICTION["stokeslet2dx"] else (c, node)
-        fl = f.reshape(19, ncell)
+        fl = f.reshape(f.shape[0], ncell)
         for i in range(n):
-            f8 = fl[:, nfit[i]].T[None]                   # [1, 8, 19]
+            f8 = fl[:, nfit[i]].T[None]                   # [1, 8, q]
             v1, r1, sp = particle_update(f8, V[i][None], r[i][None], theta[None], xi_k[i], c[i],
                                          shape, friction, radius, None if fc is None else fc[i],
                                          cfit[i])
@@ -250,18 +259,20 @@ def vjp(f0, r0, V0, theta, xi, cf, cr, cV, friction="stokeslet", radius=0.0, fc=
     gr = np.array(cr, dtype=np.float64)
     gV = np.array(cV, dtype=np.float64)
     gth = np.zeros(4)
-    eye19 = np.eye(19)
+    q = f0.shape[0]
+    E, _ = _tables(q)
+    eyeq = np.eye(q)
     for k in range(len(xi) - 1, -1, -1):
         f, r, V, F = traj[k]
         # streaming: f^{n+1}_a(x + e_a) = fs_a(x)  =>  gfs_a(x) = gf_a(x + e_a)
         gfs = np.empty_like(gf)
-        for a in range(19):
-            ex, ey, ez = (int(v) for v in _E[a])
+        for a in range(q):
+            ex, ey, ez = (int(v) for v in E[a])
             gfs[a] = np.roll(gf[a], shift=(-ez, -ey, -ex), axis=(0, 1, 2))
         # collision, node by node: columns of d fs / d f by the complex step
         gfn = np.zeros_like(gf)
-        for b in range(19):
-            pert = f + 1j * H * eye19[b].reshape(19, 1, 1, 1)
+        for b in range(q):
+            pert = f + 1j * H * eyeq[b].reshape(q, 1, 1, 1)
             col = np.imag(collide(pert, F.astype(complex), theta[1])) / H   # d fs_a / d f_b
             gfn[b] = (col * gfs).sum(axis=0)
         gF = np.zeros((3,) + shape)
@@ -278,29 +289,31 @@ def vjp(f0, r0, V0, theta, xi, cf, cr, cV, friction="stokeslet", radius=0.0, fc=
             c, node = corners(r, shape)
             wide = fr_mode == FRICTION["stokeslet2dx"]
             cfit, nfit = fit_corners(r, shape) if wide else (c, node)
-            fl = f.reshape(19, ncell)
+            fl = f.reshape(q, ncell)
             gFl = gF.reshape(3, ncell)
-            gfl = gfn.reshape(19, ncell)
+            gfl = gfn.reshape(q, ncell)
             new_gr = np.zeros_like(gr)
             new_gV = np.zeros_like(gV)
             for i in range(n):
-                f8 = fl[:, nfit[i]].T                      # [8, 19]
-                nin = 8 * 19 + 3 + 3 + 4
+                f8 = fl[:, nfit[i]].T                      # [8, q]
+                nq = 8 * q
+                nin = nq + 3 + 3 + 4
                 base = np.concatenate([f8.ravel(), V[i], r[i], theta]).astype(complex)
                 X = np.tile(base, (nin, 1)) + 1j * H * np.eye(nin)
-                v1, r1, sp = particle_update(X[:, :152].reshape(nin, 8, 19), X[:, 152:155],
-                                             X[:, 155:158], X[:, 158:162], xi[k][i], c[i], shape,
+                v1, r1, sp = particle_update(X[:, :nq].reshape(nin, 8, q), X[:, nq:nq + 3],
+                                             X[:, nq + 3:nq + 6], X[:, nq + 6:nq + 10], xi[k][i],
+                                             c[i], shape,
                                              fr_mode, radius, None if fc is None else fc[i],
                                              cfit[i])
                 jv, jr, jsp = np.imag(v1) / H, np.imag(r1) / H, np.imag(sp) / H
                 ybar_sp = gFl[:, node[i]].T                # [8, 3] gradient of each node force
                 xbar = jv @ gV[i] + jr @ gr[i] + np.einsum("bpk,pk->b", jsp, ybar_sp)
-                g8 = xbar[:152].reshape(8, 19)
+                g8 = xbar[:nq].reshape(8, q)
                 for p in range(8):
                     gfl[:, nfit[i, p]] += g8[p]
-                new_gV[i] = xbar[152:155]
-                new_gr[i] = xbar[155:158]
-                gth += xbar[158:162]
+                new_gV[i] = xbar[nq:nq + 3]
+                new_gr[i] = xbar[nq + 3:nq + 6]
+                gth += xbar[nq + 6:nq + 10]
             gr, gV = new_gr, new_gV
         gf = gfn
     return gf, gr, gV, gth

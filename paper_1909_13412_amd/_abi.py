@@ -33,7 +33,8 @@ LBM_NUM_SHAPES = 4
 class GridDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("tau", ctypes.c_double), ("storage", ctypes.c_int32),
-                ("f16_scale_log2", ctypes.c_int32)]
+                ("f16_scale_log2", ctypes.c_int32), ("velocities", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class ParticleDesc(ctypes.Structure):

@@ -33,7 +33,7 @@
 #include "lbmbp.h"
 #include "codec.hpp"
 #include "collide.hpp"
-#include "d3q19.hpp"
+#include "velocities.hpp"
 #include "particle.hpp"
 #include "philox.hpp"
 
@@ -63,16 +63,16 @@ struct AdjParticleArgs {
 };
 
 // Storage index of population a at node x + e_a (the streaming target of x).
-template <int a>
+template <class Vs, int a>
 __device__ inline uint64_t push_index(const Neighbours &nb, const Grid &g) {
-    return pop_index(g, nb.sx[1 - D3Q19::ex[a]], nb.sy[1 - D3Q19::ey[a]], nb.sz[1 - D3Q19::ez[a]],
-                     a);
+    return pop_index<Vs>(g, nb.sx[1 - Vs::ex[a]], nb.sy[1 - Vs::ey[a]], nb.sz[1 - Vs::ez[a]], a);
 }
 
 template <class C>
 __global__ __launch_bounds__(kParticleBlock) void k_adj_particle(
     const typename C::T *__restrict__ A, Grid g, typename C::R dec_s,
     const double *__restrict__ Abar, Grid gd, AdjParticleArgs pa, AdjField cur, AdjField old) {
+    using Vs = typename C::V;
     const uint32_t gt = blockIdx.x * kParticleBlock + threadIdx.x;
     const int32_t i = int32_t(gt >> 3);
     const int p = int(gt & 7u);
@@ -118,22 +118,22 @@ __global__ __launch_bounds__(kParticleBlock) void k_adj_particle(
     if (coupled) {
         const Neighbours nf(fnode[0], fnode[1], fnode[2], g);
         const Neighbours nb(node[0], node[1], node[2], g);
-        static_for<1, D3Q19::Q>([&](auto ac) {
+        static_for<1, Vs::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            const double gvl = double(C::dec(A[nf.pop<a>(g)], dec_s));
-            const double fs = Abar[push_index<a>(nb, gd)];
-            const double w3 = 3.0 * D3Q19::w<double>(a);
-            if constexpr (D3Q19::ex[a] != 0) {
-                u[0] += D3Q19::ex[a] > 0 ? gvl : -gvl;
-                Fb[0] += D3Q19::ex[a] > 0 ? w3 * fs : -w3 * fs;
+            const double gvl = double(C::dec(A[nf.template pop<Vs, a>(g)], dec_s));
+            const double fs = Abar[push_index<Vs, a>(nb, gd)];
+            const double w3 = 3.0 * Vs::template w<double>(a);
+            if constexpr (Vs::ex[a] != 0) {
+                u[0] += Vs::ex[a] > 0 ? gvl : -gvl;
+                Fb[0] += Vs::ex[a] > 0 ? w3 * fs : -w3 * fs;
             }
-            if constexpr (D3Q19::ey[a] != 0) {
-                u[1] += D3Q19::ey[a] > 0 ? gvl : -gvl;
-                Fb[1] += D3Q19::ey[a] > 0 ? w3 * fs : -w3 * fs;
+            if constexpr (Vs::ey[a] != 0) {
+                u[1] += Vs::ey[a] > 0 ? gvl : -gvl;
+                Fb[1] += Vs::ey[a] > 0 ? w3 * fs : -w3 * fs;
             }
-            if constexpr (D3Q19::ez[a] != 0) {
-                u[2] += D3Q19::ez[a] > 0 ? gvl : -gvl;
-                Fb[2] += D3Q19::ez[a] > 0 ? w3 * fs : -w3 * fs;
+            if constexpr (Vs::ez[a] != 0) {
+                u[2] += Vs::ez[a] > 0 ? gvl : -gvl;
+                Fb[2] += Vs::ez[a] > 0 ? w3 * fs : -w3 * fs;
             }
         });
     }
@@ -301,6 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(const typename C::T *__r
                                                         double *__restrict__ Bbar, Grid gd,
                                                         double omega, AdjField uf,
                                                         double *__restrict__ wacc) {
+    using Vs = typename C::V;
     const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
     double wsum = 0.0;
     if (cell < g.ncell) {
@@ -309,28 +310,28 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(const typename C::T *__r
         const uint32_t y = t % g.ny;
         const uint32_t z = t / g.ny;
         const Neighbours nb(x, y, z, g);
-        double gv[D3Q19::Q], fs[D3Q19::Q];
-        static_for<0, D3Q19::Q>([&](auto ac) {
+        double gv[Vs::Q], fs[Vs::Q];
+        static_for<0, Vs::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            gv[a] = double(C::dec(A[nb.pop<a>(g)], dec_s));
-            fs[a] = Abar[push_index<a>(nb, gd)];
+            gv[a] = double(C::dec(A[nb.template pop<Vs, a>(g)], dec_s));
+            fs[a] = Abar[push_index<Vs, a>(nb, gd)];
         });
         bool flagged = false;
         if constexpr (FORCED) flagged = (uf.mask[cell >> 5] >> (cell & 31)) & 1u;
         double drho = 0.0, ux = 0.0, uy = 0.0, uz = 0.0;
-        static_for<0, D3Q19::Q>([&](auto ac) {
+        static_for<0, Vs::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
             drho += gv[a];
-            if constexpr (D3Q19::ex[a] != 0) ux += D3Q19::ex[a] > 0 ? gv[a] : -gv[a];
-            if constexpr (D3Q19::ey[a] != 0) uy += D3Q19::ey[a] > 0 ? gv[a] : -gv[a];
-            if constexpr (D3Q19::ez[a] != 0) uz += D3Q19::ez[a] > 0 ? gv[a] : -gv[a];
+            if constexpr (Vs::ex[a] != 0) ux += Vs::ex[a] > 0 ? gv[a] : -gv[a];
+            if constexpr (Vs::ey[a] != 0) uy += Vs::ey[a] > 0 ? gv[a] : -gv[a];
+            if constexpr (Vs::ez[a] != 0) uz += Vs::ez[a] > 0 ? gv[a] : -gv[a];
         });
         const double uu = ux * ux + uy * uy + uz * uz;
         double P = 0.0, Qx = 0.0, Qy = 0.0, Qz = 0.0, Tx = 0.0, Ty = 0.0, Tz = 0.0;
-        static_for<0, D3Q19::Q>([&](auto ac) {
+        static_for<0, Vs::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            constexpr int cx = D3Q19::ex[a], cy = D3Q19::ey[a], cz = D3Q19::ez[a];
-            const double w = D3Q19::w<double>(a);
+            constexpr int cx = Vs::ex[a], cy = Vs::ey[a], cz = Vs::ez[a];
+            const double w = Vs::template w<double>(a);
             const double eu = double(cx) * ux + double(cy) * uy + double(cz) * uz;
             const double geq = w * (drho + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
             wsum += fs[a] * (geq - gv[a]);
@@ -354,10 +355,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(const typename C::T *__r
         const double Gx = 3.0 * Qx + 9.0 * Tx - 3.0 * P * ux;
         const double Gy = 3.0 * Qy + 9.0 * Ty - 3.0 * P * uy;
         const double Gz = 3.0 * Qz + 9.0 * Tz - 3.0 * P * uz;
-        const uint64_t row_base = uint64_t(z * g.ny + y) * D3Q19::Q * gd.chunk + x;
-        static_for<0, D3Q19::Q>([&](auto ac) {
+        const uint64_t row_base = uint64_t(z * g.ny + y) * Vs::Q * gd.chunk + x;
+        static_for<0, Vs::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            constexpr int cx = D3Q19::ex[a], cy = D3Q19::ey[a], cz = D3Q19::ez[a];
+            constexpr int cx = Vs::ex[a], cy = Vs::ey[a], cz = Vs::ez[a];
             double out = (1.0 - omega) * fs[a] +
                          omega * (P + double(cx) * Gx + double(cy) * Gy + double(cz) * Gz);
             if constexpr (FORCED) out += double(cx) * Ux + double(cy) * Uy + double(cz) * Uz;
@@ -377,22 +378,24 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(const typename C::T *__r
 }
 
 // Canonical FP64 [19][nz][ny][nx] <-> adjoint lattice (interleaved rows).
+template <class Vs>
 __global__ __launch_bounds__(kBlock) void k_adj_import(const double *__restrict__ canon,
                                                        double *__restrict__ Abar, Grid gd) {
     const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
     if (cell >= gd.ncell) return;
     const uint32_t x = cell % gd.nx, t = cell / gd.nx, y = t % gd.ny, z = t / gd.ny;
-    for (int a = 0; a < D3Q19::Q; ++a)
-        Abar[pop_index(gd, x, y, z, a)] = canon[uint64_t(a) * gd.ncell + cell];
+    for (int a = 0; a < Vs::Q; ++a)
+        Abar[pop_index<Vs>(gd, x, y, z, a)] = canon[uint64_t(a) * gd.ncell + cell];
 }
 
+template <class Vs>
 __global__ __launch_bounds__(kBlock) void k_adj_export(const double *__restrict__ Abar,
                                                        double *__restrict__ canon, Grid gd) {
     const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
     if (cell >= gd.ncell) return;
     const uint32_t x = cell % gd.nx, t = cell / gd.nx, y = t % gd.ny, z = t / gd.ny;
-    for (int a = 0; a < D3Q19::Q; ++a)
-        canon[uint64_t(a) * gd.ncell + cell] = Abar[pop_index(gd, x, y, z, a)];
+    for (int a = 0; a < Vs::Q; ++a)
+        canon[uint64_t(a) * gd.ncell + cell] = Abar[pop_index<Vs>(gd, x, y, z, a)];
 }
 
 // dJ/d(gamma, tau, M, kT): per-particle running sums plus the collision's

@@ -1,4 +1,4 @@
-// Fused pull stream-collide of the D3Q19 BGK lattice with sparse node forcing
+// Fused pull stream-collide of the BGK lattice with sparse node forcing
 // (section 2.2: Eqs. s2-lbe, s2-collision, s2-eq, s2-coll, s2-trans and the
 // second Eq. s2-force), and the data layout it streams.
 //
@@ -17,7 +17,7 @@
 #include <type_traits>
 
 #include "codec.hpp"
-#include "d3q19.hpp"
+#include "velocities.hpp"
 
 namespace lbmbp {
 
@@ -36,9 +36,10 @@ struct Grid {
     uint32_t chunk;  // elements per population row (nx padded to a 128-byte line)
 };
 
-// Storage index of population a at node (x, y, z).
+// Storage index of population a at node (x, y, z) for velocity set V.
+template <class V>
 __device__ inline uint64_t pop_index(const Grid &g, uint32_t x, uint32_t y, uint32_t z, int a) {
-    return (uint64_t(z * g.ny + y) * D3Q19::Q + uint32_t(a)) * g.chunk + x;
+    return (uint64_t(z * g.ny + y) * V::Q + uint32_t(a)) * g.chunk + x;
 }
 
 // Node forces of one step: a dense fixed-point field, written only at the
@@ -66,14 +67,14 @@ struct Neighbours {
         sz[2] = (z == 0) ? g.nz - 1 : z - 1;
     }
     // linear node index of x - e_a (canonical [z][y][x] order)
-    template <int a>
+    template <class V, int a>
     __device__ inline uint32_t src(const Grid &g) const {
-        return (sz[D3Q19::ez[a] + 1] * g.ny + sy[D3Q19::ey[a] + 1]) * g.nx + sx[D3Q19::ex[a] + 1];
+        return (sz[V::ez[a] + 1] * g.ny + sy[V::ey[a] + 1]) * g.nx + sx[V::ex[a] + 1];
     }
     // storage index of population a at x - e_a
-    template <int a>
+    template <class V, int a>
     __device__ inline uint64_t pop(const Grid &g) const {
-        return pop_index(g, sx[D3Q19::ex[a] + 1], sy[D3Q19::ey[a] + 1], sz[D3Q19::ez[a] + 1], a);
+        return pop_index<V>(g, sx[V::ex[a] + 1], sy[V::ey[a] + 1], sz[V::ez[a] + 1], a);
     }
 };
 
@@ -126,21 +127,22 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
                                     typename C::R Gz, uint32_t lane_cell, double (&acc)[4]) {
     using T = typename C::T;
     using R = typename C::R;
+    using V = typename C::V;
     const uint32_t x = lane_cell % g.nx;
     const uint32_t t = lane_cell / g.nx;
     const uint32_t rows = g.ny / CPT;
     const uint32_t y0 = t % rows;
     const uint32_t z = t / rows;
 
-    T raw[CPT][D3Q19::Q];
+    T raw[CPT][V::Q];
     uint32_t flags[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const uint32_t y = y0 + uint32_t(c) * rows;
         const Neighbours nb(x, y, z, g);
-        static_for<0, D3Q19::Q>([&](auto ac) {
+        static_for<0, V::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            raw[c][a] = A[nb.pop<a>(g)];
+            raw[c][a] = A[nb.template pop<V, a>(g)];
         });
         if constexpr (FORCED) {
             const uint32_t cell = (z * g.ny + y) * g.nx + x;
@@ -150,18 +152,18 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const uint32_t y = y0 + uint32_t(c) * rows;
-        R gv[D3Q19::Q];
-        static_for<0, D3Q19::Q>([&](auto ac) {
+        R gv[V::Q];
+        static_for<0, V::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
             gv[a] = C::dec(raw[c][a], dec_s);
         });
         R drho = R(0), ux = R(0), uy = R(0), uz = R(0);
-        static_for<0, D3Q19::Q>([&](auto ac) {
+        static_for<0, V::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
             drho += gv[a];
-            if constexpr (D3Q19::ex[a] != 0) ux += D3Q19::ex[a] > 0 ? gv[a] : -gv[a];
-            if constexpr (D3Q19::ey[a] != 0) uy += D3Q19::ey[a] > 0 ? gv[a] : -gv[a];
-            if constexpr (D3Q19::ez[a] != 0) uz += D3Q19::ez[a] > 0 ? gv[a] : -gv[a];
+            if constexpr (V::ex[a] != 0) ux += V::ex[a] > 0 ? gv[a] : -gv[a];
+            if constexpr (V::ey[a] != 0) uy += V::ey[a] > 0 ? gv[a] : -gv[a];
+            if constexpr (V::ez[a] != 0) uz += V::ez[a] > 0 ? gv[a] : -gv[a];
         });
         const R uu = ux * ux + uy * uy + uz * uz;
         if constexpr (MOMENTS) {
@@ -179,11 +181,11 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
                 Fz += R(double(ff.f[3 * cell + 2]) * kFixInv);
             }
         }
-        const uint64_t row_base = uint64_t(z * g.ny + y) * D3Q19::Q * g.chunk + x;
-        static_for<0, D3Q19::Q>([&](auto ac) {
+        const uint64_t row_base = uint64_t(z * g.ny + y) * V::Q * g.chunk + x;
+        static_for<0, V::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            constexpr int cx = D3Q19::ex[a], cy = D3Q19::ey[a], cz = D3Q19::ez[a];
-            const R w = D3Q19::w<R>(a);
+            constexpr int cx = V::ex[a], cy = V::ey[a], cz = V::ez[a];
+            const R w = V::template w<R>(a);
             const R eu = R(cx) * ux + R(cy) * uy + R(cz) * uz;
             const R geq = w * (drho + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
             R gn = gv[a] + omega * (geq - gv[a]);

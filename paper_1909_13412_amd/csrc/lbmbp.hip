@@ -30,7 +30,7 @@
 #include "adjoint.hpp"
 #include "codec.hpp"
 #include "collide.hpp"
-#include "d3q19.hpp"
+#include "velocities.hpp"
 #include "particle.hpp"
 #include "philox.hpp"
 
@@ -165,14 +165,15 @@ template <class C>
 __global__ __launch_bounds__(kBlock) void k_get_populations(const typename C::T *__restrict__ A,
                                                             Grid g, typename C::R dec_s,
                                                             double *__restrict__ f) {
+    using Vs = typename C::V;
     const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
     if (cell >= g.ncell) return;
     const uint32_t x = cell % g.nx, t = cell / g.nx, y = t % g.ny, z = t / g.ny;
     const Neighbours nb(x, y, z, g);
-    static_for<0, D3Q19::Q>([&](auto ac) {
+    static_for<0, Vs::Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         f[uint64_t(a) * g.ncell + cell] =
-            double(C::dec(A[nb.pop<a>(g)], dec_s)) + D3Q19::w<double>(a);
+            double(C::dec(A[nb.template pop<Vs, a>(g)], dec_s)) + Vs::template w<double>(a);
     });
 }
 
@@ -181,18 +182,19 @@ __global__ __launch_bounds__(kBlock) void k_get_moments(const typename C::T *__r
                                                         Grid g, typename C::R dec_s,
                                                         double *__restrict__ rho,
                                                         double *__restrict__ u) {
+    using Vs = typename C::V;
     const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
     if (cell >= g.ncell) return;
     const uint32_t x = cell % g.nx, t = cell / g.nx, y = t % g.ny, z = t / g.ny;
     const Neighbours nb(x, y, z, g);
     double dr = 0.0, m[3] = {0.0, 0.0, 0.0};
-    static_for<0, D3Q19::Q>([&](auto ac) {
+    static_for<0, Vs::Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
-        const double gvl = double(C::dec(A[nb.pop<a>(g)], dec_s));
+        const double gvl = double(C::dec(A[nb.template pop<Vs, a>(g)], dec_s));
         dr += gvl;
-        m[0] += D3Q19::ex[a] * gvl;
-        m[1] += D3Q19::ey[a] * gvl;
-        m[2] += D3Q19::ez[a] * gvl;
+        m[0] += Vs::ex[a] * gvl;
+        m[1] += Vs::ey[a] * gvl;
+        m[2] += Vs::ez[a] * gvl;
     });
     if (rho) rho[cell] = 1.0 + dr;
     if (u) {
@@ -208,15 +210,16 @@ template <class C>
 __global__ __launch_bounds__(kBlock) void k_set_populations(const double *__restrict__ f,
                                                             typename C::T *__restrict__ A, Grid g,
                                                             typename C::R enc_s) {
+    using Vs = typename C::V;
     const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
     if (cell >= g.ncell) return;
     const uint32_t x = cell % g.nx, t = cell / g.nx, y = t % g.ny, z = t / g.ny;
     const Neighbours nb(x, y, z, g);  // nb.src of the opposite direction is y + e_a
-    static_for<0, D3Q19::Q>([&](auto ac) {
+    static_for<0, Vs::Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         constexpr int o = (a == 0) ? 0 : ((a & 1) ? a + 1 : a - 1);
-        const double gvl = f[uint64_t(a) * g.ncell + nb.src<o>(g)] - D3Q19::w<double>(a);
-        A[pop_index(g, x, y, z, a)] = C::enc(typename C::R(gvl), enc_s);
+        const double gvl = f[uint64_t(a) * g.ncell + nb.template src<Vs, o>(g)] - Vs::template w<double>(a);
+        A[pop_index<Vs>(g, x, y, z, a)] = C::enc(typename C::R(gvl), enc_s);
     });
 }
 
@@ -225,14 +228,15 @@ __global__ __launch_bounds__(kBlock) void k_set_equilibrium(const double *__rest
                                                             const double *__restrict__ u,
                                                             typename C::T *__restrict__ A, Grid g,
                                                             typename C::R enc_s) {
+    using Vs = typename C::V;
     const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
     if (cell >= g.ncell) return;
     const uint32_t x = cell % g.nx, t = cell / g.nx, y = t % g.ny, z = t / g.ny;
     const Neighbours nb(x, y, z, g);
-    static_for<0, D3Q19::Q>([&](auto ac) {
+    static_for<0, Vs::Q>([&](auto ac) {
         constexpr int a = decltype(ac)::value;
         constexpr int o = (a == 0) ? 0 : ((a & 1) ? a + 1 : a - 1);
-        const uint32_t src = nb.src<o>(g);  // node y + e_a
+        const uint32_t src = nb.template src<Vs, o>(g);  // node y + e_a
         const double dr = rho ? rho[src] - 1.0 : 0.0;
         double uc[3] = {0.0, 0.0, 0.0};
         if (u) {
@@ -240,10 +244,10 @@ __global__ __launch_bounds__(kBlock) void k_set_equilibrium(const double *__rest
             uc[1] = u[uint64_t(g.ncell) + src];
             uc[2] = u[2 * uint64_t(g.ncell) + src];
         }
-        const double eu = D3Q19::ex[a] * uc[0] + D3Q19::ey[a] * uc[1] + D3Q19::ez[a] * uc[2];
+        const double eu = Vs::ex[a] * uc[0] + Vs::ey[a] * uc[1] + Vs::ez[a] * uc[2];
         const double uu = uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2];
-        const double geq = D3Q19::w<double>(a) * (dr + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-        A[pop_index(g, x, y, z, a)] = C::enc(typename C::R(geq), enc_s);
+        const double geq = Vs::template w<double>(a) * (dr + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+        A[pop_index<Vs>(g, x, y, z, a)] = C::enc(typename C::R(geq), enc_s);
     });
 }
 
@@ -253,19 +257,20 @@ template <class C>
 __global__ __launch_bounds__(kBlock) void k_fluid_partials(const typename C::T *__restrict__ A,
                                                            Grid g, typename C::R dec_s,
                                                            double *__restrict__ partials) {
+    using Vs = typename C::V;
     __shared__ double sh[4][kBlock];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (uint32_t cell = blockIdx.x * kBlock + threadIdx.x; cell < g.ncell;
          cell += gridDim.x * kBlock) {
         const uint32_t x = cell % g.nx, t = cell / g.nx, y = t % g.ny, z = t / g.ny;
         const Neighbours nb(x, y, z, g);
-        static_for<0, D3Q19::Q>([&](auto ac) {
+        static_for<0, Vs::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            const double gvl = double(C::dec(A[nb.pop<a>(g)], dec_s));
+            const double gvl = double(C::dec(A[nb.template pop<Vs, a>(g)], dec_s));
             acc[0] += gvl;
-            acc[1] += D3Q19::ex[a] * gvl;
-            acc[2] += D3Q19::ey[a] * gvl;
-            acc[3] += D3Q19::ez[a] * gvl;
+            acc[1] += Vs::ex[a] * gvl;
+            acc[2] += Vs::ey[a] * gvl;
+            acc[3] += Vs::ez[a] * gvl;
         });
     }
     for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
@@ -312,6 +317,7 @@ using namespace lbmbp;
 struct lbm_ctx {
     lbm_grid_desc desc;
     Grid g;
+    int q;  // velocity set: 19 or 15
     size_t elem;
     void *pop[2];  // pop[cur] holds post-collision values of the last step
     int cur;
@@ -378,6 +384,8 @@ size_t elem_size(int storage) {
     }
 }
 
+int velocity_count(const lbm_grid_desc *g) { return g->velocities == 15 ? 15 : 19; }
+
 bool grid_ok(const lbm_grid_desc *g) {
     if (!g) return false;
     if (g->nx < 2 || g->ny < 2 || g->nz < 2) return false;
@@ -386,6 +394,8 @@ bool grid_ok(const lbm_grid_desc *g) {
     if (!(g->tau > 0.5) || !isfinite(g->tau)) return false;
     if (elem_size(g->storage) == 0) return false;
     if (g->storage == LBM_STORE_F16 && (g->f16_scale_log2 < 0 || g->f16_scale_log2 > 24)) return false;
+    if (g->velocities != 0 && g->velocities != 19 && g->velocities != 15) return false;
+    if (g->reserved != 0) return false;
     return true;
 }
 
@@ -656,14 +666,33 @@ void launch_partials(lbm_ctx *c) {
                        typename C::R(c->dec_s), c->partials);
 }
 
-#define LBM_DISPATCH(ctx, FN, ...)                                            \
-    do {                                                                      \
-        switch ((ctx)->desc.storage) {                                        \
-            case LBM_STORE_F64: FN<CodecF64>(ctx, ##__VA_ARGS__); break;      \
-            case LBM_STORE_F32: FN<CodecF32>(ctx, ##__VA_ARGS__); break;      \
-            case LBM_STORE_BF16: FN<CodecBF16>(ctx, ##__VA_ARGS__); break;    \
-            case LBM_STORE_F16: FN<CodecF16>(ctx, ##__VA_ARGS__); break;      \
-        }                                                                     \
+// The storage codec x velocity set combinations the library instantiates.
+using F64Q19 = Cfg<CodecF64, D3Q19>;
+using F32Q19 = Cfg<CodecF32, D3Q19>;
+using BF16Q19 = Cfg<CodecBF16, D3Q19>;
+using F16Q19 = Cfg<CodecF16, D3Q19>;
+using F64Q15 = Cfg<CodecF64, D3Q15>;
+using F32Q15 = Cfg<CodecF32, D3Q15>;
+using BF16Q15 = Cfg<CodecBF16, D3Q15>;
+using F16Q15 = Cfg<CodecF16, D3Q15>;
+
+#define LBM_DISPATCH(ctx, FN, ...)                                                      \
+    do {                                                                                \
+        if ((ctx)->q == 15) {                                                           \
+            switch ((ctx)->desc.storage) {                                              \
+                case LBM_STORE_F64: FN<F64Q15>(ctx, ##__VA_ARGS__); break;              \
+                case LBM_STORE_F32: FN<F32Q15>(ctx, ##__VA_ARGS__); break;              \
+                case LBM_STORE_BF16: FN<BF16Q15>(ctx, ##__VA_ARGS__); break;            \
+                case LBM_STORE_F16: FN<F16Q15>(ctx, ##__VA_ARGS__); break;              \
+            }                                                                           \
+        } else {                                                                        \
+            switch ((ctx)->desc.storage) {                                              \
+                case LBM_STORE_F64: FN<F64Q19>(ctx, ##__VA_ARGS__); break;              \
+                case LBM_STORE_F32: FN<F32Q19>(ctx, ##__VA_ARGS__); break;              \
+                case LBM_STORE_BF16: FN<BF16Q19>(ctx, ##__VA_ARGS__); break;            \
+                case LBM_STORE_F16: FN<F16Q19>(ctx, ##__VA_ARGS__); break;              \
+            }                                                                           \
+        }                                                                               \
     } while (0)
 
 }  // namespace
@@ -672,7 +701,8 @@ extern "C" {
 
 lbm_status lbm_lattice_bytes(const lbm_grid_desc *grid, size_t *bytes) {
     if (!grid_ok(grid) || !bytes) return LBM_E_INVAL;
-    *bytes = align_up(size_t(row_chunk(grid)) * LBM_Q * size_t(grid->ny) * size_t(grid->nz) *
+    *bytes = align_up(size_t(row_chunk(grid)) * size_t(velocity_count(grid)) * size_t(grid->ny) *
+                          size_t(grid->nz) *
                           elem_size(grid->storage),
                       kAlign);
     return LBM_OK;
@@ -709,6 +739,7 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
     c->g.nz = uint32_t(grid->nz);
     c->g.ncell = uint32_t(ncell_of(grid));
     c->g.chunk = row_chunk(grid);
+    c->q = velocity_count(grid);
     c->elem = elem_size(grid->storage);
     c->pop[0] = pop_a;
     c->pop[1] = pop_b;
@@ -952,12 +983,7 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen
     if (!ctx || iters < 1 || iters > 10000) return LBM_E_INVAL;
     double t[kNumShapes];
     hipError_t err = hipSuccess;
-    switch (ctx->desc.storage) {
-        case LBM_STORE_F64: time_shapes<CodecF64>(ctx, iters, t, &err); break;
-        case LBM_STORE_F32: time_shapes<CodecF32>(ctx, iters, t, &err); break;
-        case LBM_STORE_BF16: time_shapes<CodecBF16>(ctx, iters, t, &err); break;
-        case LBM_STORE_F16: time_shapes<CodecF16>(ctx, iters, t, &err); break;
-    }
+    LBM_DISPATCH(ctx, time_shapes, iters, t, &err);
     if (err != hipSuccess || launch_status() != LBM_OK) return LBM_E_DEVICE;
     int best = 0;
     for (int k = 0; k < kNumShapes; ++k)
@@ -1205,10 +1231,10 @@ void ens_launch_step(lbm_ens *e, int cur, int par) {
 
 void ens_dispatch_step(lbm_ens *e, int cur, int par) {
     switch (e->desc.storage) {
-        case LBM_STORE_F64: ens_launch_step<CodecF64>(e, cur, par); break;
-        case LBM_STORE_F32: ens_launch_step<CodecF32>(e, cur, par); break;
-        case LBM_STORE_BF16: ens_launch_step<CodecBF16>(e, cur, par); break;
-        case LBM_STORE_F16: ens_launch_step<CodecF16>(e, cur, par); break;
+        case LBM_STORE_F64: ens_launch_step<F64Q19>(e, cur, par); break;
+        case LBM_STORE_F32: ens_launch_step<F32Q19>(e, cur, par); break;
+        case LBM_STORE_BF16: ens_launch_step<BF16Q19>(e, cur, par); break;
+        case LBM_STORE_F16: ens_launch_step<F16Q19>(e, cur, par); break;
     }
 }
 
@@ -1274,10 +1300,10 @@ void ens_time_dispatch(lbm_ens *e, int k) {
 
 void ens_time_any(lbm_ens *e, int k) {
     switch (e->desc.storage) {
-        case LBM_STORE_F64: ens_time_dispatch<CodecF64>(e, k); break;
-        case LBM_STORE_F32: ens_time_dispatch<CodecF32>(e, k); break;
-        case LBM_STORE_BF16: ens_time_dispatch<CodecBF16>(e, k); break;
-        case LBM_STORE_F16: ens_time_dispatch<CodecF16>(e, k); break;
+        case LBM_STORE_F64: ens_time_dispatch<F64Q19>(e, k); break;
+        case LBM_STORE_F32: ens_time_dispatch<F32Q19>(e, k); break;
+        case LBM_STORE_BF16: ens_time_dispatch<BF16Q19>(e, k); break;
+        case LBM_STORE_F16: ens_time_dispatch<F16Q19>(e, k); break;
     }
 }
 
@@ -1538,10 +1564,10 @@ lbm_status lbm_ens_observables(lbm_ens *e, int32_t replica, double out[7]) {
     hipLaunchKernelGGL(k_fluid_partials<CODEC>, dim3(kRedBlocks), dim3(kBlock), 0, e->stream, \
                        reinterpret_cast<const CODEC::T *>(A), t.g, CODEC::R(e->dec_s),          \
                        e->partials)
-        case LBM_STORE_F64: LBM_ENS_PARTIALS(CodecF64); break;
-        case LBM_STORE_F32: LBM_ENS_PARTIALS(CodecF32); break;
-        case LBM_STORE_BF16: LBM_ENS_PARTIALS(CodecBF16); break;
-        case LBM_STORE_F16: LBM_ENS_PARTIALS(CodecF16); break;
+        case LBM_STORE_F64: LBM_ENS_PARTIALS(F64Q19); break;
+        case LBM_STORE_F32: LBM_ENS_PARTIALS(F32Q19); break;
+        case LBM_STORE_BF16: LBM_ENS_PARTIALS(BF16Q19); break;
+        case LBM_STORE_F16: LBM_ENS_PARTIALS(F16Q19); break;
 #undef LBM_ENS_PARTIALS
     }
     hipLaunchKernelGGL(k_final_sums, dim3(1), dim3(kBlock), 0, e->stream, e->partials, kRedBlocks,
@@ -1571,10 +1597,10 @@ lbm_status lbm_ens_get_populations(lbm_ens *e, int32_t replica, double *f) {
 #define LBM_ENS_POPS(CODEC)                                                                      \
     hipLaunchKernelGGL(k_get_populations<CODEC>, dim3(blocks_for(t.g.ncell)), dim3(kBlock), 0, \
                        e->stream, reinterpret_cast<const CODEC::T *>(A), t.g, CODEC::R(e->dec_s), f)
-        case LBM_STORE_F64: LBM_ENS_POPS(CodecF64); break;
-        case LBM_STORE_F32: LBM_ENS_POPS(CodecF32); break;
-        case LBM_STORE_BF16: LBM_ENS_POPS(CodecBF16); break;
-        case LBM_STORE_F16: LBM_ENS_POPS(CodecF16); break;
+        case LBM_STORE_F64: LBM_ENS_POPS(F64Q19); break;
+        case LBM_STORE_F32: LBM_ENS_POPS(F32Q19); break;
+        case LBM_STORE_BF16: LBM_ENS_POPS(BF16Q19); break;
+        case LBM_STORE_F16: LBM_ENS_POPS(F16Q19); break;
 #undef LBM_ENS_POPS
     }
     return launch_status();
@@ -1632,7 +1658,7 @@ Grid adj_grid(const lbm_ctx *c) {
 
 size_t adj_lattice_bytes(const lbm_ctx *c) {
     const Grid gd = adj_grid(c);
-    return align_up(size_t(gd.chunk) * D3Q19::Q * gd.ny * gd.nz * 8, kAlign);
+    return align_up(size_t(gd.chunk) * size_t(c->q) * gd.ny * gd.nz * 8, kAlign);
 }
 
 struct AdjLayout {
@@ -1737,7 +1763,7 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
     memset_(pgrad, 0, size_t(np) * 4 * 8);
     memset_(wacc, 0, size_t(blocks_for(c->g.ncell)) * 8);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_import, dim3(blocks_for(c->g.ncell)), dim3(kBlock), 0, st, adj_pop,
+    hipLaunchKernelGGL(k_adj_import<typename C::V>, dim3(blocks_for(c->g.ncell)), dim3(kBlock), 0, st, adj_pop,
                        abar[0], gd);
 
     // Forward recompute: the particle kernel without VACF or sums.
@@ -1839,7 +1865,7 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
         }
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_export, dim3(cgrid), dim3(kBlock), 0, st, abar[cur], adj_pop, gd);
+    hipLaunchKernelGGL(k_adj_export<typename C::V>, dim3(cgrid), dim3(kBlock), 0, st, abar[cur], adj_pop, gd);
     hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(kBlock), 0, st, pgrad, np, wacc,
                        int32_t(cgrid), c->desc.tau, adj_param);
     return hipGetLastError();

@@ -12,7 +12,7 @@
 #include "lbmbp.h"
 #include "codec.hpp"
 #include "collide.hpp"
-#include "d3q19.hpp"
+#include "velocities.hpp"
 #include "philox.hpp"
 
 namespace lbmbp {
@@ -163,6 +163,7 @@ template <class C>
 __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R dec_s,
                                      const ParticleArgs &pa, int32_t i, int p, bool valid,
                                      const double (&r)[3], const double (&V)[3]) {
+    using Vs = typename C::V;
     const typename C::T *__restrict__ A = site.A;
     const Grid &g = site.g;
     const ForceField &cur = site.cur;
@@ -194,12 +195,12 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
     // Issue the gather of f^n at this lane's fitting node (pull from node -
     // e_a); the values are consumed only after the VACF sample and the
     // Brownian force, which overlap the load latency.
-    typename C::T raw[D3Q19::Q];
+    typename C::T raw[Vs::Q];
     if (coupled) {
         const Neighbours nb(fnode[0], fnode[1], fnode[2], g);
-        static_for<1, D3Q19::Q>([&](auto ac) {
+        static_for<1, Vs::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            raw[a] = A[nb.pop<a>(g)];
+            raw[a] = A[nb.template pop<Vs, a>(g)];
         });
     }
 
@@ -242,12 +243,12 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
     double u[3] = {0.0, 0.0, 0.0};
     if (coupled) {
         // u^n at this lane's node: u = sum_a e_a f_a = sum_a e_a g_a (Eq. s2-fv).
-        static_for<1, D3Q19::Q>([&](auto ac) {
+        static_for<1, Vs::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
             const double gvl = double(C::dec(raw[a], dec_s));
-            if constexpr (D3Q19::ex[a] != 0) u[0] += D3Q19::ex[a] > 0 ? gvl : -gvl;
-            if constexpr (D3Q19::ey[a] != 0) u[1] += D3Q19::ey[a] > 0 ? gvl : -gvl;
-            if constexpr (D3Q19::ez[a] != 0) u[2] += D3Q19::ez[a] > 0 ? gvl : -gvl;
+            if constexpr (Vs::ex[a] != 0) u[0] += Vs::ex[a] > 0 ? gvl : -gvl;
+            if constexpr (Vs::ey[a] != 0) u[1] += Vs::ey[a] > 0 ? gvl : -gvl;
+            if constexpr (Vs::ez[a] != 0) u[2] += Vs::ez[a] > 0 ? gvl : -gvl;
         });
     }
     FitTrace tr;

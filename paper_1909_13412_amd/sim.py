@@ -45,18 +45,23 @@ class Lattice:
     """One periodic box of nx*ny*nz nodes with two population lattices.
 
     storage: "f64", "f32", "bf16" (shifted, round-to-nearest-even) or "f16"
-    (shifted, scaled by 2^f16_scale_log2).
+    (shifted, scaled by 2^f16_scale_log2).  velocities: 19 (D3Q19) or 15 (D3Q15).
     """
 
     def __init__(self, nx: int, ny: int, nz: int, tau: float, storage: str = "f32",
-                 f16_scale_log2: int = 16, device="cuda:0", stream: torch.cuda.Stream | None = None):
+                 f16_scale_log2: int = 16, device="cuda:0", stream: torch.cuda.Stream | None = None,
+                 velocities: int = 19):
         self.lib = _abi.load()
         self.device = torch.device(device)
         self.shape = (nz, ny, nx)
         self.ncell = nx * ny * nz
         self.tau = float(tau)
         self.storage = storage
-        self.desc = _abi.GridDesc(nx, ny, nz, float(tau), _abi.STORAGE[storage], int(f16_scale_log2))
+        if velocities not in (15, 19):
+            raise ValueError("velocities must be 19 or 15")
+        self.q = int(velocities)
+        self.desc = _abi.GridDesc(nx, ny, nz, float(tau), _abi.STORAGE[storage], int(f16_scale_log2),
+                                  self.q, 0)
         sz = ctypes.c_size_t()
         _abi.check("lbm_lattice_bytes", self.lib.lbm_lattice_bytes(ctypes.byref(self.desc), ctypes.byref(sz)))
         self.lattice_bytes = sz.value
@@ -98,7 +103,7 @@ class Lattice:
                    self.lib.lbm_set_equilibrium(self.ctx, _ptr(self._rho_in), _ptr(self._u_in)))
 
     def set_populations(self, f):
-        self._f_in = _device_f64(f, self.device, (Q * self.ncell,))
+        self._f_in = _device_f64(f, self.device, (self.q * self.ncell,))
         _abi.check("lbm_set_populations", self.lib.lbm_set_populations(self.ctx, _ptr(self._f_in)))
 
     def set_body_force(self, g=None):
@@ -107,7 +112,7 @@ class Lattice:
         _abi.check("lbm_set_body_force", self.lib.lbm_set_body_force(self.ctx, arr))
 
     def populations(self) -> torch.Tensor:
-        out = torch.empty((Q,) + self.shape, dtype=torch.float64, device=self.device)
+        out = torch.empty((self.q,) + self.shape, dtype=torch.float64, device=self.device)
         _abi.check("lbm_get_populations", self.lib.lbm_get_populations(self.ctx, _ptr(out)))
         return out
 
@@ -245,7 +250,7 @@ class Lattice:
         are zero."""
         if tape is not getattr(self, "_tape", None):
             raise ValueError("adjoint() needs the tape of this lattice's last record()")
-        pop = torch.zeros((Q,) + self.shape, dtype=torch.float64, device=self.device)
+        pop = torch.zeros((self.q,) + self.shape, dtype=torch.float64, device=self.device)
         if adj_pop is not None:
             pop.copy_(_device_f64(adj_pop, self.device).reshape(pop.shape))
         n = tape.n

@@ -23,7 +23,7 @@ def announce(msg: str):
 
 def run_pair(oracle_mod, L, tau, storage, r, v, steps, *, mass=10.0, gamma=1.0, kT=0.0, seed=0,
              friction="stokeslet", radius=0.0, rho=None, u=None, trace=False, vacf=None,
-             f16_scale_log2=16):
+             f16_scale_log2=16, q=19):
     """Run the oracle and the GPU side by side.  L is (nx, ny, nz).
     Returns dict with final fields/particles of both, and per-step traces."""
     import torch
@@ -31,8 +31,8 @@ def run_pair(oracle_mod, L, tau, storage, r, v, steps, *, mass=10.0, gamma=1.0, 
     from paper_1909_13412_amd import Lattice
 
     nx, ny, nz = L
-    gpu = Lattice(nx, ny, nz, tau, storage=storage, f16_scale_log2=f16_scale_log2)
-    ref = oracle_mod.Sim(nx, ny, nz, tau)
+    gpu = Lattice(nx, ny, nz, tau, storage=storage, f16_scale_log2=f16_scale_log2, velocities=q)
+    ref = oracle_mod.Sim(nx, ny, nz, tau, q=q)
     if rho is not None or u is not None:
         gpu.set_equilibrium(rho, u)
         ref.set_equilibrium(rho, u)

@@ -41,16 +41,16 @@ def test_library_exports_every_declared_symbol(lib):
 def test_struct_layouts_match_header(lib):
     from paper_1909_13412_amd import _abi
 
-    assert ctypes.sizeof(_abi.GridDesc) == 32
+    assert ctypes.sizeof(_abi.GridDesc) == 40
     assert ctypes.sizeof(_abi.ParticleDesc) == 56
     assert ctypes.sizeof(_abi.EnsembleDesc) == 56
     assert ctypes.sizeof(_abi.ReplicaDesc) == 40
 
 
-def _grid(nx=16, ny=16, nz=16, tau=0.8, storage=1, s=16):
+def _grid(nx=16, ny=16, nz=16, tau=0.8, storage=1, s=16, q=0, reserved=0):
     from paper_1909_13412_amd import _abi
 
-    return _abi.GridDesc(nx, ny, nz, tau, storage, s)
+    return _abi.GridDesc(nx, ny, nz, tau, storage, s, q, reserved)
 
 
 def test_lattice_and_scratch_sizes(lib):
@@ -68,6 +68,10 @@ def test_lattice_and_scratch_sizes(lib):
     g = _grid(nx=256, ny=256, nz=256)
     assert lib.lbm_lattice_bytes(ctypes.byref(g), ctypes.byref(sz)) == 0
     assert sz.value == 19 * 256**3 * 4
+    for q in (19, 15):
+        gq = _grid(nx=256, ny=256, nz=256, q=q)
+        assert lib.lbm_lattice_bytes(ctypes.byref(gq), ctypes.byref(sz)) == 0
+        assert sz.value == q * 256**3 * 4
     assert lib.lbm_grid_scratch_bytes(ctypes.byref(g), ctypes.byref(sz)) == 0
     assert sz.value >= 2 * 256**3 // 8
     assert lib.lbm_particle_scratch_bytes(ctypes.byref(g), 4096, ctypes.byref(sz)) == 0
@@ -80,7 +84,8 @@ def test_lattice_and_scratch_sizes(lib):
 
 @pytest.mark.parametrize("bad", [
     dict(nx=1), dict(ny=0), dict(nz=-4), dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")),
-    dict(storage=7), dict(storage=3, s=40), dict(nx=2048, ny=2048, nz=1024),
+    dict(storage=7), dict(storage=3, s=40), dict(nx=2048, ny=2048, nz=1024), dict(q=27),
+    dict(q=16), dict(reserved=1),
 ])
 def test_invalid_grids_rejected(lib, bad):
     kw = dict(nx=8, ny=8, nz=8, tau=0.8, storage=1, s=16)

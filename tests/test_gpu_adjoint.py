@@ -28,10 +28,10 @@ def _cuda():
 BOX = (12, 10, 9)  # nx, ny, nz: unequal sides catch axis mix-ups
 
 
-def _case(oracle_mod, seed, n=5, tau=0.8, box=BOX, amp=0.02):
+def _case(oracle_mod, seed, n=5, tau=0.8, box=BOX, amp=0.02, q=19):
     rng = np.random.default_rng(seed)
     nx, ny, nz = box
-    o = oracle_mod.Sim(nx, ny, nz, tau)
+    o = oracle_mod.Sim(nx, ny, nz, tau, q=q)
     o.set_equilibrium(1.0 + 0.01 * rng.standard_normal((nz, ny, nx)),
                       amp * rng.standard_normal((3, nz, ny, nx)))
     f0 = o.populations()
@@ -49,7 +49,7 @@ def _gpu_grad(storage, f0, r0, v0, theta, cf, cr, cv, nsteps, every, friction, r
 
     gamma, tau, M, kT = theta
     nx, ny, nz = box
-    lat = Lattice(nx, ny, nz, tau, storage=storage)
+    lat = Lattice(nx, ny, nz, tau, storage=storage, velocities=f0.shape[0])
     lat.set_populations(f0)
     lat.particles_couple(r0, v0, mass=M, gamma=gamma, kT=kT, radius=radius, seed=seed,
                          friction=friction)
@@ -78,6 +78,23 @@ def test_adjoint_f64_matches_oracle(oracle_mod, friction, kT, radius):
     assert max(errs) < 1e-10
     for k in range(4):
         assert abs(g["params"][k] - gth[k]) <= 1e-10 * max(1.0, abs(gth[k])), k
+
+
+@pytest.mark.parametrize("friction", ["stokeslet", "stokeslet2dx"])
+def test_adjoint_fifteen_velocities_matches_oracle(oracle_mod, friction):
+    from oracle import adjoint as A
+
+    f0, r0, v0, cf, cr, cv = _case(oracle_mod, 17, q=15)
+    theta = (1.0, 0.8, 10.0, 1e-4)
+    N, every, seed = 19, 7, 33
+    announce(f"adjoint D3Q15 f64 {friction} box={BOX} N={N}")
+    _, _, g = _gpu_grad("f64", f0, r0, v0, theta, cf, cr, cv, N, every, friction, 0.9, seed)
+    gf, gr, gv, gth = A.vjp(f0, r0, v0, np.array(theta), A.noise(len(r0), N, seed), cf, cr, cv,
+                            friction, 0.9)
+    errs = (nmax_err(g["pop"], gf), nmax_err(g["r"], gr), nmax_err(g["v"], gv),
+            nmax_err(g["params"], gth))
+    announce(f"  {errs}")
+    assert g["pop"].shape[0] == 15 and max(errs) < 1e-10
 
 
 def test_adjoint_f32_close_to_oracle(oracle_mod):

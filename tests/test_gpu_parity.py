@@ -24,10 +24,10 @@ def _cuda():
     yield
 
 
-def _w():
+def _w(q=19):
     import oracle
 
-    _, w = oracle.lattice()
+    _, w = oracle.lattice(q)
     return w
 
 
@@ -36,9 +36,9 @@ def _compare_fields(gpu, ref, tol, what="", flow_scale=0.0):
     the largest reference value, or by `flow_scale` (a velocity scale of the
     run) when that is larger: once a flow has decayed, the oracle's unshifted
     FP64 populations carry a rounding floor of ~1e-16 x steps absolute."""
-    w = _w()
     fg = gpu.populations().cpu().numpy()
     fr = ref.populations()
+    w = _w(fg.shape[0])
     gg = fg - w[:, None, None, None]
     gr = fr - w[:, None, None, None]
     g_scale = max(np.max(np.abs(gr)), flow_scale / 6.0)  # |g| ~ 3 w |u|, w <= 1/18
@@ -426,3 +426,37 @@ def test_wide_fit_at_seams_and_shared_nodes(oracle_mod):
                    friction="stokeslet2dx", radius=1.2)
     _compare_particles(out["gpu"], out["ref"], 1e-10, "wide fit seams")
     _compare_fields(out["gpu"], out["ref"], 1e-10, "wide fit seams")
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("friction", ["stokeslet", "pointwise", "stokeslet2dx"])
+def test_fifteen_velocity_suspension(oracle_mod, storage, friction):
+    # The paper's own velocity set: ragged box, noise, body force, three
+    # friction models.
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    L = (29, 17, 13)
+    r = particle_positions(7, L, seed=15)
+    v = particle_velocities(7, 1e-5, seed=15)
+    announce(f"D3Q15 {storage} {friction} box={L}")
+    out = run_pair(oracle_mod, L, 0.7, storage, r, v, 1, kT=1e-4, seed=515, friction=friction,
+                   radius=0.9 if friction == "stokeslet2dx" else 0.0, q=15)
+    G = np.array([1e-6, 2e-6, -1e-6])
+    out["gpu"].set_body_force(G)
+    out["ref"].set_body_force(np.broadcast_to(G.reshape(3, 1, 1, 1), (3, L[2], L[1], L[0])).copy())
+    out["gpu"].step(50)
+    out["ref"].step(50)
+    tol = TOL[storage]
+    _compare_particles(out["gpu"], out["ref"], tol, f"D3Q15 {storage}/{friction}")
+    _compare_fields(out["gpu"], out["ref"], tol, f"D3Q15 {storage}/{friction}")
+
+
+@pytest.mark.parametrize("tau", [0.6, 1.0])
+def test_fifteen_velocity_shear_wave(oracle_mod, tau):
+    L = (4, 6, 24)
+    nz = L[2]
+    z = np.arange(nz)
+    u = np.zeros((3, nz, L[1], L[0]))
+    u[0] = 1e-2 * np.sin(2 * np.pi * z / nz)[:, None, None]
+    out = run_pair(oracle_mod, L, tau, "f64", None, None, 80, u=u, q=15)
+    _compare_fields(out["gpu"], out["ref"], 1e-10, f"D3Q15 shear tau={tau}")

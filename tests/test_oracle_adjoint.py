@@ -19,11 +19,11 @@ from oracle import adjoint as A
 E, W = oracle.lattice()
 
 
-def _setup(L=8, n=3, seed=1, tau=0.8, amp=0.02):
+def _setup(L=8, n=3, seed=1, tau=0.8, amp=0.02, q=19):
     rng = np.random.default_rng(seed)
     rho = 1.0 + 0.01 * rng.standard_normal((L, L, L))
     u = amp * rng.standard_normal((3, L, L, L))
-    o = oracle.Sim(L, L, L, tau)
+    o = oracle.Sim(L, L, L, tau, q=q)
     o.set_equilibrium(rho, u)
     f0 = o.populations()
     r0 = rng.uniform(0.0, L, (n, 3))
@@ -34,7 +34,7 @@ def _setup(L=8, n=3, seed=1, tau=0.8, amp=0.02):
 def _oracle_run(f0, r0, v0, theta, nsteps, friction, radius=0.0, seed=5, fc=None):
     gamma, tau, M, kT = theta
     L = f0.shape[1]
-    o = oracle.Sim(L, L, L, tau)
+    o = oracle.Sim(L, L, L, tau, q=f0.shape[0])
     o.set_populations(f0)
     o.set_particles(r0, v0, mass=M, gamma=gamma, kT=kT, radius=radius, seed=seed,
                     friction=friction)
@@ -60,6 +60,30 @@ def test_forward_matches_c_oracle(friction, kT, radius, force):
     assert np.max(np.abs(f - fr)) < 1e-14
     assert np.max(np.abs(r - rr)) < 1e-13
     assert np.max(np.abs(v - vr)) < 1e-15
+
+
+@pytest.mark.parametrize("friction", ["stokeslet", "stokeslet2dx"])
+def test_fifteen_velocities_forward_and_transpose(friction):
+    rng, f0, r0, v0 = _setup(seed=8, q=15)
+    theta = np.array([1.0, 0.8, 10.0, 1e-4])
+    N = 6
+    fr, rr, vr = _oracle_run(f0, r0, v0, theta, N, friction, 1.0)
+    xi = A.noise(3, N, 5)
+    f, r, v = A.run(f0, r0, v0, theta, xi, friction, 1.0)
+    assert f.shape[0] == 15
+    assert np.max(np.abs(f - fr)) < 1e-14 and np.max(np.abs(v - vr)) < 1e-15
+    cf = rng.standard_normal(f0.shape)
+    cr = rng.standard_normal(r0.shape)
+    cv = rng.standard_normal(v0.shape)
+    gf, gr, gv, gth = A.vjp(f0, r0, v0, theta, xi, cf, cr, cv, friction, 1.0)
+    df = rng.standard_normal(f0.shape)
+    dr = rng.standard_normal(r0.shape)
+    dv = rng.standard_normal(v0.shape)
+    dth = rng.standard_normal(4)
+    jf, jr, jv = A.jvp(f0, r0, v0, theta, xi, df, dr, dv, dth, friction, 1.0)
+    lhs = (gf * df).sum() + (gr * dr).sum() + (gv * dv).sum() + (gth * dth).sum()
+    rhs = (cf * jf).sum() + (cr * jr).sum() + (cv * jv).sum()
+    assert abs(lhs - rhs) < 1e-11 * (abs(rhs) + 1.0)
 
 
 def test_forward_with_body_force_matches_c_oracle():
