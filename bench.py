@@ -69,21 +69,28 @@ def pmc_traffic(storage: str):
     return (c["fetch_kib"] * rec["fetch_scale"] + c["write_kib"] * rec["write_scale"]) * 1024.0
 
 
-def collide_bytes_per_node(storage: str) -> float:
-    """Algorithmic bytes of one stream-collide node update: 19 population loads
-    and 19 stores, plus the one-bit forcing flag."""
-    return 2 * 19 * ELEM[storage] + 1.0 / 8.0
+def parse_variant(name: str):
+    """'bf16' -> ('bf16', 19); 'f32q15' -> ('f32', 15): storage and velocity set."""
+    if name.endswith("q15"):
+        return name[:-3], 15
+    return name, 19
+
+
+def collide_bytes_per_node(storage: str, q: int = 19) -> float:
+    """Algorithmic bytes of one stream-collide node update: q population loads
+    and q stores, plus the one-bit forcing flag."""
+    return 2 * q * ELEM[storage] + 1.0 / 8.0
 
 
 SERIES_EVERY = 10  # FP64 mass/momentum sums recorded inside the step kernels every 10 steps
 
 
-def make_lattice(w, storage, device="cuda:0", series_capacity=0):
+def make_lattice(w, storage, device="cuda:0", series_capacity=0, q=19):
     from paper_1909_13412_amd import Lattice
     from paper_1909_13412_amd.inputs import workload_particles
 
     L = w["L"]
-    lat = Lattice(L, L, L, w["tau"], storage=storage, device=device)
+    lat = Lattice(L, L, L, w["tau"], storage=storage, device=device, velocities=q)
     r, v = workload_particles(w["name"])
     lat.particles_couple(r, v, mass=w["mass"], gamma=w["gamma"], kT=w["kT"], radius=w["radius"],
                          seed=w["seed"])
@@ -93,7 +100,7 @@ def make_lattice(w, storage, device="cuda:0", series_capacity=0):
     return lat
 
 
-def time_storage(w, storage, steps, warmup, prof_steps):
+def time_storage(w, variant, steps, warmup, prof_steps):
     """Autotune the stream-collide launch shape, time `steps` whole steps with
     nothing but the kernels on the stream (-> MLUPS), then time `prof_steps`
     more with HIP events around every kernel launch (-> per-kernel durations;
@@ -101,7 +108,9 @@ def time_storage(w, storage, steps, warmup, prof_steps):
     of the first region)."""
     import torch
 
-    lat = make_lattice(w, storage, series_capacity=(2 * warmup + steps + prof_steps) // SERIES_EVERY + 2)
+    storage, q = parse_variant(variant)
+    lat = make_lattice(w, storage, q=q,
+                       series_capacity=(2 * warmup + steps + prof_steps) // SERIES_EVERY + 2)
     lat.step(warmup)
     torch.cuda.synchronize()
     shape, shape_ms = lat.autotune(20)
@@ -124,9 +133,10 @@ def time_storage(w, storage, steps, warmup, prof_steps):
     ncell = w["L"] ** 3
     coll_ms = prof["collide_ms"] / max(prof["collide_launches"], 1)
     part_ms = prof["particle_ms"] / max(prof["particle_launches"], 1)
-    achieved = ncell * collide_bytes_per_node(storage) / (coll_ms * 1e-3) / 1e9
+    achieved = ncell * collide_bytes_per_node(storage, q) / (coll_ms * 1e-3) / 1e9
     res = {
         "storage": storage,
+        "velocities": q,
         "mlups": ncell * steps / (t1 - t0) / 1e6,
         "ms_per_step": (t1 - t0) * 1e3 / steps,
         "profiled_ms_per_step": (t3 - t2) * 1e3 / prof_steps,
@@ -325,7 +335,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="suspension256")
     ap.add_argument("--storage", default="f32")
-    ap.add_argument("--variants", default="bf16,f16")
+    ap.add_argument("--variants", default="bf16,f16,f32q15,bf16q15",
+                    help="storages to time besides --storage; a q15 suffix selects D3Q15")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps timed (0 = skip)")
     ap.add_argument("--precision-steps", type=int, default=2000, help="0 = skip the VACF error study")
     ap.add_argument("--prof-steps", type=int, default=300, help="steps timed with per-kernel events")
