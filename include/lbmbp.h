@@ -224,18 +224,27 @@ lbm_status lbm_profile_enable(lbm_ctx *ctx, int32_t enable);
  * out[2] summed particle-phase milliseconds, out[3] particle-phase launches. */
 lbm_status lbm_profile_read(lbm_ctx *ctx, double out[4]);
 
-/* Stream-collide launch shapes: 0 = one node per lane, 512-lane blocks;
- * 1 = one node, 256; 2 = two nodes (rows y and y + ny/2), 512; 3 = two
- * nodes, 256 (shapes 2 and 3 need an even ny). */
-#define LBM_NUM_SHAPES 4
+/* Stream-collide launch configurations k = 0..7.  k & 3 is the geometric
+ * shape: 0 = one node per lane, 512-lane blocks; 1 = one node, 256; 2 = two
+ * nodes (rows y and y + ny/2), 512; 3 = two nodes, 256 (2 and 3 need an even
+ * ny).  k >= 4 writes the populations with non-temporal stores (streamed past
+ * the caches), which pays off once a lattice no longer fits in the GPU's
+ * last-level cache.  Until lbm_autotune runs a context uses shape 0, with
+ * non-temporal stores when one lattice is at least 256 MiB. */
+#define LBM_NUM_SHAPES 8
 
-/* Time every valid stream-collide shape on this context's lattice (iters
+/* Time every valid stream-collide configuration on this context's lattice (iters
  * launches each, reading the current populations and writing the spare
  * lattice, so the simulation state is not changed) and keep the fastest for
  * later lbm_step calls.  Synchronises the stream.  ms (host, LBM_NUM_SHAPES
  * entries, may be NULL) receives the mean milliseconds per launch (-1 for a
  * shape that does not apply); *chosen (may be NULL) the shape kept. */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen);
+
+/* Use launch configuration k (0 .. LBM_NUM_SHAPES - 1) for later steps;
+ * LBM_E_INVAL if k is out of range or does not apply to this box.  Every
+ * configuration gives bit-identical results. */
+lbm_status lbm_set_shape(lbm_ctx *ctx, int32_t k);
 
 /* Number of steps taken since lbm_init. */
 lbm_status lbm_get_step(const lbm_ctx *ctx, int64_t *step);

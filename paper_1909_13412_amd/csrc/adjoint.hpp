@@ -294,7 +294,7 @@ __global__ __launch_bounds__(kParticleBlock) void k_adj_particle(
     }
 }
 
-template <class C, bool FORCED>
+template <class C, bool FORCED, bool NTS>
 __global__ __launch_bounds__(kBlock) void k_adj_collide(const typename C::T *__restrict__ A, Grid g,
                                                         typename C::R dec_s,
                                                         const double *__restrict__ Abar,
@@ -362,7 +362,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(const typename C::T *__r
             double out = (1.0 - omega) * fs[a] +
                          omega * (P + double(cx) * Gx + double(cy) * Gy + double(cz) * Gz);
             if constexpr (FORCED) out += double(cx) * Ux + double(cy) * Uy + double(cz) * Uz;
-            Bbar[row_base + uint64_t(a) * gd.chunk] = out;
+            if constexpr (NTS)
+                __builtin_nontemporal_store(out, &Bbar[row_base + uint64_t(a) * gd.chunk]);
+            else
+                Bbar[row_base + uint64_t(a) * gd.chunk] = out;
         });
     }
     // dJ/domega of this block, added to its own running slot (fixed order).

@@ -119,7 +119,9 @@ __device__ inline void block_sum(double (&v)[N], double *__restrict__ out) {
 // With MOMENTS the FP64 sums of (rho~ - 1, u) over these nodes are added to acc.
 // The force at a node is the uniform body force G plus, where the node is
 // flagged (FORCED), the particles' reaction force.
-template <class C, bool FORCED, bool MOMENTS, int CPT>
+// NTS: write the populations with non-temporal stores (streamed past the
+// caches); pays off once the lattice no longer fits in the last-level cache.
+template <class C, bool FORCED, bool MOMENTS, int CPT, bool NTS>
 __device__ inline void collide_lane(const typename C::T *__restrict__ A,
                                     typename C::T *__restrict__ B, const Grid &g,
                                     typename C::R omega, typename C::R enc_s, typename C::R dec_s,
@@ -194,12 +196,16 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
             if constexpr (cy != 0) eF += cy > 0 ? Fy : -Fy;
             if constexpr (cz != 0) eF += cz > 0 ? Fz : -Fz;
             if constexpr (a != 0) gn += R(3) * w * eF;
-            B[row_base + uint64_t(a) * g.chunk] = C::enc(gn, enc_s);
+            // written once and read only by the next step
+            if constexpr (NTS)
+                __builtin_nontemporal_store(C::enc(gn, enc_s), &B[row_base + uint64_t(a) * g.chunk]);
+            else
+                B[row_base + uint64_t(a) * g.chunk] = C::enc(gn, enc_s);
         });
     }
 }
 
-template <class C, bool FORCED, bool MOMENTS, int CPT, int BS>
+template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS>
 __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__restrict__ A,
                                                        typename C::T *__restrict__ B, Grid g,
                                                        typename C::R omega, typename C::R enc_s,
@@ -213,16 +219,21 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
     }
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (active)
-        collide_lane<C, FORCED, MOMENTS, CPT>(A, B, g, omega, enc_s, dec_s, ff, Gx, Gy, Gz,
-                                              lane_cell, acc);
+        collide_lane<C, FORCED, MOMENTS, CPT, NTS>(A, B, g, omega, enc_s, dec_s, ff, Gx, Gy, Gz,
+                                                   lane_cell, acc);
     if constexpr (MOMENTS) block_sum<4, BS>(acc, mom + 4 * uint64_t(blockIdx.x));
 }
 
-// Launch shapes of the stream-collide, chosen per context (lbm_autotune).
+// Launch configurations of the stream-collide, chosen per context
+// (lbm_autotune): configuration k uses the geometric shape kShapes[k & 3]
+// and non-temporal stores when k >= 4.
 struct CollideShape {
     int cpt, bs;
 };
 constexpr CollideShape kShapes[] = {{1, 512}, {1, 256}, {2, 512}, {2, 256}};
-constexpr int kNumShapes = 4;
+constexpr int kNumGeomShapes = 4;
+constexpr int kNumShapes = 2 * kNumGeomShapes;
+// Lattices of at least this many bytes default to non-temporal stores.
+constexpr size_t kStreamStoreBytes = size_t(256) << 20;
 
 }  // namespace lbmbp

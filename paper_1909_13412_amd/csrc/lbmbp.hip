@@ -64,7 +64,7 @@ struct EnsClock {
     int64_t vacf_t;  // VACF sample clock
 };
 
-template <class C, int CPT, int BS>
+template <class C, int CPT, int BS, bool NTS>
 __global__ __launch_bounds__(BS) void k_ens_collide(const typename C::T *__restrict__ A,
                                                     typename C::T *__restrict__ B,
                                                     const Replica *__restrict__ reps,
@@ -85,8 +85,8 @@ __global__ __launch_bounds__(BS) void k_ens_collide(const typename C::T *__restr
     const ForceField ff{force + 3 * rp.cell_off, mask + rp.mask_off};
     double acc[4];
     using R = typename C::R;
-    collide_lane<C, true, false, CPT>(A + rp.pop_off, B + rp.pop_off, rp.g, R(rp.omega), enc_s,
-                                      dec_s, ff, R(0), R(0), R(0), lane_cell, acc);
+    collide_lane<C, true, false, CPT, NTS>(A + rp.pop_off, B + rp.pop_off, rp.g, R(rp.omega),
+                                           enc_s, dec_s, ff, R(0), R(0), R(0), lane_cell, acc);
 }
 
 template <class C>
@@ -451,18 +451,33 @@ lbm_status launch_status() {
 }
 
 unsigned blocks_for(uint64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
-bool shape_ok(const lbm_ctx *c, int k) { return c->g.ny % uint32_t(kShapes[k].cpt) == 0; }
+// Launch configuration k of the stream-collide: shape k & 3, non-temporal
+// stores for k >= 4.
+#define LBM_CONFIG_SWITCH(k, CALL)                  \
+    switch (k) {                                    \
+        case 1: CALL(1, 256, false); break;         \
+        case 2: CALL(2, 512, false); break;         \
+        case 3: CALL(2, 256, false); break;         \
+        case 4: CALL(1, 512, true); break;          \
+        case 5: CALL(1, 256, true); break;          \
+        case 6: CALL(2, 512, true); break;          \
+        case 7: CALL(2, 256, true); break;          \
+        default: CALL(1, 512, false); break;        \
+    }
+
+bool shape_ok(const lbm_ctx *c, int k) { return c->g.ny % uint32_t(kShapes[k & 3].cpt) == 0; }
 
 uint32_t collide_grid(const lbm_ctx *c, int shape) {
-    const uint64_t band = c->g.ncell / uint32_t(kShapes[shape].cpt);
-    return uint32_t((band + kShapes[shape].bs - 1) / kShapes[shape].bs);
+    const CollideShape &sh = kShapes[shape & 3];
+    const uint64_t band = c->g.ncell / uint32_t(sh.cpt);
+    return uint32_t((band + sh.bs - 1) / sh.bs);
 }
 
-template <class C, bool FORCED, bool MOMENTS, int CPT, int BS>
+template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS>
 void launch_collide_shape(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff,
                           double *mom, unsigned grid) {
     using R = typename C::R;
-    hipLaunchKernelGGL((k_stream_collide<C, FORCED, MOMENTS, CPT, BS>), dim3(grid), dim3(BS), 0,
+    hipLaunchKernelGGL((k_stream_collide<C, FORCED, MOMENTS, CPT, BS, NTS>), dim3(grid), dim3(BS), 0,
                        c->stream, A, B, c->g, R(c->omega), R(c->enc_s), R(c->dec_s), ff,
                        R(c->body[0]), R(c->body[1]), R(c->body[2]), mom);
 }
@@ -472,19 +487,14 @@ template <class C, bool FORCED>
 void launch_collide(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff, int shape,
                     double *mom = nullptr) {
     const unsigned grid = collide_grid(c, shape);
-#define LBM_SHAPE(CPT, BS)                                                              \
-    do {                                                                               \
-        if (mom)                                                                       \
-            launch_collide_shape<C, FORCED, true, CPT, BS>(c, A, B, ff, mom, grid);    \
-        else                                                                           \
-            launch_collide_shape<C, FORCED, false, CPT, BS>(c, A, B, ff, mom, grid);   \
+#define LBM_SHAPE(CPT, BS, NTS)                                                              \
+    do {                                                                                     \
+        if (mom)                                                                             \
+            launch_collide_shape<C, FORCED, true, CPT, BS, NTS>(c, A, B, ff, mom, grid);     \
+        else                                                                                 \
+            launch_collide_shape<C, FORCED, false, CPT, BS, NTS>(c, A, B, ff, mom, grid);    \
     } while (0)
-    switch (shape) {
-        case 1: LBM_SHAPE(1, 256); break;
-        case 2: LBM_SHAPE(2, 512); break;
-        case 3: LBM_SHAPE(2, 256); break;
-        default: LBM_SHAPE(1, 512); break;
-    }
+    LBM_CONFIG_SWITCH(shape, LBM_SHAPE)
 #undef LBM_SHAPE
 }
 
@@ -740,6 +750,11 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
     c->g.ncell = uint32_t(ncell_of(grid));
     c->g.chunk = row_chunk(grid);
     c->q = velocity_count(grid);
+    {
+        size_t lat = 0;
+        lbm_lattice_bytes(grid, &lat);
+        c->shape = lat >= kStreamStoreBytes ? kNumGeomShapes : 0;  // until lbm_autotune
+    }
     c->elem = elem_size(grid->storage);
     c->pop[0] = pop_a;
     c->pop[1] = pop_b;
@@ -995,6 +1010,12 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen
     return LBM_OK;
 }
 
+lbm_status lbm_set_shape(lbm_ctx *ctx, int32_t k) {
+    if (!ctx || k < 0 || k >= kNumShapes || !shape_ok(ctx, k)) return LBM_E_INVAL;
+    ctx->shape = k;
+    return LBM_OK;
+}
+
 lbm_status lbm_series_config(lbm_ctx *ctx, int32_t every, double *series, int64_t capacity) {
     if (!ctx || every < 0) return LBM_E_INVAL;
     if (every > 0 && (!series || capacity < 1)) return LBM_E_INVAL;
@@ -1055,11 +1076,11 @@ struct lbm_ens {
     hipStream_t stream;
     double enc_s, dec_s;
     uint64_t total_cells, total_pop;
-    uint32_t total_blocks[kNumShapes];
+    uint32_t total_blocks[kNumGeomShapes];
     int32_t n;  // particles in all replicas
     // scratch
     Replica *reps;
-    uint16_t *blk_rep[kNumShapes];
+    uint16_t *blk_rep[kNumGeomShapes];
     uint16_t *part_rep;
     uint32_t *mask[2];
     long long *force[2];
@@ -1094,11 +1115,11 @@ uint32_t ens_chunk(int storage, int32_t nx) {
 
 struct EnsLayout {
     uint64_t total_cells = 0, total_pop = 0, total_mask_words = 0;
-    uint32_t total_blocks[kNumShapes] = {0, 0, 0, 0};
+    uint32_t total_blocks[kNumGeomShapes] = {0, 0, 0, 0};
     int32_t n = 0;
     size_t lattice_bytes = 0, scratch_bytes = 0;
     // scratch offsets
-    size_t o_reps, o_blk[kNumShapes], o_part, o_mask[2], o_force[2], o_prev, o_fh, o_fr, o_clock,
+    size_t o_reps, o_blk[kNumGeomShapes], o_part, o_mask[2], o_force[2], o_prev, o_fh, o_fr, o_clock,
         o_err, o_partials, o_result;
 };
 
@@ -1130,7 +1151,7 @@ EnsLayout ens_layout(const lbm_ensemble_desc *d, const lbm_replica_desc *reps) {
         L.total_cells += cells;
         L.total_pop += uint64_t(ens_chunk(d->storage, r.nx)) * D3Q19::Q * r.ny * r.nz;
         L.total_mask_words += mask_words(cells);
-        for (int s = 0; s < kNumShapes; ++s) {
+        for (int s = 0; s < kNumGeomShapes; ++s) {
             const uint64_t band = (r.ny % kShapes[s].cpt == 0) ? cells / kShapes[s].cpt : 0;
             L.total_blocks[s] += uint32_t((band + kShapes[s].bs - 1) / kShapes[s].bs);
         }
@@ -1140,7 +1161,7 @@ EnsLayout ens_layout(const lbm_ensemble_desc *d, const lbm_replica_desc *reps) {
     size_t o = 0;
     L.o_reps = o;
     o += align_up(sizeof(Replica) * size_t(d->nrep), kAlign);
-    for (int s = 0; s < kNumShapes; ++s) {
+    for (int s = 0; s < kNumGeomShapes; ++s) {
         L.o_blk[s] = o;
         o += align_up(size_t(L.total_blocks[s]) * 2 + 2, kAlign);
     }
@@ -1201,12 +1222,13 @@ ParticleArgs ens_particle_args(lbm_ens *e) {
     return pa;
 }
 
-template <class C, int CPT, int BS>
+template <class C, int CPT, int BS, bool NTS>
 void ens_collide_shape(lbm_ens *e, const typename C::T *A, typename C::T *B, int par) {
     using R = typename C::R;
-    hipLaunchKernelGGL((k_ens_collide<C, CPT, BS>), dim3(e->total_blocks[e->shape]), dim3(BS), 0,
-                       e->stream, A, B, e->reps, e->blk_rep[e->shape], e->shape, e->force[par],
-                       e->mask[par], R(e->enc_s), R(e->dec_s), e->clock, e->vacf_on);
+    const int sh = e->shape & 3;
+    hipLaunchKernelGGL((k_ens_collide<C, CPT, BS, NTS>), dim3(e->total_blocks[sh]), dim3(BS), 0,
+                       e->stream, A, B, e->reps, e->blk_rep[sh], sh, e->force[par], e->mask[par],
+                       R(e->enc_s), R(e->dec_s), e->clock, e->vacf_on);
 }
 
 // One step of every replica; par = field parity of this step.
@@ -1221,12 +1243,9 @@ void ens_launch_step(lbm_ens *e, int cur, int par) {
                        dim3(unsigned((uint64_t(e->n) * 8 + kParticleBlock - 1) / kParticleBlock)),
                        dim3(kParticleBlock), 0, e->stream, A, e->reps, e->part_rep, R(e->dec_s), pa,
                        e->clock, e->force[par], e->mask[par], e->force[par ^ 1], e->mask[par ^ 1]);
-    switch (e->shape) {
-        case 1: ens_collide_shape<C, 1, 256>(e, A, B, par); break;
-        case 2: ens_collide_shape<C, 2, 512>(e, A, B, par); break;
-        case 3: ens_collide_shape<C, 2, 256>(e, A, B, par); break;
-        default: ens_collide_shape<C, 1, 512>(e, A, B, par); break;
-    }
+#define LBM_ENS_CALL(CPT, BS, NTS) ens_collide_shape<C, CPT, BS, NTS>(e, A, B, par)
+    LBM_CONFIG_SWITCH(e->shape, LBM_ENS_CALL)
+#undef LBM_ENS_CALL
 }
 
 void ens_dispatch_step(lbm_ens *e, int cur, int par) {
@@ -1276,26 +1295,23 @@ bool ens_capture(lbm_ens *e) {
     return true;
 }
 
-template <class C, int CPT, int BS>
+template <class C, int CPT, int BS, bool NTS>
 void ens_time_shape(lbm_ens *e, int k) {
     // A -> B without swapping (the state in A is untouched); the caller
     // restores the device clock the launches advance.
     const int saved = e->shape;
     e->shape = k;
-    ens_collide_shape<C, CPT, BS>(e, static_cast<const typename C::T *>(e->pop[e->cur]),
-                                  static_cast<typename C::T *>(e->pop[e->cur ^ 1]),
-                                  int((e->step + 1) & 1));  // last step's node forces
+    ens_collide_shape<C, CPT, BS, NTS>(e, static_cast<const typename C::T *>(e->pop[e->cur]),
+                                       static_cast<typename C::T *>(e->pop[e->cur ^ 1]),
+                                       int((e->step + 1) & 1));  // last step's node forces
     e->shape = saved;
 }
 
 template <class C>
 void ens_time_dispatch(lbm_ens *e, int k) {
-    switch (k) {
-        case 1: ens_time_shape<C, 1, 256>(e, k); break;
-        case 2: ens_time_shape<C, 2, 512>(e, k); break;
-        case 3: ens_time_shape<C, 2, 256>(e, k); break;
-        default: ens_time_shape<C, 1, 512>(e, k); break;
-    }
+#define LBM_ENS_TIME(CPT, BS, NTS) ens_time_shape<C, CPT, BS, NTS>(e, k)
+    LBM_CONFIG_SWITCH(k, LBM_ENS_TIME)
+#undef LBM_ENS_TIME
 }
 
 void ens_time_any(lbm_ens *e, int k) {
@@ -1333,14 +1349,14 @@ lbm_status lbm_ens_init(const lbm_ensemble_desc *desc, const lbm_replica_desc *r
     e->nrep = desc->nrep;
     e->host_reps = static_cast<lbm_replica_desc *>(malloc(sizeof(lbm_replica_desc) * e->nrep));
     e->host_table = static_cast<Replica *>(calloc(e->nrep, sizeof(Replica)));
-    uint16_t *blk[kNumShapes];
-    for (int s = 0; s < kNumShapes; ++s)
+    uint16_t *blk[kNumGeomShapes];
+    for (int s = 0; s < kNumGeomShapes; ++s)
         blk[s] = static_cast<uint16_t *>(malloc(size_t(L.total_blocks[s]) * 2 + 2));
     uint16_t *prep = static_cast<uint16_t *>(malloc(size_t(L.n) * 2));
     bool ok = e->host_reps && e->host_table && prep;
-    for (int s = 0; s < kNumShapes; ++s) ok = ok && blk[s];
+    for (int s = 0; s < kNumGeomShapes; ++s) ok = ok && blk[s];
     if (!ok) {
-        for (int s = 0; s < kNumShapes; ++s) free(blk[s]);
+        for (int s = 0; s < kNumGeomShapes; ++s) free(blk[s]);
         free(prep);
         free(e->host_reps);
         free(e->host_table);
@@ -1361,11 +1377,12 @@ lbm_status lbm_ens_init(const lbm_ensemble_desc *desc, const lbm_replica_desc *r
     e->total_cells = L.total_cells;
     e->total_pop = L.total_pop;
     e->total_mask_words = L.total_mask_words;
-    for (int s = 0; s < kNumShapes; ++s) e->total_blocks[s] = L.total_blocks[s];
+    e->shape = L.lattice_bytes >= kStreamStoreBytes ? kNumGeomShapes : 0;  // until autotune
+    for (int s = 0; s < kNumGeomShapes; ++s) e->total_blocks[s] = L.total_blocks[s];
     e->n = L.n;
     char *base = static_cast<char *>(scratch);
     e->reps = reinterpret_cast<Replica *>(base + L.o_reps);
-    for (int s = 0; s < kNumShapes; ++s) e->blk_rep[s] = reinterpret_cast<uint16_t *>(base + L.o_blk[s]);
+    for (int s = 0; s < kNumGeomShapes; ++s) e->blk_rep[s] = reinterpret_cast<uint16_t *>(base + L.o_blk[s]);
     e->part_rep = reinterpret_cast<uint16_t *>(base + L.o_part);
     for (int k = 0; k < 2; ++k) {
         e->mask[k] = reinterpret_cast<uint32_t *>(base + L.o_mask[k]);
@@ -1383,7 +1400,7 @@ lbm_status lbm_ens_init(const lbm_ensemble_desc *desc, const lbm_replica_desc *r
     e->use_graph = 1;
     // replica table, block and particle maps
     uint64_t pop_off = 0, cell_off = 0, mask_off = 0;
-    uint32_t first[kNumShapes] = {0, 0, 0, 0};
+    uint32_t first[kNumGeomShapes] = {0, 0, 0, 0};
     uint32_t part_off = 0;
     for (int32_t k = 0; k < e->nrep; ++k) {
         const lbm_replica_desc &rd = reps[k];
@@ -1403,7 +1420,7 @@ lbm_status lbm_ens_init(const lbm_ensemble_desc *desc, const lbm_replica_desc *r
         t.omega = 1.0 / rd.tau;
         const double nu = (rd.tau - 0.5) / 3.0;
         t.R = desc->radius > 0.0 ? desc->radius : desc->gamma / (6.0 * M_PI * nu);
-        for (int s = 0; s < kNumShapes; ++s) {
+        for (int s = 0; s < kNumGeomShapes; ++s) {
             t.first_block[s] = first[s];
             const uint64_t band = (rd.ny % kShapes[s].cpt == 0) ? t.g.ncell / kShapes[s].cpt : 0;
             const uint32_t nb = uint32_t((band + kShapes[s].bs - 1) / kShapes[s].bs);
@@ -1424,14 +1441,14 @@ lbm_status lbm_ens_init(const lbm_ensemble_desc *desc, const lbm_replica_desc *r
     if (err == hipSuccess)
         err = hipMemcpyAsync(e->reps, e->host_table, sizeof(Replica) * e->nrep,
                              hipMemcpyHostToDevice, e->stream);
-    for (int s = 0; s < kNumShapes && err == hipSuccess; ++s)
+    for (int s = 0; s < kNumGeomShapes && err == hipSuccess; ++s)
         if (L.total_blocks[s] > 0)
             err = hipMemcpyAsync(e->blk_rep[s], blk[s], size_t(L.total_blocks[s]) * 2,
                                  hipMemcpyHostToDevice, e->stream);
     if (err == hipSuccess)
         err = hipMemcpyAsync(e->part_rep, prep, size_t(L.n) * 2, hipMemcpyHostToDevice, e->stream);
     if (err == hipSuccess) err = hipStreamSynchronize(e->stream);  // host staging is freed below
-    for (int s = 0; s < kNumShapes; ++s) free(blk[s]);
+    for (int s = 0; s < kNumGeomShapes; ++s) free(blk[s]);
     free(prep);
     if (err != hipSuccess) {
         free(e->host_reps);
@@ -1525,9 +1542,9 @@ lbm_status lbm_ens_autotune(lbm_ens *e, int32_t iters, double *ms, int32_t *chos
     double t[kNumShapes];
     for (int k = 0; k < kNumShapes && err == hipSuccess; ++k) {
         t[k] = -1.0;
-        if (e->total_blocks[k] == 0) continue;
+        if (e->total_blocks[k & 3] == 0) continue;
         bool all = true;
-        for (int32_t q = 0; q < e->nrep; ++q) all = all && (e->host_reps[q].ny % kShapes[k].cpt == 0);
+        for (int32_t q = 0; q < e->nrep; ++q) all = all && (e->host_reps[q].ny % kShapes[k & 3].cpt == 0);
         if (!all) continue;
         for (int w = 0; w < 2; ++w) ens_time_any(e, k);
         (void)hipEventRecord(e0, e->stream);
@@ -1811,6 +1828,8 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
     ap.replica = pd.replica;
     const unsigned pgrid = np > 0 ? unsigned(particle_blocks(np)) : 0;
     const unsigned cgrid = blocks_for(c->g.ncell);
+    // the adjoint lattice is FP64: stream its stores once it outgrows the cache
+    const bool stream_stores = adj_lattice_bytes(c) >= kStreamStoreBytes;
 
     int cur = 0;
     const int32_t nseg = (N + K - 1) / K;
@@ -1851,11 +1870,20 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
                 hipLaunchKernelGGL(k_adj_particle<C>, dim3(pgrid), dim3(kParticleBlock), 0, st,
                                    seg(k), c->g, R(c->dec_s), abar[cur], gd, ap, uf[par],
                                    uf[par ^ 1]);
-                hipLaunchKernelGGL((k_adj_collide<C, true>), dim3(cgrid), dim3(kBlock), 0, st,
+                if (stream_stores)
+                    hipLaunchKernelGGL((k_adj_collide<C, true, true>), dim3(cgrid), dim3(kBlock), 0,
+                                       st, seg(k), c->g, R(c->dec_s), abar[cur], abar[cur ^ 1], gd,
+                                       1.0 / c->desc.tau, uf[par], wacc);
+                else
+                    hipLaunchKernelGGL((k_adj_collide<C, true, false>), dim3(cgrid), dim3(kBlock), 0,
+                                       st, seg(k), c->g, R(c->dec_s), abar[cur], abar[cur ^ 1], gd,
+                                       1.0 / c->desc.tau, uf[par], wacc);
+            } else if (stream_stores) {
+                hipLaunchKernelGGL((k_adj_collide<C, false, true>), dim3(cgrid), dim3(kBlock), 0, st,
                                    seg(k), c->g, R(c->dec_s), abar[cur], abar[cur ^ 1], gd,
-                                   1.0 / c->desc.tau, uf[par], wacc);
+                                   1.0 / c->desc.tau, ff_unused, wacc);
             } else {
-                hipLaunchKernelGGL((k_adj_collide<C, false>), dim3(cgrid), dim3(kBlock), 0, st,
+                hipLaunchKernelGGL((k_adj_collide<C, false, false>), dim3(cgrid), dim3(kBlock), 0, st,
                                    seg(k), c->g, R(c->dec_s), abar[cur], abar[cur ^ 1], gd,
                                    1.0 / c->desc.tau, ff_unused, wacc);
             }

@@ -223,6 +223,10 @@ class Lattice:
             self.ctx, int(iters), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(chosen)))
         return chosen.value, ms
 
+    def set_shape(self, k: int):
+        """Use stream-collide launch configuration k (see lbm_set_shape)."""
+        _abi.check("lbm_set_shape", self.lib.lbm_set_shape(self.ctx, int(k)))
+
     @property
     def step_count(self) -> int:
         s = ctypes.c_int64()

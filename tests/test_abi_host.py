@@ -153,3 +153,11 @@ def test_ensemble_sizes_and_validation(lib):
     out = ctypes.c_void_p()
     assert lib.lbm_ens_init(None, reps, None, None, None, None, None, None, ctypes.byref(out)) == 1
     assert lib.lbm_ens_step(None, 1) == 1
+
+
+def test_launch_configuration_count_matches_header():
+    from paper_1909_13412_amd import _abi
+
+    text = open(os.path.join(ROOT, "include", "lbmbp.h")).read()
+    m = re.search(r"#define LBM_NUM_SHAPES (\d+)", text)
+    assert m and int(m.group(1)) == _abi.LBM_NUM_SHAPES == 8
