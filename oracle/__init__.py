@@ -70,6 +70,8 @@ def _load():
         "ora_get_particles": (None, [vp, dp, dp]),
         "ora_get_particle_forces": (None, [vp, dp, dp]),
         "ora_set_particle_force": (None, [vp, dp]),
+        "ora_set_pair_force": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double]),
+        "ora_get_pair_forces": (None, [vp, dp]),
         "ora_radius": (ctypes.c_double, [vp]),
         "ora_vacf_config": (ctypes.c_int, [vp, i32, i32]),
         "ora_vacf_get": (None, [vp, dp, ctypes.POINTER(i64)]),
@@ -217,6 +219,16 @@ class Sim:
         """Constant force F_C on each particle, [n, 3] (None: none)."""
         self._fc = None if F is None else _f64(F, (self.np, 3))
         self._lib.ora_set_particle_force(self._h, _dp(self._fc))
+
+    def set_pair_force(self, a_f: float, r_c: float = 1.0):
+        """Soft pair repulsion a_f (1 - r/r_c) for r < r_c (a_f = 0: off)."""
+        if self._lib.ora_set_pair_force(self._h, float(a_f), float(r_c)) != 0:
+            raise ValueError("oracle: invalid pair force")
+
+    def pair_forces(self) -> np.ndarray:
+        F = np.zeros((self.np, 3))
+        self._lib.ora_get_pair_forces(self._h, _dp(F))
+        return F
 
     def particles(self):
         r = np.zeros((self.np, 3))

@@ -132,6 +132,26 @@ def fit_corners(r, shape):
     return c0, node
 
 
+def pair_forces(r, shape, a_f: float, r_c: float):
+    """Soft pair repulsion a_f (1 - |d|/r_c) d/|d| for |d| < r_c (Eq. s2-softpot
+    read as the DPD conservative force), nearest periodic image; complex-safe
+    (the image and the cutoff test use the real part)."""
+    nz, ny, nx = shape
+    Lv = np.array([nx, ny, nz], dtype=np.float64)
+    n = r.shape[0]
+    F = np.zeros(r.shape, dtype=np.result_type(r, np.float64))
+    for i in range(n):
+        for j in range(n):
+            if i == j:
+                continue
+            d = r[i] - r[j]
+            d = d - Lv * np.round(np.real(d) / Lv)
+            dist = np.sqrt((d * d).sum())
+            if np.real(dist) > 0.0 and np.real(dist) < r_c:
+                F[i] = F[i] + a_f * (1.0 - dist / r_c) / dist * d
+    return F
+
+
 def particle_update(f8, V, r, theta, xi, c, shape, friction: int, radius: float, fc=None,
                     cfit=None):
     """One particle's step as a function of the populations at its eight
@@ -186,17 +206,23 @@ def particle_update(f8, V, r, theta, xi, c, shape, friction: int, radius: float,
         spread = np.zeros(Wt.shape + (3,), dtype=np.result_type(FH, Wt))
     else:
         spread = -FH[:, None, :] * Wt[..., None]
-    Fsum = FH + FR if fc is None else fc[None, :] + FH + FR
+    if fc is None:
+        Fsum = FH + FR
+    else:
+        Fsum = (fc if np.ndim(fc) == 2 else fc[None, :]) + FH + FR
     Vn = V + Fsum / M[:, None]
     rn = r + Vn
     return Vn, rn, spread
 
 
-def step(f, r, V, theta, xi_k, friction: int, radius: float, fc=None, body=None):
+def step(f, r, V, theta, xi_k, friction: int, radius: float, fc=None, body=None, pair=None):
     """One coupled step; returns (f', r', V', F) with F the node-force field.
     fc: given force on each particle [n, 3] or None; body: uniform body force
-    [3] on every node or None."""
+    [3] on every node or None; pair: (a_f, r_c) of the pair repulsion or None."""
     shape = f.shape[1:]
+    if pair is not None and r.shape[0]:
+        fp = pair_forces(r, shape, *pair)
+        fc = fp if fc is None else fc + fp
     ncell = int(np.prod(shape))
     dtype = np.result_type(f, r, V, theta)
     F = np.zeros((3, ncell), dtype=dtype)
@@ -222,7 +248,8 @@ def step(f, r, V, theta, xi_k, friction: int, radius: float, fc=None, body=None)
     return stream(fs), rn, Vn, Fg
 
 
-def run(f0, r0, V0, theta, xi, friction="stokeslet", radius=0.0, keep=False, fc=None, body=None):
+def run(f0, r0, V0, theta, xi, friction="stokeslet", radius=0.0, keep=False, fc=None, body=None,
+        pair=None):
     """N = len(xi) steps from (f0, r0, V0) with parameters theta (gamma, tau,
     M, kT).  Returns (f, r, V) at the end, plus the per-step states (f^n, r^n,
     V^n, F^n) when keep."""
@@ -231,7 +258,7 @@ def run(f0, r0, V0, theta, xi, friction="stokeslet", radius=0.0, keep=False, fc=
     theta = np.asarray(theta)
     traj = []
     for k in range(len(xi)):
-        fn, rn, Vn, F = step(f, r, V, theta, xi[k], friction, radius, fc, body)
+        fn, rn, Vn, F = step(f, r, V, theta, xi[k], friction, radius, fc, body, pair)
         if keep:
             traj.append((f, r, V, F))
         f, r, V = fn, rn, Vn
@@ -239,20 +266,22 @@ def run(f0, r0, V0, theta, xi, friction="stokeslet", radius=0.0, keep=False, fc=
 
 
 def jvp(f0, r0, V0, theta, xi, df, dr, dV, dtheta, friction="stokeslet", radius=0.0, fc=None,
-        body=None):
+        body=None, pair=None):
     """Directional derivative of S_N along (df, dr, dV, dtheta), complex step."""
     f, r, V = run(f0 + 1j * H * df, r0 + 1j * H * dr, V0 + 1j * H * dV,
                   np.asarray(theta) + 1j * H * np.asarray(dtheta), xi, friction, radius, fc=fc,
-                  body=body)
+                  body=body, pair=pair)
     return np.imag(f) / H, np.imag(r) / H, np.imag(V) / H
 
 
-def vjp(f0, r0, V0, theta, xi, cf, cr, cV, friction="stokeslet", radius=0.0, fc=None, body=None):
+def vjp(f0, r0, V0, theta, xi, cf, cr, cV, friction="stokeslet", radius=0.0, fc=None, body=None,
+        pair=None):
     """Gradient of J = <cf, f^N> + <cr, r^N> + <cV, V^N> with respect to f0, r0,
     V0 and theta, by a reverse sweep with complex-step local Jacobians."""
     fr_mode = FRICTION[friction] if isinstance(friction, str) else int(friction)
     theta = np.asarray(theta, dtype=np.float64)
-    _, _, _, traj = run(f0, r0, V0, theta, xi, fr_mode, radius, keep=True, fc=fc, body=body)
+    _, _, _, traj = run(f0, r0, V0, theta, xi, fr_mode, radius, keep=True, fc=fc, body=body,
+                        pair=pair)
     shape = f0.shape[1:]
     ncell = int(np.prod(shape))
     gf = np.array(cf, dtype=np.float64)
@@ -294,16 +323,19 @@ def vjp(f0, r0, V0, theta, xi, cf, cr, cV, friction="stokeslet", radius=0.0, fc=
             gfl = gfn.reshape(q, ncell)
             new_gr = np.zeros_like(gr)
             new_gV = np.zeros_like(gV)
+            fstep = np.zeros((n, 3)) if fc is None else np.array(fc, dtype=np.float64)
+            if pair is not None:
+                fstep = fstep + pair_forces(r, shape, *pair)
+            gfc = np.zeros((n, 3))
             for i in range(n):
                 f8 = fl[:, nfit[i]].T                      # [8, q]
                 nq = 8 * q
-                nin = nq + 3 + 3 + 4
-                base = np.concatenate([f8.ravel(), V[i], r[i], theta]).astype(complex)
+                nin = nq + 3 + 3 + 4 + 3
+                base = np.concatenate([f8.ravel(), V[i], r[i], theta, fstep[i]]).astype(complex)
                 X = np.tile(base, (nin, 1)) + 1j * H * np.eye(nin)
                 v1, r1, sp = particle_update(X[:, :nq].reshape(nin, 8, q), X[:, nq:nq + 3],
                                              X[:, nq + 3:nq + 6], X[:, nq + 6:nq + 10], xi[k][i],
-                                             c[i], shape,
-                                             fr_mode, radius, None if fc is None else fc[i],
+                                             c[i], shape, fr_mode, radius, X[:, nq + 10:nq + 13],
                                              cfit[i])
                 jv, jr, jsp = np.imag(v1) / H, np.imag(r1) / H, np.imag(sp) / H
                 ybar_sp = gFl[:, node[i]].T                # [8, 3] gradient of each node force
@@ -314,6 +346,15 @@ def vjp(f0, r0, V0, theta, xi, cf, cr, cV, friction="stokeslet", radius=0.0, fc=
                 new_gV[i] = xbar[nq:nq + 3]
                 new_gr[i] = xbar[nq + 3:nq + 6]
                 gth += xbar[nq + 6:nq + 10]
+                gfc[i] = xbar[nq + 10:nq + 13]
+            if pair is not None:
+                # the pair forces move with every position: columns of d F_C / d r
+                for j in range(n):
+                    for kk in range(3):
+                        dr_ = np.zeros((n, 3), dtype=complex)
+                        dr_[j, kk] = 1j * H
+                        col = np.imag(pair_forces(r + dr_, shape, *pair)) / H
+                        new_gr[j, kk] += (col * gfc).sum()
             gr, gV = new_gr, new_gV
         gf = gfn
     return gf, gr, gV, gth

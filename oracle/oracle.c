@@ -74,6 +74,8 @@ struct ora_sim {
     int32_t friction;
     double *r, *v, *fh, *fr; /* [np][3] */
     double *fc;              /* optional force F_C on each particle, [np][3] */
+    double pair_a, pair_rc;  /* soft pair repulsion (a_f, cutoff); a_f = 0: off */
+    double *fpair;           /* pair forces of the current step, [np][3] */
     int64_t step;
     /* velocity autocorrelation */
     int32_t vacf_on, max_lag, stride, nslot;
@@ -284,7 +286,7 @@ void ora_destroy(ora_sim *o)
 {
     if (!o) return;
     free(o->f); free(o->fnew); free(o->rho); free(o->u); free(o->F); free(o->body);
-    free(o->r); free(o->v); free(o->fh); free(o->fr); free(o->fc);
+    free(o->r); free(o->v); free(o->fh); free(o->fr); free(o->fc); free(o->fpair);
     free(o->orig); free(o->orig_t); free(o->acc); free(o->cnt);
     free(o);
 }
@@ -354,8 +356,9 @@ int ora_set_particles(ora_sim *o, int32_t n, const double *r, const double *v,
                       uint64_t seed, uint32_t replica, int32_t friction)
 {
     if (n < 0 || !(mass > 0.0) || !(gamma >= 0.0) || !(kT >= 0.0)) return -1;
-    free(o->r); free(o->v); free(o->fh); free(o->fr); free(o->fc);
-    o->r = o->v = o->fh = o->fr = o->fc = NULL;
+    free(o->r); free(o->v); free(o->fh); free(o->fr); free(o->fc); free(o->fpair);
+    o->r = o->v = o->fh = o->fr = o->fc = o->fpair = NULL;
+    o->pair_a = 0.0;
     o->np = n;
     o->mass = mass; o->gamma = gamma; o->kT = kT;
     /* Stokes' law gamma = 6 pi eta R with eta = rho0 nu and nu = (tau - 1/2)/3
@@ -372,6 +375,27 @@ int ora_set_particles(ora_sim *o, int32_t n, const double *r, const double *v,
         memcpy(o->v, v, sizeof(double) * 3 * (size_t)n);
     }
     return 0;
+}
+
+int ora_set_pair_force(ora_sim *o, double a_f, double r_c)
+{
+    free(o->fpair);
+    o->fpair = NULL;
+    o->pair_a = 0.0;
+    if (a_f == 0.0) return 0;
+    double half = 0.5 * (double)(o->nx < o->ny ? (o->nx < o->nz ? o->nx : o->nz)
+                                               : (o->ny < o->nz ? o->ny : o->nz));
+    if (!isfinite(a_f) || !(r_c > 0.0) || r_c > half || o->np == 0) return -1;
+    o->pair_a = a_f;
+    o->pair_rc = r_c;
+    o->fpair = (double *)calloc(3 * (size_t)o->np, sizeof(double));
+    return 0;
+}
+
+void ora_get_pair_forces(const ora_sim *o, double *F)
+{
+    if (o->fpair) memcpy(F, o->fpair, sizeof(double) * 3 * (size_t)o->np);
+    else memset(F, 0, sizeof(double) * 3 * (size_t)o->np);
 }
 
 void ora_set_particle_force(ora_sim *o, const double *F)
@@ -547,14 +571,42 @@ static void collide_stream(ora_sim *o)
     o->fnew = t;
 }
 
+/* Conservative inter-particle force of Eq. s2-softpot, read as the soft
+ * repulsion of dissipative particle dynamics: every pair closer than the
+ * cutoff r_c pushes apart with a_f (1 - r/r_c) along the line of centres
+ * (the force of the potential (a_f r_c / 2)(1 - r/r_c)^2), nearest periodic
+ * image, all pairs visited. */
+static void pair_forces(ora_sim *o)
+{
+    const double L[3] = {(double)o->nx, (double)o->ny, (double)o->nz};
+    for (int i = 0; i < o->np; ++i) {
+        double F[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < o->np; ++j) {
+            if (j == i) continue;
+            double d[3], rr = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                d[k] = o->r[3 * i + k] - o->r[3 * j + k];
+                d[k] -= L[k] * round(d[k] / L[k]);
+                rr += d[k] * d[k];
+            }
+            double r = sqrt(rr);
+            if (!(r > 0.0) || !(r < o->pair_rc)) continue;
+            double mag = o->pair_a * (1.0 - r / o->pair_rc) / r;
+            for (int k = 0; k < 3; ++k) F[k] += mag * d[k];
+        }
+        for (int k = 0; k < 3; ++k) o->fpair[3 * i + k] = F[k];
+    }
+}
+
 /* Langevin update (Eqs. s2-langevin, s2-langevin2) with the lattice time step:
- * V^{n+1} = V^n + (F_C + F_H + F_R)/M, r^{n+1} = r^n + V^{n+1}.  F_C is a
- * given force per particle (zero unless set); no inter-particle force. */
+ * V^{n+1} = V^n + (F_C + F_H + F_R)/M, r^{n+1} = r^n + V^{n+1}.  F_C is the
+ * pair force of the step (if enabled) plus a given force per particle. */
 static void advance_particles(ora_sim *o)
 {
     for (int i = 0; i < o->np; ++i)
         for (int k = 0; k < 3; ++k) {
             double fc = o->fc ? o->fc[3 * i + k] : 0.0;
+            if (o->fpair) fc += o->fpair[3 * i + k];
             o->v[3 * i + k] += (fc + o->fh[3 * i + k] + o->fr[3 * i + k]) / o->mass;
             o->r[3 * i + k] += o->v[3 * i + k];
         }
@@ -570,6 +622,7 @@ void ora_step(ora_sim *o, int32_t nsteps)
         else
             memset(o->F, 0, sizeof(double) * 3 * (size_t)n);
         couple_particles(o);
+        if (o->fpair) pair_forces(o);
         if (o->vacf_on && o->np > 0) vacf_sample(o);
         collide_stream(o);
         advance_particles(o);

@@ -77,6 +77,12 @@ void ora_get_particle_forces(const ora_sim *o, double *fh, double *fr);
 /* Constant force F_C of Eq. s2-langevin on each particle, [n][3] (NULL: none);
  * cleared by ora_set_particles. */
 void ora_set_particle_force(ora_sim *o, const double *F);
+/* Soft pair repulsion (Eq. s2-softpot read as the DPD conservative force):
+ * a_f (1 - r/r_c) along the line of centres for r < r_c; a_f = 0 switches it
+ * off.  Returns -1 for r_c outside (0, min(L)/2] or without particles;
+ * cleared by ora_set_particles.  ora_get_pair_forces: last step's, [n][3]. */
+int ora_set_pair_force(ora_sim *o, double a_f, double r_c);
+void ora_get_pair_forces(const ora_sim *o, double *F);
 double ora_radius(const ora_sim *o);
 
 /* Velocity autocorrelation: origins every `stride` steps, lags 0..max_lag. */

@@ -200,3 +200,37 @@ def test_mass_and_momentum_gradients_are_exact():
     assert np.max(np.abs(gr)) < 1e-11
     assert abs(gth[0]) < 1e-11 and abs(gth[1]) < 1e-11
     assert gth[2] == pytest.approx(v0[:, 0].sum() - vN[:, 0].sum(), abs=1e-12)
+
+
+def test_pair_force_forward_and_transpose():
+    # The soft pair repulsion couples the particles through their positions.
+    rng, f0, r0, v0 = _setup(seed=9, n=5)
+    r0 = 3.0 + rng.uniform(0, 1.2, (5, 3))  # close enough to interact
+    theta = np.array([1.0, 0.8, 10.0, 1e-4])
+    N, pair = 6, (0.02, 1.0)
+    L = f0.shape[1]
+    o = oracle.Sim(L, L, L, theta[1])
+    o.set_populations(f0)
+    o.set_particles(r0, v0, mass=10.0, gamma=1.0, kT=1e-4, seed=5)
+    o.set_pair_force(*pair)
+    o.step(N)
+    xi = A.noise(5, N, 5)
+    f, r, v = A.run(f0, r0, v0, theta, xi, pair=pair)
+    assert np.max(np.abs(o.pair_forces())) > 0.0
+    assert np.max(np.abs(f - o.populations())) < 1e-14
+    assert np.max(np.abs(v - o.particles()[1])) < 1e-15
+    cf = rng.standard_normal(f0.shape)
+    cr = rng.standard_normal(r0.shape)
+    cv = rng.standard_normal(v0.shape)
+    gf, gr, gv, gth = A.vjp(f0, r0, v0, theta, xi, cf, cr, cv, pair=pair)
+    df = rng.standard_normal(f0.shape)
+    dr = rng.standard_normal(r0.shape)
+    dv = rng.standard_normal(v0.shape)
+    dth = rng.standard_normal(4)
+    jf, jr, jv = A.jvp(f0, r0, v0, theta, xi, df, dr, dv, dth, pair=pair)
+    lhs = (gf * df).sum() + (gr * dr).sum() + (gv * dv).sum() + (gth * dth).sum()
+    rhs = (cf * jf).sum() + (cr * jr).sum() + (cv * jv).sum()
+    assert abs(lhs - rhs) < 1e-11 * (abs(rhs) + 1.0)
+    # and the pair term matters: dropping it changes the position gradient
+    gf2, gr2, gv2, _ = A.vjp(f0, r0, v0, theta, xi, cf, cr, cv)
+    assert np.max(np.abs(gr2 - gr)) > 1e-6 * np.max(np.abs(gr))

@@ -451,3 +451,78 @@ def test_finite_box_momentum_plateau(oracle_mod):
     assert np.max(np.abs(v[0, 1:])) < 1e-4 * vinf
     o = s.observables()
     assert abs((o[1] + o[4]) / (M * 0.01) - 1.0) < 1e-12
+
+
+def _pair_sim(oracle_mod, r, L=12, a_f=0.5, r_c=1.5):
+    s = oracle_mod.Sim(L, L, L, 0.8)
+    s.set_particles(r, np.zeros_like(r), mass=10.0, gamma=1.0, friction="bd")
+    s.set_pair_force(a_f, r_c)
+    s.step(1)  # pair forces of the positions at the start of the step
+    return s.pair_forces()
+
+
+def test_pair_force_two_body_and_periodic_image(oracle_mod):
+    # Eq. s2-softpot as the DPD conservative force: a_f (1 - r/r_c) along the
+    # line of centres, repulsive, equal and opposite, zero beyond the cutoff,
+    # measured through the nearest periodic image.
+    a_f, r_c = 0.5, 1.5
+    rng = np.random.default_rng(41)
+    for dist in (0.2, 0.9, 1.49):
+        e = rng.standard_normal(3)
+        e /= np.linalg.norm(e)
+        r = np.array([[5.0, 6.0, 4.0], [5.0, 6.0, 4.0] + dist * e])
+        F = _pair_sim(oracle_mod, r, a_f=a_f, r_c=r_c)
+        want = a_f * (1 - dist / r_c) * (-e)
+        assert np.allclose(F[0], want, rtol=1e-12, atol=1e-17)
+        assert np.allclose(F[1], -want, rtol=1e-12, atol=1e-17)
+    F = _pair_sim(oracle_mod, np.array([[5.0, 6.0, 4.0], [6.6, 6.0, 4.0]]))
+    assert np.max(np.abs(F)) == 0.0
+    # across the box edge: x = 0.3 and x = 11.6 are 0.7 apart
+    F = _pair_sim(oracle_mod, np.array([[0.3, 2.0, 2.0], [11.6, 2.0, 2.0]]), a_f=a_f, r_c=r_c)
+    assert np.allclose(F[0], [a_f * (1 - 0.7 / r_c), 0, 0], rtol=1e-12)
+    with pytest.raises(ValueError):
+        _pair_sim(oracle_mod, np.array([[1.0, 1.0, 1.0]]), r_c=6.5)  # beyond half the box
+
+
+def test_pair_force_is_minus_gradient_of_the_pair_energy(oracle_mod):
+    # F_i = -dU/dr_i with U = sum over pairs of (a_f r_c / 2)(1 - r/r_c)^2,
+    # checked by central differences of U over a random cluster.
+    a_f, r_c, L = 0.8, 1.8, 8.0
+    rng = np.random.default_rng(42)
+    r = rng.uniform(2.0, 4.5, (7, 3))
+
+    def energy(x):
+        u = 0.0
+        for i in range(len(x)):
+            for j in range(i + 1, len(x)):
+                d = x[i] - x[j]
+                d -= L * np.round(d / L)
+                dist = np.linalg.norm(d)
+                if dist < r_c:
+                    u += 0.5 * a_f * r_c * (1 - dist / r_c) ** 2
+        return u
+
+    F = _pair_sim(oracle_mod, r, L=8, a_f=a_f, r_c=r_c)
+    h = 1e-6
+    for i in range(len(r)):
+        for k in range(3):
+            xp, xm = r.copy(), r.copy()
+            xp[i, k] += h
+            xm[i, k] -= h
+            assert abs(F[i, k] + (energy(xp) - energy(xm)) / (2 * h)) < 1e-8
+    assert np.allclose(F.sum(0), 0.0, atol=1e-15)
+
+
+def test_pair_force_conserves_total_momentum(oracle_mod):
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    L = 10
+    s = oracle_mod.Sim(L, L, L, 0.8)
+    r = particle_positions(12, (4, 4, 4), seed=5) + 3.0  # a crowded cluster
+    s.set_particles(r, particle_velocities(12, 1e-5, seed=5), mass=10.0, gamma=1.0)
+    s.set_pair_force(0.3, 1.2)
+    o = s.observables()
+    s.step(30)
+    o1 = s.observables()
+    assert np.max(np.abs(s.pair_forces())) > 0.0
+    assert np.allclose(o1[1:4] + o1[4:7], o[1:4] + o[4:7], rtol=0, atol=1e-14)
