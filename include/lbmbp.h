@@ -120,7 +120,7 @@ lbm_status lbm_lattice_bytes(const lbm_grid_desc *grid, size_t *bytes);
 lbm_status lbm_grid_scratch_bytes(const lbm_grid_desc *grid, size_t *bytes);
 
 /* Bytes of particle scratch for n particles (corner bookkeeping, last-step
- * forces). */
+ * forces, the pair-force cell list). */
 lbm_status lbm_particle_scratch_bytes(const lbm_grid_desc *grid, int32_t n, size_t *bytes);
 
 /* Bytes of the VACF origin store for n particles: (max_lag/stride + 1) * n * 3 doubles. */
@@ -168,6 +168,21 @@ lbm_status particles_couple(lbm_ctx *ctx, const lbm_particle_desc *desc, double 
  * only through the friction.  LBM_E_STATE without particles; particles_couple
  * detaches it. */
 lbm_status lbm_set_particle_force(lbm_ctx *ctx, const double *f);
+
+/* Soft repulsion between particles, the conservative force F_C of Eq.
+ * s2-langevin with the potential of Eq. s2-softpot read as that of dissipative
+ * particle dynamics: a pair closer than r_c pushes apart with a_f (1 - r/r_c)
+ * along the line of centres (nearest periodic image), added to any force set
+ * with lbm_set_particle_force.  Neighbours come from a cell list (cells at
+ * least r_c wide, a deterministic sort, a fixed visiting order: bitwise
+ * reproducible).  a_f = 0 switches it off; r_c must lie in (0, min(nx, ny,
+ * nz)/2].  LBM_E_STATE without particles, LBM_E_UNSUPPORTED above 8192
+ * particles.  particles_couple switches it off.  Recorded runs differentiate
+ * through it (lbm_adjoint). */
+lbm_status lbm_set_pair_force(lbm_ctx *ctx, double a_f, double r_c);
+
+/* The pair forces of the last step into device FP64 [n][3] (zeros when off). */
+lbm_status lbm_pair_forces(lbm_ctx *ctx, double *fc);
 
 /* The radius the coupling uses (given or derived), or a negative value when no
  * particles are attached. */

@@ -17,7 +17,7 @@ FRICTION = {"stokeslet": 0, "pointwise": 1, "bd": 2, "stokeslet2dx": 3}
 EXPORTS = [
     "lbm_lattice_bytes", "lbm_grid_scratch_bytes", "lbm_particle_scratch_bytes",
     "lbm_vacf_origin_bytes", "lbm_init", "lbm_set_equilibrium", "lbm_set_populations",
-    "lbm_set_body_force", "lbm_get_populations", "lbm_get_moments", "particles_couple", "lbm_set_particle_force", "lbm_particle_radius",
+    "lbm_set_body_force", "lbm_get_populations", "lbm_get_moments", "particles_couple", "lbm_set_particle_force", "lbm_set_pair_force", "lbm_pair_forces", "lbm_particle_radius",
     "lbm_particle_forces", "lbm_vacf_config", "lbm_vacf_counts", "lbm_step", "lbm_series_config",
     "lbm_series_count", "lbm_observables",
     "lbm_profile_enable", "lbm_profile_read", "lbm_autotune", "lbm_set_shape", "lbm_get_step", "lbm_destroy",
@@ -91,6 +91,8 @@ def load() -> ctypes.CDLL:
         "particles_couple": [vp, pd, dp, dp, vp],
         "lbm_particle_forces": [vp, dp, dp],
         "lbm_set_particle_force": [vp, dp],
+        "lbm_set_pair_force": [vp, ctypes.c_double, ctypes.c_double],
+        "lbm_pair_forces": [vp, dp],
         "lbm_vacf_config": [vp, i32, i32, dp, dp],
         "lbm_vacf_counts": [vp, ctypes.POINTER(i64)],
         "lbm_step": [vp, i32],

@@ -51,7 +51,9 @@ struct AdjParticleArgs {
     const double *r, *v;   // state at step n, [n][3]
     double *rbar, *vbar;   // in: dJ/dr^{n+1}, dJ/dV^{n+1}; out: dJ/dr^n, dJ/dV^n
     double *pgrad;         // [n][4] running dJ/d(gamma, tau, M, kT)
-    const double *fext;    // given force F_C on each particle, [n][3] (nullptr: none)
+    const double *fext;    // given force on each particle, [n][3] (nullptr: none)
+    const double *fpair;   // pair forces of step n, [n][3] (nullptr: none)
+    double *fcbar;         // out: dJ/dF_C of step n, [n][3] (nullptr: not needed)
     uint32_t *prev_cell;   // [n][8] node each lane wrote one reverse step ago
     int32_t n;
     int32_t friction;
@@ -279,8 +281,10 @@ __global__ __launch_bounds__(kParticleBlock) void k_adj_particle(
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         FRb_xi += (Vt[k] / pa.mass) * xi[k];
-        const double fc = pa.fext ? pa.fext[3 * i + k] : 0.0;
+        double fc = pa.fext ? pa.fext[3 * i + k] : 0.0;
+        if (pa.fpair) fc += pa.fpair[3 * i + k];
         dM -= Vt[k] * (fc + FH[k] + pa.sig * xi[k]) / (pa.mass * pa.mass);
+        if (pa.fcbar) pa.fcbar[3 * i + k] = Vt[k] / pa.mass;
     }
     double *pg = pa.pgrad + 4 * int64_t(i);
     pg[0] += gam_b + R_b * pa.dR_dgamma + (pa.sig > 0.0 ? FRb_xi * pa.kT / pa.sig : 0.0);

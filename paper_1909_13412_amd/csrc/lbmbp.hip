@@ -31,6 +31,7 @@
 #include "codec.hpp"
 #include "collide.hpp"
 #include "velocities.hpp"
+#include "pairs.hpp"
 #include "particle.hpp"
 #include "philox.hpp"
 
@@ -340,6 +341,11 @@ struct lbm_ctx {
     uint32_t *prev_cell;
     double *fh, *fr;
     const double *fext;  // given force on each particle (lbm_set_particle_force) or null
+    // soft pair repulsion (lbm_set_pair_force)
+    int pair_on;
+    PairGrid pg;
+    uint64_t *pair_keys;  // particle scratch: [n] sorted cell keys
+    double *fpair;        // particle scratch: [n][3] pair forces of the last step
     // velocity autocorrelation
     int vacf_on;
     int32_t max_lag, stride, nslot;
@@ -366,6 +372,8 @@ struct lbm_ctx {
     lbm_particle_desc rec_pdesc;
     double rec_R;
     const double *rec_fext;
+    int rec_pair_on;
+    PairGrid rec_pg;
 };
 
 namespace {
@@ -440,6 +448,8 @@ size_t particle_scratch_size(int32_t n) {
     s += align_up(size_t(n) * 8 * 4, kAlign);  // prev cell
     s += align_up(particle_blocks(n) * 3 * 8, kAlign);  // momentum partials
     s += 2 * align_up(size_t(n) * 3 * 8, kAlign);  // fh, fr
+    s += align_up(size_t(n) * 8, kAlign);          // pair keys
+    s += align_up(size_t(n) * 3 * 8, kAlign);      // pair forces
     return s;
 }
 
@@ -499,6 +509,17 @@ void launch_collide(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceF
 }
 
 ForceField field(lbm_ctx *c, int par) { return ForceField{c->force[par], c->mask[par]}; }
+
+// Pair forces of the positions r (cell-list sort, then the neighbour sums).
+void launch_pairs(hipStream_t st, const double *r, int32_t n, const PairGrid &pg, uint64_t *keys,
+                  double *F) {
+    int32_t npad = 2;
+    while (npad < n) npad <<= 1;
+    hipLaunchKernelGGL(k_pair_sort, dim3(1), dim3(kPairSortThreads), size_t(npad) * 8, st, r, n,
+                       npad, pg, keys);
+    hipLaunchKernelGGL(k_pair_force, dim3(unsigned((n + kPairBlock - 1) / kPairBlock)),
+                       dim3(kPairBlock), 0, st, r, n, pg, keys, F);
+}
 
 // Returns the start event of a new timing pair (or nullptr when profiling is
 // off); the caller records it before the launch and prof_stop after.
@@ -580,6 +601,11 @@ void launch_step(lbm_ctx *c) {
         pa.replica = c->pdesc.replica;
         pa.step = uint32_t(c->step);
         pa.fext = c->fext;
+        pa.fpair = nullptr;
+        if (c->pair_on) {
+            launch_pairs(c->stream, c->r, c->np, c->pg, c->pair_keys, c->fpair);
+            pa.fpair = c->fpair;
+        }
         hipLaunchKernelGGL(k_particle<C>, dim3(unsigned((uint64_t(c->np) * 8 + kParticleBlock - 1) / kParticleBlock)), dim3(kParticleBlock), 0,
                            c->stream, A, c->g, R(c->dec_s), pa, field(c, par), field(c, par ^ 1));
         prof_stop(c, pk);
@@ -862,6 +888,7 @@ lbm_status particles_couple(lbm_ctx *ctx, const lbm_particle_desc *d, double *r,
     if (e != hipSuccess) return LBM_E_DEVICE;
     ctx->vacf_on = 0;
     ctx->fext = nullptr;
+    ctx->pair_on = 0;
     ctx->np = d->n;
     ctx->pdesc = *d;
     if (d->n == 0) {
@@ -881,10 +908,48 @@ lbm_status particles_couple(lbm_ctx *ctx, const lbm_particle_desc *d, double *r,
     ctx->fh = reinterpret_cast<double *>(s);
     s += align_up(size_t(d->n) * 3 * 8, kAlign);
     ctx->fr = reinterpret_cast<double *>(s);
+    s += align_up(size_t(d->n) * 3 * 8, kAlign);
+    ctx->pair_keys = reinterpret_cast<uint64_t *>(s);
+    s += align_up(size_t(d->n) * 8, kAlign);
+    ctx->fpair = reinterpret_cast<double *>(s);
     // prev_cell -> kNoNode (all ones); forces zero.
     e = hipMemsetAsync(ctx->prev_cell, 0xFF, size_t(d->n) * 8 * 4, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->fh, 0, size_t(d->n) * 3 * 8, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->fr, 0, size_t(d->n) * 3 * 8, ctx->stream);
+    return e == hipSuccess ? LBM_OK : LBM_E_DEVICE;
+}
+
+lbm_status lbm_set_pair_force(lbm_ctx *ctx, double a_f, double r_c) {
+    if (!ctx || !isfinite(a_f) || !isfinite(r_c)) return LBM_E_INVAL;
+    if (a_f == 0.0) {
+        ctx->pair_on = 0;
+        return LBM_OK;
+    }
+    if (ctx->np == 0) return LBM_E_STATE;
+    const uint32_t Ln[3] = {ctx->g.nx, ctx->g.ny, ctx->g.nz};
+    const uint32_t lmin = Ln[0] < Ln[1] ? (Ln[0] < Ln[2] ? Ln[0] : Ln[2]) : (Ln[1] < Ln[2] ? Ln[1] : Ln[2]);
+    if (!(r_c > 0.0) || r_c > 0.5 * double(lmin)) return LBM_E_INVAL;
+    if (ctx->np > kPairMax) return LBM_E_UNSUPPORTED;
+    PairGrid pg;
+    for (int k = 0; k < 3; ++k) {
+        const double cells = floor(double(Ln[k]) / r_c);
+        pg.nc[k] = cells < 1.0 ? 1u : uint32_t(cells);
+        pg.L[k] = double(Ln[k]);
+    }
+    pg.a = a_f;
+    pg.rc = r_c;
+    ctx->pg = pg;
+    ctx->pair_on = 1;
+    return LBM_OK;
+}
+
+lbm_status lbm_pair_forces(lbm_ctx *ctx, double *fc) {
+    if (!ctx || !fc) return LBM_E_INVAL;
+    if (ctx->np == 0) return LBM_E_STATE;
+    const size_t bytes = size_t(ctx->np) * 3 * 8;
+    const hipError_t e = ctx->pair_on
+                             ? hipMemcpyAsync(fc, ctx->fpair, bytes, hipMemcpyDeviceToDevice, ctx->stream)
+                             : hipMemsetAsync(fc, 0, bytes, ctx->stream);
     return e == hipSuccess ? LBM_OK : LBM_E_DEVICE;
 }
 
@@ -1684,6 +1749,7 @@ struct AdjLayout {
     size_t uf[2], um[2];       // adjoint node fields and their flags
     size_t ff[2], fm[2];       // node-force fields of the forward recompute
     size_t prev_fwd, prev_adj, fh, fr, pgrad, wacc;
+    size_t pair_keys, fpair, fcbar;  // pair forces (when recorded with them)
     size_t total;
 };
 
@@ -1726,6 +1792,12 @@ AdjLayout adj_layout(const lbm_ctx *c, int32_t np, int32_t every) {
     o += align_up(size_t(np) * 4 * 8, kAlign);
     L.wacc = o;
     o += align_up(size_t(blocks_for(c->g.ncell)) * 8, kAlign);
+    L.pair_keys = o;
+    o += align_up(size_t(np) * 8, kAlign);
+    L.fpair = o;
+    o += align_up(size_t(np) * 3 * 8, kAlign);
+    L.fcbar = o;
+    o += align_up(size_t(np) * 3 * 8, kAlign);
     L.total = o;
     return L;
 }
@@ -1762,6 +1834,10 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
     }
     double *pgrad = reinterpret_cast<double *>(at(L.pgrad));
     double *wacc = reinterpret_cast<double *>(at(L.wacc));
+    uint64_t *pkeys = reinterpret_cast<uint64_t *>(at(L.pair_keys));
+    double *fpair = reinterpret_cast<double *>(at(L.fpair));
+    double *fcbar = reinterpret_cast<double *>(at(L.fcbar));
+    const bool pairs = c->rec_pair_on && np > 0;
     uint32_t *prev_fwd = reinterpret_cast<uint32_t *>(at(L.prev_fwd));
     uint32_t *prev_adj = reinterpret_cast<uint32_t *>(at(L.prev_adj));
 
@@ -1853,6 +1929,11 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
                 pa.r = seg_r(k + 1);
                 pa.v = seg_v(k + 1);
                 pa.step = uint32_t(n);
+                pa.fpair = nullptr;
+                if (pairs) {
+                    launch_pairs(st, seg_r(k), np, c->rec_pg, pkeys, fpair);
+                    pa.fpair = fpair;
+                }
                 hipLaunchKernelGGL(k_particle<C>, dim3(pgrid), dim3(kParticleBlock), 0, st, seg(k),
                                    c->g, R(c->dec_s), pa, ff[par], ff[par ^ 1]);
                 launch_collide<C, true>(c, seg(k), seg(k + 1), ff[par], c->shape);
@@ -1867,9 +1948,19 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
                 ap.r = seg_r(k);
                 ap.v = seg_v(k);
                 ap.step = uint32_t(n);
+                ap.fpair = ap.fcbar = nullptr;
+                if (pairs) {
+                    launch_pairs(st, seg_r(k), np, c->rec_pg, pkeys, fpair);
+                    ap.fpair = fpair;
+                    ap.fcbar = fcbar;
+                }
                 hipLaunchKernelGGL(k_adj_particle<C>, dim3(pgrid), dim3(kParticleBlock), 0, st,
                                    seg(k), c->g, R(c->dec_s), abar[cur], gd, ap, uf[par],
                                    uf[par ^ 1]);
+                if (pairs)
+                    hipLaunchKernelGGL(k_adj_pair, dim3(unsigned((np + kPairBlock - 1) / kPairBlock)),
+                                       dim3(kPairBlock), 0, st, seg_r(k), np, c->rec_pg, pkeys,
+                                       fcbar, adj_r);
                 if (stream_stores)
                     hipLaunchKernelGGL((k_adj_collide<C, true, true>), dim3(cgrid), dim3(kBlock), 0,
                                        st, seg(k), c->g, R(c->dec_s), abar[cur], abar[cur ^ 1], gd,
@@ -1928,6 +2019,8 @@ lbm_status lbm_record(lbm_ctx *ctx, int32_t nsteps, int32_t every, void *tape) {
     ctx->rec_pdesc = ctx->pdesc;
     ctx->rec_R = ctx->R;
     ctx->rec_fext = ctx->fext;
+    ctx->rec_pair_on = ctx->pair_on;
+    ctx->rec_pg = ctx->pg;
     const size_t pbytes = size_t(ctx->np) * 3 * 8;
     char *tp = static_cast<char *>(tape);
     for (int32_t s = 0; s < nsteps; ++s) {

@@ -44,8 +44,10 @@ struct ParticleArgs {
     int32_t nslot, stride, max_lag;
     // per-block FP64 sums of M V^n (nullptr: off), [blocks][3]
     double *pmom;
-    // given force F_C on each particle, [n][3] (nullptr: none)
+    // given force on each particle, [n][3] (nullptr: none)
     const double *fext;
+    // pair forces of this step, [n][3] (nullptr: none); F_C = fext + fpair
+    const double *fpair;
 };
 
 __device__ inline double sum8(double v) {
@@ -292,7 +294,8 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
     // Eqs. s2-langevin, s2-langevin2 with dt = 1; F_C is the given force (or 0).
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double fc = pa.fext ? pa.fext[3 * i + k] : 0.0;
+        double fc = pa.fext ? pa.fext[3 * i + k] : 0.0;
+        if (pa.fpair) fc += pa.fpair[3 * i + k];
         const double vn = V[k] + (fc + FH[k] + FR[k]) / pa.mass;
         pa.v[3 * i + k] = vn;
         pa.r[3 * i + k] = r[k] + vn;

@@ -148,6 +148,15 @@ class Lattice:
         self._fext = None if F is None else _device_f64(F, self.device).reshape(self.n, 3).contiguous()
         _abi.check("lbm_set_particle_force", self.lib.lbm_set_particle_force(self.ctx, _ptr(self._fext)))
 
+    def set_pair_force(self, a_f: float, r_c: float = 1.0):
+        """Soft pair repulsion a_f (1 - r/r_c) for r < r_c (a_f = 0: off)."""
+        _abi.check("lbm_set_pair_force", self.lib.lbm_set_pair_force(self.ctx, float(a_f), float(r_c)))
+
+    def pair_forces(self) -> torch.Tensor:
+        out = torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
+        _abi.check("lbm_pair_forces", self.lib.lbm_pair_forces(self.ctx, _ptr(out)))
+        return out
+
     @property
     def radius(self) -> float:
         return float(self.lib.lbm_particle_radius(self.ctx))

@@ -498,3 +498,58 @@ def test_every_launch_configuration_is_bit_identical():
     lat = Lattice(9, 7, 5, 0.7)
     with pytest.raises(Exception):
         lat.set_shape(2)  # two rows per lane need an even ny
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("box,r_c", [((21, 13, 11), 1.3), ((6, 9, 13), 2.9)])
+def test_pair_repulsion(oracle_mod, storage, box, r_c):
+    # Soft pair repulsion (Eq. s2-softpot, DPD reading) on a crowded cluster:
+    # cell lists with three or more cells per axis, and with two (6 / 2.9).
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    n = 14
+    r = particle_positions(n, (4.0, 4.0, 4.0), seed=61) + 1.0
+    r[-3:] = particle_positions(3, box, seed=62)  # a few far away, one near a seam
+    r[-1] = [box[0] - 0.2, 0.3, box[2] - 0.4]
+    v = particle_velocities(n, 1e-5, seed=61)
+    announce(f"pair repulsion {storage} box={box} r_c={r_c} n={n}")
+    out = run_pair(oracle_mod, box, 0.8, storage, r, v, 0, kT=1e-4, seed=3)
+    out["gpu"].set_pair_force(0.02, r_c)
+    out["ref"].set_pair_force(0.02, r_c)
+    out["gpu"].step(1)
+    out["ref"].step(1)
+    fp_g, fp_r = out["gpu"].pair_forces().cpu().numpy(), out["ref"].pair_forces()
+    announce(f"  first-step pair forces {nmax_err(fp_g, fp_r):.2e} (max |F| {np.max(np.abs(fp_r)):.3e})")
+    assert np.max(np.abs(fp_r)) > 0.0
+    assert nmax_err(fp_g, fp_r) < 1e-12
+    out["gpu"].step(40)
+    out["ref"].step(40)
+    tol = TOL[storage]
+    _compare_particles(out["gpu"], out["ref"], tol, f"pairs {storage}")
+    _compare_fields(out["gpu"], out["ref"], tol, f"pairs {storage}")
+
+
+def test_pair_repulsion_reproducible_and_validated():
+    import torch
+
+    from paper_1909_13412_amd import Lattice, _abi
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    r = particle_positions(40, (5.0, 5.0, 5.0), seed=8) + 2.0
+    v = particle_velocities(40, 1e-5, seed=8)
+    runs = []
+    for _ in range(2):
+        lat = Lattice(16, 16, 16, 0.8, storage="f32")
+        lat.particles_couple(r, v, kT=1e-4, seed=4)
+        lat.set_pair_force(0.05, 1.5)
+        lat.step(25)
+        torch.cuda.synchronize()
+        runs.append((lat.r.clone(), lat.populations()))
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    lat = Lattice(8, 8, 8, 0.8)
+    with pytest.raises(_abi.LbmError):
+        lat.set_pair_force(0.1, 1.0)  # no particles
+    lat.particles_couple(r[:2] % 8, v[:2])
+    with pytest.raises(_abi.LbmError):
+        lat.set_pair_force(0.1, 4.5)  # beyond half the box
+    lat.set_pair_force(0.0, 0.0)  # off
