@@ -100,7 +100,7 @@ def make_lattice(w, storage, device="cuda:0", series_capacity=0, q=19):
     return lat
 
 
-def time_storage(w, variant, steps, warmup, prof_steps):
+def time_storage(w, variant, steps, warmup, prof_steps, pair=None):
     """Autotune the stream-collide launch shape, time `steps` whole steps with
     nothing but the kernels on the stream (-> MLUPS), then time `prof_steps`
     more with HIP events around every kernel launch (-> per-kernel durations;
@@ -111,6 +111,8 @@ def time_storage(w, variant, steps, warmup, prof_steps):
     storage, q = parse_variant(variant)
     lat = make_lattice(w, storage, q=q,
                        series_capacity=(2 * warmup + steps + prof_steps) // SERIES_EVERY + 2)
+    if pair is not None:
+        lat.set_pair_force(*pair)
     lat.step(warmup)
     torch.cuda.synchronize()
     shape, shape_ms = lat.autotune(20)
@@ -303,6 +305,19 @@ def time_adjoint(steps, warmup):
             "grad_gamma_tau_M_kT": [float(x) for x in g["params"].cpu().tolist()]}
 
 
+def time_pairs(w, steps, warmup, prof_steps, main):
+    """The same FP32 workload with the soft pair repulsion switched on (a_f =
+    0.05, cutoff 2R = 1): cost of the cell list and the neighbour sums, which
+    run in the particle phase."""
+    pair = (0.05, 2.0 * w["radius"])
+    r = time_storage(w, "f32", steps, warmup, prof_steps, pair=pair)
+    return {"a_f": pair[0], "r_c": pair[1], "mlups": round(r["mlups"], 1),
+            "ms_per_step": round(r["ms_per_step"], 5),
+            "particle_phase_ms": round(r["particle_phase_ms"], 5),
+            "particle_phase_ms_without": round(main["particle_phase_ms"], 5),
+            "pair_ms": round(r["particle_phase_ms"] - main["particle_phase_ms"], 5)}
+
+
 def cpu_baseline(w, steps):
     import oracle
     from paper_1909_13412_amd.inputs import workload_particles
@@ -343,6 +358,7 @@ def main():
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=1000, help="0 = skip the ensemble timing")
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="0 = skip the reverse-mode timing")
+    ap.add_argument("--no-pairs", action="store_true", help="skip the pair-repulsion timing")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -374,6 +390,10 @@ def main():
         r["speedup_vs_main"] = r["mlups"] / main_res["mlups"]
         r["traffic"] = pmc_traffic(s)
         variants[s] = r
+    pairs = None
+    if not args.no_pairs:
+        print("[bench] pair repulsion", file=sys.stderr, flush=True)
+        pairs = time_pairs(w, min(args.steps, 300), args.warmup, args.prof_steps, main_res)
     ensemble = None
     if args.ensemble_steps > 0:
         print(f"[bench] ensemble ({args.ensemble_steps} steps)", file=sys.stderr, flush=True)
@@ -433,6 +453,7 @@ def main():
         "copy_probe": copy,
         "variants": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                      for k, v in variants.items()},
+        "pairs": pairs,
         "ensemble": ensemble,
         "adjoint": adjoint,
         "precision": precision,

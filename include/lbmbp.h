@@ -173,11 +173,11 @@ lbm_status lbm_set_particle_force(lbm_ctx *ctx, const double *f);
  * s2-langevin with the potential of Eq. s2-softpot read as that of dissipative
  * particle dynamics: a pair closer than r_c pushes apart with a_f (1 - r/r_c)
  * along the line of centres (nearest periodic image), added to any force set
- * with lbm_set_particle_force.  Neighbours come from a cell list (cells at
- * least r_c wide, a deterministic sort, a fixed visiting order: bitwise
- * reproducible).  a_f = 0 switches it off; r_c must lie in (0, min(nx, ny,
- * nz)/2].  LBM_E_STATE without particles, LBM_E_UNSUPPORTED above 8192
- * particles.  particles_couple switches it off.  Recorded runs differentiate
+ * with lbm_set_particle_force.  Neighbours come from a cell list rebuilt every
+ * step (cells at least r_c wide hashed into buckets, each bucket in particle
+ * order, a fixed visiting order: bitwise reproducible).  a_f = 0 switches it
+ * off; r_c must lie in (0, min(nx, ny, nz)/2].  LBM_E_STATE without particles,
+ * LBM_E_UNSUPPORTED above 65536 particles.  particles_couple switches it off.  Recorded runs differentiate
  * through it (lbm_adjoint). */
 lbm_status lbm_set_pair_force(lbm_ctx *ctx, double a_f, double r_c);
 

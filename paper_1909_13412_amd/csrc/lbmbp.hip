@@ -344,7 +344,7 @@ struct lbm_ctx {
     // soft pair repulsion (lbm_set_pair_force)
     int pair_on;
     PairGrid pg;
-    uint64_t *pair_keys;  // particle scratch: [n] sorted cell keys
+    PairList plist;       // particle scratch: the cell list
     double *fpair;        // particle scratch: [n][3] pair forces of the last step
     // velocity autocorrelation
     int vacf_on;
@@ -442,13 +442,44 @@ size_t grid_scratch_size(const lbm_grid_desc *g) {
 
 size_t particle_blocks(int32_t n) { return (size_t(n) * 8 + kParticleBlock - 1) / kParticleBlock; }
 
+// Buckets of the pair cell list: a power of two >= 2n.
+uint32_t pair_buckets(int32_t n) {
+    uint32_t T = 64;
+    while (T < 2u * uint32_t(n)) T <<= 1;
+    return T;
+}
+
+size_t pair_list_bytes(int32_t n) {
+    const size_t T = pair_buckets(n);
+    return align_up(size_t(n) * 8, kAlign) + 3 * align_up(size_t(n) * 4, kAlign) +
+           align_up(T * 4, kAlign) + align_up((T + 1) * 4, kAlign);
+}
+
+// Carves the cell list out of pair_list_bytes(n) bytes at s.
+PairList pair_list_at(char *s, int32_t n) {
+    const size_t T = pair_buckets(n);
+    PairList pl;
+    pl.cell = reinterpret_cast<uint64_t *>(s);
+    s += align_up(size_t(n) * 8, kAlign);
+    pl.bucket = reinterpret_cast<uint32_t *>(s);
+    s += align_up(size_t(n) * 4, kAlign);
+    pl.slot = reinterpret_cast<uint32_t *>(s);
+    s += align_up(size_t(n) * 4, kAlign);
+    pl.list = reinterpret_cast<uint32_t *>(s);
+    s += align_up(size_t(n) * 4, kAlign);
+    pl.count = reinterpret_cast<uint32_t *>(s);
+    s += align_up(T * 4, kAlign);
+    pl.start = reinterpret_cast<uint32_t *>(s);
+    return pl;
+}
+
 size_t particle_scratch_size(int32_t n) {
     if (n <= 0) return 0;
     size_t s = 0;
     s += align_up(size_t(n) * 8 * 4, kAlign);  // prev cell
     s += align_up(particle_blocks(n) * 3 * 8, kAlign);  // momentum partials
     s += 2 * align_up(size_t(n) * 3 * 8, kAlign);  // fh, fr
-    s += align_up(size_t(n) * 8, kAlign);          // pair keys
+    s += pair_list_bytes(n);                       // pair cell list
     s += align_up(size_t(n) * 3 * 8, kAlign);      // pair forces
     return s;
 }
@@ -510,15 +541,17 @@ void launch_collide(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceF
 
 ForceField field(lbm_ctx *c, int par) { return ForceField{c->force[par], c->mask[par]}; }
 
-// Pair forces of the positions r (cell-list sort, then the neighbour sums).
-void launch_pairs(hipStream_t st, const double *r, int32_t n, const PairGrid &pg, uint64_t *keys,
+// Pair forces of the positions r: build the cell list (its counts start and
+// end at zero), then the neighbour sums.
+void launch_pairs(hipStream_t st, const double *r, int32_t n, const PairGrid &pg, const PairList &pl,
                   double *F) {
-    int32_t npad = 2;
-    while (npad < n) npad <<= 1;
-    hipLaunchKernelGGL(k_pair_sort, dim3(1), dim3(kPairSortThreads), size_t(npad) * 8, st, r, n,
-                       npad, pg, keys);
-    hipLaunchKernelGGL(k_pair_force, dim3(unsigned((n + kPairBlock - 1) / kPairBlock)),
-                       dim3(kPairBlock), 0, st, r, n, pg, keys, F);
+    const dim3 pblocks(unsigned((n + kPairBlock - 1) / kPairBlock));
+    hipLaunchKernelGGL(k_pair_count, pblocks, dim3(kPairBlock), 0, st, r, n, pg, pl);
+    hipLaunchKernelGGL(k_pair_scan, dim3(1), dim3(kPairScanThreads), 0, st, pg, pl);
+    hipLaunchKernelGGL(k_pair_scatter, pblocks, dim3(kPairBlock), 0, st, n, pl);
+    hipLaunchKernelGGL(k_pair_bucket_sort, dim3((pg.T + kPairBlock - 1) / kPairBlock), dim3(kPairBlock), 0,
+                       st, pg, pl);
+    hipLaunchKernelGGL(k_pair_force, pblocks, dim3(kPairBlock), 0, st, r, n, pg, pl, F);
 }
 
 // Returns the start event of a new timing pair (or nullptr when profiling is
@@ -603,7 +636,7 @@ void launch_step(lbm_ctx *c) {
         pa.fext = c->fext;
         pa.fpair = nullptr;
         if (c->pair_on) {
-            launch_pairs(c->stream, c->r, c->np, c->pg, c->pair_keys, c->fpair);
+            launch_pairs(c->stream, c->r, c->np, c->pg, c->plist, c->fpair);
             pa.fpair = c->fpair;
         }
         hipLaunchKernelGGL(k_particle<C>, dim3(unsigned((uint64_t(c->np) * 8 + kParticleBlock - 1) / kParticleBlock)), dim3(kParticleBlock), 0,
@@ -909,11 +942,13 @@ lbm_status particles_couple(lbm_ctx *ctx, const lbm_particle_desc *d, double *r,
     s += align_up(size_t(d->n) * 3 * 8, kAlign);
     ctx->fr = reinterpret_cast<double *>(s);
     s += align_up(size_t(d->n) * 3 * 8, kAlign);
-    ctx->pair_keys = reinterpret_cast<uint64_t *>(s);
-    s += align_up(size_t(d->n) * 8, kAlign);
+    ctx->plist = pair_list_at(s, d->n);
+    s += pair_list_bytes(d->n);
     ctx->fpair = reinterpret_cast<double *>(s);
-    // prev_cell -> kNoNode (all ones); forces zero.
+    // prev_cell -> kNoNode (all ones); forces and bucket counts zero.
     e = hipMemsetAsync(ctx->prev_cell, 0xFF, size_t(d->n) * 8 * 4, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(ctx->plist.count, 0, size_t(pair_buckets(d->n)) * 4, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->fh, 0, size_t(d->n) * 3 * 8, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->fr, 0, size_t(d->n) * 3 * 8, ctx->stream);
     return e == hipSuccess ? LBM_OK : LBM_E_DEVICE;
@@ -936,6 +971,7 @@ lbm_status lbm_set_pair_force(lbm_ctx *ctx, double a_f, double r_c) {
         pg.nc[k] = cells < 1.0 ? 1u : uint32_t(cells);
         pg.L[k] = double(Ln[k]);
     }
+    pg.T = pair_buckets(ctx->np);
     pg.a = a_f;
     pg.rc = r_c;
     ctx->pg = pg;
@@ -1749,7 +1785,7 @@ struct AdjLayout {
     size_t uf[2], um[2];       // adjoint node fields and their flags
     size_t ff[2], fm[2];       // node-force fields of the forward recompute
     size_t prev_fwd, prev_adj, fh, fr, pgrad, wacc;
-    size_t pair_keys, fpair, fcbar;  // pair forces (when recorded with them)
+    size_t plist, fpair, fcbar;  // pair forces (when recorded with them)
     size_t total;
 };
 
@@ -1792,8 +1828,8 @@ AdjLayout adj_layout(const lbm_ctx *c, int32_t np, int32_t every) {
     o += align_up(size_t(np) * 4 * 8, kAlign);
     L.wacc = o;
     o += align_up(size_t(blocks_for(c->g.ncell)) * 8, kAlign);
-    L.pair_keys = o;
-    o += align_up(size_t(np) * 8, kAlign);
+    L.plist = o;
+    o += pair_list_bytes(np);
     L.fpair = o;
     o += align_up(size_t(np) * 3 * 8, kAlign);
     L.fcbar = o;
@@ -1834,7 +1870,7 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
     }
     double *pgrad = reinterpret_cast<double *>(at(L.pgrad));
     double *wacc = reinterpret_cast<double *>(at(L.wacc));
-    uint64_t *pkeys = reinterpret_cast<uint64_t *>(at(L.pair_keys));
+    const PairList plist = pair_list_at(at(L.plist), np);
     double *fpair = reinterpret_cast<double *>(at(L.fpair));
     double *fcbar = reinterpret_cast<double *>(at(L.fcbar));
     const bool pairs = c->rec_pair_on && np > 0;
@@ -1855,6 +1891,7 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
     memset_(prev_adj, 0xFF, size_t(np) * 8 * 4);
     memset_(pgrad, 0, size_t(np) * 4 * 8);
     memset_(wacc, 0, size_t(blocks_for(c->g.ncell)) * 8);
+    if (pairs) memset_(plist.count, 0, size_t(c->rec_pg.T) * 4);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_adj_import<typename C::V>, dim3(blocks_for(c->g.ncell)), dim3(kBlock), 0, st, adj_pop,
                        abar[0], gd);
@@ -1931,7 +1968,7 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
                 pa.step = uint32_t(n);
                 pa.fpair = nullptr;
                 if (pairs) {
-                    launch_pairs(st, seg_r(k), np, c->rec_pg, pkeys, fpair);
+                    launch_pairs(st, seg_r(k), np, c->rec_pg, plist, fpair);
                     pa.fpair = fpair;
                 }
                 hipLaunchKernelGGL(k_particle<C>, dim3(pgrid), dim3(kParticleBlock), 0, st, seg(k),
@@ -1950,7 +1987,7 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
                 ap.step = uint32_t(n);
                 ap.fpair = ap.fcbar = nullptr;
                 if (pairs) {
-                    launch_pairs(st, seg_r(k), np, c->rec_pg, pkeys, fpair);
+                    launch_pairs(st, seg_r(k), np, c->rec_pg, plist, fpair);
                     ap.fpair = fpair;
                     ap.fcbar = fcbar;
                 }
@@ -1959,7 +1996,7 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
                                    uf[par ^ 1]);
                 if (pairs)
                     hipLaunchKernelGGL(k_adj_pair, dim3(unsigned((np + kPairBlock - 1) / kPairBlock)),
-                                       dim3(kPairBlock), 0, st, seg_r(k), np, c->rec_pg, pkeys,
+                                       dim3(kPairBlock), 0, st, seg_r(k), np, c->rec_pg, plist,
                                        fcbar, adj_r);
                 if (stream_stores)
                     hipLaunchKernelGGL((k_adj_collide<C, true, true>), dim3(cgrid), dim3(kBlock), 0,

@@ -529,6 +529,29 @@ def test_pair_repulsion(oracle_mod, storage, box, r_c):
     _compare_fields(out["gpu"], out["ref"], tol, f"pairs {storage}")
 
 
+@pytest.mark.parametrize("n,box,r_c", [(12000, (64, 48, 40), 1.0), (3000, (24, 24, 24), 1.2)])
+def test_pair_repulsion_many(oracle_mod, n, box, r_c):
+    # Many particles: more cells than buckets (several cells share a bucket and
+    # are told apart by their cell index), crowded buckets, all against the
+    # oracle's all-pairs sum.
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    r = particle_positions(n, box, seed=71)
+    v = particle_velocities(n, 1e-5, seed=71)
+    announce(f"pair repulsion many n={n} box={box} r_c={r_c}")
+    out = run_pair(oracle_mod, box, 0.8, "f64", r, v, 0, kT=1e-4, seed=5)
+    out["gpu"].set_pair_force(0.03, r_c)
+    out["ref"].set_pair_force(0.03, r_c)
+    out["gpu"].step(1)
+    out["ref"].step(1)
+    fp_g, fp_r = out["gpu"].pair_forces().cpu().numpy(), out["ref"].pair_forces()
+    touched = int(np.count_nonzero(np.any(fp_r != 0.0, axis=1)))
+    announce(f"  pair forces {nmax_err(fp_g, fp_r):.2e}, {touched} particles with neighbours")
+    assert touched > n // 10
+    assert np.array_equal(fp_g == 0.0, fp_r == 0.0)
+    assert nmax_err(fp_g, fp_r) < 1e-12
+
+
 def test_pair_repulsion_reproducible_and_validated():
     import torch
 
