@@ -541,6 +541,11 @@ void launch_collide(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceF
 
 ForceField field(lbm_ctx *c, int par) { return ForceField{c->force[par], c->mask[par]}; }
 
+// Blocks for the neighbour sums: kPairLanes lanes per particle.
+dim3 pair_group_blocks(int32_t n) {
+    return dim3(unsigned((size_t(n) * kPairLanes + kPairBlock - 1) / kPairBlock));
+}
+
 // Pair forces of the positions r: build the cell list (its counts start and
 // end at zero), then the neighbour sums.
 void launch_pairs(hipStream_t st, const double *r, int32_t n, const PairGrid &pg, const PairList &pl,
@@ -551,7 +556,7 @@ void launch_pairs(hipStream_t st, const double *r, int32_t n, const PairGrid &pg
     hipLaunchKernelGGL(k_pair_scatter, pblocks, dim3(kPairBlock), 0, st, n, pl);
     hipLaunchKernelGGL(k_pair_bucket_sort, dim3((pg.T + kPairBlock - 1) / kPairBlock), dim3(kPairBlock), 0,
                        st, pg, pl);
-    hipLaunchKernelGGL(k_pair_force, pblocks, dim3(kPairBlock), 0, st, r, n, pg, pl, F);
+    hipLaunchKernelGGL(k_pair_force, pair_group_blocks(n), dim3(kPairBlock), 0, st, r, n, pg, pl, F);
 }
 
 // Returns the start event of a new timing pair (or nullptr when profiling is
@@ -1995,9 +2000,8 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
                                    seg(k), c->g, R(c->dec_s), abar[cur], gd, ap, uf[par],
                                    uf[par ^ 1]);
                 if (pairs)
-                    hipLaunchKernelGGL(k_adj_pair, dim3(unsigned((np + kPairBlock - 1) / kPairBlock)),
-                                       dim3(kPairBlock), 0, st, seg_r(k), np, c->rec_pg, plist,
-                                       fcbar, adj_r);
+                    hipLaunchKernelGGL(k_adj_pair, pair_group_blocks(np), dim3(kPairBlock), 0, st,
+                                       seg_r(k), np, c->rec_pg, plist, fcbar, adj_r);
                 if (stream_stores)
                     hipLaunchKernelGGL((k_adj_collide<C, true, true>), dim3(cgrid), dim3(kBlock), 0,
                                        st, seg(k), c->g, R(c->dec_s), abar[cur], abar[cur ^ 1], gd,

@@ -11,8 +11,9 @@
 // and sort each bucket by particle index.  Every particle then walks the (up
 // to) 27 cells around its own in a fixed order, each cell's particles in
 // ascending index (entries of other cells hashed to the same bucket are
-// skipped): the sums are bitwise reproducible.  The adjoint kernel uses the
-// same walk.
+// skipped); the 27 cells go to 27 lanes and their sums are combined in a
+// fixed order: the result is bitwise reproducible.  The adjoint kernel uses
+// the same walk.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -72,31 +73,88 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_count(const double *__restr
     pl.slot[i] = atomicAdd(&pl.count[b], 1u);
 }
 
+// Sum of the counts of buckets [b0, b0 + per) (per a power of two; groups of
+// four as 16-byte loads, four loads in flight at a time).
+__device__ inline uint32_t pair_count_sum(const uint32_t *__restrict__ count, uint32_t b0, uint32_t per) {
+    if (per < 4) {
+        uint32_t s = 0;
+        for (uint32_t k = 0; k < per; ++k) s += count[b0 + k];
+        return s;
+    }
+    const uint4 *c4 = reinterpret_cast<const uint4 *>(count + b0);
+    const uint32_t nv = per / 4;
+    uint32_t s = 0;
+    for (uint32_t k = 0; k < nv; k += 4) {
+        uint4 v[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) v[u] = k + u < nv ? c4[k + u] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) s += v[u].x + v[u].y + v[u].z + v[u].w;
+    }
+    return s;
+}
+
 // One block: start = exclusive scan of count (start[T] = n); the counts are
-// cleared for the next build.
+// cleared for the next build.  Each thread owns T/1024 consecutive buckets
+// (one when T <= 1024); the per-thread totals are scanned within each
+// wavefront by shuffles, then across the sixteen wavefronts.
 __global__ __launch_bounds__(kPairScanThreads) void k_pair_scan(PairGrid pg, PairList pl) {
-    __shared__ uint32_t part[kPairScanThreads];
+    constexpr int kWaves = kPairScanThreads / 64;
+    __shared__ uint32_t wsum[kWaves];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const uint32_t per = pg.T / kPairScanThreads > 0 ? pg.T / kPairScanThreads : 1u;
     const uint32_t b0 = threadIdx.x * per;
-    uint32_t local = 0;
-    for (uint32_t k = 0; k < per; ++k)
-        if (b0 + k < pg.T) local += pl.count[b0 + k];
-    part[threadIdx.x] = local;
-    __syncthreads();
-    for (int off = 1; off < kPairScanThreads; off <<= 1) {  // inclusive scan of the partials
-        const uint32_t v = threadIdx.x >= uint32_t(off) ? part[threadIdx.x - off] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+    const bool mine = b0 < pg.T;
+    const uint32_t local = mine ? pair_count_sum(pl.count, b0, per) : 0u;
+    uint32_t x = local;  // inclusive scan within the wavefront
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= uint32_t(off)) x += y;
     }
-    uint32_t run = part[threadIdx.x] - local;
-    for (uint32_t k = 0; k < per; ++k)
-        if (b0 + k < pg.T) {
-            pl.start[b0 + k] = run;
-            run += pl.count[b0 + k];
-            pl.count[b0 + k] = 0u;
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    if (wave == 0) {
+        uint32_t w = lane < uint32_t(kWaves) ? wsum[lane] : 0u;
+        for (int off = 1; off < kWaves; off <<= 1) {
+            const uint32_t y = __shfl_up(w, off, 64);
+            if (lane >= uint32_t(off)) w += y;
         }
-    if (threadIdx.x == kPairScanThreads - 1) pl.start[pg.T] = part[threadIdx.x];
+        if (lane < uint32_t(kWaves)) wsum[lane] = w;
+    }
+    __syncthreads();
+    if (mine) {
+        uint32_t run = x - local + (wave > 0 ? wsum[wave - 1] : 0u);
+        if (per < 4) {
+            for (uint32_t k = 0; k < per; ++k) {
+                const uint32_t c = pl.count[b0 + k];
+                pl.start[b0 + k] = run;
+                pl.count[b0 + k] = 0u;
+                run += c;
+            }
+        } else {
+            uint4 *c4 = reinterpret_cast<uint4 *>(pl.count + b0);
+            uint4 *s4 = reinterpret_cast<uint4 *>(pl.start + b0);
+            const uint32_t nv = per / 4;
+            for (uint32_t k = 0; k < nv; k += 4) {
+                uint4 v[4];
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u) v[u] = k + u < nv ? c4[k + u] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u) {
+                    if (k + u >= nv) break;
+                    uint4 o;
+                    o.x = run;
+                    o.y = o.x + v[u].x;
+                    o.z = o.y + v[u].y;
+                    o.w = o.z + v[u].z;
+                    run = o.w + v[u].w;
+                    s4[k + u] = o;
+                    c4[k + u] = make_uint4(0, 0, 0, 0);
+                }
+            }
+        }
+    }
+    if (threadIdx.x == kPairScanThreads - 1) pl.start[pg.T] = wsum[kWaves - 1];
 }
 
 __global__ __launch_bounds__(kPairBlock) void k_pair_scatter(int32_t n, PairList pl) {
@@ -122,62 +180,72 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_bucket_sort(PairGrid pg, Pa
     }
 }
 
-// Visit every neighbour j != i within the cutoff: fn(j, d) with d = r_i - r_j
-// (nearest image) and |d| < r_c.
+// A group of kPairLanes lanes serves one particle: lane l visits the l-th of
+// its (up to) 27 neighbour cells (offsets in x fastest, then y, z) and calls
+// fn(j, d, |d|^2) for every particle j != i of that cell within the cutoff,
+// d = r_i - r_j at the nearest image, in ascending j.
+constexpr int kPairLanes = 32;
+
 template <typename Fn>
-__device__ inline void pair_neighbours(const double *__restrict__ r, const PairGrid &pg,
-                                       const PairList &pl, int32_t i, Fn &&fn) {
+__device__ inline void pair_cell_visit(const double *__restrict__ r, const PairGrid &pg,
+                                       const PairList &pl, int32_t i, uint32_t l, Fn &&fn) {
     const double ri[3] = {r[3 * i + 0], r[3 * i + 1], r[3 * i + 2]};
-    uint32_t c[3];
-    int32_t lo[3], cnt[3];
+    const uint32_t o[3] = {l % 3u, (l / 3u) % 3u, l / 9u};
+    uint32_t q[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        c[k] = pair_cell_coord(ri[k], pg.L[k], pg.nc[k]);
         // one, two or three distinct cells per axis
-        cnt[k] = pg.nc[k] >= 3 ? 3 : int32_t(pg.nc[k]);
-        lo[k] = pg.nc[k] >= 3 ? -1 : 0;
+        const uint32_t cnt = pg.nc[k] >= 3 ? 3u : pg.nc[k];
+        if (o[k] >= cnt) return;
+        const uint32_t c = pair_cell_coord(ri[k], pg.L[k], pg.nc[k]);
+        q[k] = pg.nc[k] >= 3 ? (c + o[k] + pg.nc[k] - 1u) % pg.nc[k] : (c + o[k]) % pg.nc[k];
     }
     const double rc2 = pg.rc * pg.rc;
-    for (int32_t oz = 0; oz < cnt[2]; ++oz)
-        for (int32_t oy = 0; oy < cnt[1]; ++oy)
-            for (int32_t ox = 0; ox < cnt[0]; ++ox) {
-                const int32_t o[3] = {lo[0] + ox, lo[1] + oy, lo[2] + oz};
-                uint32_t q[3];
+    const uint64_t cell = pair_cell(pg, q[0], q[1], q[2]);
+    const uint32_t b = pair_bucket(cell, pg.T);
+    const uint32_t hi = pl.start[b + 1];
+    for (uint32_t p = pl.start[b]; p < hi; ++p) {
+        const int32_t j = int32_t(pl.list[p]);
+        if (j == i || pl.cell[j] != cell) continue;
+        double d[3], rr = 0.0;
 #pragma unroll
-                for (int k = 0; k < 3; ++k)
-                    q[k] = uint32_t((int32_t(c[k]) + o[k] + int32_t(pg.nc[k])) % int32_t(pg.nc[k]));
-                const uint64_t cell = pair_cell(pg, q[0], q[1], q[2]);
-                const uint32_t b = pair_bucket(cell, pg.T);
-                for (uint32_t p = pl.start[b]; p < pl.start[b + 1]; ++p) {
-                    const int32_t j = int32_t(pl.list[p]);
-                    if (j == i || pl.cell[j] != cell) continue;
-                    double d[3], rr = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            d[k] = ri[k] - r[3 * j + k];
+            d[k] -= pg.L[k] * rint(d[k] / pg.L[k]);
+            rr += d[k] * d[k];
+        }
+        if (rr > 0.0 && rr < rc2) fn(j, d, rr);
+    }
+}
+
+// Sum of v over the kPairLanes lanes of a group, in a fixed butterfly order
+// (every lane receives it).
+__device__ inline double pair_group_sum(double v) {
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        d[k] = ri[k] - r[3 * j + k];
-                        d[k] -= pg.L[k] * rint(d[k] / pg.L[k]);
-                        rr += d[k] * d[k];
-                    }
-                    if (rr > 0.0 && rr < rc2) fn(j, d, rr);
-                }
-            }
+    for (int m = kPairLanes / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, kPairLanes);
+    return v;
 }
 
 // F[i] = sum over neighbours of a_f (1 - |d|/r_c) d/|d|.
 __global__ __launch_bounds__(kPairBlock) void k_pair_force(const double *__restrict__ r, int32_t n,
                                                            PairGrid pg, PairList pl,
                                                            double *__restrict__ F) {
-    const int32_t i = int32_t(blockIdx.x * kPairBlock + threadIdx.x);
-    if (i >= n) return;
+    const int32_t i = int32_t((blockIdx.x * kPairBlock + threadIdx.x) / kPairLanes);
+    const uint32_t l = threadIdx.x % kPairLanes;
+    if (i >= n) return;  // whole groups leave together
     double f[3] = {0.0, 0.0, 0.0};
-    pair_neighbours(r, pg, pl, i, [&](int32_t, const double (&d)[3], double rr) {
-        const double dist = sqrt(rr);
-        const double mag = pg.a * (1.0 - dist / pg.rc) / dist;
+    if (l < 27)
+        pair_cell_visit(r, pg, pl, i, l, [&](int32_t, const double (&d)[3], double rr) {
+            const double dist = sqrt(rr);
+            const double mag = pg.a * (1.0 - dist / pg.rc) / dist;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) f[k] += mag * d[k];
-    });
+            for (int k = 0; k < 3; ++k) f[k] += mag * d[k];
+        });
 #pragma unroll
-    for (int k = 0; k < 3; ++k) F[3 * i + k] = f[k];
+    for (int k = 0; k < 3; ++k) f[k] = pair_group_sum(f[k]);
+    if (l == 0)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) F[3 * i + k] = f[k];
 }
 
 // Adjoint: with Fb = dJ/dF_C of every particle, rbar[i] += sum over
@@ -188,25 +256,30 @@ __global__ __launch_bounds__(kPairBlock) void k_adj_pair(const double *__restric
                                                          PairGrid pg, PairList pl,
                                                          const double *__restrict__ Fb,
                                                          double *__restrict__ rbar) {
-    const int32_t i = int32_t(blockIdx.x * kPairBlock + threadIdx.x);
+    const int32_t i = int32_t((blockIdx.x * kPairBlock + threadIdx.x) / kPairLanes);
+    const uint32_t l = threadIdx.x % kPairLanes;
     if (i >= n) return;
     const double fi[3] = {Fb[3 * i + 0], Fb[3 * i + 1], Fb[3 * i + 2]};
     double g[3] = {0.0, 0.0, 0.0};
-    pair_neighbours(r, pg, pl, i, [&](int32_t j, const double (&d)[3], double rr) {
-        const double dist = sqrt(rr);
-        const double diag = pg.a * (1.0 / dist - 1.0 / pg.rc);
-        const double outer = pg.a / (rr * dist);
-        double w[3], dw = 0.0;
+    if (l < 27)
+        pair_cell_visit(r, pg, pl, i, l, [&](int32_t j, const double (&d)[3], double rr) {
+            const double dist = sqrt(rr);
+            const double diag = pg.a * (1.0 / dist - 1.0 / pg.rc);
+            const double outer = pg.a / (rr * dist);
+            double w[3], dw = 0.0;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            w[k] = fi[k] - Fb[3 * j + k];
-            dw += d[k] * w[k];
-        }
+            for (int k = 0; k < 3; ++k) {
+                w[k] = fi[k] - Fb[3 * j + k];
+                dw += d[k] * w[k];
+            }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) g[k] += diag * w[k] - outer * d[k] * dw;
-    });
+            for (int k = 0; k < 3; ++k) g[k] += diag * w[k] - outer * d[k] * dw;
+        });
 #pragma unroll
-    for (int k = 0; k < 3; ++k) rbar[3 * i + k] += g[k];
+    for (int k = 0; k < 3; ++k) g[k] = pair_group_sum(g[k]);
+    if (l == 0)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) rbar[3 * i + k] += g[k];
 }
 
 }  // namespace lbmbp

@@ -529,11 +529,13 @@ def test_pair_repulsion(oracle_mod, storage, box, r_c):
     _compare_fields(out["gpu"], out["ref"], tol, f"pairs {storage}")
 
 
-@pytest.mark.parametrize("n,box,r_c", [(12000, (64, 48, 40), 1.0), (3000, (24, 24, 24), 1.2)])
+@pytest.mark.parametrize("n,box,r_c", [(12000, (64, 48, 40), 1.0), (3000, (24, 24, 24), 1.2),
+                                       (700, (16, 12, 20), 1.5)])
 def test_pair_repulsion_many(oracle_mod, n, box, r_c):
     # Many particles: more cells than buckets (several cells share a bucket and
     # are told apart by their cell index), crowded buckets, all against the
-    # oracle's all-pairs sum.
+    # oracle's all-pairs sum.  The bucket counts (32768, 8192, 2048) give the
+    # one-block scan 32, 8 and 2 buckets per thread.
     from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
 
     r = particle_positions(n, box, seed=71)
