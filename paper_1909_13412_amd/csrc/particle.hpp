@@ -17,6 +17,7 @@
 
 namespace lbmbp {
 
+constexpr int kVacfBatch = 4;  // VACF origins per lane whose loads are in flight together
 constexpr int kParticleBlock = 64;  // eight particles per block: spread over every CU
 constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 
@@ -206,21 +207,53 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
         });
     }
 
+    // Loads whose results are needed only at the end: this lane's node of one
+    // step ago, and the given and pair forces.
+    const uint32_t pc = valid ? pa.prev_cell[8 * i + p] : kNoNode;
+    double fc[3] = {0.0, 0.0, 0.0};
+    if (valid && p == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (pa.fext) fc[k] = pa.fext[3 * i + k];
+            if (pa.fpair) fc[k] += pa.fpair[3 * i + k];
+        }
+    }
+
     // C_v(t) = <V(0).V(t)> (section 2.1): V^n against every active origin;
     // lane p takes the origins k = k_lo + p, k_lo + p + 8, ...  The newest
-    // origin (lag 0) is stored by the lane that owns it.
+    // origin (lag 0) is stored by the lane that owns it.  Origins go in
+    // batches of kVacfBatch: all loads of a batch before any of its stores.
     if (valid && pa.acc) {
         double *acc_i = pa.acc + int64_t(i) * (pa.max_lag + 1);
-        for (int64_t k = pa.k_lo + p; k <= pa.k_hi; k += 8) {
-            double *o = pa.origins + (int64_t(k % pa.nslot) * pa.n + i) * 3;
-            const int64_t lag = pa.t - k * pa.stride;
-            if (lag == 0) {
-                o[0] = V[0];
-                o[1] = V[1];
-                o[2] = V[2];
-                acc_i[0] += V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
-            } else {
-                acc_i[lag] += o[0] * V[0] + o[1] * V[1] + o[2] * V[2];
+        for (int64_t k0 = pa.k_lo + p; k0 <= pa.k_hi; k0 += 8 * kVacfBatch) {
+            double ov[kVacfBatch][3], av[kVacfBatch];
+#pragma unroll
+            for (int c = 0; c < kVacfBatch; ++c) {
+                const int64_t k = k0 + 8 * c;
+                const int64_t lag = pa.t - k * pa.stride;
+                ov[c][0] = ov[c][1] = ov[c][2] = av[c] = 0.0;
+                if (k <= pa.k_hi && lag != 0) {
+                    const double *o = pa.origins + (int64_t(k % pa.nslot) * pa.n + i) * 3;
+                    ov[c][0] = o[0];
+                    ov[c][1] = o[1];
+                    ov[c][2] = o[2];
+                    av[c] = acc_i[lag];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kVacfBatch; ++c) {
+                const int64_t k = k0 + 8 * c;
+                if (k > pa.k_hi) break;
+                const int64_t lag = pa.t - k * pa.stride;
+                if (lag == 0) {
+                    double *o = pa.origins + (int64_t(k % pa.nslot) * pa.n + i) * 3;
+                    o[0] = V[0];
+                    o[1] = V[1];
+                    o[2] = V[2];
+                    acc_i[0] += V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
+                } else {
+                    acc_i[lag] = av[c] + (ov[c][0] * V[0] + ov[c][1] * V[1] + ov[c][2] * V[2]);
+                }
             }
         }
     }
@@ -259,7 +292,6 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
 
     // Release this lane's node from the field used one step ago (it was
     // consumed by that step's stream-collide).
-    const uint32_t pc = pa.prev_cell[8 * i + p];
     if (pc != kNoNode) {
         old.f[3 * uint64_t(pc) + 0] = 0;
         old.f[3 * uint64_t(pc) + 1] = 0;
@@ -294,9 +326,7 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
     // Eqs. s2-langevin, s2-langevin2 with dt = 1; F_C is the given force (or 0).
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        double fc = pa.fext ? pa.fext[3 * i + k] : 0.0;
-        if (pa.fpair) fc += pa.fpair[3 * i + k];
-        const double vn = V[k] + (fc + FH[k] + FR[k]) / pa.mass;
+        const double vn = V[k] + (fc[k] + FH[k] + FR[k]) / pa.mass;
         pa.v[3 * i + k] = vn;
         pa.r[3 * i + k] = r[k] + vn;
         pa.fh[3 * i + k] = FH[k];
