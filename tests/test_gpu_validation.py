@@ -12,6 +12,11 @@ volume fraction 4 pi R^3 / (3 L^3).  The paper's conditions are used: lattice
 viscosity nu = 0.89e-6 m^2/s x 0.5 ps / (5 nm)^2 (tau = 0.5534) and
 U = 1 m/s x 0.5 ps / 5 nm = 1e-4; the box is 64 nodes (the paper: 100).
 
+Fig. 2 -- velocity relaxation after a kick (the normalised VACF, by the
+fluctuation-dissipation theorem) of the paper's particle for Brownian
+dynamics, pointwise friction and the present method, against the closed form
+with hydrodynamic memory (analytic.py).
+
 Fig. 3 -- response V_R (velocity after an instantaneous kick) against
 relaxation A_R (acceleration after a steady pulling force is released), both
 normalised at t = 0, and the thermal C_v.
@@ -125,6 +130,94 @@ def test_fig1_wide_fit_extends_stokes_law_to_larger_radius(where):
         KH = hasimoto(R, L1)
         announce(f"Fig. 1 wide fit {where}: R={R} K={K:.4f} Hasimoto {KH:.4f}")
         assert abs(K / KH - 1.0) < 0.10
+
+
+def test_fig1_unit_fit_reverses_near_a_node():
+    """Within a small distance of a node the unit-cell fit's gain is negative
+    (the closed-form limit is pinned in the oracle): the steady drag on a held
+    particle 0.02 from a node points along the stream.  The wide fit keeps
+    every corner at least sqrt(3)/2 away and follows Stokes' law there."""
+    off = (0.02, 0.0, 0.0)
+    K_unit = drag_ratio(0.4, "stokeslet", off, hold_u=False)
+    K_wide = drag_ratio(0.4, "stokeslet2dx", off)
+    announce(f"Fig. 1 near a node (0.02): unit fit K = {K_unit:.4f}, wide fit K = {K_wide:.4f}")
+    assert K_unit < 0.0
+    assert abs(K_wide / hasimoto(0.4, L1) - 1.0) < 0.10
+
+
+# ---- Fig. 2 ----------------------------------------------------------------------
+
+# The paper's Fig. 2 particle: R = 5 nm = 1 dx and M = 2e-21 kg = 16 rho0 dx^3,
+# in the fluid of Fig. 1 (tau 0.5534).  At R = 1 the unit-cell fit has
+# negative gain (R > sqrt(3)/2), so the present method runs with the fit on the
+# (2 dx)^3 cube.
+R2, M2 = 1.0, 16.0
+POS2 = [(20.3, 31.7, 40.2), (10.5, 10.5, 10.5), (33.0, 33.0, 33.0), (5.81, 47.12, 22.64)]
+
+
+def _kick_response(friction, lags):
+    """V(t)/V(0) after a kick from rest, for each position in POS2."""
+    import torch
+
+    from paper_1909_13412_amd import Lattice
+
+    nu = (TAU1 - 0.5) / 3.0
+    gamma = 6.0 * math.pi * nu * R2
+    curves = []
+    for pos in POS2:
+        lat = Lattice(L1, L1, L1, TAU1, storage="f64")
+        lat.particles_couple(np.array([pos]), np.array([[1e-3, 0.0, 0.0]]), mass=M2, gamma=gamma,
+                             friction=friction)
+        vs = []
+        for _ in range(lags):
+            lat.step(1)
+            vs.append(lat.v[0, 0].clone())
+        curves.append(np.concatenate([[1.0], torch.stack(vs).cpu().numpy() / 1e-3]))
+    return np.array(curves)
+
+
+def test_fig2_velocity_relaxation_against_hydrodynamic_memory():
+    """The velocity relaxation after a kick -- by the fluctuation-dissipation
+    theorem the normalised VACF of Fig. 2 -- against the closed form for a
+    point particle with Stokes friction and the Basset history force
+    (analytic.py).  Brownian dynamics (Eq. s2-dis0) decays exponentially, the
+    pointwise friction (Eq. s2-dis1) has a tail but lies well above the
+    closed form, and the present method follows it, tail included."""
+    from analytic import velocity_relaxation
+
+    lags = 2000
+    nu = (TAU1 - 0.5) / 3.0
+    gamma = 6.0 * math.pi * nu * R2
+    phi = velocity_relaxation(np.arange(lags + 1), M2, gamma, R2, nu)
+    present_all = _kick_response("stokeslet2dx", lags)
+    present = present_all.mean(0)
+    pointwise = _kick_response("pointwise", lags).mean(0)
+    bd = _kick_response("bd", lags)[0]
+    ks = [1, 10, 50, 100, 200, 500, 1000, 2000]
+    announce("Fig. 2 lag: " + ", ".join(f"{k}: {phi[k]:.5f} {present[k]:.5f} {pointwise[k]:.5f} {bd[k]:.5f}"
+                                        for k in ks) + " (closed form, present, pointwise, BD)")
+    k = np.arange(lags + 1)
+    # Euler-Cromer with F_H = -gamma V: exactly (1 - gamma/M)^k
+    assert np.allclose(bd[:500], (1.0 - gamma / M2) ** k[:500], rtol=1e-10, atol=0.0)
+    assert bd[1000] < 1e-8 < phi[1000]
+    # the present method: within 15% of the closed form from lag 50 on, its
+    # tail exponent -3/2, and nearly the same curve wherever the particle starts
+    late = [50, 100, 200, 500, 1000, 2000]
+    rel = np.abs(present[late] / phi[late] - 1.0)
+    announce(f"  present vs closed form, relative: {np.round(rel, 4).tolist()}")
+    assert np.max(rel) < 0.15
+    slope = math.log(present[2000] / present[500]) / math.log(4.0)
+    announce(f"  present local exponent over lags 500..2000: {slope:.3f}")
+    assert abs(slope + 1.5) < 0.2
+    spread = np.max(np.abs(present_all - present), axis=0)
+    announce(f"  spread over start positions: max {spread.max():.4f} at lag {int(spread.argmax())}, "
+             f"beyond lag 200 {spread[200:].max():.5f}")
+    assert spread.max() < 0.06
+    # the pointwise friction errs at least twice as much over lags 20..500
+    e_present = np.max(np.abs(present[20:501] - phi[20:501]))
+    e_pointwise = np.max(np.abs(pointwise[20:501] - phi[20:501]))
+    announce(f"  max deviation over lags 20..500: present {e_present:.4f}, pointwise {e_pointwise:.4f}")
+    assert e_pointwise > 2.0 * e_present
 
 
 # ---- Fig. 3 ----------------------------------------------------------------------

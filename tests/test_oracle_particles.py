@@ -65,6 +65,32 @@ def test_fit_gain_in_uniform_stream_at_cell_centre(oracle_mod):
             assert np.allclose(FH, 0.7 * W * k * e, rtol=1e-12, atol=1e-17), (R, FH)
 
 
+def test_fit_gain_near_a_node_is_negative(oracle_mod):
+    # A particle at distance r -> 0 from node 0 in a uniform relative stream W
+    # (direction e), c = cosine between the offset and e.  Node 0's shape
+    # g_0 = ca e - cb d has ca ~ -3R/(4r), cb d ~ 3R c d_hat/(4r) and dominates
+    # both sums: e.g_0 ~ -3R (1 + c^2)/(4r), |g_0|^2 ~ (3R/(4r))^2 (1 + 3c^2),
+    # so the gain e.g_0/|g_0|^2 -> -(4r/(3R)) (1 + c^2)/(1 + 3c^2) < 0: the fit
+    # pushes along the relative stream instead of against it.  (A node at
+    # exactly r = 0 is left out of the fit, so the limit point itself differs.)
+    R, gamma, W = 0.4, 0.9, 1e-4
+    e = np.array([1.0, 0.0, 0.0])
+    for dirn in ((1, 0, 0), (0, 1, 0), (1, 1, 1), (2, -1, 0)):
+        dh = np.array(dirn, dtype=float) / np.linalg.norm(dirn)
+        dh = np.abs(dh)  # the particle inside the cell [5, 6)^3 of node (5, 5, 5)
+        c = float(dh @ e)
+        for r, rtol in ((1e-5, 1e-3), (1e-4, 1e-2)):
+            s = 5.0 + r * dh
+            FH = oracle_mod.friction_force("stokeslet", R, gamma, s, np.zeros(3), np.tile(W * e, (8, 1)))
+            gain = FH[0] / (gamma * W)
+            limit = -(4.0 * r / (3.0 * R)) * (1.0 + c * c) / (1.0 + 3.0 * c * c)
+            assert gain < 0.0 and abs(gain / limit - 1.0) < rtol, (dirn, r, gain, limit)
+        # still reversed at r = 0.01 (the sign, not the asymptote)
+        FH = oracle_mod.friction_force("stokeslet", R, gamma, 5.0 + 0.01 * dh, np.zeros(3),
+                                       np.tile(W * e, (8, 1)))
+        assert FH[0] < 0.0
+
+
 def _wide_corners(s):
     c0 = np.floor(s + 0.5) - 1.0
     return [c0 + 2 * np.array([p & 1, (p >> 1) & 1, (p >> 2) & 1]) for p in range(8)]
