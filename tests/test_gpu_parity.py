@@ -293,6 +293,77 @@ def test_suspension512_conservation():
     torch.cuda.empty_cache()
 
 
+def test_suspension512_tiled_against_oracle(oracle_mod):
+    # Full size, every node: a 32^3 state (perturbed fields, one particle,
+    # kT = 0) tiled 16 x 16 x 16 times into the 512^3 box, 4096 particles at
+    # the same place in every tile.  The 512^3 run is then the 32^3 run
+    # repeated: every tile, including those whose population offsets lie
+    # beyond 2^31 elements, must hold the same moments, in every non-temporal
+    # launch configuration the large-lattice autotuner chooses from, and tile
+    # 0 must match the oracle's 32^3 run.  The start positions are dyadic, so
+    # the first step is the same in every tile bit for bit; later positions
+    # r + V round differently at different magnitudes (FP64, ~1e-14
+    # relative), so tiles may differ by that much.
+    import torch
+
+    from paper_1909_13412_amd import Lattice
+    from paper_1909_13412_amd.inputs import WORKLOADS, perturbed_fields
+
+    w = WORKLOADS["suspension512"]
+    T, K, steps = 32, 16, 5
+    rho_t, u_t = perturbed_fields((T, T, T), seed=51, amp_rho=1e-3, amp_u=1e-3)
+    p0 = np.array([13.25, 7.8125, 21.625])
+    v0 = np.array([[2e-4, -1e-4, 5e-5]])
+    kw = dict(mass=w["mass"], gamma=w["gamma"], kT=0.0, radius=w["radius"], seed=w["seed"])
+    ref = oracle_mod.Sim(T, T, T, w["tau"])
+    ref.set_equilibrium(rho_t, u_t)
+    ref.set_particles(p0[None, :], v0, **kw)
+    ref.step(steps)
+    rho_r, u_r = ref.moments()
+    v_r = ref.particles()[1][0]
+
+    idx = np.stack(np.meshgrid(np.arange(K), np.arange(K), np.arange(K), indexing="ij"), -1).reshape(-1, 3)
+    r = (T * idx + p0).astype(np.float64)
+    v = np.repeat(v0, len(r), axis=0)
+    L = T * K
+    announce(f"suspension512 tiled: {L}^3 FP32 of {T}^3 tiles, {len(r)} particles, {steps} steps")
+    dev = torch.device("cuda")
+    rho_d = torch.from_numpy(rho_t).to(dev).repeat(K, K, K)
+    u_d = torch.from_numpy(u_t).to(dev).repeat(1, K, K, K)
+    g = Lattice(L, L, L, w["tau"], storage="f32")
+    first = None
+    for shape in (4, 5, 6, 7):
+        g.set_shape(shape)
+        g.set_equilibrium(rho_d, u_d)
+        g.particles_couple(r, v, **kw)
+        g.step(steps)
+        rho_g, u_g = g.moments()
+        rv = rho_g.view(K, T, K, T, K, T)
+        uv = u_g.view(3, K, T, K, T, K, T)
+        d_rho = (rv - rv[:1, :, :1, :, :1, :]).abs().max().item()
+        d_u = (uv - uv[:, :1, :, :1, :, :1, :]).abs().max().item()
+        vg = g.v.cpu().numpy()
+        d_v = np.abs(vg - vg[:1]).max()
+        tile_rho = rho_g[:T, :T, :T].cpu().numpy()
+        tile_u = u_g[:, :T, :T, :T].cpu().numpy()
+        e_rho = nmax_err(tile_rho - 1.0, rho_r - 1.0)
+        e_u = nmax_err(tile_u, u_r)
+        e_v = nmax_err(vg[0], v_r)
+        announce(f"  shape {shape}: tiles differ by rho {d_rho:.1e} u {d_u:.1e} v {d_v:.1e}; "
+                 f"tile 0 vs oracle rho-1 {e_rho:.2e} u {e_u:.2e} v {e_v:.2e}")
+        assert d_rho <= 1e-9 and d_u <= 1e-9 and d_v <= 1e-10 * np.abs(v0).max()
+        assert e_rho < 1e-5 and e_u < 1e-5 and e_v < 1e-5
+        # the launch configuration does not change the result
+        if first is None:
+            first = (tile_rho, tile_u, vg[0].copy())
+        else:
+            assert np.array_equal(first[0], tile_rho) and np.array_equal(first[1], tile_u)
+            assert np.array_equal(first[2], vg[0])
+        del rho_g, u_g, rv, uv
+    del g, rho_d, u_d
+    torch.cuda.empty_cache()
+
+
 def test_nonfinite_detected(oracle_mod):
     from paper_1909_13412_amd import LbmError, Lattice
 
