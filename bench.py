@@ -350,7 +350,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="suspension256")
     ap.add_argument("--storage", default="f32")
-    ap.add_argument("--variants", default="bf16,f16,f32q15,bf16q15",
+    ap.add_argument("--variants", default="bf16,f16,f64,f32q15,bf16q15",
                     help="storages to time besides --storage; a q15 suffix selects D3Q15")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps timed (0 = skip)")
     ap.add_argument("--precision-steps", type=int, default=2000, help="0 = skip the VACF error study")
