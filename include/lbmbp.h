@@ -244,8 +244,10 @@ lbm_status lbm_profile_read(lbm_ctx *ctx, double out[4]);
  * nodes (rows y and y + ny/2), 512; 3 = two nodes, 256 (2 and 3 need an even
  * ny).  k >= 4 writes the populations with non-temporal stores (streamed past
  * the caches), which pays off once a lattice no longer fits in the GPU's
- * last-level cache.  Until lbm_autotune runs a context uses shape 0, with
- * non-temporal stores when one lattice is at least 256 MiB. */
+ * last-level cache.  Until lbm_autotune runs, a context uses the configuration
+ * the autotuner last chose in this process for the same device, storage,
+ * velocity set and box size, if any; otherwise shape 0, with non-temporal
+ * stores when one lattice is at least 256 MiB. */
 #define LBM_NUM_SHAPES 8
 
 /* Time every valid stream-collide configuration on this context's lattice (iters
@@ -253,13 +255,18 @@ lbm_status lbm_profile_read(lbm_ctx *ctx, double out[4]);
  * lattice, so the simulation state is not changed) and keep the fastest for
  * later lbm_step calls.  Synchronises the stream.  ms (host, LBM_NUM_SHAPES
  * entries, may be NULL) receives the mean milliseconds per launch (-1 for a
- * shape that does not apply); *chosen (may be NULL) the shape kept. */
+ * shape that does not apply); *chosen (may be NULL) the shape kept.  The choice
+ * is also remembered for contexts created later with the same device, storage,
+ * velocity set and box size (process lifetime, thread-safe). */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen);
 
 /* Use launch configuration k (0 .. LBM_NUM_SHAPES - 1) for later steps;
  * LBM_E_INVAL if k is out of range or does not apply to this box.  Every
  * configuration gives bit-identical results. */
 lbm_status lbm_set_shape(lbm_ctx *ctx, int32_t k);
+
+/* The launch configuration later lbm_step calls use. */
+lbm_status lbm_get_shape(const lbm_ctx *ctx, int32_t *k);
 
 /* Number of steps taken since lbm_init. */
 lbm_status lbm_get_step(const lbm_ctx *ctx, int64_t *step);
@@ -375,8 +382,13 @@ lbm_status lbm_ens_vacf_counts(const lbm_ens *ens, int64_t *cnt);
 lbm_status lbm_ens_step(lbm_ens *ens, int32_t nsteps);
 
 /* Time the stream-collide launch shapes on the ensemble (state unchanged) and
- * keep the fastest; as lbm_autotune. */
+ * keep the fastest; as lbm_autotune.  The choice is remembered for ensembles
+ * created later on the same device with the same storage and the same box
+ * sizes in the same order, which start from it. */
 lbm_status lbm_ens_autotune(lbm_ens *ens, int32_t iters, double *ms, int32_t *chosen);
+
+/* The launch configuration later lbm_ens_step calls use. */
+lbm_status lbm_ens_get_shape(const lbm_ens *ens, int32_t *k);
 
 /* Per-replica FP64 sums (as lbm_observables) and populations (as
  * lbm_get_populations, the replica's own box). */

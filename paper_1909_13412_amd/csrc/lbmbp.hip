@@ -24,7 +24,11 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
+#include <vector>
 
 #include "lbmbp.h"
 #include "adjoint.hpp"
@@ -357,7 +361,8 @@ struct lbm_ctx {
     hipEvent_t *prof_ev;    // pairs: [2k] start, [2k+1] stop
     int32_t *prof_kind;     // per pair: 0 stream-collide, 1 particle phase
     int32_t prof_used, prof_cap;
-    int shape;  // index into kShapes
+    int shape;   // index into kShapes
+    int device;  // device current at lbm_init (autotune cache key)
     // recorded observables (lbm_series_config)
     int32_t series_every;
     double *series;
@@ -800,6 +805,49 @@ lbm_status lbm_vacf_origin_bytes(int32_t n, int32_t max_lag, int32_t stride, siz
     return LBM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Launch configurations the autotuners chose, kept for the life of the
+// process and keyed by device, storage, velocity set and the sizes of every
+// box: a context or ensemble created later with the same key starts from that
+// choice instead of the size-based default.
+struct TuneKey {
+    int device, storage, q;
+    std::vector<int32_t> dims;  // nx, ny, nz of each box
+    bool operator<(const TuneKey &o) const {
+        return std::tie(device, storage, q, dims) < std::tie(o.device, o.storage, o.q, o.dims);
+    }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+
+int current_device() {
+    int d = 0;
+    return hipGetDevice(&d) == hipSuccess ? d : -1;
+}
+
+int tune_lookup(const TuneKey &k, int fallback) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find(k);
+    return it == g_tune.end() ? fallback : it->second;
+}
+
+void tune_store(const TuneKey &k, int shape) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[k] = shape;
+}
+
+TuneKey ctx_tune_key(const lbm_ctx *c) {
+    return TuneKey{c->device, c->desc.storage, c->q, {c->desc.nx, c->desc.ny, c->desc.nz}};
+}
+
+}  // namespace
+
+extern "C" {
+
 lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *grid_scratch,
                     void *stream, lbm_ctx **out) {
     if (!grid_ok(grid) || !pop_a || !pop_b || !grid_scratch || !out) return LBM_E_INVAL;
@@ -814,10 +862,12 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
     c->g.ncell = uint32_t(ncell_of(grid));
     c->g.chunk = row_chunk(grid);
     c->q = velocity_count(grid);
+    c->device = current_device();
     {
         size_t lat = 0;
         lbm_lattice_bytes(grid, &lat);
-        c->shape = lat >= kStreamStoreBytes ? kNumGeomShapes : 0;  // until lbm_autotune
+        // until lbm_autotune: the last choice for this key, else by lattice size
+        c->shape = tune_lookup(ctx_tune_key(c), lat >= kStreamStoreBytes ? kNumGeomShapes : 0);
     }
     c->elem = elem_size(grid->storage);
     c->pop[0] = pop_a;
@@ -1110,6 +1160,7 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen
     for (int k = 0; k < kNumShapes; ++k)
         if (t[k] > 0.0 && (t[best] <= 0.0 || t[k] < t[best])) best = k;
     ctx->shape = best;
+    tune_store(ctx_tune_key(ctx), best);
     if (ms)
         for (int k = 0; k < kNumShapes; ++k) ms[k] = t[k];
     if (chosen) *chosen = best;
@@ -1119,6 +1170,12 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen
 lbm_status lbm_set_shape(lbm_ctx *ctx, int32_t k) {
     if (!ctx || k < 0 || k >= kNumShapes || !shape_ok(ctx, k)) return LBM_E_INVAL;
     ctx->shape = k;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_shape(const lbm_ctx *ctx, int32_t *k) {
+    if (!ctx || !k) return LBM_E_INVAL;
+    *k = ctx->shape;
     return LBM_OK;
 }
 
@@ -1204,6 +1261,7 @@ struct lbm_ens {
     int64_t vacf_t;
     int64_t step;
     int shape;
+    int device;  // device current at lbm_ens_init (autotune cache key)
     // two-step graph, captured on a private stream and replayed on `stream`
     int use_graph;
     hipGraphExec_t graph;
@@ -1213,6 +1271,17 @@ struct lbm_ens {
 };
 
 namespace {
+
+TuneKey ens_tune_key(const lbm_ens *e) {
+    TuneKey k{e->device, e->desc.storage, int(D3Q19::Q), {}};
+    k.dims.reserve(3 * size_t(e->nrep));
+    for (int32_t q = 0; q < e->nrep; ++q) {
+        k.dims.push_back(e->host_reps[q].nx);
+        k.dims.push_back(e->host_reps[q].ny);
+        k.dims.push_back(e->host_reps[q].nz);
+    }
+    return k;
+}
 
 uint32_t ens_chunk(int storage, int32_t nx) {
     const uint32_t per_line = uint32_t(128 / elem_size(storage));
@@ -1483,7 +1552,9 @@ lbm_status lbm_ens_init(const lbm_ensemble_desc *desc, const lbm_replica_desc *r
     e->total_cells = L.total_cells;
     e->total_pop = L.total_pop;
     e->total_mask_words = L.total_mask_words;
-    e->shape = L.lattice_bytes >= kStreamStoreBytes ? kNumGeomShapes : 0;  // until autotune
+    e->device = current_device();
+    // until lbm_ens_autotune: the last choice for this key, else by lattice size
+    e->shape = tune_lookup(ens_tune_key(e), L.lattice_bytes >= kStreamStoreBytes ? kNumGeomShapes : 0);
     for (int s = 0; s < kNumGeomShapes; ++s) e->total_blocks[s] = L.total_blocks[s];
     e->n = L.n;
     char *base = static_cast<char *>(scratch);
@@ -1672,6 +1743,7 @@ lbm_status lbm_ens_autotune(lbm_ens *e, int32_t iters, double *ms, int32_t *chos
         if (t[k] > 0.0 && (t[best] <= 0.0 || t[k] < t[best])) best = k;
     if (best != e->shape) ens_drop_graph(e);
     e->shape = best;
+    tune_store(ens_tune_key(e), best);
     if (ms)
         for (int k = 0; k < kNumShapes; ++k) ms[k] = t[k];
     if (chosen) *chosen = best;
@@ -1727,6 +1799,12 @@ lbm_status lbm_ens_get_populations(lbm_ens *e, int32_t replica, double *f) {
 #undef LBM_ENS_POPS
     }
     return launch_status();
+}
+
+lbm_status lbm_ens_get_shape(const lbm_ens *e, int32_t *k) {
+    if (!e || !k) return LBM_E_INVAL;
+    *k = e->shape;
+    return LBM_OK;
 }
 
 lbm_status lbm_ens_get_step(const lbm_ens *e, int64_t *step) {

@@ -237,6 +237,13 @@ class Lattice:
         _abi.check("lbm_set_shape", self.lib.lbm_set_shape(self.ctx, int(k)))
 
     @property
+    def shape(self) -> int:
+        """The stream-collide launch configuration later steps use."""
+        k = ctypes.c_int32()
+        _abi.check("lbm_get_shape", self.lib.lbm_get_shape(self.ctx, ctypes.byref(k)))
+        return k.value
+
+    @property
     def step_count(self) -> int:
         s = ctypes.c_int64()
         _abi.check("lbm_get_step", self.lib.lbm_get_step(self.ctx, ctypes.byref(s)))
@@ -361,6 +368,13 @@ class Ensemble:
         _abi.check("lbm_ens_autotune", self.lib.lbm_ens_autotune(
             self.ctx, int(iters), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(chosen)))
         return chosen.value, ms
+
+    @property
+    def shape(self) -> int:
+        """The stream-collide launch configuration later steps use."""
+        k = ctypes.c_int32()
+        _abi.check("lbm_ens_get_shape", self.lib.lbm_ens_get_shape(self.ctx, ctypes.byref(k)))
+        return k.value
 
     def vacf_config(self, max_lag: int, stride: int):
         sz = ctypes.c_size_t()

@@ -134,3 +134,19 @@ def test_ensemble64_workload():
     for k in range(len(reps)):
         o = ens.observables(k)
         assert abs(o[0] - reps[k]["nx"] ** 3) < 1e-6 * reps[k]["nx"] ** 3
+
+
+def test_autotune_choice_is_remembered():
+    # lbm_ens_autotune's choice is kept for the process: a later ensemble of
+    # the same boxes (same order, storage, device) starts from it; other box
+    # lists start from the size-based default.
+    from paper_1909_13412_amd import Ensemble
+
+    reps = _small_replicas()
+    a = Ensemble(reps, storage="f32", kT=1e-4)
+    k, ms = a.autotune(3)
+    assert a.shape == k and ms[k] > 0.0
+    b = Ensemble(reps, storage="f32", kT=1e-4)
+    assert b.shape == k
+    c = Ensemble(reps[::-1], storage="f32", kT=1e-4)
+    assert c.shape == 0  # small boxes: one node per lane, 512 lanes, plain stores

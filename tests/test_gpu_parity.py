@@ -364,6 +364,23 @@ def test_suspension512_tiled_against_oracle(oracle_mod):
     torch.cuda.empty_cache()
 
 
+def test_autotune_choice_is_remembered():
+    # lbm_autotune's choice is kept for the process, per device, storage,
+    # velocity set and box size: a later context of the same key starts from
+    # it, any other key from the size-based default.
+    from paper_1909_13412_amd import Lattice
+
+    for dims in ((40, 30, 22), (33, 17, 12)):
+        a = Lattice(*dims, 0.8, storage="f32")
+        k, ms = a.autotune(3)
+        assert a.shape == k and ms[k] > 0.0
+        assert Lattice(*dims, 0.8, storage="f32").shape == k
+        assert Lattice(*dims, 0.8, storage="f32", velocities=15).shape == 0
+        assert Lattice(dims[0], dims[1], dims[2] + 1, 0.8, storage="f32").shape == 0
+    # a lattice beyond the last-level cache defaults to non-temporal stores
+    assert Lattice(256, 256, 256, 0.6, storage="f32").shape == 4
+
+
 def test_nonfinite_detected(oracle_mod):
     from paper_1909_13412_amd import LbmError, Lattice
 
@@ -649,3 +666,8 @@ def test_pair_repulsion_reproducible_and_validated():
     with pytest.raises(_abi.LbmError):
         lat.set_pair_force(0.1, 4.5)  # beyond half the box
     lat.set_pair_force(0.0, 0.0)  # off
+    big = Lattice(32, 32, 32, 0.8)
+    n_big = 65537  # one above the cell list's limit
+    big.particles_couple(particle_positions(n_big, 32.0, seed=9), np.zeros((n_big, 3)))
+    with pytest.raises(_abi.LbmError):
+        big.set_pair_force(0.1, 1.0)
