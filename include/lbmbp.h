@@ -188,6 +188,23 @@ lbm_status lbm_pair_forces(lbm_ctx *ctx, double *fc);
  * particles are attached. */
 double lbm_particle_radius(const lbm_ctx *ctx);
 
+/* Advisory conditions of the attached particle set (not errors; section 2.2
+ * gives the parameter ranges), as a bit set:
+ *   LBM_WARN_RADIUS_BOUND     R > sqrt(3) dx for the unit-cell Stokeslet fit
+ *                             (R > 2 sqrt(3) dx for the (2 dx)^3 cube): the
+ *                             particle covers the fitting nodes;
+ *   LBM_WARN_NEGATIVE_GAIN    R > sqrt(3)/2 dx for the unit-cell fit (sqrt(3)
+ *                             dx for the cube): the fit's gain in a uniform
+ *                             stream is negative at the cell (cube) centre, so
+ *                             friction can turn into propulsion;
+ *   LBM_WARN_VOLUME_FRACTION  n (4/3) pi R^3 / (nx ny nz) > 0.1, beyond the
+ *                             volume fractions the method was checked for.
+ * Zero without particles. */
+#define LBM_WARN_RADIUS_BOUND 1u
+#define LBM_WARN_NEGATIVE_GAIN 2u
+#define LBM_WARN_VOLUME_FRACTION 4u
+lbm_status lbm_warnings(const lbm_ctx *ctx, uint32_t *flags);
+
 /* Copy the friction F_H and random force F_R of the most recent step into
  * device FP64 [n][3] buffers (either may be NULL). */
 lbm_status lbm_particle_forces(lbm_ctx *ctx, double *fh, double *fr);

@@ -17,7 +17,7 @@ FRICTION = {"stokeslet": 0, "pointwise": 1, "bd": 2, "stokeslet2dx": 3}
 EXPORTS = [
     "lbm_lattice_bytes", "lbm_grid_scratch_bytes", "lbm_particle_scratch_bytes",
     "lbm_vacf_origin_bytes", "lbm_init", "lbm_set_equilibrium", "lbm_set_populations",
-    "lbm_set_body_force", "lbm_get_populations", "lbm_get_moments", "particles_couple", "lbm_set_particle_force", "lbm_set_pair_force", "lbm_pair_forces", "lbm_particle_radius",
+    "lbm_set_body_force", "lbm_get_populations", "lbm_get_moments", "particles_couple", "lbm_set_particle_force", "lbm_set_pair_force", "lbm_pair_forces", "lbm_particle_radius", "lbm_warnings",
     "lbm_particle_forces", "lbm_vacf_config", "lbm_vacf_counts", "lbm_step", "lbm_series_config",
     "lbm_series_count", "lbm_observables",
     "lbm_profile_enable", "lbm_profile_read", "lbm_autotune", "lbm_set_shape", "lbm_get_shape", "lbm_get_step", "lbm_destroy",
@@ -28,6 +28,12 @@ EXPORTS = [
     "lbm_status_string",
 ]
 LBM_NUM_SHAPES = 8
+# advisory bits of lbm_warnings
+WARNINGS = {
+    1: "radius beyond sqrt(3) dx (2 sqrt(3) dx for the (2 dx)^3 fit): the particle covers the fitting nodes",
+    2: "radius beyond sqrt(3)/2 dx (sqrt(3) dx for the (2 dx)^3 fit): the fit's gain turns negative at the cell centre",
+    4: "volume fraction above 0.1, beyond the range the method was checked for",
+}
 
 
 class GridDesc(ctypes.Structure):
@@ -104,6 +110,7 @@ def load() -> ctypes.CDLL:
         "lbm_autotune": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],
         "lbm_set_shape": [vp, i32],
         "lbm_get_shape": [vp, ctypes.POINTER(i32)],
+        "lbm_warnings": [vp, ctypes.POINTER(ctypes.c_uint32)],
         "lbm_get_step": [vp, ctypes.POINTER(i64)],
         "lbm_destroy": [vp],
         "lbm_tape_bytes": [vp, i32, i32, ctypes.POINTER(sz)],

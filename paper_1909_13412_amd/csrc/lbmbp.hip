@@ -345,6 +345,7 @@ struct lbm_ctx {
     uint32_t *prev_cell;
     double *fh, *fr;
     const double *fext;  // given force on each particle (lbm_set_particle_force) or null
+    uint32_t warnings;   // LBM_WARN_* of the attached particles
     // soft pair repulsion (lbm_set_pair_force)
     int pair_on;
     PairGrid pg;
@@ -446,6 +447,21 @@ size_t grid_scratch_size(const lbm_grid_desc *g) {
 }
 
 size_t particle_blocks(int32_t n) { return (size_t(n) * 8 + kParticleBlock - 1) / kParticleBlock; }
+
+// Advisory conditions of a particle set (section 2.2's parameter ranges and
+// the sign of the fit's gain); see LBM_WARN_* in the header.
+uint32_t coupling_warnings(int32_t friction, double R, int32_t n, double ncell) {
+    uint32_t w = 0;
+    const double s3 = sqrt(3.0);
+    if (friction == LBM_FRICTION_STOKESLET || friction == LBM_FRICTION_STOKESLET_2DX) {
+        const double span = friction == LBM_FRICTION_STOKESLET_2DX ? 2.0 : 1.0;  // cube edge
+        if (R > s3 * span) w |= LBM_WARN_RADIUS_BOUND;
+        if (R > 0.5 * s3 * span) w |= LBM_WARN_NEGATIVE_GAIN;
+    }
+    if (friction != LBM_FRICTION_BD && double(n) * (4.0 / 3.0) * M_PI * R * R * R > 0.1 * ncell)
+        w |= LBM_WARN_VOLUME_FRACTION;
+    return w;
+}
 
 // Buckets of the pair cell list: a power of two >= 2n.
 uint32_t pair_buckets(int32_t n) {
@@ -979,6 +995,7 @@ lbm_status particles_couple(lbm_ctx *ctx, const lbm_particle_desc *d, double *r,
     ctx->pair_on = 0;
     ctx->np = d->n;
     ctx->pdesc = *d;
+    ctx->warnings = 0;
     if (d->n == 0) {
         ctx->R = -1.0;
         return LBM_OK;
@@ -986,6 +1003,7 @@ lbm_status particles_couple(lbm_ctx *ctx, const lbm_particle_desc *d, double *r,
     // Stokes' law gamma = 6 pi eta R, eta = rho0 nu, nu = (tau - 1/2)/3.
     const double nu = (ctx->desc.tau - 0.5) / 3.0;
     ctx->R = d->radius > 0.0 ? d->radius : d->gamma / (6.0 * M_PI * nu);
+    ctx->warnings = coupling_warnings(d->friction, ctx->R, d->n, double(ctx->g.ncell));
     ctx->r = r;
     ctx->v = v;
     char *s = static_cast<char *>(particle_scratch);
@@ -1170,6 +1188,12 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen
 lbm_status lbm_set_shape(lbm_ctx *ctx, int32_t k) {
     if (!ctx || k < 0 || k >= kNumShapes || !shape_ok(ctx, k)) return LBM_E_INVAL;
     ctx->shape = k;
+    return LBM_OK;
+}
+
+lbm_status lbm_warnings(const lbm_ctx *ctx, uint32_t *flags) {
+    if (!ctx || !flags) return LBM_E_INVAL;
+    *flags = ctx->warnings;
     return LBM_OK;
 }
 

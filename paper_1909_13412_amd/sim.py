@@ -3,6 +3,7 @@ every step of the method runs in the HIP kernels of liblbmbp.so."""
 from __future__ import annotations
 
 import ctypes
+import warnings as _warnings
 
 import numpy as np
 import torch
@@ -142,6 +143,16 @@ class Lattice:
         self._vacf = None
         self.fh = torch.zeros((n, 3), dtype=torch.float64, device=self.device)
         self.fr = torch.zeros((n, 3), dtype=torch.float64, device=self.device)
+        for bit, text in _abi.WARNINGS.items():
+            if self.warnings & bit:
+                _warnings.warn(f"particles_couple: {text} (R = {self.radius:.4g})", stacklevel=2)
+
+    @property
+    def warnings(self) -> int:
+        """LBM_WARN_* bits of the attached particle set (advisory, not errors)."""
+        f = ctypes.c_uint32()
+        _abi.check("lbm_warnings", self.lib.lbm_warnings(self.ctx, ctypes.byref(f)))
+        return f.value
 
     def set_particle_force(self, F=None):
         """Constant force F_C on each particle ([n, 3]; None detaches it)."""
@@ -237,7 +248,7 @@ class Lattice:
         _abi.check("lbm_set_shape", self.lib.lbm_set_shape(self.ctx, int(k)))
 
     @property
-    def shape(self) -> int:
+    def launch_config(self) -> int:
         """The stream-collide launch configuration later steps use."""
         k = ctypes.c_int32()
         _abi.check("lbm_get_shape", self.lib.lbm_get_shape(self.ctx, ctypes.byref(k)))
@@ -370,7 +381,7 @@ class Ensemble:
         return chosen.value, ms
 
     @property
-    def shape(self) -> int:
+    def launch_config(self) -> int:
         """The stream-collide launch configuration later steps use."""
         k = ctypes.c_int32()
         _abi.check("lbm_ens_get_shape", self.lib.lbm_ens_get_shape(self.ctx, ctypes.byref(k)))

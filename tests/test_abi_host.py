@@ -125,6 +125,8 @@ def test_null_context_rejected(lib):
     assert lib.lbm_set_pair_force(None, ctypes.c_double(0.1), ctypes.c_double(1.0)) == 1
     assert lib.lbm_pair_forces(None, None) == 1
     assert lib.lbm_autotune(None, 5, None, None) == 1
+    f = ctypes.c_uint32()
+    assert lib.lbm_warnings(None, ctypes.byref(f)) == 1
 
 
 def test_status_strings(lib):
@@ -168,3 +170,25 @@ def test_launch_configuration_count_matches_header():
     text = open(os.path.join(ROOT, "include", "lbmbp.h")).read()
     m = re.search(r"#define LBM_NUM_SHAPES (\d+)", text)
     assert m and int(m.group(1)) == _abi.LBM_NUM_SHAPES == 8
+
+
+def test_binding_attributes_not_shadowed_by_properties():
+    # An attribute the binding assigns on its instances must not also be a
+    # read-only property of the class (the assignment would fail at run time,
+    # and only on a GPU).
+    import ast
+
+    src = open(os.path.join(ROOT, "paper_1909_13412_amd", "sim.py")).read()
+    for cls in (n for n in ast.parse(src).body if isinstance(n, ast.ClassDef)):
+        props, assigned = set(), set()
+        for fn in (n for n in cls.body if isinstance(n, ast.FunctionDef)):
+            if any(isinstance(d, ast.Name) and d.id == "property" for d in fn.decorator_list):
+                props.add(fn.name)
+            for node in ast.walk(fn):
+                targets = node.targets if isinstance(node, ast.Assign) else (
+                    [node.target] if isinstance(node, (ast.AugAssign, ast.AnnAssign)) else [])
+                for t in targets:
+                    for e in (t.elts if isinstance(t, ast.Tuple) else [t]):
+                        if isinstance(e, ast.Attribute) and isinstance(e.value, ast.Name) and e.value.id == "self":
+                            assigned.add(e.attr)
+        assert not (props & assigned), (cls.name, props & assigned)

@@ -145,8 +145,8 @@ def test_autotune_choice_is_remembered():
     reps = _small_replicas()
     a = Ensemble(reps, storage="f32", kT=1e-4)
     k, ms = a.autotune(3)
-    assert a.shape == k and ms[k] > 0.0
+    assert a.launch_config == k and ms[k] > 0.0
     b = Ensemble(reps, storage="f32", kT=1e-4)
-    assert b.shape == k
+    assert b.launch_config == k
     c = Ensemble(reps[::-1], storage="f32", kT=1e-4)
-    assert c.shape == 0  # small boxes: one node per lane, 512 lanes, plain stores
+    assert c.launch_config == 0  # small boxes: one node per lane, 512 lanes, plain stores

@@ -373,12 +373,45 @@ def test_autotune_choice_is_remembered():
     for dims in ((40, 30, 22), (33, 17, 12)):
         a = Lattice(*dims, 0.8, storage="f32")
         k, ms = a.autotune(3)
-        assert a.shape == k and ms[k] > 0.0
-        assert Lattice(*dims, 0.8, storage="f32").shape == k
-        assert Lattice(*dims, 0.8, storage="f32", velocities=15).shape == 0
-        assert Lattice(dims[0], dims[1], dims[2] + 1, 0.8, storage="f32").shape == 0
+        assert a.launch_config == k and ms[k] > 0.0
+        assert Lattice(*dims, 0.8, storage="f32").launch_config == k
+        assert Lattice(*dims, 0.8, storage="f32", velocities=15).launch_config == 0
+        assert Lattice(dims[0], dims[1], dims[2] + 1, 0.8, storage="f32").launch_config == 0
     # a lattice beyond the last-level cache defaults to non-temporal stores
-    assert Lattice(256, 256, 256, 0.6, storage="f32").shape == 4
+    assert Lattice(256, 256, 256, 0.6, storage="f32").launch_config == 4
+
+
+def test_coupling_warnings():
+    # Advisory bits of section 2.2's parameter ranges, raised as warnings by
+    # the binding; never errors.
+    import warnings
+
+    from paper_1909_13412_amd import Lattice
+    from paper_1909_13412_amd.inputs import particle_positions
+
+    lat = Lattice(24, 24, 24, 0.6)
+    r = particle_positions(4, 24.0, seed=1)
+    v = np.zeros((4, 3))
+    with warnings.catch_warnings():
+        warnings.simplefilter("error")
+        lat.particles_couple(r, v, radius=0.5)
+        assert lat.warnings == 0
+        lat.particles_couple(r, v, radius=1.59, friction="stokeslet2dx")  # within the cube's range
+        assert lat.warnings == 0
+        lat.particles_couple(r, v, radius=3.0, friction="bd")  # no fit, no fluid coupling
+        assert lat.warnings == 0
+    with pytest.warns(UserWarning, match="negative"):
+        lat.particles_couple(r, v, gamma=1.0)  # Stokes' law at tau 0.6: R = 1.59
+    assert lat.warnings == 2 and abs(lat.radius - 1.0 / (6 * np.pi * 0.1 / 3)) < 1e-12
+    with pytest.warns(UserWarning, match="covers"):
+        lat.particles_couple(r, v, radius=1.8)
+    assert lat.warnings == 3
+    with pytest.warns(UserWarning, match="volume fraction"):
+        lat.particles_couple(particle_positions(4096, 24.0, seed=2), np.zeros((4096, 3)), radius=0.5)
+    assert lat.warnings == 4
+    lat.particles_couple(np.zeros((0, 3)), np.zeros((0, 3)))
+    assert lat.warnings == 0
+    lat.step(2)
 
 
 def test_nonfinite_detected(oracle_mod):
