@@ -112,7 +112,8 @@ typedef struct lbm_particle_desc {
 typedef struct lbm_ctx lbm_ctx;
 
 /* Bytes of ONE population lattice (the library uses two, A and B, swapped every
- * step).  Planes may be padded; the caller only allocates this many bytes. */
+ * step): Q x nx x ny x nz elements rounded up to 256 bytes; the caller only
+ * allocates this many bytes. */
 lbm_status lbm_lattice_bytes(const lbm_grid_desc *grid, size_t *bytes);
 
 /* Bytes of grid scratch: two node-force fields (24 bytes per node each) with

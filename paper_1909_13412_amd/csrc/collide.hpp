@@ -4,9 +4,10 @@
 //
 // Layout: for every lattice row (y, z) the 19 population rows are stored one
 // after another, x fastest: element (a, x, y, z) sits at
-// ((z*ny + y)*19 + a)*chunk + x, chunk = nx rounded up to a 128-byte line.  A
-// block streams whole rows, so each wave reads nine contiguous 19-row groups
-// and writes one; this beats one plane per velocity (38 far-apart streams).
+// ((z*ny + y)*Q + a)*chunk + x with chunk = nx (no padding: the rows of a
+// group are back to back).  A block streams whole rows, so each wave reads
+// from nine 19-row groups and writes one contiguous group; this beats one
+// plane per velocity (38 far-apart streams).
 // Lattice A holds post-collision values at their source node, so the
 // post-streaming population is read by pulling from x - e_a.
 #pragma once
@@ -33,7 +34,7 @@ constexpr uint32_t kErrFixRange = 1u;
 struct Grid {
     uint32_t nx, ny, nz;
     uint32_t ncell;
-    uint32_t chunk;  // elements per population row (nx padded to a 128-byte line)
+    uint32_t chunk;  // elements per population row (nx)
 };
 
 // Storage index of population a at node (x, y, z) for velocity set V.

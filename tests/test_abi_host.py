@@ -61,10 +61,8 @@ def test_lattice_and_scratch_sizes(lib):
         ncell = 37 * 23 * 19
         assert sz.value >= 19 * ncell * elem
         assert sz.value % 256 == 0
-        # population rows are padded to whole 128-byte lines
-        per_line = 128 // elem
-        chunk = -(-37 // per_line) * per_line
-        assert sz.value == -(-(19 * chunk * 23 * 19 * elem) // 256) * 256
+        # unpadded rows, the total rounded up to 256 bytes
+        assert sz.value == -(-(19 * 37 * 23 * 19 * elem) // 256) * 256
     g = _grid(nx=256, ny=256, nz=256)
     assert lib.lbm_lattice_bytes(ctypes.byref(g), ctypes.byref(sz)) == 0
     assert sz.value == 19 * 256**3 * 4
@@ -146,8 +144,7 @@ def test_ensemble_sizes_and_validation(lib):
                                   _abi.ReplicaDesc(96, 96, 96, 8, 0.8, 3, 2, 0))
     lat, scr = ctypes.c_size_t(), ctypes.c_size_t()
     assert lib.lbm_ens_bytes(ctypes.byref(d), reps, ctypes.byref(lat), ctypes.byref(scr)) == 0
-    chunk = lambda nx: -(-nx // 32) * 32
-    want = 19 * 4 * (chunk(48) * 48 * 48 + chunk(37) * 20 * 11 + chunk(96) * 96 * 96)
+    want = 19 * 4 * (48 * 48 * 48 + 37 * 20 * 11 + 96 * 96 * 96)
     assert lat.value == -(-want // 256) * 256
     cells = 48**3 + 37 * 20 * 11 + 96**3
     assert scr.value > 2 * 24 * cells
