@@ -257,16 +257,19 @@ lbm_status lbm_profile_enable(lbm_ctx *ctx, int32_t enable);
  * out[2] summed particle-phase milliseconds, out[3] particle-phase launches. */
 lbm_status lbm_profile_read(lbm_ctx *ctx, double out[4]);
 
-/* Stream-collide launch configurations k = 0..7.  k & 3 is the geometric
- * shape: 0 = one node per lane, 512-lane blocks; 1 = one node, 256; 2 = two
- * nodes (rows y and y + ny/2), 512; 3 = two nodes, 256 (2 and 3 need an even
- * ny).  k >= 4 writes the populations with non-temporal stores (streamed past
- * the caches), which pays off once a lattice no longer fits in the GPU's
- * last-level cache.  Until lbm_autotune runs, a context uses the configuration
- * the autotuner last chose in this process for the same device, storage,
- * velocity set and box size, if any; otherwise shape 0, with non-temporal
- * stores when one lattice is at least 256 MiB. */
-#define LBM_NUM_SHAPES 8
+/* Stream-collide launch configurations k = 0..9.  For k < 8, lanes take
+ * consecutive nodes and k & 3 is the geometric shape: 0 = one node per lane,
+ * 512-lane blocks; 1 = one node, 256; 2 = two nodes (rows y and y + ny/2),
+ * 512; 3 = two nodes, 256 (2 and 3 need an even ny); k >= 4 writes the
+ * populations with non-temporal stores (streamed past the caches), which pays
+ * off once a lattice no longer fits in the GPU's last-level cache.  k = 8 and
+ * 9 align lanes with rows (one node per lane, 256-lane blocks, every row
+ * starting a 64-lane wavefront; faster when nx is not a multiple of 64), with
+ * plain and non-temporal stores; single boxes only.  Until lbm_autotune runs,
+ * a context uses the configuration the autotuner last chose in this process
+ * for the same device, storage, velocity set and box size, if any; otherwise
+ * shape 0, with non-temporal stores when one lattice is at least 256 MiB. */
+#define LBM_NUM_SHAPES 10
 
 /* Time every valid stream-collide configuration on this context's lattice (iters
  * launches each, reading the current populations and writing the spare

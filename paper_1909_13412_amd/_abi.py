@@ -27,7 +27,7 @@ EXPORTS = [
     "lbm_ens_get_populations", "lbm_ens_get_step", "lbm_ens_graph_replays", "lbm_ens_destroy",
     "lbm_status_string",
 ]
-LBM_NUM_SHAPES = 8
+LBM_NUM_SHAPES = 10
 # advisory bits of lbm_warnings
 WARNINGS = {
     1: "radius beyond sqrt(3) dx (2 sqrt(3) dx for the (2 dx)^3 fit): the particle covers the fitting nodes",

@@ -206,15 +206,40 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
     }
 }
 
-template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS>
+// Lanes per row of the row-aligned mapping: nx rounded up to whole wavefronts.
+__host__ __device__ inline uint32_t row_lanes(uint32_t nx) { return (nx + 63u) & ~63u; }
+
+// ROW: lanes map to whole rows (every row starts a wavefront: a block of BS
+// lanes holds BS / row_lanes rows, or a row spans several blocks), so no wave
+// straddles two rows when nx is not a multiple of 64; otherwise lanes map to
+// consecutive nodes (rows y and y + ny/CPT for CPT = 2).
+template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW>
 __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__restrict__ A,
                                                        typename C::T *__restrict__ B, Grid g,
                                                        typename C::R omega, typename C::R enc_s,
                                                        typename C::R dec_s, ForceField ff,
                                                        typename C::R Gx, typename C::R Gy,
                                                        typename C::R Gz, double *__restrict__ mom) {
-    const uint32_t lane_cell = blockIdx.x * BS + threadIdx.x;  // node index in the first row band
-    const bool active = lane_cell < g.ncell / CPT;
+    uint32_t lane_cell;  // node index (in the first row band when CPT = 2)
+    bool active;
+    if constexpr (ROW) {
+        static_assert(CPT == 1, "the row-aligned mapping takes one node per lane");
+        const uint32_t lpr = row_lanes(g.nx);
+        uint32_t row, x;
+        if (lpr <= uint32_t(BS)) {
+            row = blockIdx.x * (uint32_t(BS) / lpr) + threadIdx.x / lpr;
+            x = threadIdx.x % lpr;
+        } else {
+            const uint32_t bpr = (lpr + BS - 1) / BS;  // blocks per row
+            row = blockIdx.x / bpr;
+            x = (blockIdx.x % bpr) * BS + threadIdx.x;
+        }
+        active = x < g.nx && row < g.ny * g.nz;
+        lane_cell = row * g.nx + x;
+    } else {
+        lane_cell = blockIdx.x * BS + threadIdx.x;
+        active = lane_cell < g.ncell / CPT;
+    }
     if constexpr (!MOMENTS) {
         if (!active) return;
     }
@@ -226,14 +251,19 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
 }
 
 // Launch configurations of the stream-collide, chosen per context
-// (lbm_autotune): configuration k uses the geometric shape kShapes[k & 3]
-// and non-temporal stores when k >= 4.
+// (lbm_autotune): configurations 0-7 map lanes to consecutive nodes with the
+// geometric shape kShapes[k & 3], non-temporal stores when k >= 4;
+// configurations 8 and 9 use the row-aligned mapping (one node per lane,
+// 256-lane blocks) with plain and non-temporal stores.  Ensembles use 0-7.
 struct CollideShape {
     int cpt, bs;
 };
 constexpr CollideShape kShapes[] = {{1, 512}, {1, 256}, {2, 512}, {2, 256}};
 constexpr int kNumGeomShapes = 4;
-constexpr int kNumShapes = 2 * kNumGeomShapes;
+constexpr int kNumFlatShapes = 2 * kNumGeomShapes;
+constexpr int kNumShapes = kNumFlatShapes + 2;
+constexpr int kRowBlock = 256;
+constexpr bool config_row(int k) { return k >= kNumFlatShapes; }
 // Lattices of at least this many bytes default to non-temporal stores.
 constexpr size_t kStreamStoreBytes = size_t(256) << 20;
 

@@ -512,34 +512,46 @@ lbm_status launch_status() {
 }
 
 unsigned blocks_for(uint64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
-// Launch configuration k of the stream-collide: shape k & 3, non-temporal
-// stores for k >= 4.
+// Launch configuration k of the stream-collide: CALL(nodes per lane, block,
+// non-temporal stores, row-aligned mapping).  Ensembles take k < 8 only.
 #define LBM_CONFIG_SWITCH(k, CALL)                  \
     switch (k) {                                    \
-        case 1: CALL(1, 256, false); break;         \
-        case 2: CALL(2, 512, false); break;         \
-        case 3: CALL(2, 256, false); break;         \
-        case 4: CALL(1, 512, true); break;          \
-        case 5: CALL(1, 256, true); break;          \
-        case 6: CALL(2, 512, true); break;          \
-        case 7: CALL(2, 256, true); break;          \
-        default: CALL(1, 512, false); break;        \
+        case 1: CALL(1, 256, false, false); break;  \
+        case 2: CALL(2, 512, false, false); break;  \
+        case 3: CALL(2, 256, false, false); break;  \
+        case 4: CALL(1, 512, true, false); break;   \
+        case 5: CALL(1, 256, true, false); break;   \
+        case 6: CALL(2, 512, true, false); break;   \
+        case 7: CALL(2, 256, true, false); break;   \
+        case 8: CALL(1, 256, false, true); break;   \
+        case 9: CALL(1, 256, true, true); break;    \
+        default: CALL(1, 512, false, false); break; \
     }
 
-bool shape_ok(const lbm_ctx *c, int k) { return c->g.ny % uint32_t(kShapes[k & 3].cpt) == 0; }
+bool shape_ok(const lbm_ctx *c, int k) {
+    return config_row(k) || c->g.ny % uint32_t(kShapes[k & 3].cpt) == 0;
+}
 
 uint32_t collide_grid(const lbm_ctx *c, int shape) {
+    if (config_row(shape)) {
+        const uint32_t lpr = row_lanes(c->g.nx), nrows = c->g.ny * c->g.nz;
+        if (lpr <= uint32_t(kRowBlock)) {
+            const uint32_t rpb = uint32_t(kRowBlock) / lpr;  // rows per block
+            return (nrows + rpb - 1) / rpb;
+        }
+        return nrows * ((lpr + kRowBlock - 1) / kRowBlock);
+    }
     const CollideShape &sh = kShapes[shape & 3];
     const uint64_t band = c->g.ncell / uint32_t(sh.cpt);
     return uint32_t((band + sh.bs - 1) / sh.bs);
 }
 
-template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS>
+template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW>
 void launch_collide_shape(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff,
                           double *mom, unsigned grid) {
     using R = typename C::R;
-    hipLaunchKernelGGL((k_stream_collide<C, FORCED, MOMENTS, CPT, BS, NTS>), dim3(grid), dim3(BS), 0,
-                       c->stream, A, B, c->g, R(c->omega), R(c->enc_s), R(c->dec_s), ff,
+    hipLaunchKernelGGL((k_stream_collide<C, FORCED, MOMENTS, CPT, BS, NTS, ROW>), dim3(grid), dim3(BS),
+                       0, c->stream, A, B, c->g, R(c->omega), R(c->enc_s), R(c->dec_s), ff,
                        R(c->body[0]), R(c->body[1]), R(c->body[2]), mom);
 }
 
@@ -548,12 +560,12 @@ template <class C, bool FORCED>
 void launch_collide(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff, int shape,
                     double *mom = nullptr) {
     const unsigned grid = collide_grid(c, shape);
-#define LBM_SHAPE(CPT, BS, NTS)                                                              \
-    do {                                                                                     \
-        if (mom)                                                                             \
-            launch_collide_shape<C, FORCED, true, CPT, BS, NTS>(c, A, B, ff, mom, grid);     \
-        else                                                                                 \
-            launch_collide_shape<C, FORCED, false, CPT, BS, NTS>(c, A, B, ff, mom, grid);    \
+#define LBM_SHAPE(CPT, BS, NTS, ROW)                                                          \
+    do {                                                                                      \
+        if (mom)                                                                              \
+            launch_collide_shape<C, FORCED, true, CPT, BS, NTS, ROW>(c, A, B, ff, mom, grid);  \
+        else                                                                                  \
+            launch_collide_shape<C, FORCED, false, CPT, BS, NTS, ROW>(c, A, B, ff, mom, grid); \
     } while (0)
     LBM_CONFIG_SWITCH(shape, LBM_SHAPE)
 #undef LBM_SHAPE
@@ -1438,7 +1450,7 @@ void ens_launch_step(lbm_ens *e, int cur, int par) {
                        dim3(unsigned((uint64_t(e->n) * 8 + kParticleBlock - 1) / kParticleBlock)),
                        dim3(kParticleBlock), 0, e->stream, A, e->reps, e->part_rep, R(e->dec_s), pa,
                        e->clock, e->force[par], e->mask[par], e->force[par ^ 1], e->mask[par ^ 1]);
-#define LBM_ENS_CALL(CPT, BS, NTS) ens_collide_shape<C, CPT, BS, NTS>(e, A, B, par)
+#define LBM_ENS_CALL(CPT, BS, NTS, ROW) ens_collide_shape<C, CPT, BS, NTS>(e, A, B, par)
     LBM_CONFIG_SWITCH(e->shape, LBM_ENS_CALL)
 #undef LBM_ENS_CALL
 }
@@ -1504,7 +1516,7 @@ void ens_time_shape(lbm_ens *e, int k) {
 
 template <class C>
 void ens_time_dispatch(lbm_ens *e, int k) {
-#define LBM_ENS_TIME(CPT, BS, NTS) ens_time_shape<C, CPT, BS, NTS>(e, k)
+#define LBM_ENS_TIME(CPT, BS, NTS, ROW) ens_time_shape<C, CPT, BS, NTS>(e, k)
     LBM_CONFIG_SWITCH(k, LBM_ENS_TIME)
 #undef LBM_ENS_TIME
 }
@@ -1739,7 +1751,7 @@ lbm_status lbm_ens_autotune(lbm_ens *e, int32_t iters, double *ms, int32_t *chos
     double t[kNumShapes];
     for (int k = 0; k < kNumShapes && err == hipSuccess; ++k) {
         t[k] = -1.0;
-        if (e->total_blocks[k & 3] == 0) continue;
+        if (config_row(k) || e->total_blocks[k & 3] == 0) continue;  // rows: single boxes only
         bool all = true;
         for (int32_t q = 0; q < e->nrep; ++q) all = all && (e->host_reps[q].ny % kShapes[k & 3].cpt == 0);
         if (!all) continue;

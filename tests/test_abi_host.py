@@ -166,7 +166,7 @@ def test_launch_configuration_count_matches_header():
 
     text = open(os.path.join(ROOT, "include", "lbmbp.h")).read()
     m = re.search(r"#define LBM_NUM_SHAPES (\d+)", text)
-    assert m and int(m.group(1)) == _abi.LBM_NUM_SHAPES == 8
+    assert m and int(m.group(1)) == _abi.LBM_NUM_SHAPES == 10
 
 
 def test_binding_attributes_not_shadowed_by_properties():

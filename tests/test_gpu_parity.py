@@ -299,7 +299,7 @@ def test_suspension512_tiled_against_oracle(oracle_mod):
     # the same place in every tile.  The 512^3 run is then the 32^3 run
     # repeated: every tile, including those whose population offsets lie
     # beyond 2^31 elements, must hold the same moments, in every non-temporal
-    # launch configuration the large-lattice autotuner chooses from, and tile
+    # launch configuration (row-aligned included), and tile
     # 0 must match the oracle's 32^3 run.  The start positions are dyadic, so
     # the first step is the same in every tile bit for bit; later positions
     # r + V round differently at different magnitudes (FP64, ~1e-14
@@ -332,7 +332,7 @@ def test_suspension512_tiled_against_oracle(oracle_mod):
     u_d = torch.from_numpy(u_t).to(dev).repeat(1, K, K, K)
     g = Lattice(L, L, L, w["tau"], storage="f32")
     first = None
-    for shape in (4, 5, 6, 7):
+    for shape in (4, 5, 6, 7, 9):
         g.set_shape(shape)
         g.set_equilibrium(rho_d, u_d)
         g.particles_couple(r, v, **kw)
@@ -584,38 +584,41 @@ def test_fifteen_velocity_shear_wave(oracle_mod, tau):
 
 
 def test_every_launch_configuration_is_bit_identical():
-    # Four geometric shapes x plain / non-temporal stores: the same step, the
-    # same bits, also with the FP64 sums fused in.
+    # Four geometric shapes x plain / non-temporal stores, and the row-aligned
+    # mapping x plain / non-temporal: the same step, the same bits, also with
+    # the FP64 sums fused in.  Boxes with 64 | nx (four rows per block), a row
+    # of three wavefronts with 62 idle lanes, and rows longer than a block.
     import torch
 
-    from paper_1909_13412_amd import Lattice
+    from paper_1909_13412_amd import Lattice, _abi
     from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
 
-    L = (40, 24, 16)
-    r = particle_positions(9, L, seed=31)
-    v = particle_velocities(9, 1e-5, seed=31)
-    for storage in ("f32", "bf16"):
-        ref, sums = None, {}
-        for k in range(8):
-            lat = Lattice(*L, 0.7, storage=storage)
-            lat.particles_couple(r, v, kT=1e-4, seed=8)
-            lat.series_config(3, 8)
-            lat.set_shape(k)
-            lat.step(13)
-            f = lat.populations()
-            torch.cuda.synchronize()
-            ser = lat.series()
-            if ref is None:
-                ref = (f.clone(), lat.v.clone(), ser)
-            else:
-                assert torch.equal(f, ref[0]), (storage, k)
-                assert torch.equal(lat.v, ref[1]), (storage, k)
-                # FP64 sums: per-block partials follow the block size, so only
-                # the same geometric shape reproduces them bit for bit
-                assert np.allclose(ser, ref[2], rtol=1e-12, atol=1e-15), (storage, k)
-            if k & 3 in sums:
-                assert np.array_equal(ser, sums[k & 3]), (storage, k)
-            sums[k & 3] = ser
+    for L in ((40, 24, 16), (130, 6, 8), (300, 6, 5)):
+        r = particle_positions(9, L, seed=31)
+        v = particle_velocities(9, 1e-5, seed=31)
+        for storage in ("f32", "bf16"):
+            ref, sums = None, {}
+            for k in range(_abi.LBM_NUM_SHAPES):
+                lat = Lattice(*L, 0.7, storage=storage)
+                lat.particles_couple(r, v, kT=1e-4, seed=8)
+                lat.series_config(3, 8)
+                lat.set_shape(k)
+                lat.step(13)
+                f = lat.populations()
+                torch.cuda.synchronize()
+                ser = lat.series()
+                if ref is None:
+                    ref = (f.clone(), lat.v.clone(), ser)
+                else:
+                    assert torch.equal(f, ref[0]), (L, storage, k)
+                    assert torch.equal(lat.v, ref[1]), (L, storage, k)
+                    # FP64 sums: per-block partials follow the lane mapping, so
+                    # only the same mapping reproduces them bit for bit
+                    assert np.allclose(ser, ref[2], rtol=1e-12, atol=1e-15), (L, storage, k)
+                key = "row" if k >= 8 else k & 3
+                if key in sums:
+                    assert np.array_equal(ser, sums[key]), (L, storage, k)
+                sums[key] = ser
     lat = Lattice(9, 7, 5, 0.7)
     with pytest.raises(Exception):
         lat.set_shape(2)  # two rows per lane need an even ny
