@@ -426,10 +426,23 @@ uint32_t mask_words(uint64_t ncell) { return uint32_t(align_up((ncell + 31) / 32
 
 size_t force_field_bytes(const lbm_grid_desc *g) { return align_up(ncell_of(g) * 3 * 8, kAlign); }
 
-// Per-block moment partials of the largest stream-collide grid (256-lane
-// blocks, one node per lane).
+// Blocks of the row-aligned stream-collide grid (configurations 8, 9).
+uint32_t row_grid_blocks(uint32_t nx, uint32_t ny, uint32_t nz) {
+    const uint32_t lpr = row_lanes(nx), nrows = ny * nz;
+    if (lpr <= uint32_t(kRowBlock)) {
+        const uint32_t rpb = uint32_t(kRowBlock) / lpr;  // rows per block
+        return (nrows + rpb - 1) / rpb;
+    }
+    return nrows * ((lpr + kRowBlock - 1) / kRowBlock);
+}
+
+// Per-block moment partials of the largest stream-collide grid: 256-lane
+// blocks with one node per lane, or the row-aligned grid, whichever is
+// larger.
 size_t fluid_partials_bytes(const lbm_grid_desc *g) {
-    return align_up((ncell_of(g) / 256 + 1) * 4 * 8, kAlign);
+    const size_t flat = ncell_of(g) / 256 + 1;
+    const size_t row = row_grid_blocks(uint32_t(g->nx), uint32_t(g->ny), uint32_t(g->nz));
+    return align_up((flat > row ? flat : row) * 4 * 8, kAlign);
 }
 
 size_t grid_scratch_size(const lbm_grid_desc *g) {
@@ -533,14 +546,7 @@ bool shape_ok(const lbm_ctx *c, int k) {
 }
 
 uint32_t collide_grid(const lbm_ctx *c, int shape) {
-    if (config_row(shape)) {
-        const uint32_t lpr = row_lanes(c->g.nx), nrows = c->g.ny * c->g.nz;
-        if (lpr <= uint32_t(kRowBlock)) {
-            const uint32_t rpb = uint32_t(kRowBlock) / lpr;  // rows per block
-            return (nrows + rpb - 1) / rpb;
-        }
-        return nrows * ((lpr + kRowBlock - 1) / kRowBlock);
-    }
+    if (config_row(shape)) return row_grid_blocks(c->g.nx, c->g.ny, c->g.nz);
     const CollideShape &sh = kShapes[shape & 3];
     const uint64_t band = c->g.ncell / uint32_t(sh.cpt);
     return uint32_t((band + sh.bs - 1) / sh.bs);
@@ -920,6 +926,12 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
     s += force_field_bytes(grid);
     c->fluid_partials = reinterpret_cast<double *>(s);
     s += fluid_partials_bytes(grid);
+    // every configuration's grid must fit the per-block partials
+    for (int k = 0; k < kNumShapes; ++k)
+        if (shape_ok(c, k) && size_t(collide_grid(c, k)) * 4 * 8 > fluid_partials_bytes(grid)) {
+            free(c);
+            return LBM_E_UNSUPPORTED;
+        }
     c->series_stage = reinterpret_cast<double *>(s);
     s += align_up(size_t(kSeriesBlocks) * 7 * 8, kAlign);
     c->partials = reinterpret_cast<double *>(s);
