@@ -226,15 +226,19 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
         static_assert(CPT == 1, "the row-aligned mapping takes one node per lane");
         const uint32_t lpr = row_lanes(g.nx);
         uint32_t row, x;
+        bool in_rows = true;  // lanes past the block's last whole row stay idle
         if (lpr <= uint32_t(BS)) {
-            row = blockIdx.x * (uint32_t(BS) / lpr) + threadIdx.x / lpr;
+            const uint32_t rpb = uint32_t(BS) / lpr;  // rows per block
+            const uint32_t slot = threadIdx.x / lpr;
+            in_rows = slot < rpb;
+            row = blockIdx.x * rpb + slot;
             x = threadIdx.x % lpr;
         } else {
             const uint32_t bpr = (lpr + BS - 1) / BS;  // blocks per row
             row = blockIdx.x / bpr;
             x = (blockIdx.x % bpr) * BS + threadIdx.x;
         }
-        active = x < g.nx && row < g.ny * g.nz;
+        active = in_rows && x < g.nx && row < g.ny * g.nz;
         lane_cell = row * g.nx + x;
     } else {
         lane_cell = blockIdx.x * BS + threadIdx.x;

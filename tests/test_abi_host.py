@@ -189,3 +189,29 @@ def test_binding_attributes_not_shadowed_by_properties():
                         if isinstance(e, ast.Attribute) and isinstance(e.value, ast.Name) and e.value.id == "self":
                             assigned.add(e.attr)
         assert not (props & assigned), (cls.name, props & assigned)
+
+
+def test_row_aligned_mapping_covers_every_node_once():
+    # The lane -> node map of the row-aligned stream-collide configurations,
+    # restated: each row takes nx rounded up to whole 64-lane wavefronts; a
+    # 256-lane block holds 256 // lanes whole rows (lanes past them idle) or a
+    # row spans several blocks.  Every node must be visited exactly once for
+    # widths that divide the block, that do not, and rows longer than a block.
+    BS = 256
+    for nx in (2, 40, 48, 64, 65, 100, 129, 130, 192, 193, 250, 256, 257, 300, 513, 700):
+        ny, nz = 3, 2
+        lpr = (nx + 63) // 64 * 64
+        nrows = ny * nz
+        grid = -(-nrows // (BS // lpr)) if lpr <= BS else nrows * -(-lpr // BS)
+        count = {}
+        for b in range(grid):
+            for t in range(BS):
+                if lpr <= BS:
+                    slot = t // lpr
+                    ok, row, x = slot < BS // lpr, b * (BS // lpr) + slot, t % lpr
+                else:
+                    bpr = -(-lpr // BS)
+                    ok, row, x = True, b // bpr, (b % bpr) * BS + t
+                if ok and x < nx and row < nrows:
+                    count[row * nx + x] = count.get(row * nx + x, 0) + 1
+        assert sorted(count) == list(range(nx * nrows)) and set(count.values()) == {1}, nx
