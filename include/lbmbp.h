@@ -268,7 +268,8 @@ lbm_status lbm_profile_read(lbm_ctx *ctx, double out[4]);
  * plain and non-temporal stores; single boxes only.  Until lbm_autotune runs,
  * a context uses the configuration the autotuner last chose in this process
  * for the same device, storage, velocity set and box size, if any; otherwise
- * shape 0, with non-temporal stores when one lattice is at least 256 MiB. */
+ * configuration 8 when nx >= 96 is not a multiple of 64, else shape 0, with
+ * non-temporal stores when one lattice is at least 256 MiB. */
 #define LBM_NUM_SHAPES 10
 
 /* Time every valid stream-collide configuration on this context's lattice (iters
@@ -276,7 +277,9 @@ lbm_status lbm_profile_read(lbm_ctx *ctx, double out[4]);
  * lattice, so the simulation state is not changed) and keep the fastest for
  * later lbm_step calls.  Synchronises the stream.  ms (host, LBM_NUM_SHAPES
  * entries, may be NULL) receives the mean milliseconds per launch (-1 for a
- * shape that does not apply); *chosen (may be NULL) the shape kept.  The choice
+ * configuration that does not apply, or that repeats another's lane mapping
+ * exactly: 8 and 9 when 64 | nx and nx divides 256 or 256 divides nx); *chosen
+ * (may be NULL) the configuration kept.  The choice
  * is also remembered for contexts created later with the same device, storage,
  * velocity set and box size (process lifetime, thread-safe). */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen);

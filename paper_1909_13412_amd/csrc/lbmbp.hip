@@ -541,6 +541,11 @@ unsigned blocks_for(uint64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
         default: CALL(1, 512, false, false); break; \
     }
 
+// The row-aligned mapping places lanes exactly as configurations 1 and 5 do
+// when every 256-lane block holds whole rows that fill it (64 | nx and nx
+// divides 256) or every row fills whole blocks (256 | nx).
+bool row_mapping_is_flat(uint32_t nx) { return nx % 64 == 0 && (256 % nx == 0 || nx % 256 == 0); }
+
 bool shape_ok(const lbm_ctx *c, int k) {
     return config_row(k) || c->g.ny % uint32_t(kShapes[k & 3].cpt) == 0;
 }
@@ -729,7 +734,7 @@ void time_shapes(lbm_ctx *c, int32_t iters, double *ms, hipError_t *err) {
     };
     for (int k = 0; k < kNumShapes && *err == hipSuccess; ++k) {
         ms[k] = -1.0;
-        if (!shape_ok(c, k)) continue;
+        if (!shape_ok(c, k) || (config_row(k) && row_mapping_is_flat(c->g.nx))) continue;
         for (int w = 0; w < 2; ++w) launch(k);
         (void)hipEventRecord(e0, c->stream);
         for (int it = 0; it < iters; ++it) launch(k);
@@ -899,8 +904,13 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
     {
         size_t lat = 0;
         lbm_lattice_bytes(grid, &lat);
-        // until lbm_autotune: the last choice for this key, else by lattice size
-        c->shape = tune_lookup(ctx_tune_key(c), lat >= kStreamStoreBytes ? kNumGeomShapes : 0);
+        // until lbm_autotune: the last choice for this key, else the row-aligned
+        // mapping for rows that are not whole wavefronts (and long enough that
+        // idle lanes are few), else by lattice size
+        const int fallback = (grid->nx % 64 != 0 && grid->nx >= 96) ? kNumFlatShapes
+                             : lat >= kStreamStoreBytes              ? kNumGeomShapes
+                                                                     : 0;
+        c->shape = tune_lookup(ctx_tune_key(c), fallback);
     }
     c->elem = elem_size(grid->storage);
     c->pop[0] = pop_a;
