@@ -384,6 +384,21 @@ def test_autotune_choice_is_remembered():
     assert Lattice(48, 20, 10, 0.6, storage="f32").launch_config == 0
 
 
+def test_fixed_point_range_flagged():
+    # A reaction force beyond the fixed-point node fields' range (|F W| >=
+    # 16384) is not spread: the node receives nothing, the error is flagged and
+    # the next observables call reports it (then clears it).
+    from paper_1909_13412_amd import LbmError, Lattice
+
+    lat = Lattice(8, 8, 8, 0.8, storage="f64")
+    lat.particles_couple(np.array([[3.5, 3.5, 3.5]]), np.array([[1e6, 0.0, 0.0]]), mass=1.0, gamma=1.0)
+    lat.step(1)
+    with pytest.raises(LbmError):
+        lat.observables()
+    obs = lat.observables()  # the flag was cleared; nothing reached the fluid
+    assert obs[0] == 512.0 and np.all(obs[1:4] == 0.0)
+
+
 def test_coupling_warnings():
     # Advisory bits of section 2.2's parameter ranges, raised as warnings by
     # the binding; never errors.
