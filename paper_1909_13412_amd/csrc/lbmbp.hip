@@ -593,17 +593,12 @@ dim3 pair_group_blocks(int32_t n) {
 // end at zero), then the neighbour sums.
 void launch_pairs(hipStream_t st, const double *r, int32_t n, const PairGrid &pg, const PairList &pl,
                   double *F) {
-    if (n <= kPairSmall) {  // the whole list in one block, in LDS
-        hipLaunchKernelGGL(k_pair_build_block, dim3(1), dim3(kPairScanThreads),
-                           pair_block_lds_bytes(n, pg.T), st, r, n, pg, pl);
-    } else {
-        const dim3 pblocks(unsigned((n + kPairBlock - 1) / kPairBlock));
-        hipLaunchKernelGGL(k_pair_count, pblocks, dim3(kPairBlock), 0, st, r, n, pg, pl);
-        hipLaunchKernelGGL(k_pair_scan, dim3(1), dim3(kPairScanThreads), 0, st, pg, pl);
-        hipLaunchKernelGGL(k_pair_scatter, pblocks, dim3(kPairBlock), 0, st, n, pl);
-        hipLaunchKernelGGL(k_pair_bucket_sort, dim3((pg.T + kPairBlock - 1) / kPairBlock),
-                           dim3(kPairBlock), 0, st, pg, pl);
-    }
+    const dim3 pblocks(unsigned((n + kPairBlock - 1) / kPairBlock));
+    hipLaunchKernelGGL(k_pair_count, pblocks, dim3(kPairBlock), 0, st, r, n, pg, pl);
+    hipLaunchKernelGGL(k_pair_scan, dim3(1), dim3(kPairScanThreads), 0, st, pg, pl);
+    hipLaunchKernelGGL(k_pair_scatter, pblocks, dim3(kPairBlock), 0, st, n, pl);
+    hipLaunchKernelGGL(k_pair_bucket_sort, dim3((pg.T + kPairBlock - 1) / kPairBlock), dim3(kPairBlock), 0,
+                       st, pg, pl);
     hipLaunchKernelGGL(k_pair_force, pair_group_blocks(n), dim3(kPairBlock), 0, st, r, n, pg, pl, F);
 }
 

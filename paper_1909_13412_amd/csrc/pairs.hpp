@@ -180,107 +180,6 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_bucket_sort(PairGrid pg, Pa
     }
 }
 
-// The whole cell list in one block for n <= kPairSmall: the counts, bucket
-// offsets, scatter and per-bucket sort run in LDS, then start[], list[] and
-// cell[] go to memory: one launch instead of four, the same list.  LDS holds
-// the offsets (T + 1) and the list (n); each thread keeps its particles'
-// buckets and arrival slots in registers.
-constexpr int kPairSmall = 4096;
-constexpr int kPairPer = kPairSmall / kPairScanThreads;  // particles per thread
-constexpr int kPairSmallBucketsPerThread = 2 * kPairSmall / kPairScanThreads;  // T <= 2 kPairSmall
-
-__host__ __device__ inline size_t pair_block_lds_bytes(int32_t n, uint32_t T) {
-    return (size_t(T) + 1 + size_t(n)) * 4;
-}
-
-__global__ __launch_bounds__(kPairScanThreads) void k_pair_build_block(const double *__restrict__ r,
-                                                                      int32_t n, PairGrid pg,
-                                                                      PairList pl) {
-    extern __shared__ uint32_t lds[];
-    uint32_t *off = lds;             // [T + 1]: counts, then offsets
-    uint32_t *lst = lds + pg.T + 1;  // [n]
-    constexpr int kWaves = kPairScanThreads / 64;
-    __shared__ uint32_t wsum[kWaves];
-    const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
-    for (uint32_t b = t; b <= pg.T; b += kPairScanThreads) off[b] = 0u;
-    __syncthreads();
-    uint32_t bkt[kPairPer], slot[kPairPer];
-#pragma unroll
-    for (int j = 0; j < kPairPer; ++j) {
-        const int32_t i = int32_t(t) + j * kPairScanThreads;
-        bkt[j] = slot[j] = 0u;
-        if (i < n) {
-            const uint32_t cx = pair_cell_coord(r[3 * i + 0], pg.L[0], pg.nc[0]);
-            const uint32_t cy = pair_cell_coord(r[3 * i + 1], pg.L[1], pg.nc[1]);
-            const uint32_t cz = pair_cell_coord(r[3 * i + 2], pg.L[2], pg.nc[2]);
-            const uint64_t cell = pair_cell(pg, cx, cy, cz);
-            pl.cell[i] = cell;
-            bkt[j] = pair_bucket(cell, pg.T);
-            slot[j] = atomicAdd(&off[bkt[j]], 1u);
-        }
-    }
-    __syncthreads();
-    // exclusive scan of the T counts: thread t owns `per` consecutive buckets
-    const uint32_t per = pg.T / kPairScanThreads > 0 ? pg.T / kPairScanThreads : 1u;
-    const uint32_t b0 = t * per;
-    const bool mine = b0 < pg.T;
-    uint32_t c[kPairSmallBucketsPerThread];
-    uint32_t local = 0;
-#pragma unroll
-    for (int k = 0; k < kPairSmallBucketsPerThread; ++k) {
-        c[k] = (mine && uint32_t(k) < per) ? off[b0 + k] : 0u;
-        local += c[k];
-    }
-    uint32_t x = local;
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, 64);
-        if (lane >= uint32_t(d)) x += y;
-    }
-    if (lane == 63) wsum[wave] = x;
-    __syncthreads();
-    if (wave == 0) {
-        uint32_t w = lane < uint32_t(kWaves) ? wsum[lane] : 0u;
-        for (int d = 1; d < kWaves; d <<= 1) {
-            const uint32_t y = __shfl_up(w, d, 64);
-            if (lane >= uint32_t(d)) w += y;
-        }
-        if (lane < uint32_t(kWaves)) wsum[lane] = w;
-    }
-    __syncthreads();
-    if (mine) {
-        uint32_t run = x - local + (wave > 0 ? wsum[wave - 1] : 0u);
-#pragma unroll
-        for (int k = 0; k < kPairSmallBucketsPerThread; ++k)
-            if (uint32_t(k) < per) {
-                off[b0 + k] = run;
-                run += c[k];
-            }
-    }
-    if (t == 0) off[pg.T] = uint32_t(n);
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kPairPer; ++j) {
-        const int32_t i = int32_t(t) + j * kPairScanThreads;
-        if (i < n) lst[off[bkt[j]] + slot[j]] = uint32_t(i);
-    }
-    __syncthreads();
-    for (uint32_t b = t; b < pg.T; b += kPairScanThreads) {  // each bucket in particle order
-        const uint32_t lo = off[b], hi = off[b + 1];
-        for (uint32_t p = lo + 1; p < hi; ++p) {
-            const uint32_t v = lst[p];
-            uint32_t q = p;
-            while (q > lo && lst[q - 1] > v) {
-                lst[q] = lst[q - 1];
-                --q;
-            }
-            lst[q] = v;
-        }
-    }
-    __syncthreads();
-    for (uint32_t b = t; b <= pg.T; b += kPairScanThreads) pl.start[b] = off[b];
-    for (int32_t i = int32_t(t); i < n; i += kPairScanThreads) pl.list[i] = lst[i];
-}
-
 // A group of kPairLanes lanes serves one particle: lane l visits the l-th of
 // its (up to) 27 neighbour cells (offsets in x fastest, then y, z) and calls
 // fn(j, d, |d|^2) for every particle j != i of that cell within the cutoff,
