@@ -23,7 +23,7 @@ def announce(msg: str):
 
 def run_pair(oracle_mod, L, tau, storage, r, v, steps, *, mass=10.0, gamma=1.0, kT=0.0, seed=0,
              friction="stokeslet", radius=0.0, rho=None, u=None, trace=False, vacf=None,
-             f16_scale_log2=16, q=19):
+             f16_scale_log2=16, q=19, autotune=False):
     """Run the oracle and the GPU side by side.  L is (nx, ny, nz).
     Returns dict with final fields/particles of both, and per-step traces."""
     import torch
@@ -44,6 +44,9 @@ def run_pair(oracle_mod, L, tau, storage, r, v, steps, *, mass=10.0, gamma=1.0, 
         if vacf:
             gpu.vacf_config(*vacf)
             ref.vacf_config(*vacf)
+    if autotune:  # the launch configuration the benchmark would time
+        out_shape, _ = gpu.autotune(10)
+        announce(f"  autotuned launch configuration {out_shape}")
     out = {"gpu_trace_v": [], "ref_trace_v": [], "gpu_obs": [], "ref_obs": []}
     if trace:
         for _ in range(steps):

@@ -253,7 +253,7 @@ def test_suspension256_bench_configuration(oracle_mod):
     announce("suspension256: 256^3 FP32, 4096 particles, 3 steps")
     out = run_pair(oracle_mod, (w["L"],) * 3, w["tau"], "f32", r, v, 3, mass=w["mass"],
                    gamma=w["gamma"], kT=w["kT"], radius=w["radius"], seed=w["seed"],
-                   vacf=(w["max_lag"], w["stride"]))
+                   vacf=(w["max_lag"], w["stride"]), autotune=True)
     _compare_particles(out["gpu"], out["ref"], 1e-5, "suspension256")
     rho_g, u_g = out["gpu"].moments()
     rho_r, u_r = out["ref"].moments()
