@@ -305,6 +305,26 @@ def time_adjoint(steps, warmup):
             "grad_gamma_tau_M_kT": [float(x) for x in g["params"].cpu().tolist()]}
 
 
+def time_large(steps, warmup):
+    """The same workload at 512^3 (134M nodes, 19 x 512^3 > 2^31 population
+    elements), FP32 and BF16 storage: whole-step MLUPS and the stream-collide's
+    fraction of the HBM peak."""
+    import torch
+
+    from paper_1909_13412_amd.inputs import WORKLOADS
+
+    w = dict(WORKLOADS["suspension512"])
+    w["name"] = "suspension512"
+    out = {"box": [w["L"]] * 3, "nodes": w["L"] ** 3, "particles": w["n"], "steps": steps}
+    for storage in ("f32", "bf16"):
+        r = time_storage(w, storage, steps, min(warmup, 20), min(steps, 50))
+        out[storage] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 5),
+                        "collide_ms": round(r["collide_ms"], 5), "collide_GBs": round(r["collide_GBs"], 1),
+                        "collide_frac": round(r["collide_frac"], 4), "collide_shape": r["collide_shape"]}
+        torch.cuda.empty_cache()
+    return out
+
+
 def time_pairs(w, steps, warmup, prof_steps, main):
     """The same FP32 workload with the soft pair repulsion switched on (a_f =
     0.05, cutoff 2R = 1): cost of the cell list and the neighbour sums, which
@@ -359,6 +379,8 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=1000, help="0 = skip the ensemble timing")
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="0 = skip the reverse-mode timing")
     ap.add_argument("--no-pairs", action="store_true", help="skip the pair-repulsion timing")
+    ap.add_argument("--large-steps", type=int, default=200,
+                    help="steps of the 512^3 leg per storage (0 = skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -390,6 +412,10 @@ def main():
         r["speedup_vs_main"] = r["mlups"] / main_res["mlups"]
         r["traffic"] = pmc_traffic(s)
         variants[s] = r
+    large = None
+    if args.large_steps > 0 and args.workload == "suspension256":
+        print(f"[bench] suspension512 ({args.large_steps} steps per storage)", file=sys.stderr, flush=True)
+        large = time_large(args.large_steps, args.warmup)
     pairs = None
     if not args.no_pairs:
         print("[bench] pair repulsion", file=sys.stderr, flush=True)
@@ -453,6 +479,7 @@ def main():
         "copy_probe": copy,
         "variants": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                      for k, v in variants.items()},
+        "suspension512": large,
         "pairs": pairs,
         "ensemble": ensemble,
         "adjoint": adjoint,
