@@ -212,8 +212,8 @@ lbm_status lbm_particle_forces(lbm_ctx *ctx, double *fh, double *fr);
 
 /* Start accumulating C_i(l) = sum over origins t0 of V_i(t0).V_i(t0 + l), for
  * lags 0..max_lag, origins every `stride` steps counted from this call;
- * V sampled before each step's update.  acc: device FP64 [n][max_lag+1],
- * zeroed here.  origins: device buffer of lbm_vacf_origin_bytes.  Requires
+ * V sampled before each step's update.  acc: device FP64 [max_lag+1][n]
+ * (lag-major: C_i(l) at acc[l * n + i]), zeroed here.  origins: device buffer of lbm_vacf_origin_bytes.  Requires
  * attached particles.  max_lag = -1 switches the accumulation off. */
 lbm_status lbm_vacf_config(lbm_ctx *ctx, int32_t max_lag, int32_t stride, double *acc,
                            double *origins);

@@ -224,7 +224,10 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
     // origin (lag 0) is stored by the lane that owns it.  Origins go in
     // batches of kVacfBatch: all loads of a batch before any of its stores.
     if (valid && pa.acc) {
-        double *acc_i = pa.acc + int64_t(i) * (pa.max_lag + 1);
+        // accumulators are lag-major (acc[lag][n]): the same lane of the eight
+        // particles of a wavefront updates eight consecutive doubles
+        double *acc_i = pa.acc + i;
+        const int64_t n = pa.n;
         for (int64_t k0 = pa.k_lo + p; k0 <= pa.k_hi; k0 += 8 * kVacfBatch) {
             double ov[kVacfBatch][3], av[kVacfBatch];
 #pragma unroll
@@ -237,7 +240,7 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
                     ov[c][0] = o[0];
                     ov[c][1] = o[1];
                     ov[c][2] = o[2];
-                    av[c] = acc_i[lag];
+                    av[c] = acc_i[lag * n];
                 }
             }
 #pragma unroll
@@ -252,7 +255,7 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
                     o[2] = V[2];
                     acc_i[0] += V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
                 } else {
-                    acc_i[lag] = av[c] + (ov[c][0] * V[0] + ov[c][1] * V[1] + ov[c][2] * V[2]);
+                    acc_i[lag * n] = av[c] + (ov[c][0] * V[0] + ov[c][1] * V[1] + ov[c][2] * V[2]);
                 }
             }
         }

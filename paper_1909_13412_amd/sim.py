@@ -185,19 +185,20 @@ class Lattice:
         sz = ctypes.c_size_t()
         _abi.check("lbm_vacf_origin_bytes",
                    self.lib.lbm_vacf_origin_bytes(self.n, max_lag, stride, ctypes.byref(sz)))
-        acc = torch.empty((self.n, max_lag + 1), dtype=torch.float64, device=self.device)
+        acc = torch.empty((max_lag + 1, self.n), dtype=torch.float64, device=self.device)  # lag-major
         origins = _alloc_bytes(sz.value, self.device)
         _abi.check("lbm_vacf_config",
                    self.lib.lbm_vacf_config(self.ctx, max_lag, stride, _ptr(acc), _ptr(origins)))
         self._vacf = (acc, origins, max_lag)
 
     def vacf(self):
-        """(acc [n, max_lag+1] device FP64, counts [max_lag+1] numpy int64)."""
+        """(acc [n, max_lag+1] device FP64 (a view of the lag-major buffer),
+        counts [max_lag+1] numpy int64)."""
         acc, _, max_lag = self._vacf
         cnt = np.zeros(max_lag + 1, dtype=np.int64)
         _abi.check("lbm_vacf_counts", self.lib.lbm_vacf_counts(
             self.ctx, cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
-        return acc, cnt
+        return acc.t(), cnt
 
     # -- recorded observables --------------------------------------------
     def series_config(self, every: int, capacity: int):
@@ -391,7 +392,7 @@ class Ensemble:
         sz = ctypes.c_size_t()
         _abi.check("lbm_vacf_origin_bytes",
                    self.lib.lbm_vacf_origin_bytes(self.n, max_lag, stride, ctypes.byref(sz)))
-        acc = torch.empty((self.n, max_lag + 1), dtype=torch.float64, device=self.device)
+        acc = torch.empty((max_lag + 1, self.n), dtype=torch.float64, device=self.device)  # lag-major
         origins = _alloc_bytes(sz.value, self.device)
         _abi.check("lbm_ens_vacf_config",
                    self.lib.lbm_ens_vacf_config(self.ctx, max_lag, stride, _ptr(acc), _ptr(origins)))
@@ -402,7 +403,7 @@ class Ensemble:
         cnt = np.zeros(max_lag + 1, dtype=np.int64)
         _abi.check("lbm_ens_vacf_counts", self.lib.lbm_ens_vacf_counts(
             self.ctx, cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
-        return acc, cnt
+        return acc.t(), cnt  # [all particles, max_lag+1] view of the lag-major buffer
 
     def particles(self, k: int):
         a, b = int(self.offsets[k]), int(self.offsets[k + 1])
