@@ -292,16 +292,6 @@ lbm_status lbm_set_shape(lbm_ctx *ctx, int32_t k);
 /* The launch configuration later lbm_step calls use. */
 lbm_status lbm_get_shape(const lbm_ctx *ctx, int32_t *k);
 
-/* Split steps (1) or plain ones (0).  In a split step the particle kernel
- * flags the lattice rows the next step's particle kernel will read, and the
- * stream-collide runs as two launches: the flagged rows, then the rest; the
- * next particle kernel runs on an internal stream of the library as soon as
- * the first launch is done, overlapping the second.  Results are bit for bit
- * the same either way; only the time differs.  Default: on for lattices of at
- * least 64 MiB.  Steps that record FP64 sums (lbm_series_config) and
- * Brownian-dynamics friction run unsplit. */
-lbm_status lbm_set_overlap(lbm_ctx *ctx, int32_t on);
-
 /* Number of steps taken since lbm_init. */
 lbm_status lbm_get_step(const lbm_ctx *ctx, int64_t *step);
 

@@ -122,15 +122,12 @@ __device__ inline void block_sum(double (&v)[N], double *__restrict__ out) {
 // flagged (FORCED), the particles' reaction force.
 // NTS: write the populations with non-temporal stores (streamed past the
 // caches); pays off once the lattice no longer fits in the last-level cache.
-// PART: 0 every node; 1 only nodes whose row (y, z) is set in rowmask (one bit
-// per row z*ny + y); 2 only the others.
-template <class C, bool FORCED, bool MOMENTS, int CPT, bool NTS, int PART = 0>
+template <class C, bool FORCED, bool MOMENTS, int CPT, bool NTS>
 __device__ inline void collide_lane(const typename C::T *__restrict__ A,
                                     typename C::T *__restrict__ B, const Grid &g,
                                     typename C::R omega, typename C::R enc_s, typename C::R dec_s,
                                     const ForceField &ff, typename C::R Gx, typename C::R Gy,
-                                    typename C::R Gz, uint32_t lane_cell, double (&acc)[4],
-                                    const uint32_t *__restrict__ rowmask = nullptr) {
+                                    typename C::R Gz, uint32_t lane_cell, double (&acc)[4]) {
     using T = typename C::T;
     using R = typename C::R;
     using V = typename C::V;
@@ -142,16 +139,9 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
 
     T raw[CPT][V::Q];
     uint32_t flags[CPT];
-    bool take[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const uint32_t y = y0 + uint32_t(c) * rows;
-        take[c] = true;
-        if constexpr (PART != 0) {
-            const uint32_t row = z * g.ny + y;
-            take[c] = (((rowmask[row >> 5] >> (row & 31)) & 1u) != 0u) == (PART == 1);
-        }
-        if (!take[c]) continue;
         const Neighbours nb(x, y, z, g);
         static_for<0, V::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
@@ -164,7 +154,6 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
     }
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-        if (!take[c]) continue;
         const uint32_t y = y0 + uint32_t(c) * rows;
         R gv[V::Q];
         static_for<0, V::Q>([&](auto ac) {
@@ -224,19 +213,13 @@ __host__ __device__ inline uint32_t row_lanes(uint32_t nx) { return (nx + 63u) &
 // lanes holds BS / row_lanes rows, or a row spans several blocks), so no wave
 // straddles two rows when nx is not a multiple of 64; otherwise lanes map to
 // consecutive nodes (rows y and y + ny/CPT for CPT = 2).
-// PART selects rows as in collide_lane; clear (if not null) is a row mask of
-// clear_words words that this launch zeroes for a later step.
-template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW, int PART>
+template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW>
 __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__restrict__ A,
                                                        typename C::T *__restrict__ B, Grid g,
                                                        typename C::R omega, typename C::R enc_s,
                                                        typename C::R dec_s, ForceField ff,
                                                        typename C::R Gx, typename C::R Gy,
-                                                       typename C::R Gz, double *__restrict__ mom,
-                                                       const uint32_t *__restrict__ rowmask,
-                                                       uint32_t *__restrict__ clear, uint32_t clear_words) {
-    if (clear)
-        for (uint32_t w = blockIdx.x * BS + threadIdx.x; w < clear_words; w += gridDim.x * BS) clear[w] = 0u;
+                                                       typename C::R Gz, double *__restrict__ mom) {
     uint32_t lane_cell;  // node index (in the first row band when CPT = 2)
     bool active;
     if constexpr (ROW) {
@@ -266,8 +249,8 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
     }
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (active)
-        collide_lane<C, FORCED, MOMENTS, CPT, NTS, PART>(A, B, g, omega, enc_s, dec_s, ff, Gx, Gy, Gz,
-                                                         lane_cell, acc, rowmask);
+        collide_lane<C, FORCED, MOMENTS, CPT, NTS>(A, B, g, omega, enc_s, dec_s, ff, Gx, Gy, Gz,
+                                                   lane_cell, acc);
     if constexpr (MOMENTS) block_sum<4, BS>(acc, mom + 4 * uint64_t(blockIdx.x));
 }
 
@@ -287,8 +270,5 @@ constexpr int kRowBlock = 256;
 constexpr bool config_row(int k) { return k >= kNumFlatShapes; }
 // Lattices of at least this many bytes default to non-temporal stores.
 constexpr size_t kStreamStoreBytes = size_t(256) << 20;
-// Lattices of at least this many bytes default to split steps (the particle
-// kernel overlapping the stream-collide); see lbm_set_overlap.
-constexpr size_t kOverlapBytes = size_t(64) << 20;
 
 }  // namespace lbmbp

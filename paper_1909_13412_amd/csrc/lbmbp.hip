@@ -364,15 +364,6 @@ struct lbm_ctx {
     int32_t prof_used, prof_cap;
     int shape;   // index into kShapes
     int device;  // device current at lbm_init (autotune cache key)
-    // Split steps: the particle kernel runs on `side` and overlaps the second
-    // part of the previous step's stream-collide (lbm_set_overlap).
-    int overlap;
-    hipStream_t side;
-    hipEvent_t ev_rows;   // on stream: the rows the next particle kernel reads are final
-    hipEvent_t ev_part;   // on side: the particle kernel is done
-    bool rows_ready;      // ev_rows covers every earlier piece of work on stream
-    uint32_t *rowmask[2]; // grid scratch: row flags, alternating between steps
-    uint32_t rowmask_words;
     // recorded observables (lbm_series_config)
     int32_t series_every;
     double *series;
@@ -435,12 +426,6 @@ uint32_t mask_words(uint64_t ncell) { return uint32_t(align_up((ncell + 31) / 32
 
 size_t force_field_bytes(const lbm_grid_desc *g) { return align_up(ncell_of(g) * 3 * 8, kAlign); }
 
-// One bit per lattice row (y, z): the rows a split step's first part covers.
-uint32_t rowmask_words_of(const lbm_grid_desc *g) {
-    return uint32_t((uint64_t(g->ny) * uint64_t(g->nz) + 31) / 32);
-}
-size_t rowmask_bytes(const lbm_grid_desc *g) { return align_up(size_t(rowmask_words_of(g)) * 4, kAlign); }
-
 // Blocks of the row-aligned stream-collide grid (configurations 8, 9).
 uint32_t row_grid_blocks(uint32_t nx, uint32_t ny, uint32_t nz) {
     const uint32_t lpr = row_lanes(nx), nrows = ny * nz;
@@ -466,7 +451,6 @@ size_t grid_scratch_size(const lbm_grid_desc *g) {
     s += 2 * align_up(words * 4, kAlign);            // two bitmasks
     s += 2 * force_field_bytes(g);                   // two node-force fields
     s += fluid_partials_bytes(g);                    // recorded-moment partials
-    s += 2 * rowmask_bytes(g);                       // row flags of split steps
     s += align_up(size_t(kSeriesBlocks) * 7 * 8, kAlign);
     s += align_up(size_t(kRedBlocks) * 4 * 8, kAlign);  // partials
     s += align_up(8 * 8, kAlign);                    // result
@@ -573,45 +557,26 @@ uint32_t collide_grid(const lbm_ctx *c, int shape) {
     return uint32_t((band + sh.bs - 1) / sh.bs);
 }
 
-// Rows of the stream-collide for one launch: all of them, or (split steps)
-// the rows flagged for the next particle kernel first and the rest after.
-struct CollideRows {
-    int part = 0;                      // 0 all, 1 flagged, 2 not flagged
-    const uint32_t *mask = nullptr;    // the row flags (part 1, 2)
-    uint32_t *clear = nullptr;         // a row mask this launch zeroes, or null
-    uint32_t clear_words = 0;
-};
-
-template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW, int PART>
+template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW>
 void launch_collide_shape(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff,
-                          double *mom, unsigned grid, const CollideRows &rows) {
+                          double *mom, unsigned grid) {
     using R = typename C::R;
-    hipLaunchKernelGGL((k_stream_collide<C, FORCED, MOMENTS, CPT, BS, NTS, ROW, PART>), dim3(grid),
-                       dim3(BS), 0, c->stream, A, B, c->g, R(c->omega), R(c->enc_s), R(c->dec_s), ff,
-                       R(c->body[0]), R(c->body[1]), R(c->body[2]), mom, rows.mask, rows.clear,
-                       rows.clear_words);
+    hipLaunchKernelGGL((k_stream_collide<C, FORCED, MOMENTS, CPT, BS, NTS, ROW>), dim3(grid), dim3(BS),
+                       0, c->stream, A, B, c->g, R(c->omega), R(c->enc_s), R(c->dec_s), ff,
+                       R(c->body[0]), R(c->body[1]), R(c->body[2]), mom);
 }
 
-// mom != nullptr: also leave the per-block FP64 moment sums there (every row,
-// rows.part must be 0).  Split parts exist for the forced kernel only.
+// mom != nullptr: also leave the per-block FP64 moment sums there.
 template <class C, bool FORCED>
 void launch_collide(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff, int shape,
-                    double *mom = nullptr, const CollideRows &rows = CollideRows{}) {
+                    double *mom = nullptr) {
     const unsigned grid = collide_grid(c, shape);
-#define LBM_SHAPE(CPT, BS, NTS, ROW)                                                                  \
-    do {                                                                                              \
-        if (mom)                                                                                      \
-            launch_collide_shape<C, FORCED, true, CPT, BS, NTS, ROW, 0>(c, A, B, ff, mom, grid, rows); \
-        else if (!FORCED || rows.part == 0)                                                           \
-            launch_collide_shape<C, FORCED, false, CPT, BS, NTS, ROW, 0>(c, A, B, ff, mom, grid, rows); \
-        else if constexpr (FORCED) {                                                                  \
-            if (rows.part == 1)                                                                       \
-                launch_collide_shape<C, FORCED, false, CPT, BS, NTS, ROW, 1>(c, A, B, ff, mom, grid,   \
-                                                                             rows);                   \
-            else                                                                                      \
-                launch_collide_shape<C, FORCED, false, CPT, BS, NTS, ROW, 2>(c, A, B, ff, mom, grid,   \
-                                                                             rows);                   \
-        }                                                                                             \
+#define LBM_SHAPE(CPT, BS, NTS, ROW)                                                          \
+    do {                                                                                      \
+        if (mom)                                                                              \
+            launch_collide_shape<C, FORCED, true, CPT, BS, NTS, ROW>(c, A, B, ff, mom, grid);  \
+        else                                                                                  \
+            launch_collide_shape<C, FORCED, false, CPT, BS, NTS, ROW>(c, A, B, ff, mom, grid); \
     } while (0)
     LBM_CONFIG_SWITCH(shape, LBM_SHAPE)
 #undef LBM_SHAPE
@@ -653,17 +618,17 @@ bool prof_grow(lbm_ctx *c) {
     return true;
 }
 
-int32_t prof_start(lbm_ctx *c, int32_t kind, hipStream_t st) {
+int32_t prof_start(lbm_ctx *c, int32_t kind) {
     if (!c->prof_on) return -1;
     if (c->prof_used == c->prof_cap && !prof_grow(c)) return -1;
     const int32_t k = c->prof_used++;
     c->prof_kind[k] = kind;
-    (void)hipEventRecord(c->prof_ev[2 * k], st);
+    (void)hipEventRecord(c->prof_ev[2 * k], c->stream);
     return k;
 }
 
-void prof_stop(lbm_ctx *c, int32_t k, hipStream_t st) {
-    if (k >= 0) (void)hipEventRecord(c->prof_ev[2 * k + 1], st);
+void prof_stop(lbm_ctx *c, int32_t k) {
+    if (k >= 0) (void)hipEventRecord(c->prof_ev[2 * k + 1], c->stream);
 }
 
 template <class C>
@@ -678,21 +643,9 @@ void launch_step(lbm_ctx *c) {
                         c->series_count < c->series_cap;
     if (c->series_every > 0) c->series_t += 1;
     double *mom = sample ? c->fluid_partials : nullptr;
-    // Split step: the particle kernel runs on the side stream once the rows it
-    // reads are final (the previous step's first stream-collide part), and
-    // this step's stream-collide covers the rows the next particle kernel
-    // reads (flagged by this one) first and the rest second, so that the next
-    // particle kernel overlaps the second part.
-    const bool split = c->overlap && c->np > 0 && c->pdesc.friction != LBM_FRICTION_BD;
-    hipStream_t pst = c->stream;
-    if (split) {
-        if (!c->rows_ready) (void)hipEventRecord(c->ev_rows, c->stream);
-        (void)hipStreamWaitEvent(c->side, c->ev_rows, 0);
-        pst = c->side;
-    }
     if (c->np > 0) {
-        const int32_t pk = prof_start(c, 1, pst);
-        ParticleArgs pa{};
+        const int32_t pk = prof_start(c, 1);
+        ParticleArgs pa;
         pa.pmom = sample ? c->part_partials : nullptr;
         pa.acc = nullptr;
         pa.origins = nullptr;
@@ -730,49 +683,21 @@ void launch_step(lbm_ctx *c) {
         pa.step = uint32_t(c->step);
         pa.fext = c->fext;
         pa.fpair = nullptr;
-        pa.rowmask = split ? c->rowmask[par] : nullptr;
         if (c->pair_on) {
-            launch_pairs(pst, c->r, c->np, c->pg, c->plist, c->fpair);
+            launch_pairs(c->stream, c->r, c->np, c->pg, c->plist, c->fpair);
             pa.fpair = c->fpair;
         }
         hipLaunchKernelGGL(k_particle<C>, dim3(unsigned((uint64_t(c->np) * 8 + kParticleBlock - 1) / kParticleBlock)), dim3(kParticleBlock), 0,
-                           pst, A, c->g, R(c->dec_s), pa, field(c, par), field(c, par ^ 1));
-        prof_stop(c, pk, pst);
-        if (split) {
-            (void)hipEventRecord(c->ev_part, c->side);
-            (void)hipStreamWaitEvent(c->stream, c->ev_part, 0);
-        }
-        const int32_t ck = prof_start(c, 0, c->stream);
-        if (!split) {
-            launch_collide<C, true>(c, A, B, field(c, par), c->shape, mom);
-        } else {
-            // the flags of the next split step start from zero
-            CollideRows rows;
-            rows.clear = c->rowmask[par ^ 1];
-            rows.clear_words = c->rowmask_words;
-            if (sample) {
-                launch_collide<C, true>(c, A, B, field(c, par), c->shape, mom, rows);
-            } else {
-                rows.part = 1;
-                rows.mask = c->rowmask[par];
-                launch_collide<C, true>(c, A, B, field(c, par), c->shape, nullptr, rows);
-                (void)hipEventRecord(c->ev_rows, c->stream);
-                rows.part = 2;
-                rows.clear = nullptr;
-                rows.clear_words = 0;
-                launch_collide<C, true>(c, A, B, field(c, par), c->shape, nullptr, rows);
-            }
-        }
-        prof_stop(c, ck, c->stream);
+                           c->stream, A, c->g, R(c->dec_s), pa, field(c, par), field(c, par ^ 1));
+        prof_stop(c, pk);
+        const int32_t ck = prof_start(c, 0);
+        launch_collide<C, true>(c, A, B, field(c, par), c->shape, mom);
+        prof_stop(c, ck);
     } else {
-        const int32_t ck = prof_start(c, 0, c->stream);
+        const int32_t ck = prof_start(c, 0);
         launch_collide<C, false>(c, A, B, field(c, par), c->shape, mom);
-        prof_stop(c, ck, c->stream);
+        prof_stop(c, ck);
     }
-    // The next particle kernel may start after the first part unless this step
-    // ran unsplit or recorded sums (the series reduction reads the particle
-    // partials the next particle kernel overwrites).
-    c->rows_ready = split && !sample;
     if (sample) {
         const int32_t np_blocks = c->np > 0 ? int32_t(particle_blocks(c->np)) : 0;
         hipLaunchKernelGGL(k_series_stage1, dim3(kSeriesBlocks), dim3(kBlock), 0, c->stream,
@@ -1017,11 +942,6 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
             free(c);
             return LBM_E_UNSUPPORTED;
         }
-    c->rowmask_words = rowmask_words_of(grid);
-    for (int k = 0; k < 2; ++k) {
-        c->rowmask[k] = reinterpret_cast<uint32_t *>(s);
-        s += rowmask_bytes(grid);
-    }
     c->series_stage = reinterpret_cast<double *>(s);
     s += align_up(size_t(kSeriesBlocks) * 7 * 8, kAlign);
     c->partials = reinterpret_cast<double *>(s);
@@ -1036,19 +956,10 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
     hipError_t e = hipMemsetAsync(pop_a, 0, lat, c->stream);  // g = 0 is the rest state
     if (e == hipSuccess) e = hipMemsetAsync(pop_b, 0, lat, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(grid_scratch, 0, grid_scratch_size(grid), c->stream);
-    // the side stream of split steps (default priority, no implicit ordering
-    // with the null stream: every dependency is an explicit event)
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_rows, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_part, hipEventDisableTiming);
     if (e != hipSuccess) {
-        if (c->ev_rows) (void)hipEventDestroy(c->ev_rows);
-        if (c->side) (void)hipStreamDestroy(c->side);
         free(c);
         return LBM_E_DEVICE;
     }
-    c->rows_ready = false;
-    c->overlap = lat >= kOverlapBytes ? 1 : 0;
     *out = c;
     return LBM_OK;
 }
@@ -1239,15 +1150,8 @@ lbm_status lbm_vacf_counts(const lbm_ctx *ctx, int64_t *cnt) {
 
 lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps) {
     if (!ctx || nsteps < 0) return LBM_E_INVAL;
-    ctx->rows_ready = false;  // the caller may have changed state on the stream since
     for (int32_t s = 0; s < nsteps; ++s) LBM_DISPATCH(ctx, launch_step);
     return launch_status();
-}
-
-lbm_status lbm_set_overlap(lbm_ctx *ctx, int32_t on) {
-    if (!ctx || (on != 0 && on != 1)) return LBM_E_INVAL;
-    ctx->overlap = on;
-    return LBM_OK;
 }
 
 lbm_status lbm_observables(lbm_ctx *ctx, double out[7]) {
@@ -1357,10 +1261,6 @@ lbm_status lbm_get_step(const lbm_ctx *ctx, int64_t *step) {
 
 lbm_status lbm_destroy(lbm_ctx *ctx) {
     if (!ctx) return LBM_E_INVAL;
-    (void)hipStreamSynchronize(ctx->side);
-    (void)hipEventDestroy(ctx->ev_rows);
-    (void)hipEventDestroy(ctx->ev_part);
-    (void)hipStreamDestroy(ctx->side);
     for (int32_t k = 0; k < 2 * ctx->prof_cap; ++k) (void)hipEventDestroy(ctx->prof_ev[k]);
     free(ctx->prof_ev);
     free(ctx->prof_kind);
@@ -1523,7 +1423,7 @@ EnsLayout ens_layout(const lbm_ensemble_desc *d, const lbm_replica_desc *reps) {
 }
 
 ParticleArgs ens_particle_args(lbm_ens *e) {
-    ParticleArgs pa{};
+    ParticleArgs pa;
     memset(&pa, 0, sizeof(pa));
     pa.r = e->r;
     pa.v = e->v;
@@ -2311,7 +2211,6 @@ lbm_status lbm_record(lbm_ctx *ctx, int32_t nsteps, int32_t every, void *tape) {
                 ctx->rec_tape = nullptr;
                 return LBM_E_DEVICE;
             }
-            ctx->rows_ready = false;  // the copy reads r and v
         }
         LBM_DISPATCH(ctx, launch_step);
     }

@@ -49,10 +49,6 @@ struct ParticleArgs {
     const double *fext;
     // pair forces of this step, [n][3] (nullptr: none); F_C = fext + fpair
     const double *fpair;
-    // rows (one bit per row z*ny + y) this step's stream-collide must finish
-    // before the next particle kernel may run: the rows of this step's force
-    // nodes and the rows the next step's gather pulls from (nullptr: off)
-    uint32_t *rowmask;
 };
 
 __device__ inline double sum8(double v) {
@@ -215,7 +211,7 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
     // step ago, and the given and pair forces.
     const uint32_t pc = valid ? pa.prev_cell[8 * i + p] : kNoNode;
     double fc[3] = {0.0, 0.0, 0.0};
-    if (valid) {
+    if (valid && p == 0) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             if (pa.fext) fc[k] = pa.fext[3 * i + k];
@@ -329,48 +325,13 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
     }
     pa.prev_cell[8 * i + p] = my_cell;
 
-    // Eqs. s2-langevin, s2-langevin2 with dt = 1; F_C is the given force (or 0).
-    // Every lane evaluates the update (the same operations on the same values).
-    double vn[3], rn[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        vn[k] = V[k] + (fc[k] + FH[k] + FR[k]) / pa.mass;
-        rn[k] = r[k] + vn[k];
-    }
-    if (pa.rowmask && coupled) {
-        // this step's force node, then the 3 x 3 rows around the node this lane
-        // gathers from next step (pulls reach one row either way)
-        const uint32_t own = node[2] * g.ny + node[1];
-        atomicOr(&pa.rowmask[own >> 5], 1u << (own & 31));
-        uint32_t nf[3];
-        double dn[3];
-        if (pa.friction == LBM_FRICTION_STOKESLET_2DX) {
-            wide_corner(rn, Ln, b, nf, dn);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const double L = double(Ln[k]);
-                const double sk = rn[k] - L * floor(rn[k] / L);
-                int32_t ci = (int32_t(floor(sk)) + b[k]) % int32_t(Ln[k]);
-                nf[k] = uint32_t(ci < 0 ? ci + int32_t(Ln[k]) : ci);
-            }
-        }
-#pragma unroll
-        for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-            for (int dy = -1; dy <= 1; ++dy) {
-                const uint32_t yy = (nf[1] + g.ny + uint32_t(dy)) % g.ny;
-                const uint32_t zz = (nf[2] + g.nz + uint32_t(dz)) % g.nz;
-                const uint32_t row = zz * g.ny + yy;
-                atomicOr(&pa.rowmask[row >> 5], 1u << (row & 31));
-            }
-    }
-
     if (p != 0) return;
+    // Eqs. s2-langevin, s2-langevin2 with dt = 1; F_C is the given force (or 0).
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        pa.v[3 * i + k] = vn[k];
-        pa.r[3 * i + k] = rn[k];
+        const double vn = V[k] + (fc[k] + FH[k] + FR[k]) / pa.mass;
+        pa.v[3 * i + k] = vn;
+        pa.r[3 * i + k] = r[k] + vn;
         pa.fh[3 * i + k] = FH[k];
         pa.fr[3 * i + k] = FR[k];
     }

@@ -255,11 +255,6 @@ class Lattice:
         _abi.check("lbm_get_shape", self.lib.lbm_get_shape(self.ctx, ctypes.byref(k)))
         return k.value
 
-    def set_overlap(self, on: bool):
-        """Split steps (the particle kernel overlapping the stream-collide) on or
-        off; the results are the same bits either way (see lbm_set_overlap)."""
-        _abi.check("lbm_set_overlap", self.lib.lbm_set_overlap(self.ctx, int(bool(on))))
-
     @property
     def step_count(self) -> int:
         s = ctypes.c_int64()
