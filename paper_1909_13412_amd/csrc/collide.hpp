@@ -128,6 +128,11 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
                                     typename C::R omega, typename C::R enc_s, typename C::R dec_s,
                                     const ForceField &ff, typename C::R Gx, typename C::R Gy,
                                     typename C::R Gz, uint32_t lane_cell, double (&acc)[4]) {
+    // Multiply-adds fuse only within one expression: fusion across statements
+    // depends on how the compiler lays out the blocks, which differs between
+    // launch configurations, and every configuration must round each node the
+    // same way.
+#pragma clang fp contract(on)
     using T = typename C::T;
     using R = typename C::R;
     using V = typename C::V;
