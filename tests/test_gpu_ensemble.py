@@ -67,16 +67,16 @@ def test_ensemble_equals_single_box_runs():
     reps = _small_replicas()
     ens = Ensemble(reps, storage="f32", kT=1e-4)
     ens.step(24)
-    bitwise = True
+    # The ensemble kernels run the single-box node and particle updates with
+    # the same rounding (multiply-adds fuse only within one expression), so
+    # every replica must reproduce its single-box run bit for bit.
     for k, rd in enumerate(reps):
         one = Lattice(rd["nx"], rd["ny"], rd["nz"], rd["tau"], storage="f32")
         one.particles_couple(rd["r"], rd["v"], kT=1e-4, seed=rd["seed"], replica=rd["replica"])
         one.step(24)
         fe, fo = ens.populations(k).cpu().numpy(), one.populations().cpu().numpy()
         ve, vo = ens.particles(k)[1].cpu().numpy(), one.v.cpu().numpy()
-        bitwise = bitwise and np.array_equal(fe, fo) and np.array_equal(ve, vo)
-        assert np.allclose(fe, fo, rtol=0, atol=1e-12) and nmax_err(ve, vo) < 1e-12
-    announce(f"  ensemble vs single-box runs bit-identical: {bitwise}")
+        assert np.array_equal(fe, fo) and np.array_equal(ve, vo), (k, np.max(np.abs(fe - fo)), nmax_err(ve, vo))
 
 
 def test_graph_replays_match_plain_launches():
