@@ -131,6 +131,8 @@ def time_storage(w, variant, steps, warmup, prof_steps, pair=None):
     t3 = time.perf_counter()
     prof = lat.profile_read()
     lat.profile_enable(False)
+    # the same data movement without the arithmetic, same launch configuration
+    ceil_ms = lat.stream_ceiling(20)
     obs = lat.observables()
     ncell = w["L"] ** 3
     coll_ms = prof["collide_ms"] / max(prof["collide_launches"], 1)
@@ -147,6 +149,8 @@ def time_storage(w, variant, steps, warmup, prof_steps, pair=None):
         "collide_GBs": achieved,
         "collide_frac": achieved / HBM_PEAK_GBS,
         "collide_shape": shape,
+        "stream_only_ms": ceil_ms,
+        "of_stream_only": ceil_ms / coll_ms,
         "autotune_ms": [round(float(x), 5) for x in shape_ms],
         "mass": obs[0],
     }
@@ -473,6 +477,15 @@ def main():
             "avg_launch_ms": round(main_res["collide_ms"], 5),
             "launch_shape": main_res["collide_shape"],
             "autotune_ms": main_res["autotune_ms"],
+            "pattern_ceiling": {
+                "kernel": "k_stream_only",
+                "what": "the stream-collide's pulls and stores alone (no arithmetic), same layout and launch configuration",
+                "avg_launch_ms": round(main_res["stream_only_ms"], 5),
+                "bytes_per_node": 2 * 19 * ELEM[args.storage],
+                "achieved": round(2 * 19 * ELEM[args.storage] * ncell / (main_res["stream_only_ms"] * 1e-3) / 1e9, 1),
+                "frac": round(2 * 19 * ELEM[args.storage] * ncell / (main_res["stream_only_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "kernel_vs_ceiling": round(main_res["of_stream_only"], 4),
+            },
         },
         "profiled_ms_per_step": round(main_res["profiled_ms_per_step"], 5),
         "particle_phase_ms": round(main_res["particle_phase_ms"], 5),

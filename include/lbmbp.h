@@ -284,6 +284,20 @@ lbm_status lbm_profile_read(lbm_ctx *ctx, double out[4]);
  * velocity set and box size (process lifetime, thread-safe). */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen);
 
+/* Ceiling of the stream-collide's data movement (the pull streaming of the
+ * stream-collide step, section 2.2, without its arithmetic): *ms (host)
+ * receives the mean milliseconds per launch, over iters (1..10000) launches
+ * after two warm-up launches, of a kernel that pulls every population from
+ * x - e_a and stores it unchanged at x, with the layout, lane mapping and store
+ * policy of launch configuration k (k < 0: the context's current one).  The
+ * stream-collide moves the same bytes the same way, so its duration over this
+ * one is the fraction of the access pattern's ceiling it reaches.  Reads the
+ * current populations and overwrites the spare lattice (as lbm_autotune does):
+ * the simulation state is unchanged.  Synchronises the stream.  LBM_E_INVAL for
+ * a NULL ctx or ms, iters out of range, or a configuration that does not apply
+ * to this box; LBM_E_DEVICE if a launch fails. */
+lbm_status lbm_stream_ceiling(lbm_ctx *ctx, int32_t k, int32_t iters, double *ms);
+
 /* Use launch configuration k (0 .. LBM_NUM_SHAPES - 1) for later steps;
  * LBM_E_INVAL if k is out of range or does not apply to this box.  Every
  * configuration gives bit-identical results. */

@@ -214,19 +214,13 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
 // Lanes per row of the row-aligned mapping: nx rounded up to whole wavefronts.
 __host__ __device__ inline uint32_t row_lanes(uint32_t nx) { return (nx + 63u) & ~63u; }
 
-// ROW: lanes map to whole rows (every row starts a wavefront: a block of BS
-// lanes holds BS / row_lanes rows, or a row spans several blocks), so no wave
-// straddles two rows when nx is not a multiple of 64; otherwise lanes map to
-// consecutive nodes (rows y and y + ny/CPT for CPT = 2).
-template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW>
-__global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__restrict__ A,
-                                                       typename C::T *__restrict__ B, Grid g,
-                                                       typename C::R omega, typename C::R enc_s,
-                                                       typename C::R dec_s, ForceField ff,
-                                                       typename C::R Gx, typename C::R Gy,
-                                                       typename C::R Gz, double *__restrict__ mom) {
-    uint32_t lane_cell;  // node index (in the first row band when CPT = 2)
-    bool active;
+// The node of this lane (in the first row band when CPT = 2); false for lanes
+// without one.  ROW: lanes map to whole rows (every row starts a wavefront: a
+// block of BS lanes holds BS / row_lanes rows, or a row spans several blocks),
+// so no wave straddles two rows when nx is not a multiple of 64; otherwise
+// lanes map to consecutive nodes (rows y and y + ny/CPT for CPT = 2).
+template <int CPT, int BS, bool ROW>
+__device__ inline bool lane_node(const Grid &g, uint32_t &lane_cell) {
     if constexpr (ROW) {
         static_assert(CPT == 1, "the row-aligned mapping takes one node per lane");
         const uint32_t lpr = row_lanes(g.nx);
@@ -243,12 +237,23 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
             row = blockIdx.x / bpr;
             x = (blockIdx.x % bpr) * BS + threadIdx.x;
         }
-        active = in_rows && x < g.nx && row < g.ny * g.nz;
         lane_cell = row * g.nx + x;
+        return in_rows && x < g.nx && row < g.ny * g.nz;
     } else {
         lane_cell = blockIdx.x * BS + threadIdx.x;
-        active = lane_cell < g.ncell / CPT;
+        return lane_cell < g.ncell / CPT;
     }
+}
+
+template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW>
+__global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__restrict__ A,
+                                                       typename C::T *__restrict__ B, Grid g,
+                                                       typename C::R omega, typename C::R enc_s,
+                                                       typename C::R dec_s, ForceField ff,
+                                                       typename C::R Gx, typename C::R Gy,
+                                                       typename C::R Gz, double *__restrict__ mom) {
+    uint32_t lane_cell;
+    const bool active = lane_node<CPT, BS, ROW>(g, lane_cell);
     if constexpr (!MOMENTS) {
         if (!active) return;
     }
@@ -257,6 +262,45 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
         collide_lane<C, FORCED, MOMENTS, CPT, NTS>(A, B, g, omega, enc_s, dec_s, ff, Gx, Gy, Gz,
                                                    lane_cell, acc);
     if constexpr (MOMENTS) block_sum<4, BS>(acc, mom + 4 * uint64_t(blockIdx.x));
+}
+
+// The stream-collide's data movement alone: every population is pulled from
+// x - e_a and stored unchanged at x (no moments, collision or forcing), with
+// the same layout, lanes and store policy as configuration <CPT, BS, NTS,
+// ROW>.  Its duration is the ceiling of this access pattern, which the
+// stream-collide is measured against; B does not hold a lattice update.
+template <class C, int CPT, int BS, bool NTS, bool ROW>
+__global__ __launch_bounds__(BS) void k_stream_only(const typename C::T *__restrict__ A,
+                                                    typename C::T *__restrict__ B, Grid g) {
+    using T = typename C::T;
+    using V = typename C::V;
+    uint32_t lane_cell;
+    if (!lane_node<CPT, BS, ROW>(g, lane_cell)) return;
+    const uint32_t x = lane_cell % g.nx;
+    const uint32_t t = lane_cell / g.nx;
+    const uint32_t rows = g.ny / CPT;
+    const uint32_t y0 = t % rows;
+    const uint32_t z = t / rows;
+    T raw[CPT][V::Q];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const Neighbours nb(x, y0 + uint32_t(c) * rows, z, g);
+        static_for<0, V::Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            raw[c][a] = A[nb.template pop<V, a>(g)];
+        });
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const uint64_t row_base = uint64_t(z * g.ny + y0 + uint32_t(c) * rows) * V::Q * g.chunk + x;
+        static_for<0, V::Q>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            if constexpr (NTS)
+                __builtin_nontemporal_store(raw[c][a], &B[row_base + uint64_t(a) * g.chunk]);
+            else
+                B[row_base + uint64_t(a) * g.chunk] = raw[c][a];
+        });
+    }
 }
 
 // Launch configurations of the stream-collide, chosen per context

@@ -748,6 +748,36 @@ void time_shapes(lbm_ctx *c, int32_t iters, double *ms, hipError_t *err) {
     (void)hipEventDestroy(e1);
 }
 
+// Mean time per launch of the streaming-only kernel in configuration k, over
+// iters launches (A -> B, as the autotuner's trial launches).
+template <class C>
+void time_stream_only(lbm_ctx *c, int k, int32_t iters, double *ms, hipError_t *err) {
+    using T = typename C::T;
+    const T *A = static_cast<const T *>(c->pop[c->cur]);
+    T *B = static_cast<T *>(c->pop[c->cur ^ 1]);
+    const unsigned grid = collide_grid(c, k);
+    auto launch = [&]() {
+#define LBM_STREAM_ONLY(CPT, BS, NTS, ROW) \
+    hipLaunchKernelGGL((k_stream_only<C, CPT, BS, NTS, ROW>), dim3(grid), dim3(BS), 0, c->stream, A, B, c->g)
+        LBM_CONFIG_SWITCH(k, LBM_STREAM_ONLY)
+#undef LBM_STREAM_ONLY
+    };
+    hipEvent_t e0, e1;
+    *err = hipEventCreate(&e0);
+    if (*err == hipSuccess) *err = hipEventCreate(&e1);
+    if (*err != hipSuccess) return;
+    for (int w = 0; w < 2; ++w) launch();
+    (void)hipEventRecord(e0, c->stream);
+    for (int it = 0; it < iters; ++it) launch();
+    (void)hipEventRecord(e1, c->stream);
+    *err = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (*err == hipSuccess) *err = hipEventElapsedTime(&t, e0, e1);
+    *ms = double(t) / iters;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
 template <class C>
 void launch_get_populations(lbm_ctx *c, double *f) {
     hipLaunchKernelGGL(k_get_populations<C>, dim3(blocks_for(c->g.ncell)), dim3(kBlock), 0,
@@ -1215,6 +1245,18 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen
     if (ms)
         for (int k = 0; k < kNumShapes; ++k) ms[k] = t[k];
     if (chosen) *chosen = best;
+    return LBM_OK;
+}
+
+lbm_status lbm_stream_ceiling(lbm_ctx *ctx, int32_t k, int32_t iters, double *ms) {
+    if (!ctx || !ms || iters < 1 || iters > 10000) return LBM_E_INVAL;
+    if (k < 0) k = ctx->shape;
+    if (k >= kNumShapes || !shape_ok(ctx, k)) return LBM_E_INVAL;
+    hipError_t err = hipSuccess;
+    double t = 0.0;
+    LBM_DISPATCH(ctx, time_stream_only, k, iters, &t, &err);
+    if (err != hipSuccess || launch_status() != LBM_OK) return LBM_E_DEVICE;
+    *ms = t;
     return LBM_OK;
 }
 

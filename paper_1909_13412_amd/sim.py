@@ -244,6 +244,14 @@ class Lattice:
             self.ctx, int(iters), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(chosen)))
         return chosen.value, ms
 
+    def stream_ceiling(self, iters: int = 20, config: int = -1) -> float:
+        """Milliseconds per launch of the stream-collide's data movement alone
+        (pull and store, no arithmetic) in launch configuration `config`
+        (-1: the current one); state unchanged (see lbm_stream_ceiling)."""
+        ms = ctypes.c_double()
+        _abi.check("lbm_stream_ceiling", self.lib.lbm_stream_ceiling(self.ctx, int(config), int(iters), ctypes.byref(ms)))
+        return ms.value
+
     def set_shape(self, k: int):
         """Use stream-collide launch configuration k (see lbm_set_shape)."""
         _abi.check("lbm_set_shape", self.lib.lbm_set_shape(self.ctx, int(k)))

@@ -123,6 +123,8 @@ def test_null_context_rejected(lib):
     assert lib.lbm_set_pair_force(None, ctypes.c_double(0.1), ctypes.c_double(1.0)) == 1
     assert lib.lbm_pair_forces(None, None) == 1
     assert lib.lbm_autotune(None, 5, None, None) == 1
+    ms = ctypes.c_double()
+    assert lib.lbm_stream_ceiling(None, -1, 5, ctypes.byref(ms)) == 1
     f = ctypes.c_uint32()
     assert lib.lbm_warnings(None, ctypes.byref(f)) == 1
 

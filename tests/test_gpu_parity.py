@@ -643,6 +643,55 @@ def test_every_launch_configuration_is_bit_identical():
         lat.set_shape(2)  # two rows per lane need an even ny
 
 
+# D3Q19 velocity order of the C ABI (the convention its header documents).
+E19 = [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+       (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1), (1, 0, -1),
+       (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f64"])
+def test_stream_ceiling_kernel_pulls_every_population(storage):
+    # The streaming-only kernel that bounds the stream-collide (lbm_stream_ceiling)
+    # must move exactly the stream-collide's bytes: the spare lattice holds every
+    # population pulled from x - e_a, unchanged, in every launch configuration,
+    # and the simulation state is left as it was.
+    import torch
+
+    from paper_1909_13412_amd import Lattice, _abi
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    dt = {"f32": torch.float32, "bf16": torch.int16, "f64": torch.float64}[storage]
+    for L in ((40, 24, 16), (130, 6, 8)):
+        nx, ny, nz = L
+        lat = Lattice(*L, 0.7, storage=storage)
+        lat.particles_couple(particle_positions(9, L, seed=33), particle_velocities(9, 1e-4, seed=33),
+                             kT=1e-4, seed=8)
+        lat.step(6)  # even: the current populations are back in the first buffer
+        torch.cuda.synchronize()
+        f0 = lat.populations().clone()
+        n = 19 * nx * ny * nz
+
+        def raw(buf):
+            return buf[: n * buf.new_empty(0, dtype=dt).element_size()].view(dt).reshape(nz, ny, 19, nx).cpu().numpy()
+
+        a0 = raw(lat.pop_a)
+        expect = np.empty_like(a0)
+        for a, (ex, ey, ez) in enumerate(E19):
+            expect[:, :, a, :] = np.roll(a0[:, :, a, :], shift=(ez, ey, ex), axis=(0, 1, 2))
+        for k in range(_abi.LBM_NUM_SHAPES):
+            lat.pop_b.zero_()
+            torch.cuda.synchronize()
+            ms = lat.stream_ceiling(1, config=k)
+            assert ms > 0.0
+            assert np.array_equal(raw(lat.pop_b), expect), (L, storage, k)
+        assert np.array_equal(raw(lat.pop_a), a0)
+        assert torch.equal(lat.populations(), f0)
+        with pytest.raises(Exception):
+            lat.stream_ceiling(0)
+        with pytest.raises(Exception):
+            lat.stream_ceiling(1, config=_abi.LBM_NUM_SHAPES)
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("box,r_c", [((21, 13, 11), 1.3), ((6, 9, 13), 2.9)])
 def test_pair_repulsion(oracle_mod, storage, box, r_c):
