@@ -324,7 +324,9 @@ def time_large(steps, warmup):
         r = time_storage(w, storage, steps, min(warmup, 20), min(steps, 50))
         out[storage] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 5),
                         "collide_ms": round(r["collide_ms"], 5), "collide_GBs": round(r["collide_GBs"], 1),
-                        "collide_frac": round(r["collide_frac"], 4), "collide_shape": r["collide_shape"]}
+                        "collide_frac": round(r["collide_frac"], 4), "collide_shape": r["collide_shape"],
+                        "stream_only_ms": round(r["stream_only_ms"], 5),
+                        "of_stream_only": round(r["of_stream_only"], 4)}
         torch.cuda.empty_cache()
     return out
 
