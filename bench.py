@@ -369,6 +369,22 @@ def cpu_baseline(w, steps):
     }
 
 
+
+def cpu_baseline_one_thread(w, steps):
+    """The same oracle run on one host thread (OMP_NUM_THREADS=1), in a child
+    process that never touches the GPU; None if it fails."""
+    import subprocess
+
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    code = ("import json, sys; sys.path.insert(0, {root!r}); import bench; "
+            "print(json.dumps(bench.cpu_baseline({w!r}, {steps})))").format(root=ROOT, w=dict(w), steps=int(steps))
+    res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    if res.returncode != 0:
+        print(f"[bench] one-thread oracle run failed: {res.stderr[-500:]}", file=sys.stderr, flush=True)
+        return None
+    return json.loads(res.stdout.strip().splitlines()[-1])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,6 +395,8 @@ def main():
     ap.add_argument("--variants", default="bf16,f16,f64,f32q15,bf16q15",
                     help="storages to time besides --storage; a q15 suffix selects D3Q15")
     ap.add_argument("--cpu-steps", type=int, default=90, help="oracle steps timed (0 = skip; 90 is ~11 s on 16 host threads)")
+    ap.add_argument("--cpu-steps-one-thread", type=int, default=2,
+                    help="oracle steps timed on one host thread, in a child process (0 = skip; also skipped with --cpu-steps 0; 2 is ~10 s)")
     ap.add_argument("--precision-steps", type=int, default=2000, help="0 = skip the VACF error study")
     ap.add_argument("--prof-steps", type=int, default=300, help="steps timed with per-kernel events")
     ap.add_argument("--no-copy-probe", action="store_true")
@@ -443,6 +461,11 @@ def main():
     if args.cpu_steps > 0:
         print(f"[bench] oracle baseline ({args.cpu_steps} steps)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(w, args.cpu_steps)
+    cpu1 = None
+    if args.cpu_steps > 0 and args.cpu_steps_one_thread > 0:
+        print(f"[bench] oracle baseline, one thread ({args.cpu_steps_one_thread} steps)", file=sys.stderr,
+              flush=True)
+        cpu1 = cpu_baseline_one_thread(w, args.cpu_steps_one_thread)
 
     ncell = w["L"] ** 3
     out = {
@@ -500,6 +523,7 @@ def main():
         "adjoint": adjoint,
         "precision": precision,
         "cpu_baseline": cpu,
+        "cpu_baseline_one_thread": cpu1,
     }
     print(json.dumps(out), flush=True)
 
