@@ -395,8 +395,8 @@ def main():
     ap.add_argument("--variants", default="bf16,f16,f64,f32q15,bf16q15",
                     help="storages to time besides --storage; a q15 suffix selects D3Q15")
     ap.add_argument("--cpu-steps", type=int, default=90, help="oracle steps timed (0 = skip; 90 is ~11 s on 16 host threads)")
-    ap.add_argument("--cpu-steps-one-thread", type=int, default=2,
-                    help="oracle steps timed on one host thread, in a child process (0 = skip; also skipped with --cpu-steps 0; 2 is ~10 s)")
+    ap.add_argument("--cpu-steps-one-thread", type=int, default=6,
+                    help="oracle steps timed on one host thread, in a child process (0 = skip; also skipped with --cpu-steps 0; 6 is ~10 s)")
     ap.add_argument("--precision-steps", type=int, default=2000, help="0 = skip the VACF error study")
     ap.add_argument("--prof-steps", type=int, default=300, help="steps timed with per-kernel events")
     ap.add_argument("--no-copy-probe", action="store_true")
