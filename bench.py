@@ -394,6 +394,9 @@ def main():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--variants", default="bf16,f16,f64,f32q15,bf16q15",
                     help="storages to time besides --storage; a q15 suffix selects D3Q15")
+    ap.add_argument("--vacf128-steps", type=int, default=20000,
+                    help="steps of the 128^3 / 64-particle VACF workload per storage for the "
+                         "precision study at that workload (0 = skip; also skipped with --precision-steps 0; ~8 s for all four storages)")
     ap.add_argument("--cpu-steps", type=int, default=90, help="oracle steps timed (0 = skip; 90 is ~11 s on 16 host threads)")
     ap.add_argument("--cpu-steps-one-thread", type=int, default=6,
                     help="oracle steps timed on one host thread, in a child process (0 = skip; also skipped with --cpu-steps 0; 6 is ~10 s)")
@@ -457,6 +460,15 @@ def main():
         print(f"[bench] precision study ({args.precision_steps} steps per storage)", file=sys.stderr,
               flush=True)
         precision = precision_study(w, args.precision_steps)
+    precision128 = None
+    if args.precision_steps > 0 and args.vacf128_steps > 0:
+        print(f"[bench] precision study, vacf128 ({args.vacf128_steps} steps per storage)", file=sys.stderr,
+              flush=True)
+        from paper_1909_13412_amd.inputs import WORKLOADS
+
+        w128 = dict(WORKLOADS["vacf128"])
+        w128["name"] = "vacf128"
+        precision128 = precision_study(w128, args.vacf128_steps)
     cpu = None
     if args.cpu_steps > 0:
         print(f"[bench] oracle baseline ({args.cpu_steps} steps)", file=sys.stderr, flush=True)
@@ -522,6 +534,7 @@ def main():
         "ensemble": ensemble,
         "adjoint": adjoint,
         "precision": precision,
+        "precision_vacf128": precision128,
         "cpu_baseline": cpu,
         "cpu_baseline_one_thread": cpu1,
     }
