@@ -224,19 +224,19 @@ def test_vacf_accumulation(oracle_mod):
 
 
 def test_vacf128_truncated(oracle_mod):
-    # The 128^3 / 64-particle / FP32 workload, first 100 steps.
+    # The 128^3 / 64-particle / FP32 workload, first 500 steps.
     from paper_1909_13412_amd.inputs import WORKLOADS, workload_particles
 
     w = WORKLOADS["vacf128"]
     r, v = workload_particles("vacf128")
-    announce("vacf128: 128^3 FP32, 64 particles, 100 steps")
-    out = run_pair(oracle_mod, (w["L"],) * 3, w["tau"], "f32", r, v, 100, mass=w["mass"],
+    announce("vacf128: 128^3 FP32, 64 particles, 500 steps")
+    out = run_pair(oracle_mod, (w["L"],) * 3, w["tau"], "f32", r, v, 500, mass=w["mass"],
                    gamma=w["gamma"], kT=w["kT"], seed=w["seed"], vacf=(w["max_lag"], w["stride"]))
     _compare_particles(out["gpu"], out["ref"], 1e-5, "vacf128")
     acc_g, cnt_g = out["gpu"].vacf()
     acc_r, cnt_r = out["ref"].vacf()
     assert np.array_equal(cnt_g, cnt_r)
-    e = nmax_err(acc_g.cpu().numpy()[:, :100], acc_r[:, :100])
+    e = nmax_err(acc_g.cpu().numpy()[:, :500], acc_r[:, :500])
     announce(f"  vacf acc {e:.2e}")
     assert e < 1e-5
     _compare_fields(out["gpu"], out["ref"], 1e-5, "vacf128")
