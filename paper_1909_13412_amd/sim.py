@@ -2,6 +2,7 @@
 every step of the method runs in the HIP kernels of liblbmbp.so."""
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import warnings as _warnings
 
@@ -35,6 +36,51 @@ def _alloc_bytes(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
+class _StreamOrder:
+    """Ordering between the caller's current stream and the context's stream
+    (they differ only when a stream is passed in): work a call enqueues on the
+    context's stream starts after what the caller had enqueued on its current
+    stream, and tensors a call returns (and r, v) are safe to use on the
+    caller's stream.  Waiting for an idle stream costs nothing, so contexts on
+    their own streams, driven from one host thread, run concurrently."""
+
+    def _same_stream(self) -> bool:
+        return torch.cuda.current_stream(self.device).cuda_stream == self.stream.cuda_stream
+
+    def _after_caller(self):
+        if not self._same_stream():
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    @contextlib.contextmanager
+    def _staging(self):
+        # inputs and buffers are made on the context's stream
+        if self._same_stream():
+            yield
+            return
+        self._after_caller()
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            yield
+
+    def _handover(self, *ts):
+        if not self._same_stream():
+            cur = torch.cuda.current_stream(self.device)
+            cur.wait_stream(self.stream)
+            for t in ts:
+                if t is not None:
+                    t.record_stream(cur)
+        return ts[0] if len(ts) == 1 else ts
+
+    @property
+    def r(self):
+        """Particle positions [n, 3] (device FP64, unwrapped), updated in place by every step."""
+        return self._handover(self._r)
+
+    @property
+    def v(self):
+        """Particle velocities [n, 3] (device FP64), updated in place by every step."""
+        return self._handover(self._v)
+
+
 class Tape:
     """Checkpoints of a recorded run (device buffer owned here)."""
 
@@ -42,7 +88,7 @@ class Tape:
         self.buf, self.nsteps, self.every, self.n = buf, nsteps, every, n
 
 
-class Lattice:
+class Lattice(_StreamOrder):
     """One periodic box of nx*ny*nz nodes with two population lattices.
 
     storage: "f64", "f32", "bf16" (shifted, round-to-nearest-even) or "f16"
@@ -68,6 +114,7 @@ class Lattice:
         self.lattice_bytes = sz.value
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with self._staging():
             self.pop_a = _alloc_bytes(self.lattice_bytes, self.device)
             self.pop_b = _alloc_bytes(self.lattice_bytes, self.device)
             _abi.check("lbm_grid_scratch_bytes",
@@ -80,7 +127,7 @@ class Lattice:
                                                      ctypes.byref(ctx)))
         self.ctx = ctx
         self.n = 0
-        self.r = self.v = None
+        self._r = self._v = None
         self._vacf = None
 
     # -- lifetime ---------------------------------------------------------
@@ -98,14 +145,16 @@ class Lattice:
 
     # -- fluid ------------------------------------------------------------
     def set_equilibrium(self, rho=None, u=None):
-        self._rho_in = _device_f64(rho, self.device, (self.ncell,))
-        self._u_in = _device_f64(u, self.device, (3 * self.ncell,))
-        _abi.check("lbm_set_equilibrium",
-                   self.lib.lbm_set_equilibrium(self.ctx, _ptr(self._rho_in), _ptr(self._u_in)))
+        with self._staging():
+            self._rho_in = _device_f64(rho, self.device, (self.ncell,))
+            self._u_in = _device_f64(u, self.device, (3 * self.ncell,))
+            _abi.check("lbm_set_equilibrium",
+                       self.lib.lbm_set_equilibrium(self.ctx, _ptr(self._rho_in), _ptr(self._u_in)))
 
     def set_populations(self, f):
-        self._f_in = _device_f64(f, self.device, (self.q * self.ncell,))
-        _abi.check("lbm_set_populations", self.lib.lbm_set_populations(self.ctx, _ptr(self._f_in)))
+        with self._staging():
+            self._f_in = _device_f64(f, self.device, (self.q * self.ncell,))
+            _abi.check("lbm_set_populations", self.lib.lbm_set_populations(self.ctx, _ptr(self._f_in)))
 
     def set_body_force(self, g=None):
         """Uniform body force (gx, gy, gz) on every node from the next step on."""
@@ -113,19 +162,28 @@ class Lattice:
         _abi.check("lbm_set_body_force", self.lib.lbm_set_body_force(self.ctx, arr))
 
     def populations(self) -> torch.Tensor:
-        out = torch.empty((self.q,) + self.shape, dtype=torch.float64, device=self.device)
-        _abi.check("lbm_get_populations", self.lib.lbm_get_populations(self.ctx, _ptr(out)))
-        return out
+        with self._staging():
+            out = torch.empty((self.q,) + self.shape, dtype=torch.float64, device=self.device)
+            _abi.check("lbm_get_populations", self.lib.lbm_get_populations(self.ctx, _ptr(out)))
+        return self._handover(out)
 
     def moments(self):
-        rho = torch.empty(self.shape, dtype=torch.float64, device=self.device)
-        u = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
-        _abi.check("lbm_get_moments", self.lib.lbm_get_moments(self.ctx, _ptr(rho), _ptr(u)))
-        return rho, u
+        with self._staging():
+            rho = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+            u = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+            _abi.check("lbm_get_moments", self.lib.lbm_get_moments(self.ctx, _ptr(rho), _ptr(u)))
+        return self._handover(rho, u)
 
     # -- particles --------------------------------------------------------
     def particles_couple(self, r, v, mass=10.0, gamma=1.0, kT=0.0, radius=0.0, seed=0,
                          replica=0, friction="stokeslet"):
+        with self._staging():
+            self._couple(r, v, mass, gamma, kT, radius, seed, replica, friction)
+        for bit, text in _abi.WARNINGS.items():
+            if self.warnings & bit:
+                _warnings.warn(f"particles_couple: {text} (R = {self.radius:.4g})", stacklevel=2)
+
+    def _couple(self, r, v, mass, gamma, kT, radius, seed, replica, friction):
         r = _device_f64(r, self.device).reshape(-1, 3).clone()
         v = _device_f64(v, self.device).reshape(-1, 3).clone()
         n = r.shape[0]
@@ -139,13 +197,10 @@ class Lattice:
         scratch = _alloc_bytes(sz.value, self.device)
         _abi.check("particles_couple", self.lib.particles_couple(self.ctx, ctypes.byref(pd), _ptr(r),
                                                                  _ptr(v), _ptr(scratch)))
-        self.n, self.r, self.v, self.pdesc, self._pscratch = n, r, v, pd, scratch
+        self.n, self._r, self._v, self.pdesc, self._pscratch = n, r, v, pd, scratch
         self._vacf = None
         self.fh = torch.zeros((n, 3), dtype=torch.float64, device=self.device)
         self.fr = torch.zeros((n, 3), dtype=torch.float64, device=self.device)
-        for bit, text in _abi.WARNINGS.items():
-            if self.warnings & bit:
-                _warnings.warn(f"particles_couple: {text} (R = {self.radius:.4g})", stacklevel=2)
 
     @property
     def warnings(self) -> int:
@@ -156,17 +211,19 @@ class Lattice:
 
     def set_particle_force(self, F=None):
         """Constant force F_C on each particle ([n, 3]; None detaches it)."""
-        self._fext = None if F is None else _device_f64(F, self.device).reshape(self.n, 3).contiguous()
-        _abi.check("lbm_set_particle_force", self.lib.lbm_set_particle_force(self.ctx, _ptr(self._fext)))
+        with self._staging():
+            self._fext = None if F is None else _device_f64(F, self.device).reshape(self.n, 3).contiguous()
+            _abi.check("lbm_set_particle_force", self.lib.lbm_set_particle_force(self.ctx, _ptr(self._fext)))
 
     def set_pair_force(self, a_f: float, r_c: float = 1.0):
         """Soft pair repulsion a_f (1 - r/r_c) for r < r_c (a_f = 0: off)."""
         _abi.check("lbm_set_pair_force", self.lib.lbm_set_pair_force(self.ctx, float(a_f), float(r_c)))
 
     def pair_forces(self) -> torch.Tensor:
-        out = torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
-        _abi.check("lbm_pair_forces", self.lib.lbm_pair_forces(self.ctx, _ptr(out)))
-        return out
+        with self._staging():
+            out = torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
+            _abi.check("lbm_pair_forces", self.lib.lbm_pair_forces(self.ctx, _ptr(out)))
+        return self._handover(out)
 
     @property
     def radius(self) -> float:
@@ -177,18 +234,20 @@ class Lattice:
         return self.r, self.v
 
     def particle_forces(self):
-        _abi.check("lbm_particle_forces", self.lib.lbm_particle_forces(self.ctx, _ptr(self.fh), _ptr(self.fr)))
-        return self.fh, self.fr
+        with self._staging():
+            _abi.check("lbm_particle_forces", self.lib.lbm_particle_forces(self.ctx, _ptr(self.fh), _ptr(self.fr)))
+        return self._handover(self.fh, self.fr)
 
     # -- velocity autocorrelation ----------------------------------------
     def vacf_config(self, max_lag: int, stride: int):
         sz = ctypes.c_size_t()
         _abi.check("lbm_vacf_origin_bytes",
                    self.lib.lbm_vacf_origin_bytes(self.n, max_lag, stride, ctypes.byref(sz)))
-        acc = torch.empty((max_lag + 1, self.n), dtype=torch.float64, device=self.device)  # lag-major
-        origins = _alloc_bytes(sz.value, self.device)
-        _abi.check("lbm_vacf_config",
-                   self.lib.lbm_vacf_config(self.ctx, max_lag, stride, _ptr(acc), _ptr(origins)))
+        with self._staging():
+            acc = torch.empty((max_lag + 1, self.n), dtype=torch.float64, device=self.device)  # lag-major
+            origins = _alloc_bytes(sz.value, self.device)
+            _abi.check("lbm_vacf_config",
+                       self.lib.lbm_vacf_config(self.ctx, max_lag, stride, _ptr(acc), _ptr(origins)))
         self._vacf = (acc, origins, max_lag)
 
     def vacf(self):
@@ -198,27 +257,30 @@ class Lattice:
         cnt = np.zeros(max_lag + 1, dtype=np.int64)
         _abi.check("lbm_vacf_counts", self.lib.lbm_vacf_counts(
             self.ctx, cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
-        return acc.t(), cnt
+        return self._handover(acc).t(), cnt
 
     # -- recorded observables --------------------------------------------
     def series_config(self, every: int, capacity: int):
         """Record {step, mass, fluid momentum, particle momentum} every `every`
         steps (fused into the step kernels) into a device buffer."""
-        self._series = torch.zeros((max(int(capacity), 1), 8), dtype=torch.float64, device=self.device)
-        _abi.check("lbm_series_config", self.lib.lbm_series_config(
-            self.ctx, int(every), _ptr(self._series), int(capacity) if every > 0 else 0))
+        with self._staging():
+            self._series = torch.zeros((max(int(capacity), 1), 8), dtype=torch.float64, device=self.device)
+            _abi.check("lbm_series_config", self.lib.lbm_series_config(
+                self.ctx, int(every), _ptr(self._series), int(capacity) if every > 0 else 0))
 
     def series(self) -> np.ndarray:
         """[count, 8] numpy array: step, mass, P_fluid (3), P_particle (3)."""
         n = ctypes.c_int64()
         _abi.check("lbm_series_count", self.lib.lbm_series_count(self.ctx, ctypes.byref(n)))
-        return self._series[: n.value].cpu().numpy()
+        return self._handover(self._series)[: n.value].cpu().numpy()
 
     # -- stepping and diagnostics ----------------------------------------
     def step(self, nsteps: int = 1):
+        self._after_caller()
         _abi.check("lbm_step", self.lib.lbm_step(self.ctx, int(nsteps)))
 
     def observables(self, allow_nonfinite: bool = False) -> np.ndarray:
+        self._after_caller()
         out = np.zeros(7)
         code = self.lib.lbm_observables(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         _abi.check("lbm_observables", code, allow=(4,) if allow_nonfinite else ())
@@ -238,6 +300,7 @@ class Lattice:
     def autotune(self, iters: int = 20):
         """Time the stream-collide launch shapes on this lattice (state unchanged)
         and keep the fastest.  Returns (chosen shape, ms per launch of each)."""
+        self._after_caller()
         ms = np.zeros(_abi.LBM_NUM_SHAPES)
         chosen = ctypes.c_int32()
         _abi.check("lbm_autotune", self.lib.lbm_autotune(
@@ -248,6 +311,7 @@ class Lattice:
         """Milliseconds per launch of the stream-collide's data movement alone
         (pull and store, no arithmetic) in launch configuration `config`
         (-1: the current one); state unchanged (see lbm_stream_ceiling)."""
+        self._after_caller()
         ms = ctypes.c_double()
         _abi.check("lbm_stream_ceiling", self.lib.lbm_stream_ceiling(self.ctx, int(config), int(iters), ctypes.byref(ms)))
         return ms.value
@@ -276,9 +340,10 @@ class Lattice:
         sz = ctypes.c_size_t()
         _abi.check("lbm_tape_bytes", self.lib.lbm_tape_bytes(self.ctx, int(nsteps), int(every),
                                                              ctypes.byref(sz)))
-        tape = Tape(_alloc_bytes(sz.value, self.device), int(nsteps), int(every), self.n)
-        _abi.check("lbm_record", self.lib.lbm_record(self.ctx, int(nsteps), int(every),
-                                                     _ptr(tape.buf)))
+        with self._staging():
+            tape = Tape(_alloc_bytes(sz.value, self.device), int(nsteps), int(every), self.n)
+            _abi.check("lbm_record", self.lib.lbm_record(self.ctx, int(nsteps), int(every),
+                                                         _ptr(tape.buf)))
         self._tape = tape
         return tape
 
@@ -290,29 +355,31 @@ class Lattice:
         are zero."""
         if tape is not getattr(self, "_tape", None):
             raise ValueError("adjoint() needs the tape of this lattice's last record()")
-        pop = torch.zeros((self.q,) + self.shape, dtype=torch.float64, device=self.device)
-        if adj_pop is not None:
-            pop.copy_(_device_f64(adj_pop, self.device).reshape(pop.shape))
-        n = tape.n
-        r = torch.zeros((n, 3), dtype=torch.float64, device=self.device)
-        v = torch.zeros((n, 3), dtype=torch.float64, device=self.device)
-        if adj_r is not None:
-            r.copy_(_device_f64(adj_r, self.device).reshape(n, 3))
-        if adj_v is not None:
-            v.copy_(_device_f64(adj_v, self.device).reshape(n, 3))
-        params = torch.zeros(4, dtype=torch.float64, device=self.device)
-        sz = ctypes.c_size_t()
-        _abi.check("lbm_adjoint_work_bytes",
-                   self.lib.lbm_adjoint_work_bytes(self.ctx, ctypes.byref(sz)))
-        work = _alloc_bytes(sz.value, self.device)
-        _abi.check("lbm_adjoint", self.lib.lbm_adjoint(
-            self.ctx, _ptr(tape.buf), _ptr(work), _ptr(pop), _ptr(r if n else None),
-            _ptr(v if n else None), _ptr(params)))
-        self._adj_keep = (pop, r, v, params, work)  # alive until the stream reaches them
+        with self._staging():
+            pop = torch.zeros((self.q,) + self.shape, dtype=torch.float64, device=self.device)
+            if adj_pop is not None:
+                pop.copy_(_device_f64(adj_pop, self.device).reshape(pop.shape))
+            n = tape.n
+            r = torch.zeros((n, 3), dtype=torch.float64, device=self.device)
+            v = torch.zeros((n, 3), dtype=torch.float64, device=self.device)
+            if adj_r is not None:
+                r.copy_(_device_f64(adj_r, self.device).reshape(n, 3))
+            if adj_v is not None:
+                v.copy_(_device_f64(adj_v, self.device).reshape(n, 3))
+            params = torch.zeros(4, dtype=torch.float64, device=self.device)
+            sz = ctypes.c_size_t()
+            _abi.check("lbm_adjoint_work_bytes",
+                       self.lib.lbm_adjoint_work_bytes(self.ctx, ctypes.byref(sz)))
+            work = _alloc_bytes(sz.value, self.device)
+            _abi.check("lbm_adjoint", self.lib.lbm_adjoint(
+                self.ctx, _ptr(tape.buf), _ptr(work), _ptr(pop), _ptr(r if n else None),
+                _ptr(v if n else None), _ptr(params)))
+            self._adj_keep = (pop, r, v, params, work)  # alive until the stream reaches them
+        pop, r, v, params = self._handover(pop, r, v, params)
         return {"pop": pop, "r": r, "v": v, "params": params}
 
 
-class Ensemble:
+class Ensemble(_StreamOrder):
     """Many independent periodic boxes stepped together (one launch per kernel
     per step, replayed from a captured two-step graph).
 
@@ -346,15 +413,16 @@ class Ensemble:
                                                            ctypes.byref(lat), ctypes.byref(scr)))
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with self._staging():
             self.pop_a = _alloc_bytes(lat.value, self.device)
             self.pop_b = _alloc_bytes(lat.value, self.device)
             self.scratch = _alloc_bytes(scr.value, self.device)
-            self.r = _device_f64(np.concatenate(rs), self.device).clone()
-            self.v = _device_f64(np.concatenate(vs), self.device).clone()
+            self._r = _device_f64(np.concatenate(rs), self.device).clone()
+            self._v = _device_f64(np.concatenate(vs), self.device).clone()
             ctx = ctypes.c_void_p()
             _abi.check("lbm_ens_init", self.lib.lbm_ens_init(
                 ctypes.byref(self.desc), reps, _ptr(self.pop_a), _ptr(self.pop_b), _ptr(self.scratch),
-                _ptr(self.r), _ptr(self.v), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+                _ptr(self._r), _ptr(self._v), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
         self.ctx = ctx
         self._vacf = None
 
@@ -374,6 +442,7 @@ class Ensemble:
         _abi.check("lbm_ens_use_graph", self.lib.lbm_ens_use_graph(self.ctx, int(bool(use))))
 
     def step(self, nsteps: int = 1):
+        self._after_caller()
         _abi.check("lbm_ens_step", self.lib.lbm_ens_step(self.ctx, int(nsteps)))
 
     @property
@@ -383,6 +452,7 @@ class Ensemble:
         return n.value
 
     def autotune(self, iters: int = 10):
+        self._after_caller()
         ms = np.zeros(_abi.LBM_NUM_SHAPES)
         chosen = ctypes.c_int32()
         _abi.check("lbm_ens_autotune", self.lib.lbm_ens_autotune(
@@ -400,10 +470,11 @@ class Ensemble:
         sz = ctypes.c_size_t()
         _abi.check("lbm_vacf_origin_bytes",
                    self.lib.lbm_vacf_origin_bytes(self.n, max_lag, stride, ctypes.byref(sz)))
-        acc = torch.empty((max_lag + 1, self.n), dtype=torch.float64, device=self.device)  # lag-major
-        origins = _alloc_bytes(sz.value, self.device)
-        _abi.check("lbm_ens_vacf_config",
-                   self.lib.lbm_ens_vacf_config(self.ctx, max_lag, stride, _ptr(acc), _ptr(origins)))
+        with self._staging():
+            acc = torch.empty((max_lag + 1, self.n), dtype=torch.float64, device=self.device)  # lag-major
+            origins = _alloc_bytes(sz.value, self.device)
+            _abi.check("lbm_ens_vacf_config",
+                       self.lib.lbm_ens_vacf_config(self.ctx, max_lag, stride, _ptr(acc), _ptr(origins)))
         self._vacf = (acc, origins, max_lag)
 
     def vacf(self):
@@ -411,18 +482,20 @@ class Ensemble:
         cnt = np.zeros(max_lag + 1, dtype=np.int64)
         _abi.check("lbm_ens_vacf_counts", self.lib.lbm_ens_vacf_counts(
             self.ctx, cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
-        return acc.t(), cnt  # [all particles, max_lag+1] view of the lag-major buffer
+        return self._handover(acc).t(), cnt  # [all particles, max_lag+1] view of the lag-major buffer
 
     def particles(self, k: int):
         a, b = int(self.offsets[k]), int(self.offsets[k + 1])
         return self.r[a:b], self.v[a:b]
 
     def populations(self, k: int) -> torch.Tensor:
-        out = torch.empty((Q,) + self.shapes[k], dtype=torch.float64, device=self.device)
-        _abi.check("lbm_ens_get_populations", self.lib.lbm_ens_get_populations(self.ctx, int(k), _ptr(out)))
-        return out
+        with self._staging():
+            out = torch.empty((Q,) + self.shapes[k], dtype=torch.float64, device=self.device)
+            _abi.check("lbm_ens_get_populations", self.lib.lbm_ens_get_populations(self.ctx, int(k), _ptr(out)))
+        return self._handover(out)
 
     def observables(self, k: int) -> np.ndarray:
+        self._after_caller()
         out = np.zeros(7)
         _abi.check("lbm_ens_observables", self.lib.lbm_ens_observables(
             self.ctx, int(k), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))

@@ -178,11 +178,20 @@ def test_binding_attributes_not_shadowed_by_properties():
     import ast
 
     src = open(os.path.join(ROOT, "paper_1909_13412_amd", "sim.py")).read()
-    for cls in (n for n in ast.parse(src).body if isinstance(n, ast.ClassDef)):
-        props, assigned = set(), set()
+    classes = {n.name: n for n in ast.parse(src).body if isinstance(n, ast.ClassDef)}
+
+    def props_of(cls):
+        own = {fn.name for fn in cls.body if isinstance(fn, ast.FunctionDef)
+               and any(isinstance(d, ast.Name) and d.id == "property" for d in fn.decorator_list)}
+        for b in cls.bases:  # properties inherited from classes of the same module
+            if isinstance(b, ast.Name) and b.id in classes:
+                own |= props_of(classes[b.id])
+        return own
+
+    checked = 0
+    for cls in classes.values():
+        assigned = set()
         for fn in (n for n in cls.body if isinstance(n, ast.FunctionDef)):
-            if any(isinstance(d, ast.Name) and d.id == "property" for d in fn.decorator_list):
-                props.add(fn.name)
             for node in ast.walk(fn):
                 targets = node.targets if isinstance(node, ast.Assign) else (
                     [node.target] if isinstance(node, (ast.AugAssign, ast.AnnAssign)) else [])
@@ -190,7 +199,9 @@ def test_binding_attributes_not_shadowed_by_properties():
                     for e in (t.elts if isinstance(t, ast.Tuple) else [t]):
                         if isinstance(e, ast.Attribute) and isinstance(e.value, ast.Name) and e.value.id == "self":
                             assigned.add(e.attr)
-        assert not (props & assigned), (cls.name, props & assigned)
+        assert not (props_of(cls) & assigned), (cls.name, props_of(cls) & assigned)
+        checked += "r" in props_of(cls)
+    assert checked >= 2  # Lattice and Ensemble inherit r and v
 
 
 def test_row_aligned_mapping_covers_every_node_once():
