@@ -129,6 +129,25 @@ def test_null_context_rejected(lib):
     assert lib.lbm_warnings(None, ctypes.byref(f)) == 1
 
 
+def test_every_entry_point_validates_null_arguments(lib):
+    # Every status-returning entry point, called with each pointer NULL and
+    # each number zero, rejects the call (LBM_E_INVAL) before it touches
+    # memory or the device.
+    from paper_1909_13412_amd import _abi
+
+    numbers = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t,
+               ctypes.c_int)
+    checked = 0
+    for name in _abi.EXPORTS:
+        fn = getattr(lib, name)
+        if fn.restype is not ctypes.c_int:
+            continue  # lbm_particle_radius, lbm_status_string
+        args = [0.0 if t is ctypes.c_double else 0 if t in numbers else None for t in fn.argtypes]
+        assert fn(*args) == 1, name
+        checked += 1
+    assert checked >= 40
+
+
 def test_status_strings(lib):
     for code in range(6):
         s = lib.lbm_status_string(code)
