@@ -331,6 +331,44 @@ def time_large(steps, warmup):
     return out
 
 
+
+def size_sweep(sizes, storages):
+    """Stream-collide of cubic boxes of the given edges (tau 0.6, 200
+    particles): every launch configuration's milliseconds (autotuner timing,
+    best of two rounds), the best flat (0-7) and row-aligned (8, 9) ones, and
+    the streaming-only ceiling of the best."""
+    import numpy as np
+    import torch
+
+    from paper_1909_13412_amd import Lattice
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    out = []
+    for st in storages:
+        for L in sizes:
+            lat = Lattice(L, L, L, 0.6, storage=st)
+            lat.particles_couple(particle_positions(200, L, seed=3), particle_velocities(200, 1e-5, seed=3),
+                                 radius=0.5, kT=1e-4, seed=3)
+            lat.step(10)
+            ms = np.min(np.array([lat.autotune(20)[1] for _ in range(2)]), axis=0)
+            valid = ms > 0
+            k = int(np.argmin(np.where(valid, ms, np.inf)))
+            ceil = lat.stream_ceiling(20, config=k)
+            alg = collide_bytes_per_node(st) * L ** 3
+            flat = ms[:8][valid[:8]]
+            row = ms[8:][valid[8:]]
+            out.append({"box": L, "storage": st, "config": k, "ms": round(float(ms[k]), 5),
+                        "GBs": round(alg / (ms[k] * 1e-3) / 1e9, 1),
+                        "frac": round(alg / (ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "flat_best_ms": round(float(flat.min()), 5),
+                        "row_best_ms": round(float(row.min()), 5) if row.size else None,
+                        "stream_only_ms": round(ceil, 5), "of_stream_only": round(ceil / float(ms[k]), 4),
+                        "all_ms": [round(float(x), 5) for x in ms]})
+            print(f"[bench] size sweep {L}^3 {st}: config {k} {ms[k]:.4f} ms", file=sys.stderr, flush=True)
+            del lat
+            torch.cuda.empty_cache()
+    return out
+
 def time_pairs(w, steps, warmup, prof_steps, main):
     """The same FP32 workload with the soft pair repulsion switched on (a_f =
     0.05, cutoff 2R = 1): cost of the cell list and the neighbour sums, which
@@ -394,6 +432,10 @@ def main():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--variants", default="bf16,f16,f64,f32q15,bf16q15",
                     help="storages to time besides --storage; a q15 suffix selects D3Q15")
+    ap.add_argument("--size-sweep", default="",
+                    help="comma-separated box edges for a stream-collide size sweep (off by default), "
+                         "e.g. 48,64,96,100,128,200,250,256")
+    ap.add_argument("--size-sweep-storages", default="f32,bf16")
     ap.add_argument("--vacf128-steps", type=int, default=20000,
                     help="steps of the 128^3 / 64-particle VACF workload per storage for the "
                          "precision study at that workload (0 = skip; also skipped with --precision-steps 0; ~8 s for all four storages)")
@@ -460,6 +502,10 @@ def main():
         print(f"[bench] precision study ({args.precision_steps} steps per storage)", file=sys.stderr,
               flush=True)
         precision = precision_study(w, args.precision_steps)
+    sweep = None
+    if args.size_sweep:
+        sweep = size_sweep([int(x) for x in args.size_sweep.split(",") if x],
+                           [x for x in args.size_sweep_storages.split(",") if x])
     precision128 = None
     if args.precision_steps > 0 and args.vacf128_steps > 0:
         print(f"[bench] precision study, vacf128 ({args.vacf128_steps} steps per storage)", file=sys.stderr,
@@ -535,6 +581,7 @@ def main():
         "adjoint": adjoint,
         "precision": precision,
         "precision_vacf128": precision128,
+        "size_sweep": sweep,
         "cpu_baseline": cpu,
         "cpu_baseline_one_thread": cpu1,
     }
