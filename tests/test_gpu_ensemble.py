@@ -79,6 +79,30 @@ def test_ensemble_equals_single_box_runs():
         assert np.array_equal(fe, fo) and np.array_equal(ve, vo), (k, np.max(np.abs(fe - fo)), nmax_err(ve, vo))
 
 
+def test_ensemble_on_its_own_stream():
+    # An ensemble driven on a stream of its own (graph replays included) gives
+    # the bits it gives on the caller's stream, and its results are safe to
+    # read on the caller's stream.
+    import torch
+
+    from paper_1909_13412_amd import Ensemble
+
+    reps = _small_replicas()
+    out = []
+    for stream in (None, torch.cuda.Stream()):
+        e = Ensemble(reps, storage="f32", kT=1e-4, stream=stream)
+        e.vacf_config(9, 4)
+        e.step(21)
+        acc, cnt = e.vacf()
+        out.append(([e.populations(k).cpu().numpy() for k in range(len(reps))],
+                    e.v.cpu().numpy(), acc.cpu().numpy(), cnt))
+        e.close()
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, b)
+    for a, b in zip(out[0][1:], out[1][1:]):
+        assert np.array_equal(a, b)
+
+
 def test_graph_replays_match_plain_launches():
     # Replays of the captured two-step graph, with eager work and
     # synchronisation between them, against the same ensemble stepped with
