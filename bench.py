@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -100,7 +101,7 @@ def make_lattice(w, storage, device="cuda:0", series_capacity=0, q=19):
     return lat
 
 
-def time_storage(w, variant, steps, warmup, prof_steps, pair=None):
+def time_storage(w, variant, steps, warmup, prof_steps, pair=None, repeats=0):
     """Autotune the stream-collide launch shape, time `steps` whole steps with
     nothing but the kernels on the stream (-> MLUPS), then time `prof_steps`
     more with HIP events around every kernel launch (-> per-kernel durations;
@@ -122,6 +123,13 @@ def time_storage(w, variant, steps, warmup, prof_steps, pair=None):
     lat.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # further regions of the same `steps` steps, for the spread of the figure
+    more = []
+    for _ in range(repeats):
+        a = time.perf_counter()
+        lat.step(steps)
+        torch.cuda.synchronize()
+        more.append(w["L"] ** 3 * steps / (time.perf_counter() - a) / 1e6)
     lat.profile_enable(True)
     lat.profile_read()
     torch.cuda.synchronize()
@@ -142,6 +150,7 @@ def time_storage(w, variant, steps, warmup, prof_steps, pair=None):
         "storage": storage,
         "velocities": q,
         "mlups": ncell * steps / (t1 - t0) / 1e6,
+        "mlups_more_regions": more,
         "ms_per_step": (t1 - t0) * 1e3 / steps,
         "profiled_ms_per_step": (t3 - t2) * 1e3 / prof_steps,
         "collide_ms": coll_ms,
@@ -432,6 +441,9 @@ def main():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--variants", default="bf16,f16,f64,f32q15,bf16q15",
                     help="storages to time besides --storage; a q15 suffix selects D3Q15")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed regions of --steps steps for the main storage: `value` is the first, "
+                         "`value_regions` lists all with their median (1 = the first only)")
     ap.add_argument("--size-sweep", default="",
                     help="comma-separated box edges for a stream-collide size sweep (off by default), "
                          "e.g. 48,64,96,100,128,200,250,256")
@@ -473,7 +485,8 @@ def main():
         copy = copy_probe(19 * w["L"] ** 3 * ELEM[args.storage])
     print(f"[bench] timing {args.workload} storage={args.storage} steps={args.steps}", file=sys.stderr,
           flush=True)
-    main_res = time_storage(w, args.storage, args.steps, args.warmup, args.prof_steps)
+    main_res = time_storage(w, args.storage, args.steps, args.warmup, args.prof_steps,
+                            repeats=max(args.repeats - 1, 0))
     variants = {}
     for s in [v for v in args.variants.split(",") if v and v != args.storage]:
         print(f"[bench] timing storage={s}", file=sys.stderr, flush=True)
@@ -526,6 +539,7 @@ def main():
         cpu1 = cpu_baseline_one_thread(w, args.cpu_steps_one_thread)
 
     ncell = w["L"] ** 3
+    regions = [main_res["mlups"]] + main_res["mlups_more_regions"]
     out = {
         "metric": METRIC,
         "value": round(main_res["mlups"], 1),
@@ -534,6 +548,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(main_res["ms_per_step"], 5),
+        "value_regions": {"mlups": [round(x, 1) for x in regions],
+                          "median": round(statistics.median(regions), 1)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
