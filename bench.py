@@ -540,6 +540,7 @@ def main():
 
     ncell = w["L"] ** 3
     regions = [main_res["mlups"]] + main_res["mlups_more_regions"]
+    traffic = pmc_traffic(args.storage)
     out = {
         "metric": METRIC,
         "value": round(main_res["mlups"], 1),
@@ -568,7 +569,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(main_res["collide_frac"], 4),
-            "traffic": pmc_traffic(args.storage),
+            "traffic": traffic,
+            "traffic_frac": (round(traffic / (main_res["collide_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                             if traffic else None),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, "
                             "copy-calibrated; null if the kernels changed since)",
             "algorithmic_bytes_per_launch": collide_bytes_per_node(args.storage) * ncell,
