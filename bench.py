@@ -254,7 +254,16 @@ def time_ensemble(steps, warmup):
         ens.use_graph(use_graph)
         ens.step(warmup)
         torch.cuda.synchronize()
-        shape, _ = ens.autotune(10)
+        shape, tune_ms = ens.autotune(10)
+        if use_graph:
+            # the stream-collide (autotuner timing) against the same data
+            # movement without the arithmetic, same configuration
+            ceil = ens.stream_ceiling(10)
+            out["collide_ms"] = round(float(tune_ms[shape]), 5)
+            out["collide_frac"] = round(nodes * collide_bytes_per_node(w["storage"]) / (tune_ms[shape] * 1e-3)
+                                        / 1e9 / HBM_PEAK_GBS, 4)
+            out["stream_only_ms"] = round(ceil, 5)
+            out["of_stream_only"] = round(ceil / float(tune_ms[shape]), 4)
         ens.step(warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

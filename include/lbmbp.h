@@ -425,6 +425,16 @@ lbm_status lbm_ens_step(lbm_ens *ens, int32_t nsteps);
  * sizes in the same order, which start from it. */
 lbm_status lbm_ens_autotune(lbm_ens *ens, int32_t iters, double *ms, int32_t *chosen);
 
+/* Ceiling of the ensemble stream-collide's data movement, as lbm_stream_ceiling:
+ * *ms receives the mean milliseconds per launch (iters 1..10000, after two
+ * warm-up launches) of a kernel that pulls and stores every population of every
+ * box unchanged, with the ensemble's block -> box table and launch
+ * configuration k (k < 0: the current one; 0..7 only).  Reads the current
+ * populations and overwrites the spare lattice: the state is unchanged.
+ * Synchronises the stream.  LBM_E_INVAL for a NULL ens or ms, iters out of
+ * range, or a configuration that does not apply to every box. */
+lbm_status lbm_ens_stream_ceiling(lbm_ens *ens, int32_t k, int32_t iters, double *ms);
+
 /* The launch configuration later lbm_ens_step calls use. */
 lbm_status lbm_ens_get_shape(const lbm_ens *ens, int32_t *k);
 

@@ -23,7 +23,7 @@ EXPORTS = [
     "lbm_profile_enable", "lbm_profile_read", "lbm_autotune", "lbm_stream_ceiling", "lbm_set_shape", "lbm_get_shape", "lbm_get_step", "lbm_destroy",
     "lbm_tape_bytes", "lbm_record", "lbm_adjoint_work_bytes", "lbm_adjoint",
     "lbm_ens_bytes", "lbm_ens_init", "lbm_ens_use_graph", "lbm_ens_vacf_config",
-    "lbm_ens_vacf_counts", "lbm_ens_step", "lbm_ens_autotune", "lbm_ens_get_shape", "lbm_ens_observables",
+    "lbm_ens_vacf_counts", "lbm_ens_step", "lbm_ens_autotune", "lbm_ens_stream_ceiling", "lbm_ens_get_shape", "lbm_ens_observables",
     "lbm_ens_get_populations", "lbm_ens_get_step", "lbm_ens_graph_replays", "lbm_ens_destroy",
     "lbm_status_string",
 ]
@@ -127,6 +127,7 @@ def load() -> ctypes.CDLL:
         "lbm_ens_vacf_counts": [vp, ctypes.POINTER(i64)],
         "lbm_ens_step": [vp, i32],
         "lbm_ens_autotune": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],
+        "lbm_ens_stream_ceiling": [vp, i32, i32, ctypes.POINTER(ctypes.c_double)],
         "lbm_ens_observables": [vp, i32, ctypes.POINTER(ctypes.c_double)],
         "lbm_ens_get_populations": [vp, i32, dp],
         "lbm_ens_get_step": [vp, ctypes.POINTER(i64)],

@@ -264,18 +264,17 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
     if constexpr (MOMENTS) block_sum<4, BS>(acc, mom + 4 * uint64_t(blockIdx.x));
 }
 
-// The stream-collide's data movement alone: every population is pulled from
-// x - e_a and stored unchanged at x (no moments, collision or forcing), with
-// the same layout, lanes and store policy as configuration <CPT, BS, NTS,
-// ROW>.  Its duration is the ceiling of this access pattern, which the
-// stream-collide is measured against; B does not hold a lattice update.
-template <class C, int CPT, int BS, bool NTS, bool ROW>
-__global__ __launch_bounds__(BS) void k_stream_only(const typename C::T *__restrict__ A,
-                                                    typename C::T *__restrict__ B, Grid g) {
+// The stream-collide's data movement alone, for the nodes of one lane (as in
+// collide_lane): every population is pulled from x - e_a and stored
+// unchanged at x (no moments, collision or forcing), with the same layout and
+// store policy.  Its duration bounds what the stream-collide can reach with
+// this access pattern; B does not hold a lattice update.
+template <class C, int CPT, bool NTS>
+__device__ inline void stream_only_lane(const typename C::T *__restrict__ A,
+                                        typename C::T *__restrict__ B, const Grid &g,
+                                        uint32_t lane_cell) {
     using T = typename C::T;
     using V = typename C::V;
-    uint32_t lane_cell;
-    if (!lane_node<CPT, BS, ROW>(g, lane_cell)) return;
     const uint32_t x = lane_cell % g.nx;
     const uint32_t t = lane_cell / g.nx;
     const uint32_t rows = g.ny / CPT;
@@ -301,6 +300,16 @@ __global__ __launch_bounds__(BS) void k_stream_only(const typename C::T *__restr
                 B[row_base + uint64_t(a) * g.chunk] = raw[c][a];
         });
     }
+}
+
+// Streaming-only counterpart of k_stream_collide in configuration <CPT, BS,
+// NTS, ROW> (same lanes).
+template <class C, int CPT, int BS, bool NTS, bool ROW>
+__global__ __launch_bounds__(BS) void k_stream_only(const typename C::T *__restrict__ A,
+                                                    typename C::T *__restrict__ B, Grid g) {
+    uint32_t lane_cell;
+    if (!lane_node<CPT, BS, ROW>(g, lane_cell)) return;
+    stream_only_lane<C, CPT, NTS>(A, B, g, lane_cell);
 }
 
 // Launch configurations of the stream-collide, chosen per context

@@ -94,6 +94,20 @@ __global__ __launch_bounds__(BS) void k_ens_collide(const typename C::T *__restr
                                            enc_s, dec_s, ff, R(0), R(0), R(0), lane_cell, acc);
 }
 
+// Streaming-only counterpart of k_ens_collide (same block -> box table, lanes
+// and store policy): the ceiling the ensemble stream-collide is measured
+// against.
+template <class C, int CPT, int BS, bool NTS>
+__global__ __launch_bounds__(BS) void k_ens_stream_only(const typename C::T *__restrict__ A,
+                                                        typename C::T *__restrict__ B,
+                                                        const Replica *__restrict__ reps,
+                                                        const uint16_t *__restrict__ blk_rep, int shape) {
+    const Replica &rp = reps[blk_rep[blockIdx.x]];
+    const uint32_t lane_cell = (blockIdx.x - rp.first_block[shape]) * BS + threadIdx.x;
+    if (lane_cell >= rp.g.ncell / CPT) return;
+    stream_only_lane<C, CPT, NTS>(A + rp.pop_off, B + rp.pop_off, rp.g, lane_cell);
+}
+
 template <class C>
 __global__ __launch_bounds__(kParticleBlock) void k_ens_particle(
     const typename C::T *__restrict__ A, const Replica *__restrict__ reps,
@@ -1585,6 +1599,28 @@ void ens_time_dispatch(lbm_ens *e, int k) {
 #undef LBM_ENS_TIME
 }
 
+template <class C>
+void ens_stream_only(lbm_ens *e, int k) {
+    using T = typename C::T;
+    const int sh = k & 3;
+    const T *A = static_cast<const T *>(e->pop[e->cur]);
+    T *B = static_cast<T *>(e->pop[e->cur ^ 1]);
+#define LBM_ENS_STREAM_ONLY(CPT, BS, NTS, ROW)                                                      \
+    hipLaunchKernelGGL((k_ens_stream_only<C, CPT, BS, NTS>), dim3(e->total_blocks[sh]), dim3(BS), 0, \
+                       e->stream, A, B, e->reps, e->blk_rep[sh], sh)
+    LBM_CONFIG_SWITCH(k, LBM_ENS_STREAM_ONLY)
+#undef LBM_ENS_STREAM_ONLY
+}
+
+void ens_stream_only_any(lbm_ens *e, int k) {
+    switch (e->desc.storage) {
+        case LBM_STORE_F64: ens_stream_only<F64Q19>(e, k); break;
+        case LBM_STORE_F32: ens_stream_only<F32Q19>(e, k); break;
+        case LBM_STORE_BF16: ens_stream_only<BF16Q19>(e, k); break;
+        case LBM_STORE_F16: ens_stream_only<F16Q19>(e, k); break;
+    }
+}
+
 void ens_time_any(lbm_ens *e, int k) {
     switch (e->desc.storage) {
         case LBM_STORE_F64: ens_time_dispatch<F64Q19>(e, k); break;
@@ -1843,6 +1879,32 @@ lbm_status lbm_ens_autotune(lbm_ens *e, int32_t iters, double *ms, int32_t *chos
     if (ms)
         for (int k = 0; k < kNumShapes; ++k) ms[k] = t[k];
     if (chosen) *chosen = best;
+    return LBM_OK;
+}
+
+lbm_status lbm_ens_stream_ceiling(lbm_ens *e, int32_t k, int32_t iters, double *ms) {
+    if (!e || !ms || iters < 1 || iters > 10000) return LBM_E_INVAL;
+    if (k < 0) k = e->shape;
+    if (k >= kNumShapes || config_row(k) || e->total_blocks[k & 3] == 0) return LBM_E_INVAL;
+    for (int32_t q = 0; q < e->nrep; ++q)
+        if (e->host_reps[q].ny % kShapes[k & 3].cpt != 0) return LBM_E_INVAL;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return LBM_E_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return LBM_E_DEVICE;
+    }
+    for (int w = 0; w < 2; ++w) ens_stream_only_any(e, k);
+    (void)hipEventRecord(e0, e->stream);
+    for (int32_t it = 0; it < iters; ++it) ens_stream_only_any(e, k);
+    (void)hipEventRecord(e1, e->stream);
+    hipError_t err = hipEventSynchronize(e1);
+    float f = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&f, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess || launch_status() != LBM_OK) return LBM_E_DEVICE;
+    *ms = double(f) / iters;
     return LBM_OK;
 }
 

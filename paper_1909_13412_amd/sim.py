@@ -459,6 +459,16 @@ class Ensemble(_StreamOrder):
             self.ctx, int(iters), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(chosen)))
         return chosen.value, ms
 
+    def stream_ceiling(self, iters: int = 20, config: int = -1) -> float:
+        """Milliseconds per launch of the ensemble stream-collide's data movement
+        alone in launch configuration `config` (-1: the current one); state
+        unchanged (see lbm_ens_stream_ceiling)."""
+        self._after_caller()
+        ms = ctypes.c_double()
+        _abi.check("lbm_ens_stream_ceiling",
+                   self.lib.lbm_ens_stream_ceiling(self.ctx, int(config), int(iters), ctypes.byref(ms)))
+        return ms.value
+
     @property
     def launch_config(self) -> int:
         """The stream-collide launch configuration later steps use."""

@@ -64,3 +64,19 @@ def run_pair(oracle_mod, L, tau, storage, r, v, steps, *, mass=10.0, gamma=1.0, 
     out["gpu"] = gpu
     out["ref"] = ref
     return out
+
+
+# D3Q19 velocity order of the C ABI (the convention its header documents).
+E19 = [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+       (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1), (1, 0, -1),
+       (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]
+
+
+def pulled(a, nx, ny, nz):
+    """The stream-collide's pull applied to one raw lattice of the C ABI layout
+    ((z * ny + y) * 19 + a) * nx + x: plane a of node x taken from x - e_a."""
+    a = a.reshape(nz, ny, 19, nx)
+    out = np.empty_like(a)
+    for k, (ex, ey, ez) in enumerate(E19):
+        out[:, :, k, :] = np.roll(a[:, :, k, :], shift=(ez, ey, ex), axis=(0, 1, 2))
+    return out

@@ -4,7 +4,7 @@ against a single-box run with the same inputs."""
 import numpy as np
 import pytest
 
-from helpers import announce, nmax_err
+from helpers import announce, nmax_err, pulled
 
 pytestmark = pytest.mark.gpu
 
@@ -101,6 +101,49 @@ def test_ensemble_on_its_own_stream():
         assert np.array_equal(a, b)
     for a, b in zip(out[0][1:], out[1][1:]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_ensemble_stream_ceiling_pulls_every_population(storage):
+    # The ensemble's streaming-only kernel (lbm_ens_stream_ceiling) moves
+    # exactly the ensemble stream-collide's bytes: box after box in the spare
+    # lattice, every population pulled from x - e_a unchanged, in every
+    # configuration that applies (two-node shapes need an even ny in every box);
+    # the state is left as it was.
+    import torch
+
+    from paper_1909_13412_amd import Ensemble
+
+    reps = _small_replicas()
+    e = Ensemble(reps, storage=storage, kT=1e-4)
+    e.step(6)  # even: the current populations are back in the first buffer
+    f0 = [e.populations(k).clone() for k in range(len(reps))]
+    torch.cuda.synchronize()
+    dt, el = {"f32": (torch.float32, 4), "bf16": (torch.int16, 2)}[storage]
+    sizes = [19 * rd["nx"] * rd["ny"] * rd["nz"] for rd in reps]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+
+    def raw(buf):
+        return buf[: int(offs[-1]) * el].view(dt).cpu().numpy()
+
+    a0 = raw(e.pop_a)
+    expect = np.concatenate([pulled(a0[offs[k]:offs[k + 1]], rd["nx"], rd["ny"], rd["nz"]).ravel()
+                             for k, rd in enumerate(reps)])
+    even_ny = all(rd["ny"] % 2 == 0 for rd in reps)
+    for k in range(8):
+        if (k & 3) >= 2 and not even_ny:
+            with pytest.raises(Exception):
+                e.stream_ceiling(1, config=k)
+            continue
+        e.pop_b.zero_()
+        torch.cuda.synchronize()
+        assert e.stream_ceiling(1, config=k) > 0.0
+        assert np.array_equal(raw(e.pop_b), expect), (storage, k)
+    with pytest.raises(Exception):
+        e.stream_ceiling(1, config=8)  # row-aligned: single boxes only
+    assert np.array_equal(raw(e.pop_a), a0)
+    for k in range(len(reps)):
+        assert torch.equal(e.populations(k), f0[k])
 
 
 def test_graph_replays_match_plain_launches():

@@ -8,7 +8,7 @@ positions.
 import numpy as np
 import pytest
 
-from helpers import announce, nmax_err, run_pair
+from helpers import announce, nmax_err, pulled, run_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -805,12 +805,6 @@ def test_every_launch_configuration_is_bit_identical():
         lat.set_shape(2)  # two rows per lane need an even ny
 
 
-# D3Q19 velocity order of the C ABI (the convention its header documents).
-E19 = [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
-       (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1), (1, 0, -1),
-       (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]
-
-
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f64"])
 def test_stream_ceiling_kernel_pulls_every_population(storage):
     # The streaming-only kernel that bounds the stream-collide (lbm_stream_ceiling)
@@ -837,9 +831,7 @@ def test_stream_ceiling_kernel_pulls_every_population(storage):
             return buf[: n * buf.new_empty(0, dtype=dt).element_size()].view(dt).reshape(nz, ny, 19, nx).cpu().numpy()
 
         a0 = raw(lat.pop_a)
-        expect = np.empty_like(a0)
-        for a, (ex, ey, ez) in enumerate(E19):
-            expect[:, :, a, :] = np.roll(a0[:, :, a, :], shift=(ez, ey, ex), axis=(0, 1, 2))
+        expect = pulled(a0, nx, ny, nz)
         for k in range(_abi.LBM_NUM_SHAPES):
             lat.pop_b.zero_()
             torch.cuda.synchronize()
