@@ -411,6 +411,55 @@ def test_gaussian_stream_moments(oracle_mod):
     assert abs(np.mean(a * b)) < 4 / np.sqrt(5000)
 
 
+def test_gaussian_triple_independent_within_one_block(oracle_mod):
+    # The three normals of one Philox block (Box-Muller on (u0, u1), and on
+    # (u2, u3) for the third) must be independent standard normals.  Over
+    # 1e5 blocks: pairwise correlations of (z0, z1, z2) and of their squares
+    # vanish within 4 sigma (sigma = 1/sqrt(N) for independent pairs), the
+    # radius z0^2 + z1^2 of the first pair is chi-square with two degrees of
+    # freedom (an exponential of mean 2 and variance 4), and z2 is N(0, 1).
+    # A copy of z0 in z1, or a radius reused for z2, fails these.
+    from scipy import stats
+
+    N = 100_000
+    z = np.array([oracle_mod.gauss3(31337, n, i) for n in range(1000) for i in range(100)])
+    assert z.shape == (N, 3)
+    sig = 1.0 / np.sqrt(N)
+    for a, b in ((0, 1), (0, 2), (1, 2)):
+        za, zb = z[:, a], z[:, b]
+        assert abs(np.corrcoef(za, zb)[0, 1]) < 4 * sig, (a, b)
+        assert abs(np.corrcoef(za**2, zb**2)[0, 1]) < 4 * sig, (a, b)
+    r2 = z[:, 0] ** 2 + z[:, 1] ** 2
+    assert abs(r2.mean() - 2.0) < 4 * 2.0 * sig
+    # variance of the sample variance of an exponential: (mu4 - sigma^4) / N
+    # with mu4 = 9 * 2^4 and sigma^2 = 4
+    assert abs(r2.var() - 4.0) < 4 * np.sqrt((144.0 - 16.0) / N)
+    assert stats.kstest(r2, stats.expon(scale=2.0).cdf).pvalue > 1e-4
+    for k in range(3):
+        assert stats.kstest(z[:, k], stats.norm.cdf).pvalue > 1e-4, k
+
+
+def test_gaussian_triple_inverts_to_its_philox_words(oracle_mod):
+    # Box & Muller's map is invertible: from the normals recover the uniforms
+    # and compare with the (separately pinned) Philox words of the same
+    # counter, each mapped to (x + 1/2) 2^-32.  The radius of (z0, z1) gives
+    # u0, their angle gives u1, and z2 over the radius of u2 gives the cosine
+    # of 2 pi u3; a swapped word, a reused radius or a sine in place of a
+    # cosine fails.
+    rng = np.random.default_rng(12)
+    for _ in range(300):
+        seed = int(rng.integers(0, 2**63))
+        step, part, rep, stream = (int(x) for x in rng.integers(0, 2**32, size=4))
+        z = oracle_mod.gauss3(seed, step, part, rep, stream)
+        x = oracle_mod.philox4x32_10([step, part, rep, stream], [seed & 0xFFFFFFFF, seed >> 32])
+        u = (x.astype(np.float64) + 0.5) * 2.0**-32
+        assert abs(np.exp(-(z[0] ** 2 + z[1] ** 2) / 2.0) - u[0]) < 1e-12
+        ang = np.arctan2(z[1], z[0]) / (2 * np.pi) % 1.0
+        assert min(abs(ang - u[1]), 1.0 - abs(ang - u[1])) < 1e-9
+        rad2 = np.sqrt(-2.0 * np.log(u[2]))
+        assert abs(z[2] / rad2 - np.cos(2 * np.pi * u[3])) < 1e-12
+
+
 def test_vacf_estimator_matches_trace(oracle_mod):
     # Device-style accumulation (origins every K steps, lags <= Lmax) against a
     # brute-force recomputation from the recorded velocity trace.
