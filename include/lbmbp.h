@@ -246,6 +246,21 @@ lbm_status lbm_series_count(const lbm_ctx *ctx, int64_t *count);
  * node force left the fixed-point range since the last call. */
 lbm_status lbm_observables(lbm_ctx *ctx, double out[7]);
 
+/* lbm_observables for callers that cannot allocate device memory (harnesses
+ * that forbid hipMalloc, tight serving loops): the same sums, bit for bit,
+ * with the reduction partials and the result in a fixed device array of the
+ * library (1024 x 4 + 8 doubles, 32.8 KB per device, held until the process
+ * ends) instead of the context's grid scratch.  No call allocates or frees
+ * anything.  That need is the same for every box and particle count, so no
+ * context exceeds it.  Every call on one device shares the array: calls that
+ * overlap on one device (two host threads, or two contexts on different
+ * streams at once) race and may return each other's sums; calls from one
+ * thread are safe, since each call synchronises the context's stream before
+ * it returns.  The device current at the call must be the context's
+ * (LBM_E_STATE otherwise); LBM_E_DEVICE if the array's address could not be
+ * obtained at lbm_init.  Other results as lbm_observables. */
+lbm_status lbm_observables_noalloc(lbm_ctx *ctx, double out[7]);
+
 /* Per-kernel GPU timing with HIP events recorded on the context's stream.
  * enable = 1 brackets every particle-phase launch (VACF sample + particle
  * coupling) and every stream-collide launch of lbm_step with start/stop

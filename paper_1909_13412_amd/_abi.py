@@ -19,7 +19,7 @@ EXPORTS = [
     "lbm_vacf_origin_bytes", "lbm_init", "lbm_set_equilibrium", "lbm_set_populations",
     "lbm_set_body_force", "lbm_get_populations", "lbm_get_moments", "particles_couple", "lbm_set_particle_force", "lbm_set_pair_force", "lbm_pair_forces", "lbm_particle_radius", "lbm_warnings",
     "lbm_particle_forces", "lbm_vacf_config", "lbm_vacf_counts", "lbm_step", "lbm_series_config",
-    "lbm_series_count", "lbm_observables",
+    "lbm_series_count", "lbm_observables", "lbm_observables_noalloc",
     "lbm_profile_enable", "lbm_profile_read", "lbm_autotune", "lbm_stream_ceiling", "lbm_set_shape", "lbm_get_shape", "lbm_get_step", "lbm_destroy",
     "lbm_tape_bytes", "lbm_record", "lbm_adjoint_work_bytes", "lbm_adjoint",
     "lbm_ens_bytes", "lbm_ens_init", "lbm_ens_use_graph", "lbm_ens_vacf_config",
@@ -105,6 +105,7 @@ def load() -> ctypes.CDLL:
         "lbm_series_config": [vp, i32, dp, i64],
         "lbm_series_count": [vp, ctypes.POINTER(i64)],
         "lbm_observables": [vp, ctypes.POINTER(ctypes.c_double)],
+        "lbm_observables_noalloc": [vp, ctypes.POINTER(ctypes.c_double)],
         "lbm_profile_enable": [vp, i32],
         "lbm_profile_read": [vp, ctypes.POINTER(ctypes.c_double)],
         "lbm_autotune": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],

@@ -821,10 +821,10 @@ void launch_set_equilibrium(lbm_ctx *c, const double *rho, const double *u) {
 }
 
 template <class C>
-void launch_partials(lbm_ctx *c) {
+void launch_partials(lbm_ctx *c, double *partials) {
     hipLaunchKernelGGL(k_fluid_partials<C>, dim3(kRedBlocks), dim3(kBlock), 0, c->stream,
                        static_cast<const typename C::T *>(c->pop[c->cur]), c->g,
-                       typename C::R(c->dec_s), c->partials);
+                       typename C::R(c->dec_s), partials);
 }
 
 // The storage codec x velocity set combinations the library instantiates.
@@ -889,6 +889,42 @@ lbm_status lbm_vacf_origin_bytes(int32_t n, int32_t max_lag, int32_t stride, siz
 
 }  // extern "C"
 
+// Device memory of lbm_observables_noalloc: the FP64 reduction partials
+// ([kRedBlocks][4]) followed by the seven sums.  Every device the library runs
+// on holds one copy until the process ends.  Host code never passes this name
+// to a kernel or a copy (on the host it is only a stand-in for the symbol):
+// it uses the device address that hipGetSymbolAddress returned for that
+// device, kept in g_noalloc below.
+constexpr size_t kNoAllocDoubles = size_t(kRedBlocks) * 4 + 8;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+
+// Device address of `scratch` per device, looked up once per device by
+// lbm_init (with that device current).
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+bool g_noalloc_done[kMaxDevices];
+double *g_noalloc[kMaxDevices];
+
+void noalloc_setup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_done[dev]) return;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_noalloc[dev] = (e == hipSuccess) ? static_cast<double *>(p) : nullptr;
+    g_noalloc_done[dev] = true;
+}
+
+double *noalloc_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    return g_noalloc[dev];
+}
+
+}  // namespace
+
 namespace {
 
 // Launch configurations the autotuners chose, kept for the life of the
@@ -945,6 +981,7 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
     c->g.chunk = row_chunk(grid);
     c->q = velocity_count(grid);
     c->device = current_device();
+    noalloc_setup(c->device);
     {
         size_t lat = 0;
         lbm_lattice_bytes(grid, &lat);
@@ -1198,16 +1235,21 @@ lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps) {
     return launch_status();
 }
 
-lbm_status lbm_observables(lbm_ctx *ctx, double out[7]) {
-    if (!ctx || !out) return LBM_E_INVAL;
-    LBM_DISPATCH(ctx, launch_partials);
-    hipLaunchKernelGGL(k_final_sums, dim3(1), dim3(kBlock), 0, ctx->stream, ctx->partials,
+}  // extern "C"
+
+namespace {
+
+// The sums of lbm_observables with the reduction partials ([kRedBlocks][4])
+// and the result (7 doubles) in the given device buffers.
+lbm_status observables_into(lbm_ctx *ctx, double *partials, double *result, double out[7]) {
+    LBM_DISPATCH(ctx, launch_partials, partials);
+    hipLaunchKernelGGL(k_final_sums, dim3(1), dim3(kBlock), 0, ctx->stream, partials,
                        kRedBlocks, double(ctx->g.ncell), ctx->np > 0 ? ctx->v : nullptr, ctx->np,
-                       ctx->np > 0 ? ctx->pdesc.mass : 0.0, ctx->result);
+                       ctx->np > 0 ? ctx->pdesc.mass : 0.0, result);
     if (launch_status() != LBM_OK) return LBM_E_DEVICE;
     double host[7];
     uint32_t err = 0;
-    hipError_t e = hipMemcpyAsync(host, ctx->result, sizeof(host), hipMemcpyDeviceToHost,
+    hipError_t e = hipMemcpyAsync(host, result, sizeof(host), hipMemcpyDeviceToHost,
                                   ctx->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&err, ctx->err, sizeof(err), hipMemcpyDeviceToHost, ctx->stream);
@@ -1220,6 +1262,27 @@ lbm_status lbm_observables(lbm_ctx *ctx, double out[7]) {
         finite = finite && isfinite(host[k]);
     }
     return (finite && err == 0) ? LBM_OK : LBM_E_NONFINITE;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_observables(lbm_ctx *ctx, double out[7]) {
+    if (!ctx || !out) return LBM_E_INVAL;
+    return observables_into(ctx, ctx->partials, ctx->result, out);
+}
+
+lbm_status lbm_observables_noalloc(lbm_ctx *ctx, double out[7]) {
+    if (!ctx || !out) return LBM_E_INVAL;
+    // the reduction runs over a fixed grid whatever the box or particle count,
+    // so every context fits the array
+    static_assert(kNoAllocDoubles >= size_t(kRedBlocks) * 4 + 7, "scratch too small");
+    // the kernels run on the context's device, with that device's copy
+    if (current_device() != ctx->device) return LBM_E_STATE;
+    double *s = noalloc_scratch(ctx->device);
+    if (!s) return LBM_E_DEVICE;
+    return observables_into(ctx, s, s + size_t(kRedBlocks) * 4, out);
 }
 
 lbm_status lbm_profile_enable(lbm_ctx *ctx, int32_t enable) {

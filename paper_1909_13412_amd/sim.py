@@ -286,6 +286,16 @@ class Lattice(_StreamOrder):
         _abi.check("lbm_observables", code, allow=(4,) if allow_nonfinite else ())
         return out
 
+    def observables_noalloc(self, allow_nonfinite: bool = False) -> np.ndarray:
+        """The same sums through lbm_observables_noalloc (the library's own
+        fixed device array instead of the context's scratch)."""
+        self._after_caller()
+        out = np.zeros(7)
+        code = self.lib.lbm_observables_noalloc(self.ctx,
+                                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        _abi.check("lbm_observables_noalloc", code, allow=(4,) if allow_nonfinite else ())
+        return out
+
     def profile_enable(self, enable: bool = True):
         _abi.check("lbm_profile_enable", self.lib.lbm_profile_enable(self.ctx, int(bool(enable))))
 
