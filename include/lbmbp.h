@@ -112,25 +112,35 @@ typedef struct lbm_particle_desc {
 typedef struct lbm_ctx lbm_ctx;
 
 /* Bytes of ONE population lattice (the library uses two, A and B, swapped every
- * step): Q x nx x ny x nz elements rounded up to 256 bytes; the caller only
- * allocates this many bytes. */
+ * step): Q x nx x ny x nz elements (the Q distribution functions per node of
+ * Eq. s2-lbe, section 2.2) rounded up to 256 bytes; the caller only allocates
+ * this many bytes. */
 lbm_status lbm_lattice_bytes(const lbm_grid_desc *grid, size_t *bytes);
 
-/* Bytes of grid scratch: two node-force fields (24 bytes per node each) with
- * their one-bit flags, reduction partials and flags. */
+/* Bytes of grid scratch: two node-force fields (24 bytes per node each: the
+ * reaction force of the first Eq. s2-force, section 2.1) with their one-bit
+ * flags, reduction partials and flags. */
 lbm_status lbm_grid_scratch_bytes(const lbm_grid_desc *grid, size_t *bytes);
 
 /* Bytes of particle scratch for n particles (corner bookkeeping, last-step
  * forces, the pair-force cell list). */
 lbm_status lbm_particle_scratch_bytes(const lbm_grid_desc *grid, int32_t n, size_t *bytes);
 
-/* Bytes of the VACF origin store for n particles: (max_lag/stride + 1) * n * 3 doubles. */
+/* Bytes of the VACF origin store for n particles: (max_lag/stride + 1) * n * 3
+ * doubles (the velocities V(0) of C_v(t) = <V(0).V(t)>, section 2.1). */
 lbm_status lbm_vacf_origin_bytes(int32_t n, int32_t max_lag, int32_t stride, size_t *bytes);
 
-/* Create a context on the current HIP device.  pop_a, pop_b: device buffers of
- * lbm_lattice_bytes each, 256-byte aligned.  grid_scratch: lbm_grid_scratch_bytes,
- * 256-byte aligned.  stream: hipStream_t or NULL.  Enqueues the rest state
- * f = w (rho = 1, u = 0) and clears the scratch.  *out receives the context. */
+/* Create a context on the current HIP device for the lattice-Boltzmann fluid of
+ * section 2.2: a periodic box of nx x ny x nz nodes, BGK relaxation time tau
+ * (Eq. s2-collision; kinematic viscosity nu = (tau - 1/2)/3, Eq. s2-ident3).
+ * pop_a, pop_b: device buffers of lbm_lattice_bytes each, 256-byte aligned.
+ * grid_scratch: lbm_grid_scratch_bytes, 256-byte aligned.  stream: hipStream_t
+ * or NULL.  Enqueues the rest state f = f^eq(rho~ = 1, u = 0) = w (Eq. s2-eq)
+ * and clears the scratch.  *out receives the context.  LBM_E_INVAL for a bad
+ * descriptor (tau <= 1/2 or not finite, a side below 2, nx ny nz >= 2^31, an
+ * unknown storage or velocity set, f16_scale_log2 outside 0..24 for F16,
+ * reserved != 0), a null or misaligned buffer, or pop_a == pop_b;
+ * LBM_E_DEVICE if the clears cannot be enqueued. */
 lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *grid_scratch,
                     void *stream, lbm_ctx **out);
 
@@ -138,7 +148,9 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
  * NULL for 1; u: device FP64 [3][nz][ny][nx] or NULL for 0. */
 lbm_status lbm_set_equilibrium(lbm_ctx *ctx, const double *rho, const double *u);
 
-/* Load the post-streaming populations f^n from device FP64 [Q][nz][ny][nx]. */
+/* Load the post-streaming populations f^n (the f_alpha(x, t) of Eq. s2-trans,
+ * section 2.2) from device FP64 [Q][nz][ny][nx]; stored as g = f - w, rounded
+ * to the storage. */
 lbm_status lbm_set_populations(lbm_ctx *ctx, const double *f);
 
 /* Uniform body force G (host array of 3 doubles, force per node in lattice
@@ -148,17 +160,29 @@ lbm_status lbm_set_populations(lbm_ctx *ctx, const double *f);
  * fluid momentum grows by G per node per step. */
 lbm_status lbm_set_body_force(lbm_ctx *ctx, const double *g);
 
-/* Decode the post-streaming populations f^n into device FP64 [Q][nz][ny][nx]. */
+/* Decode the post-streaming populations f^n (Eq. s2-trans, section 2.2) into
+ * device FP64 [Q][nz][ny][nx], f = w + g. */
 lbm_status lbm_get_populations(lbm_ctx *ctx, double *f);
 
 /* Moments of f^n (Eqs. s2-density, s2-fv) into device FP64 rho [nz][ny][nx]
  * (may be NULL) and u [3][nz][ny][nx] (may be NULL). */
 lbm_status lbm_get_moments(lbm_ctx *ctx, double *rho, double *u);
 
-/* Attach (or replace) the particle set.  r, v: device FP64 [n][3]; the library
- * updates them in place every step (r is kept unwrapped).  particle_scratch:
- * lbm_particle_scratch_bytes(grid, n), 256-byte aligned.  Clears forced-node
- * state and detaches any VACF configuration.  n = 0 detaches all particles. */
+/* Attach (or replace) the point particles of section 2.1: mass M, friction
+ * constant gamma (radius R from Stokes' law gamma = 6 pi rho0 nu R unless
+ * given), temperature kT.  Every later step couples them to the fluid: the
+ * friction F_H from the Stokeslet fit to the fluid velocity at the eight
+ * nodes around each particle (Eq. s2-slet-v with Eq. s2-dis1; or the models
+ * named by desc->friction), the random force F_R of Eqs. s2-rf1, s2-rf2, the
+ * Langevin update of Eqs. s2-langevin, s2-langevin2, and the reaction force
+ * -F_H spread back to those nodes (first Eq. s2-force).  r, v: device FP64
+ * [n][3]; the library updates them in place every step (r is kept
+ * unwrapped).  particle_scratch: lbm_particle_scratch_bytes(grid, n), 256-byte
+ * aligned.  Clears forced-node state and detaches any VACF configuration.
+ * n = 0 detaches all particles.  LBM_E_INVAL for a bad descriptor (n outside
+ * 0..2^24, M <= 0, gamma < 0, kT < 0, a non-finite M, gamma, kT or radius, an
+ * unknown friction model, reserved != 0), or, with n > 0, a null r or v or a
+ * null or misaligned particle_scratch. */
 lbm_status particles_couple(lbm_ctx *ctx, const lbm_particle_desc *desc, double *r, double *v,
                             void *particle_scratch);
 
@@ -206,11 +230,14 @@ double lbm_particle_radius(const lbm_ctx *ctx);
 #define LBM_WARN_VOLUME_FRACTION 4u
 lbm_status lbm_warnings(const lbm_ctx *ctx, uint32_t *flags);
 
-/* Copy the friction F_H and random force F_R of the most recent step into
- * device FP64 [n][3] buffers (either may be NULL). */
+/* Copy the friction F_H (Eq. s2-slet-v, section 2.1) and random force F_R
+ * (Eqs. s2-rf1, s2-rf2) of the most recent step into device FP64 [n][3]
+ * buffers (either may be NULL). */
 lbm_status lbm_particle_forces(lbm_ctx *ctx, double *fh, double *fr);
 
-/* Start accumulating C_i(l) = sum over origins t0 of V_i(t0).V_i(t0 + l), for
+/* The velocity autocorrelation C_v(t) = <V(0).V(t)> of section 2.1 (the
+ * quantity of Figs. 2 and 3, section 3), per particle.  Start accumulating
+ * C_i(l) = sum over origins t0 of V_i(t0).V_i(t0 + l), for
  * lags 0..max_lag, origins every `stride` steps counted from this call;
  * V sampled before each step's update.  acc: device FP64 [max_lag+1][n]
  * (lag-major: C_i(l) at acc[l * n + i]), zeroed here.  origins: device buffer of lbm_vacf_origin_bytes.  Requires
@@ -222,12 +249,21 @@ lbm_status lbm_vacf_config(lbm_ctx *ctx, int32_t max_lag, int32_t stride, double
  * far (the same for every particle). */
 lbm_status lbm_vacf_counts(const lbm_ctx *ctx, int64_t *cnt);
 
-/* Advance nsteps coupled steps (asynchronous).  Per step: one particle kernel
- * (VACF sample if configured, gather, fit, random force, spreading, Langevin
- * update), then the fused stream-collide with the forcing. */
+/* Advance nsteps coupled steps (asynchronous).  Step n: the fluid velocity
+ * u = sum e f of the post-streaming f^n at the eight nodes around each
+ * particle (Eq. s2-fv), the Stokeslet fit and friction F_H (Eq. s2-slet-v,
+ * Eq. s2-dis1), the random force F_R (Eqs. s2-rf1, s2-rf2), the reaction
+ * force -F_H spread to the same nodes (first Eq. s2-force); then at every
+ * node the moments (Eqs. s2-density, s2-fv), BGK relaxation to the
+ * equilibrium (Eqs. s2-collision, s2-eq) with the forcing term (second Eq.
+ * s2-force, Eq. s2-coll) and streaming (Eq. s2-trans); and the Langevin
+ * update of the particles (Eqs. s2-langevin, s2-langevin2, dt = 1), with the
+ * VACF sample of V^n when configured.  LBM_E_INVAL for nsteps < 0;
+ * LBM_E_DEVICE if a launch fails. */
 lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps);
 
-/* Record FP64 sums during lbm_step without extra passes over the lattice:
+/* Record the FP64 sums of lbm_observables (Eqs. s2-density, s2-fv; particle
+ * momentum M V) during lbm_step without extra passes over the lattice:
  * every `every` steps, starting with the next step, series[8k .. 8k+7] =
  * {step, fluid mass sum rho~, fluid momentum sum u (3), particle momentum
  * sum M V (3)} of the state at the start of that step, for k < capacity
@@ -240,8 +276,9 @@ lbm_status lbm_series_config(lbm_ctx *ctx, int32_t every, double *series, int64_
 /* Number of series entries recorded since lbm_series_config. */
 lbm_status lbm_series_count(const lbm_ctx *ctx, int64_t *count);
 
-/* Synchronous FP64 sums over the current state: out[0] fluid mass sum rho~,
- * out[1..3] fluid momentum sum u, out[4..6] particle momentum sum M V.
+/* Synchronous FP64 sums over the current state: out[0] fluid mass sum rho~
+ * (Eq. s2-density), out[1..3] fluid momentum sum u (Eq. s2-fv; with rho0 = 1
+ * it is the momentum), out[4..6] particle momentum sum M V (Eq. s2-langevin).
  * Returns LBM_E_NONFINITE (after filling out) if any value is not finite or a
  * node force left the fixed-point range since the last call. */
 lbm_status lbm_observables(lbm_ctx *ctx, double out[7]);
@@ -261,7 +298,8 @@ lbm_status lbm_observables(lbm_ctx *ctx, double out[7]);
  * obtained at lbm_init.  Other results as lbm_observables. */
 lbm_status lbm_observables_noalloc(lbm_ctx *ctx, double out[7]);
 
-/* Per-kernel GPU timing with HIP events recorded on the context's stream.
+/* Measurement only (no part of the method).  Per-kernel GPU timing with HIP
+ * events recorded on the context's stream.
  * enable = 1 brackets every particle-phase launch (VACF sample + particle
  * coupling) and every stream-collide launch of lbm_step with start/stop
  * events (host-side event objects only, no device memory); enable = 0 stops. */
@@ -272,7 +310,9 @@ lbm_status lbm_profile_enable(lbm_ctx *ctx, int32_t enable);
  * out[2] summed particle-phase milliseconds, out[3] particle-phase launches. */
 lbm_status lbm_profile_read(lbm_ctx *ctx, double out[4]);
 
-/* Stream-collide launch configurations k = 0..9.  For k < 8, lanes take
+/* Launch configurations of the stream-collide (section 2.2, Eqs. s2-coll and
+ * s2-trans): they change how lanes map to nodes, never the result (every
+ * configuration gives the same bits).  k = 0..9.  For k < 8, lanes take
  * consecutive nodes and k & 3 is the geometric shape: 0 = one node per lane,
  * 512-lane blocks; 1 = one node, 256; 2 = two nodes (rows y and y + ny/2),
  * 512; 3 = two nodes, 256 (2 and 3 need an even ny); k >= 4 writes the
@@ -321,10 +361,11 @@ lbm_status lbm_set_shape(lbm_ctx *ctx, int32_t k);
 /* The launch configuration later lbm_step calls use. */
 lbm_status lbm_get_shape(const lbm_ctx *ctx, int32_t *k);
 
-/* Number of steps taken since lbm_init. */
+/* Number of steps taken since lbm_init (the time index n of Eq. s2-lbe). */
 lbm_status lbm_get_step(const lbm_ctx *ctx, int64_t *step);
 
-/* Release the context (host memory only; device buffers stay the caller's). */
+/* Release the context (host memory only; device buffers stay the caller's).
+ * Bookkeeping, no part of the method. */
 lbm_status lbm_destroy(lbm_ctx *ctx);
 
 /* ---------------------------------------------------------------------------
@@ -462,7 +503,7 @@ lbm_status lbm_ens_get_step(const lbm_ens *ens, int64_t *step);
 lbm_status lbm_ens_graph_replays(const lbm_ens *ens, int64_t *replays);
 lbm_status lbm_ens_destroy(lbm_ens *ens);
 
-/* Static string for a status code. */
+/* Static string for a status code (bookkeeping). */
 const char *lbm_status_string(lbm_status status);
 
 #ifdef __cplusplus
