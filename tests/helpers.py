@@ -80,3 +80,23 @@ def pulled(a, nx, ny, nz):
     for k, (ex, ey, ez) in enumerate(E19):
         out[:, :, k, :] = np.roll(a[:, :, k, :], shift=(ez, ey, ex), axis=(0, 1, 2))
     return out
+
+
+def rounding_pin(g_gpu, g_exact, rnd, delta):
+    """One step of a 16-bit storage against the oracle's exact step.
+
+    The GPU computes g in FP32 and rounds it to the storage with `rnd`
+    (to nearest, ties to even), so what it stores is rnd(x) for some x with
+    |x - g_exact| <= delta, delta bounding the FP32 arithmetic's error.
+    Rounding is monotonic, so every stored value must lie in
+    [rnd(g_exact - delta), rnd(g_exact + delta)]: the rounded oracle value,
+    or, where the FP32 result falls on the other side of a rounding boundary,
+    its neighbour (near zero, where the format's spacing is finer than delta,
+    possibly a few neighbours).  Returns (fraction of stored values that differ
+    from rnd(g_exact), number outside the bracket)."""
+    g_want = rnd(g_exact)
+    miss = g_gpu != g_want
+    lo = rnd(g_exact[miss] - delta)
+    hi = rnd(g_exact[miss] + delta)
+    outside = int(np.sum((g_gpu[miss] < lo) | (g_gpu[miss] > hi)))
+    return float(miss.sum() / max(g_exact.size, 1)), outside

@@ -8,7 +8,7 @@ positions.
 import numpy as np
 import pytest
 
-from helpers import announce, nmax_err, pulled, run_pair
+from helpers import announce, nmax_err, pulled, rounding_pin, run_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -361,6 +361,80 @@ def test_suspension512_tiled_against_oracle(oracle_mod):
             assert np.array_equal(first[2], vg[0])
         del rho_g, u_g, rv, uv
     del g, rho_d, u_d
+    torch.cuda.empty_cache()
+
+
+def test_suspension512_tiled_bf16_one_step_pinned_to_rounding(oracle_mod):
+    # The BF16 instance at full size (19 x 512^3 elements), every node: a 32^3
+    # perturbed state whose shifted populations are rounded to BF16 (so the
+    # storage holds it exactly) is tiled 16^3 times, with one particle at the
+    # same dyadic place in every tile (4096 in all).  After one step every
+    # tile must hold the same bits, and tile 0's stored post-collision values
+    # must be BF16 roundings (to nearest, ties to even) of values within the
+    # FP32 arithmetic's error bound of the oracle's FP64 step on the 32^3
+    # tile, all but a fraction 2e-3 the rounding of the oracle's value
+    # itself; in every non-temporal launch configuration.
+    import torch
+
+    from paper_1909_13412_amd import Lattice
+    from paper_1909_13412_amd.inputs import WORKLOADS, perturbed_fields
+
+    w = WORKLOADS["suspension512"]
+    T, K = 32, 16
+    L = T * K
+    e, wts = oracle_mod.lattice(19)
+    wq = wts[:, None, None, None]
+    rho_t, u_t = perturbed_fields((T, T, T), seed=52, amp_rho=1e-3, amp_u=1e-3)
+    p0 = np.array([13.25, 7.8125, 21.625])
+    v0 = np.array([[2e-4, -1e-4, 5e-5]])
+    kw = dict(mass=w["mass"], gamma=w["gamma"], kT=0.0, radius=w["radius"], seed=w["seed"])
+    ref = oracle_mod.Sim(T, T, T, w["tau"])
+    ref.set_equilibrium(rho_t, u_t)
+    f0 = wq + _bf16_nearest_even(ref.populations() - wq)
+    ref.set_populations(f0)
+    ref.set_particles(p0[None, :], v0, **kw)
+    ref.step(1)
+    g1 = ref.populations() - wq
+    # the stored lattice holds post-collision values at their own node: the
+    # value the oracle streams to x + e_a
+    g_exact = np.stack([np.roll(g1[a], shift=(-e[a, 2], -e[a, 1], -e[a, 0]), axis=(0, 1, 2))
+                        for a in range(19)])
+    # FP32 arithmetic error bound: 64 units in the last place of FP32 at the
+    # largest population
+    delta = 64 * 2.0**-24 * float(np.max(np.abs(g_exact)))
+    v_r = ref.particles()[1][0]
+
+    idx = np.stack(np.meshgrid(np.arange(K), np.arange(K), np.arange(K), indexing="ij"), -1).reshape(-1, 3)
+    r = (T * idx + p0).astype(np.float64)
+    v = np.repeat(v0, len(r), axis=0)
+    announce(f"suspension512 tiled BF16: {L}^3 of {T}^3 tiles, {len(r)} particles, one step")
+    dev = torch.device("cuda")
+    f_d = torch.from_numpy(f0).to(dev).repeat(1, K, K, K)
+    live = g_exact != 0.0
+    for shape in (4, 5, 6, 7, 9):
+        g = Lattice(L, L, L, w["tau"], storage="bf16")
+        g.set_shape(shape)
+        g.set_populations(f_d)
+        g.particles_couple(r, v, **kw)
+        g.step(1)  # the state moves from the first lattice to the second
+        torch.cuda.synchronize()
+        raw = g.pop_b[: 19 * L**3 * 2].view(torch.int16).view(K, T, K, T, 19, K, T)
+        same = bool(torch.equal(raw, raw[:1, :, :1, :, :, :1, :].expand_as(raw)))
+        tile = raw[0, :, 0, :, :, 0, :].contiguous().view(torch.bfloat16).double().cpu().numpy()
+        g_gpu = tile.transpose(2, 0, 1, 3)  # [a][z][y][x]
+        frac, outside = rounding_pin(g_gpu, g_exact, _bf16_nearest_even, delta)
+        vg = g.v.cpu().numpy()
+        e_v = nmax_err(vg[0], v_r)
+        announce(f"  shape {shape}: tiles identical {same}; tile 0: a fraction {frac:.1e} of the "
+                 f"populations differ from the rounded oracle, {outside} outside the FP32 "
+                 f"bracket; v {e_v:.2e}")
+        assert same
+        assert live.sum() > 0.9 * g_exact.size
+        assert frac < 2e-3 and outside == 0
+        assert e_v < 1e-10 and np.array_equal(vg, np.repeat(vg[:1], len(vg), axis=0))
+        del raw, g
+        torch.cuda.empty_cache()
+    del f_d
     torch.cuda.empty_cache()
 
 
@@ -777,10 +851,13 @@ def test_every_launch_configuration_is_bit_identical():
     for L in ((40, 24, 16), (130, 6, 8), (300, 6, 5)):
         r = particle_positions(9, L, seed=31)
         v = particle_velocities(9, 1e-5, seed=31)
-        for storage in ("f32", "bf16"):
+        # every storage x velocity-set instance the library builds and the
+        # benchmark times
+        for storage, q in (("f32", 19), ("bf16", 19), ("f64", 19), ("f16", 19), ("f32", 15),
+                           ("bf16", 15)):
             ref, sums = None, {}
             for k in range(_abi.LBM_NUM_SHAPES):
-                lat = Lattice(*L, 0.7, storage=storage)
+                lat = Lattice(*L, 0.7, storage=storage, velocities=q)
                 lat.particles_couple(r, v, kT=1e-4, seed=8)
                 lat.series_config(3, 8)
                 lat.set_shape(k)
@@ -791,14 +868,14 @@ def test_every_launch_configuration_is_bit_identical():
                 if ref is None:
                     ref = (f.clone(), lat.v.clone(), ser)
                 else:
-                    assert torch.equal(f, ref[0]), (L, storage, k)
-                    assert torch.equal(lat.v, ref[1]), (L, storage, k)
+                    assert torch.equal(f, ref[0]), (L, storage, q, k)
+                    assert torch.equal(lat.v, ref[1]), (L, storage, q, k)
                     # FP64 sums: per-block partials follow the lane mapping, so
                     # only the same mapping reproduces them bit for bit
-                    assert np.allclose(ser, ref[2], rtol=1e-12, atol=1e-15), (L, storage, k)
+                    assert np.allclose(ser, ref[2], rtol=1e-12, atol=1e-15), (L, storage, q, k)
                 key = "row" if k >= 8 else k & 3
                 if key in sums:
-                    assert np.array_equal(ser, sums[key]), (L, storage, k)
+                    assert np.array_equal(ser, sums[key]), (L, storage, q, k)
                 sums[key] = ser
     lat = Lattice(9, 7, 5, 0.7)
     with pytest.raises(Exception):
