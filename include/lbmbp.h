@@ -327,16 +327,20 @@ lbm_status lbm_profile_read(lbm_ctx *ctx, double out[4]);
  * non-temporal stores when one lattice is at least 256 MiB. */
 #define LBM_NUM_SHAPES 10
 
-/* Time every valid stream-collide configuration on this context's lattice (iters
+/* Time the stream-collide's launch options on this context's lattice (iters
  * launches each, reading the current populations and writing the spare
  * lattice, so the simulation state is not changed) and keep the fastest for
- * later lbm_step calls.  Synchronises the stream.  ms (host, LBM_NUM_SHAPES
- * entries, may be NULL) receives the mean milliseconds per launch (-1 for a
- * configuration that does not apply, or that repeats another's lane mapping
- * exactly: 8 and 9 when 64 | nx and nx divides 256 or 256 divides nx); *chosen
- * (may be NULL) the configuration kept.  The choice
- * is also remembered for contexts created later with the same device, storage,
- * velocity set and box size (process lifetime, thread-safe). */
+ * later lbm_step calls: first every valid configuration in linear block order
+ * without a residency cap, then the two fastest of them with every block
+ * order and residency cap (lbm_set_sweep_launch).  Synchronises the stream.
+ * ms (host, LBM_NUM_SHAPES entries, may be NULL) receives per configuration
+ * the best mean milliseconds per launch over the options timed with it (-1
+ * for a configuration that does not apply, or that repeats another's lane
+ * mapping exactly: 8 and 9 when 64 | nx and nx divides 256 or 256 divides
+ * nx); *chosen (may be NULL) the configuration kept (lbm_get_sweep_launch
+ * gives its block order and cap).  The choice is also remembered for
+ * contexts created later with the same device, storage, velocity set and box
+ * size (process lifetime, thread-safe). */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen);
 
 /* Ceiling of the stream-collide's data movement (the pull streaming of the
@@ -344,7 +348,8 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen
  * receives the mean milliseconds per launch, over iters (1..10000) launches
  * after two warm-up launches, of a kernel that pulls every population from
  * x - e_a and stores it unchanged at x, with the layout, lane mapping and store
- * policy of launch configuration k (k < 0: the context's current one).  The
+ * policy of launch configuration k (k < 0: the context's current one) and the
+ * context's block order and residency cap.  The
  * stream-collide moves the same bytes the same way, so its duration over this
  * one is the fraction of the access pattern's ceiling it reaches.  Reads the
  * current populations and overwrites the spare lattice (as lbm_autotune does):
@@ -360,6 +365,22 @@ lbm_status lbm_set_shape(lbm_ctx *ctx, int32_t k);
 
 /* The launch configuration later lbm_step calls use. */
 lbm_status lbm_get_shape(const lbm_ctx *ctx, int32_t *k);
+
+/* Two more launch options of the stream-collide, neither of which changes a
+ * bit of the result (the same node updates, the same per-block sums):
+ *   order: 0 = blocks in node order; 1 = per-XCD slabs: the GPU hands
+ *     consecutive workgroups to its eight XCDs in turn, and order 1 renumbers
+ *     them so that XCD k sweeps the k-th contiguous eighth of the blocks;
+ *   waves_per_simd: residency cap, 0 (none), 6, 5, 4, 3 or 2 waves per SIMD,
+ *     imposed by reserving LDS the kernel does not use, so that fewer blocks
+ *     (and fewer concurrent row streams) share a compute unit.
+ * lbm_autotune chooses both; until then a context starts from the last
+ * choice for its key, else order 0 without a cap.  LBM_E_INVAL for an order
+ * or cap outside these values, or a cap the device's LDS cannot impose for
+ * the current configuration's block size (lbm_set_shape drops a cap that
+ * does not fit the new configuration). */
+lbm_status lbm_set_sweep_launch(lbm_ctx *ctx, int32_t order, int32_t waves_per_simd);
+lbm_status lbm_get_sweep_launch(const lbm_ctx *ctx, int32_t *order, int32_t *waves_per_simd);
 
 /* Number of steps taken since lbm_init (the time index n of Eq. s2-lbe). */
 lbm_status lbm_get_step(const lbm_ctx *ctx, int64_t *step);

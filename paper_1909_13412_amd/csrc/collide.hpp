@@ -214,13 +214,32 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
 // Lanes per row of the row-aligned mapping: nx rounded up to whole wavefronts.
 __host__ __device__ inline uint32_t row_lanes(uint32_t nx) { return (nx + 63u) & ~63u; }
 
+// Block orders of the sweep.  The hardware hands consecutive workgroups to
+// the eight XCDs in turn (workgroup b to XCD b mod 8).  Order 0 maps block b
+// to the b-th block of nodes, so every XCD works across the whole front of
+// the sweep; order 1 gives XCD k the k-th contiguous eighth of the blocks (a
+// slab of z-planes), so the eight XCDs sweep eight separate regions at once.
+// Both are permutations of the blocks (the last gridDim.x mod 8 blocks keep
+// their place), so the nodes updated and the results are the same.
+constexpr uint32_t kOrderLinear = 0;
+constexpr uint32_t kOrderXcdSlabs = 1;
+constexpr uint32_t kNumOrders = 2;
+constexpr uint32_t kXcds = 8;
+
+__device__ inline uint32_t sweep_block(uint32_t order) {
+    const uint32_t b = blockIdx.x;
+    if (order != kOrderXcdSlabs) return b;
+    const uint32_t per = gridDim.x / kXcds;
+    return b < per * kXcds ? (b % kXcds) * per + b / kXcds : b;
+}
+
 // The node of this lane (in the first row band when CPT = 2); false for lanes
 // without one.  ROW: lanes map to whole rows (every row starts a wavefront: a
 // block of BS lanes holds BS / row_lanes rows, or a row spans several blocks),
 // so no wave straddles two rows when nx is not a multiple of 64; otherwise
 // lanes map to consecutive nodes (rows y and y + ny/CPT for CPT = 2).
 template <int CPT, int BS, bool ROW>
-__device__ inline bool lane_node(const Grid &g, uint32_t &lane_cell) {
+__device__ inline bool lane_node(const Grid &g, uint32_t blk, uint32_t &lane_cell) {
     if constexpr (ROW) {
         static_assert(CPT == 1, "the row-aligned mapping takes one node per lane");
         const uint32_t lpr = row_lanes(g.nx);
@@ -230,17 +249,17 @@ __device__ inline bool lane_node(const Grid &g, uint32_t &lane_cell) {
             const uint32_t rpb = uint32_t(BS) / lpr;  // rows per block
             const uint32_t slot = threadIdx.x / lpr;
             in_rows = slot < rpb;
-            row = blockIdx.x * rpb + slot;
+            row = blk * rpb + slot;
             x = threadIdx.x % lpr;
         } else {
             const uint32_t bpr = (lpr + BS - 1) / BS;  // blocks per row
-            row = blockIdx.x / bpr;
-            x = (blockIdx.x % bpr) * BS + threadIdx.x;
+            row = blk / bpr;
+            x = (blk % bpr) * BS + threadIdx.x;
         }
         lane_cell = row * g.nx + x;
         return in_rows && x < g.nx && row < g.ny * g.nz;
     } else {
-        lane_cell = blockIdx.x * BS + threadIdx.x;
+        lane_cell = blk * BS + threadIdx.x;
         return lane_cell < g.ncell / CPT;
     }
 }
@@ -251,9 +270,11 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
                                                        typename C::R omega, typename C::R enc_s,
                                                        typename C::R dec_s, ForceField ff,
                                                        typename C::R Gx, typename C::R Gy,
-                                                       typename C::R Gz, double *__restrict__ mom) {
+                                                       typename C::R Gz, double *__restrict__ mom,
+                                                       uint32_t order) {
+    const uint32_t blk = sweep_block(order);
     uint32_t lane_cell;
-    const bool active = lane_node<CPT, BS, ROW>(g, lane_cell);
+    const bool active = lane_node<CPT, BS, ROW>(g, blk, lane_cell);
     if constexpr (!MOMENTS) {
         if (!active) return;
     }
@@ -261,7 +282,8 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
     if (active)
         collide_lane<C, FORCED, MOMENTS, CPT, NTS>(A, B, g, omega, enc_s, dec_s, ff, Gx, Gy, Gz,
                                                    lane_cell, acc);
-    if constexpr (MOMENTS) block_sum<4, BS>(acc, mom + 4 * uint64_t(blockIdx.x));
+    // partials by node block, so that every block order gives the same sums
+    if constexpr (MOMENTS) block_sum<4, BS>(acc, mom + 4 * uint64_t(blk));
 }
 
 // The stream-collide's data movement alone, for the nodes of one lane (as in
@@ -306,9 +328,10 @@ __device__ inline void stream_only_lane(const typename C::T *__restrict__ A,
 // NTS, ROW> (same lanes).
 template <class C, int CPT, int BS, bool NTS, bool ROW>
 __global__ __launch_bounds__(BS) void k_stream_only(const typename C::T *__restrict__ A,
-                                                    typename C::T *__restrict__ B, Grid g) {
+                                                    typename C::T *__restrict__ B, Grid g,
+                                                    uint32_t order) {
     uint32_t lane_cell;
-    if (!lane_node<CPT, BS, ROW>(g, lane_cell)) return;
+    if (!lane_node<CPT, BS, ROW>(g, sweep_block(order), lane_cell)) return;
     stream_only_lane<C, CPT, NTS>(A, B, g, lane_cell);
 }
 
@@ -326,7 +349,16 @@ constexpr int kNumFlatShapes = 2 * kNumGeomShapes;
 constexpr int kNumShapes = kNumFlatShapes + 2;
 constexpr int kRowBlock = 256;
 constexpr bool config_row(int k) { return k >= kNumFlatShapes; }
+// Lanes per block of configuration k.
+constexpr int config_block(int k) { return config_row(k) ? kRowBlock : kShapes[k & 3].bs; }
 // Lattices of at least this many bytes default to non-temporal stores.
 constexpr size_t kStreamStoreBytes = size_t(256) << 20;
+
+// Residency caps of the sweep, in waves per SIMD (0: none, the kernel's own
+// limit).  A cap is imposed by reserving LDS the kernel never touches, so
+// that only cap * 256 / BS blocks fit on a compute unit; fewer concurrent
+// blocks means fewer concurrent row streams per memory channel.
+constexpr int kResidencyCaps[] = {0, 6, 5, 4, 3, 2};
+constexpr int kNumCaps = 6;
 
 }  // namespace lbmbp

@@ -377,6 +377,9 @@ struct lbm_ctx {
     int32_t *prof_kind;     // per pair: 0 stream-collide, 1 particle phase
     int32_t prof_used, prof_cap;
     int shape;   // index into kShapes
+    int order;   // block order of the sweep (kOrderLinear / kOrderXcdSlabs)
+    int cap;     // residency cap of the sweep: index into kResidencyCaps
+    int lds_cu, lds_block;  // LDS bytes per compute unit and per block (device limits)
     int device;  // device current at lbm_init (autotune cache key)
     // recorded observables (lbm_series_config)
     int32_t series_every;
@@ -571,26 +574,52 @@ uint32_t collide_grid(const lbm_ctx *c, int shape) {
     return uint32_t((band + sh.bs - 1) / sh.bs);
 }
 
-template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW>
-void launch_collide_shape(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff,
-                          double *mom, unsigned grid) {
-    using R = typename C::R;
-    hipLaunchKernelGGL((k_stream_collide<C, FORCED, MOMENTS, CPT, BS, NTS, ROW>), dim3(grid), dim3(BS),
-                       0, c->stream, A, B, c->g, R(c->omega), R(c->enc_s), R(c->dec_s), ff,
-                       R(c->body[0]), R(c->body[1]), R(c->body[2]), mom);
+// Dynamic LDS that caps the sweep at kResidencyCaps[cap] waves per SIMD for
+// blocks of bs lanes (0: no cap); -1 if the device cannot impose that cap.
+// The kernels never touch it: it only keeps further blocks off the unit.
+// Up to 1 KiB of the unit is left for the kernels' own LDS.
+long residency_lds(int lds_cu, int lds_block, int cap, int bs) {
+    const int waves = kResidencyCaps[cap];
+    if (waves == 0) return 0;
+    // bs / 64 waves per block over the unit's four SIMDs: `blocks` resident
+    // blocks give blocks * bs / 256 waves per SIMD
+    const int blocks = waves * 256 / bs;
+    if (blocks < 1 || lds_cu <= 0) return -1;
+    const long per = (long(lds_cu) / blocks - 1024) / 512 * 512;
+    if (per <= 0 || per + 1024 > lds_block) return -1;
+    if (long(blocks + 1) * per <= lds_cu) return -1;  // would not cap
+    return per;
 }
 
-// mom != nullptr: also leave the per-block FP64 moment sums there.
+long sweep_lds(const lbm_ctx *c, int cap, int bs) { return residency_lds(c->lds_cu, c->lds_block, cap, bs); }
+
+template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW>
+void launch_collide_shape(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff,
+                          double *mom, unsigned grid, int order, int cap) {
+    using R = typename C::R;
+    const long lds = sweep_lds(c, cap, BS);
+    hipLaunchKernelGGL((k_stream_collide<C, FORCED, MOMENTS, CPT, BS, NTS, ROW>), dim3(grid), dim3(BS),
+                       lds > 0 ? size_t(lds) : 0, c->stream, A, B, c->g, R(c->omega), R(c->enc_s),
+                       R(c->dec_s), ff, R(c->body[0]), R(c->body[1]), R(c->body[2]), mom,
+                       uint32_t(order));
+}
+
+// mom != nullptr: also leave the per-block FP64 moment sums there.  order,
+// cap: block order and residency cap (-1: the context's).
 template <class C, bool FORCED>
 void launch_collide(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff, int shape,
-                    double *mom = nullptr) {
+                    double *mom = nullptr, int order = -1, int cap = -1) {
     const unsigned grid = collide_grid(c, shape);
-#define LBM_SHAPE(CPT, BS, NTS, ROW)                                                          \
-    do {                                                                                      \
-        if (mom)                                                                              \
-            launch_collide_shape<C, FORCED, true, CPT, BS, NTS, ROW>(c, A, B, ff, mom, grid);  \
-        else                                                                                  \
-            launch_collide_shape<C, FORCED, false, CPT, BS, NTS, ROW>(c, A, B, ff, mom, grid); \
+    if (order < 0) order = c->order;
+    if (cap < 0) cap = c->cap;
+#define LBM_SHAPE(CPT, BS, NTS, ROW)                                                           \
+    do {                                                                                       \
+        if (mom)                                                                               \
+            launch_collide_shape<C, FORCED, true, CPT, BS, NTS, ROW>(c, A, B, ff, mom, grid,    \
+                                                                     order, cap);              \
+        else                                                                                   \
+            launch_collide_shape<C, FORCED, false, CPT, BS, NTS, ROW>(c, A, B, ff, mom, grid,   \
+                                                                      order, cap);             \
     } while (0)
     LBM_CONFIG_SWITCH(shape, LBM_SHAPE)
 #undef LBM_SHAPE
@@ -725,12 +754,14 @@ void launch_step(lbm_ctx *c) {
     c->step += 1;
 }
 
-// Times every valid stream-collide shape on A -> B without swapping (the
-// simulation state in A is untouched; B is the next step's output anyway).
-// With particles attached the forced variant is timed, reading the node
-// forces of the last step (still in place until the next particle kernel).
+// Times stream-collide launches on A -> B without swapping (the simulation
+// state in A is untouched; B is the next step's output anyway): ms[j] for
+// the launch (ks[j], orders[j], caps[j]), -1 where it does not apply.  With
+// particles attached the forced variant is timed, reading the node forces of
+// the last step (still in place until the next particle kernel).
 template <class C>
-void time_shapes(lbm_ctx *c, int32_t iters, double *ms, hipError_t *err) {
+void time_launches(lbm_ctx *c, int32_t iters, int n, const int *ks, const int *orders,
+                   const int *caps, double *ms, hipError_t *err) {
     using T = typename C::T;
     const T *A = static_cast<const T *>(c->pop[c->cur]);
     T *B = static_cast<T *>(c->pop[c->cur ^ 1]);
@@ -740,39 +771,46 @@ void time_shapes(lbm_ctx *c, int32_t iters, double *ms, hipError_t *err) {
     if (*err != hipSuccess) return;
     const bool forced = c->np > 0;
     const ForceField last = field(c, int((c->step + 1) & 1));
-    auto launch = [&](int k) {
-        if (forced)
-            launch_collide<C, true>(c, A, B, last, k);
-        else
-            launch_collide<C, false>(c, A, B, last, k);
-    };
-    for (int k = 0; k < kNumShapes && *err == hipSuccess; ++k) {
-        ms[k] = -1.0;
+    for (int j = 0; j < n && *err == hipSuccess; ++j) {
+        const int k = ks[j], order = orders[j], cap = caps[j];
+        ms[j] = -1.0;
         if (!shape_ok(c, k) || (config_row(k) && row_mapping_is_flat(c->g.nx))) continue;
-        for (int w = 0; w < 2; ++w) launch(k);
+        if (sweep_lds(c, cap, config_block(k)) < 0) continue;
+        auto launch = [&]() {
+            if (forced)
+                launch_collide<C, true>(c, A, B, last, k, nullptr, order, cap);
+            else
+                launch_collide<C, false>(c, A, B, last, k, nullptr, order, cap);
+        };
+        for (int w = 0; w < 2; ++w) launch();
         (void)hipEventRecord(e0, c->stream);
-        for (int it = 0; it < iters; ++it) launch(k);
+        for (int it = 0; it < iters; ++it) launch();
         (void)hipEventRecord(e1, c->stream);
         *err = hipEventSynchronize(e1);
         float t = 0.0f;
         if (*err == hipSuccess) *err = hipEventElapsedTime(&t, e0, e1);
-        ms[k] = double(t) / iters;
+        ms[j] = double(t) / iters;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
 }
 
-// Mean time per launch of the streaming-only kernel in configuration k, over
-// iters launches (A -> B, as the autotuner's trial launches).
+// Mean time per launch of the streaming-only kernel in configuration k with
+// the context's block order and residency cap, over iters launches (A -> B,
+// as the autotuner's trial launches).
 template <class C>
 void time_stream_only(lbm_ctx *c, int k, int32_t iters, double *ms, hipError_t *err) {
     using T = typename C::T;
     const T *A = static_cast<const T *>(c->pop[c->cur]);
     T *B = static_cast<T *>(c->pop[c->cur ^ 1]);
     const unsigned grid = collide_grid(c, k);
+    const long lds = sweep_lds(c, c->cap, config_block(k));
+    const size_t dyn = lds > 0 ? size_t(lds) : 0;
+    const uint32_t order = uint32_t(c->order);
     auto launch = [&]() {
-#define LBM_STREAM_ONLY(CPT, BS, NTS, ROW) \
-    hipLaunchKernelGGL((k_stream_only<C, CPT, BS, NTS, ROW>), dim3(grid), dim3(BS), 0, c->stream, A, B, c->g)
+#define LBM_STREAM_ONLY(CPT, BS, NTS, ROW)                                                          \
+    hipLaunchKernelGGL((k_stream_only<C, CPT, BS, NTS, ROW>), dim3(grid), dim3(BS), dyn, c->stream, \
+                       A, B, c->g, order)
         LBM_CONFIG_SWITCH(k, LBM_STREAM_ONLY)
 #undef LBM_STREAM_ONLY
     };
@@ -932,10 +970,12 @@ namespace {
 // box: a context or ensemble created later with the same key starts from that
 // choice instead of the size-based default.
 struct TuneKey {
+    int kind;  // 0 single box (its code holds configuration, order and cap), 1 ensemble
     int device, storage, q;
     std::vector<int32_t> dims;  // nx, ny, nz of each box
     bool operator<(const TuneKey &o) const {
-        return std::tie(device, storage, q, dims) < std::tie(o.device, o.storage, o.q, o.dims);
+        return std::tie(kind, device, storage, q, dims) <
+               std::tie(o.kind, o.device, o.storage, o.q, o.dims);
     }
 };
 
@@ -958,8 +998,14 @@ void tune_store(const TuneKey &k, int shape) {
     g_tune[k] = shape;
 }
 
+// A single-box choice is kept as one code: configuration, block order and
+// residency cap (ensembles keep the configuration alone: order 0, no cap).
+int tune_code(int shape, int order, int cap) {
+    return shape + kNumShapes * (order + int(kNumOrders) * cap);
+}
+
 TuneKey ctx_tune_key(const lbm_ctx *c) {
-    return TuneKey{c->device, c->desc.storage, c->q, {c->desc.nx, c->desc.ny, c->desc.nz}};
+    return TuneKey{0, c->device, c->desc.storage, c->q, {c->desc.nx, c->desc.ny, c->desc.nz}};
 }
 
 }  // namespace
@@ -991,7 +1037,17 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
         const int fallback = (grid->nx % 64 != 0 && grid->nx >= 96) ? kNumFlatShapes
                              : lat >= kStreamStoreBytes              ? kNumGeomShapes
                                                                      : 0;
-        c->shape = tune_lookup(ctx_tune_key(c), fallback);
+        const int code = tune_lookup(ctx_tune_key(c), fallback);
+        c->shape = code % kNumShapes;
+        c->order = (code / kNumShapes) % int(kNumOrders);
+        c->cap = code / (kNumShapes * int(kNumOrders));
+        // LDS limits of the device, for the residency caps (none if unknown)
+        int v = 0;
+        c->lds_cu = (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                           c->device) == hipSuccess) ? v : 0;
+        c->lds_block = (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                              c->device) == hipSuccess) ? v : 0;
+        if (sweep_lds(c, c->cap, config_block(c->shape)) < 0) c->cap = 0;
     }
     c->elem = elem_size(grid->storage);
     c->pop[0] = pop_a;
@@ -1310,18 +1366,72 @@ lbm_status lbm_profile_read(lbm_ctx *ctx, double out[4]) {
 
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen) {
     if (!ctx || iters < 1 || iters > 10000) return LBM_E_INVAL;
-    double t[kNumShapes];
+    // Stage 1: every configuration in linear order without a residency cap.
+    int ks[kNumShapes * kNumOrders * kNumCaps], os[kNumShapes * kNumOrders * kNumCaps],
+        cs[kNumShapes * kNumOrders * kNumCaps];
+    double t[kNumShapes * kNumOrders * kNumCaps];
+    for (int k = 0; k < kNumShapes; ++k) ks[k] = k, os[k] = int(kOrderLinear), cs[k] = 0;
     hipError_t err = hipSuccess;
-    LBM_DISPATCH(ctx, time_shapes, iters, t, &err);
+    LBM_DISPATCH(ctx, time_launches, iters, kNumShapes, ks, os, cs, t, &err);
     if (err != hipSuccess || launch_status() != LBM_OK) return LBM_E_DEVICE;
-    int best = 0;
-    for (int k = 0; k < kNumShapes; ++k)
-        if (t[k] > 0.0 && (t[best] <= 0.0 || t[k] < t[best])) best = k;
-    ctx->shape = best;
-    tune_store(ctx_tune_key(ctx), best);
+    double best_k[kNumShapes];
+    for (int k = 0; k < kNumShapes; ++k) best_k[k] = t[k];
+    // Stage 2: the two fastest configurations with every block order and cap.
+    int first = -1, second = -1;
+    for (int k = 0; k < kNumShapes; ++k) {
+        if (t[k] <= 0.0) continue;
+        if (first < 0 || t[k] < t[first]) {
+            second = first;
+            first = k;
+        } else if (second < 0 || t[k] < t[second]) {
+            second = k;
+        }
+    }
+    if (first < 0) return LBM_E_DEVICE;
+    int n = 0;
+    for (int k : {first, second}) {
+        if (k < 0) continue;
+        for (int o = 0; o < int(kNumOrders); ++o)
+            for (int cap = 0; cap < kNumCaps; ++cap) {
+                if (o == int(kOrderLinear) && cap == 0) continue;  // timed in stage 1
+                ks[n] = k, os[n] = o, cs[n] = cap;
+                ++n;
+            }
+    }
+    LBM_DISPATCH(ctx, time_launches, iters, n, ks, os, cs, t, &err);
+    if (err != hipSuccess || launch_status() != LBM_OK) return LBM_E_DEVICE;
+    int bk = first, bo = int(kOrderLinear), bc = 0;
+    double bt = best_k[first];
+    for (int j = 0; j < n; ++j) {
+        if (t[j] <= 0.0) continue;
+        if (t[j] < best_k[ks[j]]) best_k[ks[j]] = t[j];
+        if (t[j] < bt) bt = t[j], bk = ks[j], bo = os[j], bc = cs[j];
+    }
+    ctx->shape = bk;
+    ctx->order = bo;
+    ctx->cap = bc;
+    tune_store(ctx_tune_key(ctx), tune_code(bk, bo, bc));
     if (ms)
-        for (int k = 0; k < kNumShapes; ++k) ms[k] = t[k];
-    if (chosen) *chosen = best;
+        for (int k = 0; k < kNumShapes; ++k) ms[k] = best_k[k];
+    if (chosen) *chosen = bk;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_sweep_launch(lbm_ctx *ctx, int32_t order, int32_t waves_per_simd) {
+    if (!ctx || order < 0 || order >= int32_t(kNumOrders)) return LBM_E_INVAL;
+    int cap = -1;
+    for (int j = 0; j < kNumCaps; ++j)
+        if (kResidencyCaps[j] == waves_per_simd) cap = j;
+    if (cap < 0 || sweep_lds(ctx, cap, config_block(ctx->shape)) < 0) return LBM_E_INVAL;
+    ctx->order = order;
+    ctx->cap = cap;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_sweep_launch(const lbm_ctx *ctx, int32_t *order, int32_t *waves_per_simd) {
+    if (!ctx || !order || !waves_per_simd) return LBM_E_INVAL;
+    *order = ctx->order;
+    *waves_per_simd = kResidencyCaps[ctx->cap];
     return LBM_OK;
 }
 
@@ -1340,6 +1450,7 @@ lbm_status lbm_stream_ceiling(lbm_ctx *ctx, int32_t k, int32_t iters, double *ms
 lbm_status lbm_set_shape(lbm_ctx *ctx, int32_t k) {
     if (!ctx || k < 0 || k >= kNumShapes || !shape_ok(ctx, k)) return LBM_E_INVAL;
     ctx->shape = k;
+    if (sweep_lds(ctx, ctx->cap, config_block(k)) < 0) ctx->cap = 0;  // cap not possible here
     return LBM_OK;
 }
 
@@ -1449,7 +1560,7 @@ struct lbm_ens {
 namespace {
 
 TuneKey ens_tune_key(const lbm_ens *e) {
-    TuneKey k{e->device, e->desc.storage, int(D3Q19::Q), {}};
+    TuneKey k{1, e->device, e->desc.storage, int(D3Q19::Q), {}};
     k.dims.reserve(3 * size_t(e->nrep));
     for (int32_t q = 0; q < e->nrep; ++q) {
         k.dims.push_back(e->host_reps[q].nx);

@@ -337,6 +337,20 @@ class Lattice(_StreamOrder):
         _abi.check("lbm_get_shape", self.lib.lbm_get_shape(self.ctx, ctypes.byref(k)))
         return k.value
 
+    def set_sweep_launch(self, order: int = 0, waves_per_simd: int = 0):
+        """Block order (0 node order, 1 per-XCD slabs) and residency cap (0, 6,
+        5, 4, 3 or 2 waves per SIMD) of the stream-collide; same results."""
+        _abi.check("lbm_set_sweep_launch",
+                   self.lib.lbm_set_sweep_launch(self.ctx, int(order), int(waves_per_simd)))
+
+    @property
+    def sweep_launch(self):
+        """(block order, residency cap in waves per SIMD) of later steps."""
+        o, w = ctypes.c_int32(), ctypes.c_int32()
+        _abi.check("lbm_get_sweep_launch",
+                   self.lib.lbm_get_sweep_launch(self.ctx, ctypes.byref(o), ctypes.byref(w)))
+        return o.value, w.value
+
     @property
     def step_count(self) -> int:
         s = ctypes.c_int64()
