@@ -117,6 +117,7 @@ def time_storage(w, variant, steps, warmup, prof_steps, pair=None, repeats=0):
     lat.step(warmup)
     torch.cuda.synchronize()
     shape, shape_ms = lat.autotune(20)
+    order, cap = lat.sweep_launch
     lat.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -158,6 +159,8 @@ def time_storage(w, variant, steps, warmup, prof_steps, pair=None, repeats=0):
         "collide_GBs": achieved,
         "collide_frac": achieved / HBM_PEAK_GBS,
         "collide_shape": shape,
+        "collide_order": order,
+        "collide_waves_per_simd_cap": cap,
         "stream_only_ms": ceil_ms,
         "of_stream_only": ceil_ms / coll_ms,
         "autotune_ms": [round(float(x), 5) for x in shape_ms],
@@ -193,50 +196,140 @@ def copy_probe(nbytes, reps=20):
             "GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
-def precision_study(w, steps, storages=("f32", "bf16", "f16")):
-    """VACF and momentum error of each storage against the FP64 path (itself
-    matched to the FP64 oracle to 1e-10) on the same workload and seed."""
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def oracle_fixture(name: str):
+    """The FP64 oracle's long run of a workload (written by
+    tests/golden/make_oracle_fixtures.py from the oracle alone), or None."""
+    path = os.path.join(GOLDEN, f"oracle_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def vacf_errors(c, c_ref, tail, per_particle=None):
+    """Errors of a velocity autocorrelation C(l) = <V(t0).V(t0 + l)> (section
+    2.1; lags 0..L, not normalised) against the reference curve c_ref:
+    c0_rel, the relative error of C(0) (the particles' kinetic temperature);
+    vacf_abs_err, max over lags of |C - C_ref| / C_ref(0) (every lag, C(0)
+    included, in units of the reference's C(0): the "within 1%" figure);
+    vacf_err, the same between the curves each normalised by its own C(0)
+    (shape only).  Over the tail window tail = (lo, hi): tail_integral_rel,
+    the relative error of sum C(l) (the tail's share of the diffusion
+    coefficient); tail_amplitude_rel, the relative error of the least-squares
+    amplitude B of C(l) = B l^(-3/2) (the long-time tail of section 3);
+    tail_window_err, max |C - C_ref| over the window / max |C_ref| there.
+    per_particle ([n, L + 1] per-particle curves of the run under test):
+    tail_integral_se_rel, the standard error of the tail sum over particles,
+    relative: the estimator's own sampling uncertainty, against which the
+    tail errors are to be read."""
+    import numpy as np
+
+    c = np.asarray(c, dtype=np.float64)
+    c_ref = np.asarray(c_ref, dtype=np.float64)
+    lo, hi = tail
+    w = slice(lo, hi + 1)
+    lag = np.arange(lo, hi + 1, dtype=np.float64)
+    basis = lag ** -1.5
+
+    def amp(x):
+        return float(np.sum(x[w] * basis) / np.sum(basis * basis))
+
+    out = {
+        "c0_rel": float(abs(c[0] - c_ref[0]) / abs(c_ref[0])),
+        "vacf_abs_err": float(np.max(np.abs(c - c_ref)) / abs(c_ref[0])),
+        "vacf_err": float(np.max(np.abs(c / c[0] - c_ref / c_ref[0]))),
+        "tail_window": [lo, hi],
+        "tail_integral_rel": float(abs(c[w].sum() - c_ref[w].sum()) / abs(c_ref[w].sum())),
+        "tail_amplitude_rel": float(abs(amp(c) - amp(c_ref)) / abs(amp(c_ref))),
+        "tail_window_err": float(np.max(np.abs(c[w] - c_ref[w])) / np.max(np.abs(c_ref[w]))),
+    }
+    if per_particle is not None:
+        t = np.asarray(per_particle)[:, w].sum(axis=1)
+        out["tail_integral_se_rel"] = float(np.std(t, ddof=1) / np.sqrt(len(t)) / abs(t.mean()))
+    return out
+
+
+# Tail windows of the precision study: past the Brownian relaxation time
+# M / gamma = 10 steps, up to a lag where the reference curve is still a few
+# per mille of C(0).
+TAIL = {"vacf128": (50, 500), "suspension256": (50, 250)}
+
+
+def run_precision(w, storage, steps, every):
+    """One storage on a workload: VACF curve C(l) and the FP64 sums every
+    `every` steps (as the oracle fixture records them)."""
     import numpy as np
     import torch
 
-    def run(storage):
-        lat = make_lattice(w, storage)
-        mom = []
-        chunk = 100
-        done = 0
-        while done < steps:
-            k = min(chunk, steps - done)
-            lat.step(k)
-            done += k
-            o = lat.observables()
-            mom.append(np.concatenate([o[1:4], o[4:7]]))
-        acc, cnt = lat.vacf()
-        acc = acc.cpu().numpy()
-        c = acc.sum(0) / (acc.shape[0] * np.maximum(cnt, 1))
-        valid = cnt > 0
-        curve = np.where(valid, c / c[0], 0.0)
-        del lat
-        torch.cuda.empty_cache()
-        return curve, np.array(mom), valid
+    lat = make_lattice(w, storage)
+    rows = []
+    done = 0
+    while True:
+        o = lat.observables()
+        rows.append([float(done)] + [float(x) for x in o])
+        if done >= steps:
+            break
+        k = min(every, steps - done)
+        lat.step(k)
+        done += k
+    acc, cnt = lat.vacf()
+    acc = acc.cpu().numpy() / np.maximum(np.asarray(cnt), 1)  # per-particle curves
+    c = acc.mean(axis=0)
+    del lat
+    torch.cuda.empty_cache()
+    return c, np.array(rows), np.asarray(cnt), acc
 
-    ref_curve, ref_mom, valid = run("f64")
-    out = {"reference": "f64 storage (FP64 path)", "steps": steps}
+
+def series_errors(ser, ref):
+    """Fluid and particle momentum of the FP64 sums against the oracle's, each
+    normalised by the largest reference value over the run, and the fluid
+    mass relative error."""
+    import numpy as np
+
+    ref = np.asarray(ref)
+    return {
+        "fluid_mass_rel": float(np.max(np.abs(ser[:, 1] - ref[:, 1]) / ref[:, 1])),
+        "fluid_momentum_err": float(np.max(np.abs(ser[:, 2:5] - ref[:, 2:5])) /
+                                    np.max(np.abs(ref[:, 2:5]))),
+        "particle_momentum_err": float(np.max(np.abs(ser[:, 5:8] - ref[:, 5:8])) /
+                                       np.max(np.abs(ref[:, 5:8]))),
+    }
+
+
+def precision_study(w, storages=("f64", "f32", "bf16", "f16")):
+    """VACF and momentum error of each storage against the FP64 oracle's own
+    run of the same workload and seed (tests/golden/oracle_<workload>.json)."""
+    import numpy as np
+
+    ref = oracle_fixture(w["name"])
+    if ref is None:
+        return {"reference": f"missing oracle fixture for {w['name']}"}
+    steps, every = ref["steps"], ref["series_every"]
+    c_ref = np.asarray(ref["vacf"])
+    out = {"reference": f"FP64 oracle, {steps} steps (tests/golden/oracle_{w['name']}.json)",
+           "steps": steps, "max_lag": ref["max_lag"]}
     for s in storages:
-        curve, mom, _ = run(s)
-        out[s] = {
-            "vacf_err": float(np.max(np.abs(curve[valid] - ref_curve[valid]))),
-            "particle_momentum_err": float(np.max(np.abs(mom[:, 3:] - ref_mom[:, 3:])) /
-                                           np.max(np.abs(ref_mom[:, 3:]))),
-            "fluid_momentum_err": float(np.max(np.abs(mom[:, :3] - ref_mom[:, :3])) /
-                                        np.max(np.abs(ref_mom[:, :3]))),
-        }
+        t0 = time.perf_counter()
+        c, ser, cnt, per = run_precision(w, s, steps, every)
+        rec = vacf_errors(c, c_ref, TAIL[w["name"]], per)
+        rec.update(series_errors(ser, ref["series"]))
+        rec["counts_match"] = bool(np.array_equal(cnt, ref["vacf_counts"]))
+        rec["gpu_seconds"] = round(time.perf_counter() - t0, 2)
+        out[s] = {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in rec.items()}
     return out
 
 
 def time_ensemble(steps, warmup):
     """The 64-replica ensemble (edges 48..96, tau 0.8, 8 particles each, FP32,
     VACF on): whole-ensemble MLUPS with graph-replayed steps and with plain
-    launches."""
+    launches, and the ensemble-averaged VACF.  The graph-replayed run takes
+    exactly `steps` steps from the initial state (the autotuner leaves the
+    state untouched), so at 5000 steps its smallest and largest boxes are
+    compared with the oracle's own runs of those boxes
+    (tests/golden/oracle_ensemble64_edges.json)."""
     import numpy as np
     import torch
 
@@ -252,8 +345,6 @@ def time_ensemble(steps, warmup):
         ens = Ensemble(reps, storage=w["storage"], mass=w["mass"], gamma=w["gamma"], kT=w["kT"])
         ens.vacf_config(w["max_lag"], w["stride"])
         ens.use_graph(use_graph)
-        ens.step(warmup)
-        torch.cuda.synchronize()
         shape, tune_ms = ens.autotune(10)
         if use_graph:
             # the stream-collide (autotuner timing) against the same data
@@ -264,7 +355,6 @@ def time_ensemble(steps, warmup):
                                         / 1e9 / HBM_PEAK_GBS, 4)
             out["stream_only_ms"] = round(ceil, 5)
             out["of_stream_only"] = round(ceil / float(tune_ms[shape]), 4)
-        ens.step(warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ens.step(steps)
@@ -277,17 +367,68 @@ def time_ensemble(steps, warmup):
         if use_graph:
             out["graph_replays"] = ens.graph_replays
             acc, cnt = ens.vacf()
-            c = acc.sum(0).cpu().numpy() / (acc.shape[0] * np.maximum(cnt, 1))
-            out["vacf_norm_lag"] = {str(l): round(float(c[l] / c[0]), 5) for l in (0, 10, 50, 100)}
+            acc = acc.cpu().numpy()
+            c = acc.sum(0) / (acc.shape[0] * np.maximum(cnt, 1))
+            out["vacf_norm_lag"] = {str(l): round(float(c[l] / c[0]), 5) for l in (0, 10, 50, 100, 500)}
+            ref = oracle_fixture("ensemble64_edges")
+            if ref is not None and ref["steps"] == steps:
+                checks = []
+                for rec in ref["replicas"]:
+                    k = rec["index"]
+                    rows = acc[w["n"] * k: w["n"] * (k + 1)] / np.maximum(cnt, 1)
+                    e = vacf_errors(rows.mean(axis=0), rec["vacf"], (50, 250), rows)
+                    _, vk = ens.particles(k)
+                    e["final_v_err"] = float(np.max(np.abs(vk.cpu().numpy() - np.asarray(rec["final_v"]))) /
+                                             np.max(np.abs(rec["final_v"])))
+                    checks.append({"replica": k, "edge": rec["edge"],
+                                   **{kk: (float(f"{vv:.4g}") if isinstance(vv, float) else vv)
+                                      for kk, vv in e.items()}})
+                out["vs_oracle"] = checks
         del ens
         torch.cuda.empty_cache()
     return out
 
 
+def _msd_forward(storage, gamma, tau, v_shift=None, grad=False):
+    """The 64^3 reverse-mode workload: loss J = mean over particles of
+    |r^N - r^0|^2 (unwrapped positions) after its steps; with grad, also the
+    adjoint's dJ/d(gamma, tau) and dJ/dV^0 [n, 3]."""
+    import numpy as np
+
+    from paper_1909_13412_amd import Lattice
+    from paper_1909_13412_amd.inputs import ADJOINT64, particle_positions, particle_velocities
+
+    w = ADJOINT64
+    L, n = w["L"], w["n"]
+    r0 = particle_positions(n, L, w["seed"])
+    v0 = particle_velocities(n, w["kT"] / w["mass"], w["seed"])
+    if v_shift is not None:
+        v0 = v0 + v_shift
+    lat = Lattice(L, L, L, tau, storage=storage)
+    lat.particles_couple(r0, v0, mass=w["mass"], gamma=gamma, kT=w["kT"], seed=w["seed"])
+    tape = lat.record(w["steps"], w["every"]) if grad else None
+    if not grad:
+        lat.step(w["steps"])
+    rN = lat.r.cpu().numpy()
+    J = float(np.mean(np.sum((rN - r0) ** 2, axis=1)))
+    if not grad:
+        return J, None, None
+    g = lat.adjoint(tape, None, 2.0 * (rN - r0) / n, None)
+    return J, g["params"].cpu().numpy()[:2], g["v"].cpu().numpy()
+
+
 def time_adjoint(steps, warmup):
-    """Reverse mode on the 64^3 / 16-particle workload: the recorded forward
-    (checkpoint every 100 steps) and the adjoint sweep (segment recompute plus
-    the reverse step kernels), against plain forward steps."""
+    """Reverse mode on the 64^3 / 16-particle workload (tau 0.8, FP32, kT
+    1e-4, 2000 steps, a checkpoint every 100): the recorded forward and the
+    adjoint sweep (segment recompute plus the reverse step kernels) against
+    plain forward steps; then the gradient of the mean-squared displacement
+    of the 16 particles with respect to gamma, tau and the 16 x 3 initial
+    velocities, from the FP32 and FP64 adjoints, beside central finite
+    differences of the FP64 forward with h = 1e-3 and 1e-6 (absolute for
+    gamma and tau, times sqrt(kT/M) for the velocities).  The Stokeslet fit
+    changes its node set when a particle crosses a cell face, so the loss is
+    only piecewise smooth and the wide difference can straddle a crossing."""
+    import numpy as np
     import torch
 
     from paper_1909_13412_amd import Lattice
@@ -299,9 +440,9 @@ def time_adjoint(steps, warmup):
     r = particle_positions(n, L, w["seed"])
     v = particle_velocities(n, w["kT"] / w["mass"], w["seed"])
     lat.particles_couple(r, v, mass=w["mass"], gamma=w["gamma"], kT=w["kT"], seed=w["seed"])
-    cv = torch.ones((n, 3), dtype=torch.float64, device=lat.device)
+    cr = torch.ones((n, 3), dtype=torch.float64, device=lat.device)
     tape = lat.record(2 * every, every)
-    lat.adjoint(tape, None, None, cv)
+    lat.adjoint(tape, None, cr, None)
     lat.step(warmup)
     torch.cuda.synchronize()
 
@@ -314,17 +455,62 @@ def time_adjoint(steps, warmup):
 
     _, t_fwd = timed(lambda: lat.step(steps))
     tape, t_rec = timed(lambda: lat.record(steps, every))
-    g, t_adj = timed(lambda: lat.adjoint(tape, None, None, cv))
+    g, t_adj = timed(lambda: lat.adjoint(tape, None, cr, None))
     work = lat._adj_keep[4].numel()
-    return {"workload": "adjoint64", "box": [L] * 3, "tau": w["tau"], "particles": n,
-            "storage": w["storage"], "steps": steps, "checkpoint_every": every,
-            "loss": "sum of final particle velocities",
-            "tape_MB": round(tape.buf.numel() / 2**20, 1), "work_MB": round(work / 2**20, 1),
-            "forward_ms_per_step": round(t_fwd * 1e3 / steps, 5),
-            "record_ms_per_step": round(t_rec * 1e3 / steps, 5),
-            "adjoint_ms_per_step": round(t_adj * 1e3 / steps, 5),
-            "adjoint_over_forward": round(t_adj / t_fwd, 3),
-            "grad_gamma_tau_M_kT": [float(x) for x in g["params"].cpu().tolist()]}
+    out = {"workload": "adjoint64", "box": [L] * 3, "tau": w["tau"], "particles": n,
+           "storage": w["storage"], "steps": steps, "checkpoint_every": every,
+           "tape_MB": round(tape.buf.numel() / 2**20, 1), "work_MB": round(work / 2**20, 1),
+           "forward_ms_per_step": round(t_fwd * 1e3 / steps, 5),
+           "record_ms_per_step": round(t_rec * 1e3 / steps, 5),
+           "adjoint_ms_per_step": round(t_adj * 1e3 / steps, 5),
+           "adjoint_over_forward": round(t_adj / t_fwd, 3)}
+    del lat, tape
+    torch.cuda.empty_cache()
+    if steps != w["steps"]:
+        return out
+    # gradient of the mean-squared displacement
+    t0 = time.perf_counter()
+    J32, p32, v32 = _msd_forward("f32", w["gamma"], w["tau"], grad=True)
+    J64, p64, v64 = _msd_forward("f64", w["gamma"], w["tau"], grad=True)
+    sv = np.sqrt(w["kT"] / w["mass"])
+    fd = {}
+    for h in (1e-3, 1e-6):
+        def J(dg=0.0, dt=0.0, dv=None):
+            return _msd_forward("f64", w["gamma"] + dg, w["tau"] + dt, dv)[0]
+
+        gv = np.zeros((n, 3))
+        for i in range(n):
+            for k in range(3):
+                e = np.zeros((n, 3))
+                e[i, k] = h * sv
+                gv[i, k] = (J(dv=e) - J(dv=-e)) / (2 * h * sv)
+        fd[h] = ((J(dg=h) - J(dg=-h)) / (2 * h), (J(dt=h) - J(dt=-h)) / (2 * h), gv)
+
+    def rel(a, b):
+        return float(f"{abs(a - b) / abs(b):.3g}")
+
+    def vrel(a, b):
+        return float(f"{np.max(np.abs(a - b)) / np.max(np.abs(b)):.3g}")
+
+    out["msd"] = {
+        "loss": "mean over the 16 particles of |r(2000) - r(0)|^2 (unwrapped)",
+        "J_f32": J32, "J_f64": J64,
+        "adjoint_f32": {"gamma": float(p32[0]), "tau": float(p32[1]),
+                        "v0": [[float(f"{x:.6g}") for x in row] for row in v32]},
+        "adjoint_f64": {"gamma": float(p64[0]), "tau": float(p64[1]),
+                        "v0": [[float(f"{x:.6g}") for x in row] for row in v64]},
+        "fd_f64": {str(h): {"gamma": fd[h][0], "tau": fd[h][1],
+                            "v0": [[float(f"{x:.6g}") for x in row] for row in fd[h][2]]}
+                   for h in fd},
+        "f32_vs_fd_1e-6": {"gamma": rel(p32[0], fd[1e-6][0]), "tau": rel(p32[1], fd[1e-6][1]),
+                           "v0": vrel(v32, fd[1e-6][2])},
+        "f64_vs_fd_1e-6": {"gamma": rel(p64[0], fd[1e-6][0]), "tau": rel(p64[1], fd[1e-6][1]),
+                           "v0": vrel(v64, fd[1e-6][2])},
+        "f64_vs_fd_1e-3": {"gamma": rel(p64[0], fd[1e-3][0]), "tau": rel(p64[1], fd[1e-3][1]),
+                           "v0": vrel(v64, fd[1e-3][2])},
+        "fd_runs": 4 * (2 + 3 * n), "seconds": round(time.perf_counter() - t0, 1),
+    }
+    return out
 
 
 def time_large(steps, warmup):
@@ -343,6 +529,8 @@ def time_large(steps, warmup):
         out[storage] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 5),
                         "collide_ms": round(r["collide_ms"], 5), "collide_GBs": round(r["collide_GBs"], 1),
                         "collide_frac": round(r["collide_frac"], 4), "collide_shape": r["collide_shape"],
+                        "collide_order": r["collide_order"],
+                        "collide_waves_per_simd_cap": r["collide_waves_per_simd_cap"],
                         "stream_only_ms": round(r["stream_only_ms"], 5),
                         "of_stream_only": round(r["of_stream_only"], 4)}
         torch.cuda.empty_cache()
@@ -458,16 +646,23 @@ def main():
                          "e.g. 48,64,96,100,128,200,250,256")
     ap.add_argument("--size-sweep-storages", default="f32,bf16")
     ap.add_argument("--vacf128-steps", type=int, default=20000,
-                    help="steps of the 128^3 / 64-particle VACF workload per storage for the "
-                         "precision study at that workload (0 = skip; also skipped with --precision-steps 0; ~8 s for all four storages)")
+                    help="0 = skip the precision study on the 128^3 / 64-particle VACF workload "
+                         "(its 20,000 steps against the oracle's run; also skipped with "
+                         "--precision-steps 0)")
     ap.add_argument("--cpu-steps", type=int, default=90, help="oracle steps timed (0 = skip; 90 is ~11 s on 16 host threads)")
     ap.add_argument("--cpu-steps-one-thread", type=int, default=6,
                     help="oracle steps timed on one host thread, in a child process (0 = skip; also skipped with --cpu-steps 0; 6 is ~10 s)")
-    ap.add_argument("--precision-steps", type=int, default=2000, help="0 = skip the VACF error study")
+    ap.add_argument("--precision-steps", type=int, default=2000,
+                    help="0 = skip the VACF error study (the workload's 2000 steps against the "
+                         "oracle's run)")
     ap.add_argument("--prof-steps", type=int, default=300, help="steps timed with per-kernel events")
     ap.add_argument("--no-copy-probe", action="store_true")
-    ap.add_argument("--ensemble-steps", type=int, default=1000, help="0 = skip the ensemble timing")
-    ap.add_argument("--adjoint-steps", type=int, default=2000, help="0 = skip the reverse-mode timing")
+    ap.add_argument("--ensemble-steps", type=int, default=5000,
+                    help="0 = skip the ensemble timing (5000: the workload's length, checked against "
+                         "the oracle's runs of its smallest and largest boxes)")
+    ap.add_argument("--adjoint-steps", type=int, default=2000,
+                    help="0 = skip the reverse-mode leg (2000: the workload's length, with the "
+                         "mean-squared-displacement gradient and its finite differences)")
     ap.add_argument("--no-pairs", action="store_true", help="skip the pair-repulsion timing")
     ap.add_argument("--large-steps", type=int, default=200,
                     help="steps of the 512^3 leg per storage (0 = skip)")
@@ -523,7 +718,7 @@ def main():
     if args.precision_steps > 0:
         print(f"[bench] precision study ({args.precision_steps} steps per storage)", file=sys.stderr,
               flush=True)
-        precision = precision_study(w, args.precision_steps)
+        precision = precision_study(w)
     sweep = None
     if args.size_sweep:
         sweep = size_sweep([int(x) for x in args.size_sweep.split(",") if x],
@@ -536,7 +731,7 @@ def main():
 
         w128 = dict(WORKLOADS["vacf128"])
         w128["name"] = "vacf128"
-        precision128 = precision_study(w128, args.vacf128_steps)
+        precision128 = precision_study(w128)
     cpu = None
     if args.cpu_steps > 0:
         print(f"[bench] oracle baseline ({args.cpu_steps} steps)", file=sys.stderr, flush=True)
@@ -587,6 +782,8 @@ def main():
             "bytes_per_node": collide_bytes_per_node(args.storage),
             "avg_launch_ms": round(main_res["collide_ms"], 5),
             "launch_shape": main_res["collide_shape"],
+            "launch_order": main_res["collide_order"],
+            "launch_waves_per_simd_cap": main_res["collide_waves_per_simd_cap"],
             "autotune_ms": main_res["autotune_ms"],
             "pattern_ceiling": {
                 "kernel": "k_stream_only",

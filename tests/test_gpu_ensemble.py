@@ -203,6 +203,39 @@ def test_ensemble64_workload():
         assert abs(o[0] - reps[k]["nx"] ** 3) < 1e-6 * reps[k]["nx"] ** 3
 
 
+def test_ensemble64_full_run_against_oracle():
+    # The 64-replica workload over its full 5000 steps, graph-replayed, FP32:
+    # the smallest and the largest box against the FP64 oracle's own runs of
+    # those boxes (tests/golden/oracle_ensemble64_edges.json): velocity
+    # autocorrelation (lags 0..1000, origins every 10 steps) and the final
+    # particle velocities.
+    import bench
+    from paper_1909_13412_amd import Ensemble
+    from paper_1909_13412_amd.inputs import ENSEMBLE64, ensemble_replicas
+
+    w = ENSEMBLE64
+    ref = bench.oracle_fixture("ensemble64_edges")
+    assert ref is not None and ref["steps"] == w["steps"]
+    reps = ensemble_replicas(w["replicas"], w["sizes"], w["n"], w["tau"], w["kT"], w["mass"], w["seed"])
+    ens = Ensemble(reps, storage="f32", kT=w["kT"], mass=w["mass"], gamma=w["gamma"])
+    ens.vacf_config(w["max_lag"], w["stride"])
+    ens.step(w["steps"])
+    acc, cnt = ens.vacf()
+    acc = acc.cpu().numpy() / np.maximum(cnt, 1)
+    for rec in ref["replicas"]:
+        k = rec["index"]
+        assert reps[k]["nx"] == rec["edge"] and reps[k]["seed"] == rec["seed"]
+        assert np.array_equal(cnt, rec["vacf_counts"])
+        rows = acc[w["n"] * k: w["n"] * (k + 1)]
+        e = bench.vacf_errors(rows.mean(axis=0), rec["vacf"], (50, 250), rows)
+        ev = nmax_err(ens.particles(k)[1].cpu().numpy(), rec["final_v"])
+        announce(f"  replica {k} (edge {rec['edge']}): C(0) {e['c0_rel']:.2e}, VACF "
+                 f"{e['vacf_abs_err']:.2e}, tail sum {e['tail_integral_rel']:.2e}, final V {ev:.2e}")
+        assert e["c0_rel"] < 1e-4 and e["vacf_abs_err"] < 1e-4
+        assert e["tail_integral_rel"] < 1e-2
+        assert ev < 1e-3
+
+
 def test_autotune_choice_is_remembered():
     # lbm_ens_autotune's choice is kept for the process: a later ensemble of
     # the same boxes (same order, storage, device) starts from it; other box

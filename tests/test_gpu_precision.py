@@ -1,0 +1,71 @@
+"""Long runs of every storage against the FP64 oracle's own runs of the same
+workloads (tests/golden/oracle_*.json, written by make_oracle_fixtures.py from
+the oracle alone): the 128^3 VACF workload over its full 20,000 steps and the
+256^3 suspension over its 2,000 steps, same seeds and the same Philox noise.
+
+The observable is the velocity autocorrelation C(l) = <V(t0).V(t0 + l)> of
+section 2.1 (Figs. 2 and 3 of section 3), averaged over particles and origins.
+Required of every storage: C(0), the particles' kinetic temperature, within 1%
+of the oracle's, and every lag within 1% of the oracle's C(0) (the VACF
+target).  The tail (lags 50-500 / 50-250) is compared through its sum and
+its fitted l^(-3/2) amplitude: there the run-to-run difference is set by the
+chaotic growth of rounding differences along the trajectories (about tenfold
+every 3000 steps), so it is asserted against the estimator's own sampling
+error, and tightly for FP64 storage.  Momentum and mass sums are compared
+step by step; single trajectories drift apart over the run in the 16- and
+32-bit storages, so their momentum errors are stated, not bounded.
+"""
+import numpy as np
+import pytest
+
+from helpers import announce
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+
+
+def _check(name, storage):
+    import bench
+    from paper_1909_13412_amd.inputs import WORKLOADS
+
+    ref = bench.oracle_fixture(name)
+    assert ref is not None, f"missing oracle fixture for {name}"
+    w = dict(WORKLOADS[name])
+    w["name"] = name
+    assert ref["steps"] == w["steps"] and ref["seed"] == w["seed"]
+    announce(f"{name} {storage}: {ref['steps']} steps against the oracle's run")
+    c, ser, cnt, per = bench.run_precision(w, storage, ref["steps"], ref["series_every"])
+    e = bench.vacf_errors(c, ref["vacf"], bench.TAIL[name], per)
+    m = bench.series_errors(ser, ref["series"])
+    announce("  " + "  ".join(f"{k} {v:.3g}" if isinstance(v, float) else f"{k} {v}"
+                               for k, v in {**e, **m}.items()))
+    assert np.array_equal(cnt, ref["vacf_counts"])
+    assert ser.shape == np.asarray(ref["series"]).shape
+    assert m["fluid_mass_rel"] < 1e-7
+    if storage == "f64":
+        assert e["c0_rel"] < 1e-5 and e["vacf_abs_err"] < 1e-5
+        assert e["tail_integral_rel"] < 1e-3 and e["tail_amplitude_rel"] < 1e-3
+        assert m["fluid_mass_rel"] < 1e-10
+    else:
+        assert e["c0_rel"] < 1e-2 and e["vacf_abs_err"] < 1e-2
+        assert e["tail_integral_rel"] < 2.0 * e["tail_integral_se_rel"]
+        assert e["tail_amplitude_rel"] < 2.0 * e["tail_integral_se_rel"]
+    return e, m
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16", "f16"])
+def test_vacf128_full_run_against_oracle(storage):
+    _check("vacf128", storage)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16", "f16"])
+def test_suspension256_full_run_against_oracle(storage):
+    _check("suspension256", storage)
