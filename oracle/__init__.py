@@ -23,7 +23,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 Q = 19
-FRICTION = {"stokeslet": 0, "pointwise": 1, "bd": 2, "stokeslet2dx": 3}
+FRICTION = {"stokeslet": 0, "pointwise": 1, "bd": 2, "stokeslet2dx": 3, "stokeslet_cube": 4}
 
 _lib = None
 

@@ -194,12 +194,14 @@ void ora_gauss3(uint64_t seed, uint32_t step, uint32_t particle, uint32_t replic
  *   2 dx around the particle (the remedy section 2.2 suggests for large R):
  *   per axis the corners are c0 and c0 + 2 with c0 = floor(s + 1/2) - 1, so
  *   the particle lies in the middle half of the cube; u8 then holds the
- *   velocities at those corners (p -> c0 + 2 (p&1, p>>1&1, p>>2&1)). */
+ *   velocities at those corners (p -> c0 + 2 (p&1, p>>1&1, p>>2&1)).
+ * mode STOKESLET_CUBE: the same fit as STOKESLET_2DX (the reaction force is
+ *   then spread to the same cube; see couple_particles). */
 void ora_friction_force(int mode, double R, double gamma, const double s[3],
                         const double V[3], const double u8[8][3], double FH[3])
 {
     double c[3], d[8][3], wgt[8];
-    const int wide = mode == ORA_FRICTION_STOKESLET_2DX;
+    const int wide = mode == ORA_FRICTION_STOKESLET_2DX || mode == ORA_FRICTION_STOKESLET_CUBE;
     for (int k = 0; k < 3; ++k) c[k] = wide ? floor(s[k] + 0.5) - 1.0 : floor(s[k]);
     for (int p = 0; p < 8; ++p) {
         int b[3] = {p & 1, (p >> 1) & 1, (p >> 2) & 1};
@@ -505,7 +507,8 @@ static void couple_particles(ora_sim *o)
             }
             for (int k = 0; k < 3; ++k) u8[p][k] = o->u[k * n + node[p]];
         }
-        if (o->friction == ORA_FRICTION_STOKESLET_2DX) {
+        const int cube = o->friction == ORA_FRICTION_STOKESLET_CUBE;
+        if (o->friction == ORA_FRICTION_STOKESLET_2DX || cube) {
             /* the fit reads the corners of the (2 dx)^3 cube instead */
             for (int p = 0; p < 8; ++p) {
                 int64_t q[3];
@@ -533,10 +536,26 @@ static void couple_particles(ora_sim *o)
         }
         /* First Eq. (s2-force): the fluid receives -F_H at the particle, spread
          * to the eight nodes with trilinear weights (sum 1, unit cell volume).
-         * The Brownian-dynamics model leaves the solvent untouched. */
-        if (o->friction != ORA_FRICTION_BD)
+         * The Brownian-dynamics model leaves the solvent untouched.  The
+         * weights "depending on the distance" are not printed; with the cube
+         * fit (STOKESLET_CUBE) the force goes to the same eight corners of
+         * the (2 dx)^3 cube the fit reads, with the cube's trilinear weights
+         * prod_k (1 - |q_k - s_k| / 2) (sum 1, first moment s). */
+        if (cube) {
+            for (int p = 0; p < 8; ++p) {
+                int64_t q[3];
+                double w = 1.0;
+                for (int k = 0; k < 3; ++k) {
+                    q[k] = (int64_t)floor(s[k] + 0.5) - 1 + 2 * ((p >> k) & 1);
+                    w *= 1.0 - fabs((double)q[k] - s[k]) / 2.0;
+                }
+                int64_t nd = cell_index(o, wrap(q[0], L[0]), wrap(q[1], L[1]), wrap(q[2], L[2]));
+                for (int k = 0; k < 3; ++k) o->F[k * n + nd] += -FH[k] * w;
+            }
+        } else if (o->friction != ORA_FRICTION_BD) {
             for (int p = 0; p < 8; ++p)
                 for (int k = 0; k < 3; ++k) o->F[k * n + node[p]] += -FH[k] * wgt[p];
+        }
     }
 }
 

@@ -28,7 +28,7 @@ extern "C" {
 #define ORA_Q 19  /* the largest velocity set */
 
 enum { ORA_FRICTION_STOKESLET = 0, ORA_FRICTION_POINTWISE = 1, ORA_FRICTION_BD = 2,
-       ORA_FRICTION_STOKESLET_2DX = 3 };
+       ORA_FRICTION_STOKESLET_2DX = 3, ORA_FRICTION_STOKESLET_CUBE = 4 };
 
 typedef struct ora_sim ora_sim;
 

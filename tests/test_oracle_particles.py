@@ -264,6 +264,97 @@ def test_first_step_spreading_moments(oracle_mod):
     assert np.allclose(v1, v0 + fh / 10.0, rtol=1e-15)
 
 
+def test_cube_mode_spreads_on_the_fitting_cube(oracle_mod):
+    # stokeslet_cube fits like stokeslet2dx (the same F_H from the same state)
+    # and spreads -F_H to the eight corners of the same (2 dx)^3 cube with
+    # weights prod_k (1 - |q_k - s_k| / 2).  From rest, one step later: the
+    # momentum added is exactly -F_H and its first moment -F_H s (the weights
+    # sum to one and are centred on the particle), and the second moment about
+    # the particle exceeds the unit-cell spreading's by exactly
+    # -F_H,j [t_k (2 - t_k) - t'_k (1 - t'_k)], the difference of the two
+    # weight distributions' variances along axis k (t_k = s_k - c0_k on the
+    # cube, t'_k = s_k - floor(s_k) in the unit cell); the streaming adds the
+    # same to both.
+    L = 16
+    r0 = np.array([[7.3, 8.61, 6.15]])
+    v0 = np.array([[0.01, -0.004, 0.002]])
+    z, y, x = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    X = [x, y, z]
+    out = {}
+    for mode in ("stokeslet2dx", "stokeslet_cube"):
+        s = oracle_mod.Sim(L, L, L, 0.8)
+        s.set_particles(r0, v0, mass=10.0, gamma=1.0, radius=1.0, friction=mode)
+        s.step(1)
+        fh, _ = s.particle_forces()
+        _, u = s.moments()
+        out[mode] = (fh[0], u)
+    fh, u = out["stokeslet_cube"]
+    assert np.array_equal(fh, out["stokeslet2dx"][0]) and np.abs(fh).max() > 1e-4
+    assert np.allclose(u.sum(axis=(1, 2, 3)), -fh, rtol=1e-13, atol=1e-18)
+    scale = abs(fh).max() * L * L
+    for j in range(3):
+        for k in range(3):
+            assert abs(np.sum(X[k] * u[j]) + fh[j] * r0[0, k]) < 1e-13 * scale
+    u2 = out["stokeslet2dx"][1]
+    for k in range(3):
+        sk = r0[0, k]
+        t = sk - (np.floor(sk + 0.5) - 1.0)
+        tu = sk - np.floor(sk)
+        dvar = t * (2.0 - t) - tu * (1.0 - tu)
+        for j in range(3):
+            d2 = np.sum((X[k] - sk) ** 2 * (u[j] - u2[j]))
+            assert abs(d2 - (-fh[j] * dvar)) < 1e-12 * scale, (j, k)
+
+
+def test_cube_mode_coupling_dissipates_for_a_close_pair(oracle_mod):
+    # Two particles 1.5 dx apart with the paper's Fig. 2 particle (R = 1 dx,
+    # M = 16, tau 0.5534, kT = 0).  The coupling's energy exchange in one step
+    # is the work of F_H on the particles, F_H . (V^n + V^(n+1)) / 2, plus the
+    # work of the spread reaction force on the fluid, sum_p (-F_H W_p) . u^n
+    # at the spreading nodes.  A friction must make it negative.  Fitting on
+    # the (2 dx)^3 cube but spreading on the unit cell makes it positive (the
+    # pair's energy then grows without bound); spreading on the same cube
+    # keeps it negative.
+    L, tau, R, M = 24, 0.5534, 1.0, 16.0
+    gamma = 6.0 * np.pi * (tau - 0.5) / 3.0 * R
+    c = np.array([L / 2 + 0.31, L / 2 + 0.17, L / 2 + 0.43])
+    r0 = np.stack([c - [0.75, 0.0, 0.0], c + [0.75, 0.0, 0.0]])
+    v0 = np.array([[1e-4, -0.5e-4, 0.3e-4], [-0.7e-4, 0.2e-4, 1e-4]])
+
+    def spread(sp, cube):
+        for p in range(8):
+            b = [(p >> k) & 1 for k in range(3)]
+            if cube:
+                q = [int(np.floor(sp[k] + 0.5)) - 1 + 2 * b[k] for k in range(3)]
+                w = np.prod([1.0 - abs(q[k] - sp[k]) / 2.0 for k in range(3)])
+            else:
+                q = [int(np.floor(sp[k])) + b[k] for k in range(3)]
+                w = np.prod([1.0 - abs(q[k] - sp[k]) for k in range(3)])
+            yield [qq % L for qq in q], w
+
+    power = {}
+    for mode in ("stokeslet2dx", "stokeslet_cube"):
+        s = oracle_mod.Sim(L, L, L, tau)
+        s.set_particles(r0, v0, mass=M, gamma=gamma, radius=R, friction=mode)
+        s.step(1500)
+        out = []
+        for _ in range(4):
+            r_n, v_n = s.particles()
+            _, u = s.moments()
+            s.step(1)
+            _, v_1 = s.particles()
+            fh, _ = s.particle_forces()
+            P = float(np.sum(fh * 0.5 * (v_n + v_1)))
+            for i in range(2):
+                for q, w in spread(r_n[i] % L, mode == "stokeslet_cube"):
+                    P += float(np.dot(-fh[i] * w, u[:, q[2], q[1], q[0]]))
+            out.append(P)
+            s.step(99)
+        power[mode] = out
+    assert all(P > 0.0 for P in power["stokeslet2dx"]), power
+    assert all(P < 0.0 for P in power["stokeslet_cube"]), power
+
+
 @pytest.mark.parametrize("q", [19, 15])
 def test_total_momentum_balance(oracle_mod, q):
     from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
