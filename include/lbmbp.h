@@ -80,12 +80,19 @@ typedef enum lbm_storage {
  * remedy section 2.2 names for large radii: the same fit on the eight corners
  * of a cube of edge 2 dx around the particle (per axis c0 and c0 + 2,
  * c0 = floor(s + 1/2) - 1); the reaction force is still spread to the corners
- * of the unit cell. */
+ * of the unit cell.  STOKESLET_CUBE: the same cube fit, with the reaction
+ * force (first Eq. s2-force, whose distance-dependent weights the paper leaves
+ * open) spread to the same eight cube corners with the cube's trilinear
+ * weights prod_k (1 - |q_k - s_k| / 2).  Reading the velocity on the cube but
+ * spreading on the unit cell lets a pair of particles within a few dx of each
+ * other gain energy from the coupling; on the same cube the exchange
+ * dissipates.  Not supported by the reverse mode (lbm_record). */
 typedef enum lbm_friction {
     LBM_FRICTION_STOKESLET = 0,
     LBM_FRICTION_POINTWISE = 1,
     LBM_FRICTION_BD = 2,
-    LBM_FRICTION_STOKESLET_2DX = 3
+    LBM_FRICTION_STOKESLET_2DX = 3,
+    LBM_FRICTION_STOKESLET_CUBE = 4
 } lbm_friction;
 
 typedef struct lbm_grid_desc {
@@ -403,7 +410,8 @@ lbm_status lbm_destroy(lbm_ctx *ctx);
  * the exact-arithmetic map taken along the stored trajectory, evaluated in
  * FP64.  The corner cell floor(s) and the fit's degenerate-case branches are
  * piecewise constant (zero derivative).  Supported for FP64 and FP32 storage
- * (LBM_E_UNSUPPORTED otherwise). */
+ * (LBM_E_UNSUPPORTED otherwise), and for every friction model but
+ * LBM_FRICTION_STOKESLET_CUBE. */
 
 /* Bytes of the checkpoint buffer for recording nsteps >= 1 with a checkpoint
  * every `every` >= 1 steps: ceil(nsteps/every) checkpoints of one lattice plus

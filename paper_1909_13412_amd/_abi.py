@@ -11,7 +11,7 @@ LBM_Q = 19
 STATUS = {0: "LBM_OK", 1: "LBM_E_INVAL", 2: "LBM_E_DEVICE", 3: "LBM_E_STATE",
           4: "LBM_E_NONFINITE", 5: "LBM_E_UNSUPPORTED"}
 STORAGE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
-FRICTION = {"stokeslet": 0, "pointwise": 1, "bd": 2, "stokeslet2dx": 3}
+FRICTION = {"stokeslet": 0, "pointwise": 1, "bd": 2, "stokeslet2dx": 3, "stokeslet_cube": 4}
 
 # every entry point of include/lbmbp.h
 EXPORTS = [

@@ -482,8 +482,9 @@ size_t particle_blocks(int32_t n) { return (size_t(n) * 8 + kParticleBlock - 1) 
 uint32_t coupling_warnings(int32_t friction, double R, int32_t n, double ncell) {
     uint32_t w = 0;
     const double s3 = sqrt(3.0);
-    if (friction == LBM_FRICTION_STOKESLET || friction == LBM_FRICTION_STOKESLET_2DX) {
-        const double span = friction == LBM_FRICTION_STOKESLET_2DX ? 2.0 : 1.0;  // cube edge
+    if (friction == LBM_FRICTION_STOKESLET || friction == LBM_FRICTION_STOKESLET_2DX ||
+        friction == LBM_FRICTION_STOKESLET_CUBE) {
+        const double span = friction == LBM_FRICTION_STOKESLET ? 1.0 : 2.0;  // cube edge
         if (R > s3 * span) w |= LBM_WARN_RADIUS_BOUND;
         if (R > 0.5 * s3 * span) w |= LBM_WARN_NEGATIVE_GAIN;
     }
@@ -1148,7 +1149,7 @@ lbm_status particles_couple(lbm_ctx *ctx, const lbm_particle_desc *d, double *r,
         if (!(d->gamma >= 0.0) || !isfinite(d->gamma)) return LBM_E_INVAL;
         if (!(d->kT >= 0.0) || !isfinite(d->kT)) return LBM_E_INVAL;
         if (!isfinite(d->radius)) return LBM_E_INVAL;
-        if (d->friction < LBM_FRICTION_STOKESLET || d->friction > LBM_FRICTION_STOKESLET_2DX)
+        if (d->friction < LBM_FRICTION_STOKESLET || d->friction > LBM_FRICTION_STOKESLET_CUBE)
             return LBM_E_INVAL;
     }
     // Node forces left by any previous particle set are cleared.
@@ -1588,7 +1589,7 @@ bool ens_desc_ok(const lbm_ensemble_desc *d, const lbm_replica_desc *reps) {
     if (d->storage == LBM_STORE_F16 && (d->f16_scale_log2 < 0 || d->f16_scale_log2 > 24)) return false;
     if (!(d->mass > 0.0) || !isfinite(d->mass) || !(d->gamma >= 0.0) || !isfinite(d->gamma)) return false;
     if (!(d->kT >= 0.0) || !isfinite(d->kT) || !isfinite(d->radius)) return false;
-    if (d->friction < LBM_FRICTION_STOKESLET || d->friction > LBM_FRICTION_STOKESLET_2DX) return false;
+    if (d->friction < LBM_FRICTION_STOKESLET || d->friction > LBM_FRICTION_STOKESLET_CUBE) return false;
     uint64_t cells = 0, n = 0;
     for (int32_t k = 0; k < d->nrep; ++k) {
         const lbm_replica_desc &r = reps[k];
@@ -2461,6 +2462,8 @@ lbm_status lbm_tape_bytes(const lbm_ctx *ctx, int32_t nsteps, int32_t every, siz
 lbm_status lbm_record(lbm_ctx *ctx, int32_t nsteps, int32_t every, void *tape) {
     if (!ctx || nsteps < 1 || every < 1 || !tape || !aligned(tape)) return LBM_E_INVAL;
     if (!adjoint_storage(ctx)) return LBM_E_UNSUPPORTED;
+    // the reverse sweep spreads on the unit cell (the cube spreading has no adjoint here)
+    if (ctx->np > 0 && ctx->pdesc.friction == LBM_FRICTION_STOKESLET_CUBE) return LBM_E_UNSUPPORTED;
     const TapeLayout t = tape_layout(ctx, ctx->np);
     ctx->rec_tape = tape;
     ctx->rec_n0 = ctx->step;
@@ -2506,6 +2509,8 @@ lbm_status lbm_adjoint(lbm_ctx *ctx, const void *tape, void *work, double *adj_p
                        double *adj_r, double *adj_v, double *adj_param) {
     if (!ctx || !tape || !work || !aligned(work) || !adj_pop || !adj_param) return LBM_E_INVAL;
     if (!adjoint_storage(ctx)) return LBM_E_UNSUPPORTED;
+    if (ctx->rec_np > 0 && ctx->rec_pdesc.friction == LBM_FRICTION_STOKESLET_CUBE)
+        return LBM_E_UNSUPPORTED;
     if (!ctx->rec_tape || tape != ctx->rec_tape) return LBM_E_STATE;
     if (ctx->rec_np > 0 && (!adj_r || !adj_v)) return LBM_E_INVAL;
     hipError_t e = hipSuccess;

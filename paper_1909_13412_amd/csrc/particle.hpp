@@ -74,8 +74,8 @@ struct FitTrace {
 // the group calls it and receives the same F_H.
 //   LBM_FRICTION_STOKESLET (Eq. s2-slet-v): e^N from the mean relative
 //     velocity, least-squares amplitude U^inf of the Stokeslet shape g_p,
-//     F_H = gamma U^inf e^N; LBM_FRICTION_STOKESLET_2DX is the same fit with
-//     u and d taken at the corners of the (2 dx)^3 cube;
+//     F_H = gamma U^inf e^N; LBM_FRICTION_STOKESLET_2DX and _CUBE are the
+//     same fit with u and d taken at the corners of the (2 dx)^3 cube;
 //   LBM_FRICTION_POINTWISE (Eq. s2-dis1): F_H = -gamma (V - u(r)) with u(r)
 //     interpolated trilinearly;
 //   LBM_FRICTION_BD (Eq. s2-dis0): F_H = -gamma V.
@@ -193,7 +193,17 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
     // The fit reads the same eight nodes, or those of the (2 dx)^3 cube.
     uint32_t fnode[3] = {node[0], node[1], node[2]};
     double dfit[3] = {d[0], d[1], d[2]};
-    if (pa.friction == LBM_FRICTION_STOKESLET_2DX) wide_corner(r, Ln, b, fnode, dfit);
+    const bool cube = pa.friction == LBM_FRICTION_STOKESLET_CUBE;
+    if (pa.friction == LBM_FRICTION_STOKESLET_2DX || cube) wide_corner(r, Ln, b, fnode, dfit);
+    // The reaction force goes to the unit cell's corner with its trilinear
+    // weight, or with the cube fit to this lane's cube corner with the cube's
+    // weight prod_k (1 - |d_k| / 2).
+    uint32_t scell = cell;
+    double sW = W;
+    if (cube) {
+        scell = (fnode[2] * g.ny + fnode[1]) * g.nx + fnode[0];
+        sW = (1.0 - 0.5 * fabs(dfit[0])) * (1.0 - 0.5 * fabs(dfit[1])) * (1.0 - 0.5 * fabs(dfit[2]));
+    }
 
     // Issue the gather of f^n at this lane's fitting node (pull from node -
     // e_a); the values are consumed only after the VACF sample and the
@@ -308,7 +318,7 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
         bool ok = true;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double c = -FH[k] * W;
+            const double c = -FH[k] * sW;
             ok = ok && (fabs(c) < kFixLimit);
             q[k] = __double2ll_rn(c * kFixScale);
         }
@@ -318,10 +328,10 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            atomicAdd(reinterpret_cast<unsigned long long *>(&cur.f[3 * uint64_t(cell) + k]),
+            atomicAdd(reinterpret_cast<unsigned long long *>(&cur.f[3 * uint64_t(scell) + k]),
                       static_cast<unsigned long long>(q[k]));
-        atomicOr(&cur.mask[cell >> 5], 1u << (cell & 31));
-        my_cell = cell;
+        atomicOr(&cur.mask[scell >> 5], 1u << (scell & 31));
+        my_cell = scell;
     }
     pa.prev_cell[8 * i + p] = my_cell;
 

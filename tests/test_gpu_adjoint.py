@@ -397,3 +397,16 @@ def test_adjoint_with_pair_repulsion_matches_oracle(oracle_mod):
             nmax_err(g["params"], gth))
     announce(f"adjoint with pair repulsion: {errs}")
     assert max(errs) < 1e-10
+
+
+def test_reverse_mode_refuses_cube_spreading():
+    # the reverse sweep spreads on the unit cell; a run with the reaction force
+    # spread on the fitting cube is refused rather than differentiated wrongly
+    from paper_1909_13412_amd import LbmError, Lattice
+
+    lat = Lattice(12, 10, 8, 0.8, storage="f64")
+    lat.particles_couple(np.array([[3.3, 4.2, 5.7]]), np.array([[1e-3, 0.0, 0.0]]),
+                         friction="stokeslet_cube", radius=0.8)
+    with pytest.raises(LbmError):
+        lat.record(5, 5)
+    lat.step(3)  # stepping itself is supported

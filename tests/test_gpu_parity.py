@@ -166,7 +166,7 @@ def test_relaxation32_full_trace(oracle_mod):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-@pytest.mark.parametrize("friction", ["stokeslet", "pointwise", "bd", "stokeslet2dx"])
+@pytest.mark.parametrize("friction", ["stokeslet", "pointwise", "bd", "stokeslet2dx", "stokeslet_cube"])
 def test_ragged_suspension(oracle_mod, storage, friction):
     # Box sizes that are not multiples of the block, several blocks, noise on.
     from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
@@ -764,22 +764,24 @@ def test_body_force_alone_is_exact_momentum_input():
     assert np.allclose(lat.observables()[1:4], o[1:4], rtol=1e-13, atol=0)
 
 
-def test_wide_fit_at_seams_and_shared_nodes(oracle_mod):
+@pytest.mark.parametrize("friction", ["stokeslet2dx", "stokeslet_cube"])
+def test_wide_fit_at_seams_and_shared_nodes(oracle_mod, friction):
     # The (2 dx)^3 fitting cube reaches one node beyond the unit cell on each
     # side: positions within half a node of the seams (c0 = -1 or c0 + 2 = L)
-    # and beyond the box, with particles sharing fitting nodes.
+    # and beyond the box, with particles sharing fitting nodes (and, with the
+    # cube spreading, the nodes their reaction forces go to).
     nx, ny, nz = (11, 9, 8)
     r = np.array([[0.2, 0.3, 0.1], [10.8, 8.7, 7.6], [-0.4, 4.5, 9.9], [5.5, 4.5, 3.5],
                   [5.9, 4.1, 3.2], [21.3, -8.6, 15.8]])
     v = np.random.default_rng(5).standard_normal((6, 3)) * 1e-3
     out = run_pair(oracle_mod, (nx, ny, nz), 0.8, "f64", r, v, 30, kT=1e-4, seed=9,
-                   friction="stokeslet2dx", radius=1.2)
-    _compare_particles(out["gpu"], out["ref"], 1e-10, "wide fit seams")
-    _compare_fields(out["gpu"], out["ref"], 1e-10, "wide fit seams")
+                   friction=friction, radius=1.2)
+    _compare_particles(out["gpu"], out["ref"], 1e-10, f"{friction} seams")
+    _compare_fields(out["gpu"], out["ref"], 1e-10, f"{friction} seams")
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-@pytest.mark.parametrize("friction", ["stokeslet", "pointwise", "stokeslet2dx"])
+@pytest.mark.parametrize("friction", ["stokeslet", "pointwise", "stokeslet2dx", "stokeslet_cube"])
 def test_fifteen_velocity_suspension(oracle_mod, storage, friction):
     # The paper's own velocity set: ragged box, noise, body force, three
     # friction models.

@@ -132,6 +132,18 @@ def test_fig1_wide_fit_extends_stokes_law_to_larger_radius(where):
         assert abs(K / KH - 1.0) < 0.10
 
 
+@pytest.mark.parametrize("where", list(POSITIONS))
+def test_fig1_cube_fit_and_spreading_follow_stokes_law(where):
+    """The cube fit with the reaction force spread on the same cube (reading
+    of the first Eq. s2-force's weights): Stokes' law within 8% at R = 0.6,
+    0.8, 1.0 wherever the particle sits (measured 3-6%)."""
+    for R in (0.6, 0.8, 1.0):
+        K = drag_ratio(R, "stokeslet_cube", POSITIONS[where])
+        KH = hasimoto(R, L1)
+        announce(f"Fig. 1 cube fit and spreading {where}: R={R} K={K:.4f} Hasimoto {KH:.4f}")
+        assert abs(K / KH - 1.0) < 0.08
+
+
 def test_fig1_unit_fit_reverses_near_a_node():
     """Within a small distance of a node the unit-cell fit's gain is negative
     (the closed-form limit is pinned in the oracle): the steady drag on a held
@@ -218,6 +230,80 @@ def test_fig2_velocity_relaxation_against_hydrodynamic_memory():
     e_pointwise = np.max(np.abs(pointwise[20:501] - phi[20:501]))
     announce(f"  max deviation over lags 20..500: present {e_present:.4f}, pointwise {e_pointwise:.4f}")
     assert e_pointwise > 2.0 * e_present
+
+
+def test_fig2_cube_spreading_relaxation():
+    """The kicked particle of Fig. 2 with the cube fit and cube spreading:
+    the closed form's tail (within 25% from lag 50 on, local exponent -3/2
+    over lags 500..2000)."""
+    from analytic import velocity_relaxation
+
+    lags = 2000
+    nu = (TAU1 - 0.5) / 3.0
+    gamma = 6.0 * math.pi * nu * R2
+    phi = velocity_relaxation(np.arange(lags + 1), M2, gamma, R2, nu)
+    cube = _kick_response("stokeslet_cube", lags).mean(0)
+    late = [50, 100, 200, 500, 1000, 2000]
+    rel = np.abs(cube[late] / phi[late] - 1.0)
+    announce("Fig. 2 cube: " + ", ".join(f"{k}: {phi[k]:.5f} {cube[k]:.5f}" for k in late)
+             + f" (closed form, cube); relative {np.round(rel, 3).tolist()}")
+    assert np.max(rel) < 0.25
+    slope = math.log(cube[2000] / cube[500]) / math.log(4.0)
+    assert abs(slope + 1.5) < 0.2
+
+
+def _thermal_fig2(friction, steps, lags=2000):
+    """The paper's thermal Fig. 2 suspension: 500 particles of R = 1 dx, M = 16,
+    friction 6 pi eta R, at kT = 3.3e-7 (300 K) in a 100^3 box at tau 0.5534,
+    FP32; 5000 steps to settle, then `steps` more with the VACF accumulated
+    (origins every 10 steps).  Returns (M<V^2>/3kT every 4000 steps, C/C(0))."""
+    from paper_1909_13412_amd import Lattice
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    L, n, M, R, kT = 100, 500, 16.0, 1.0, 3.3e-7
+    nu = (TAU1 - 0.5) / 3.0
+    lat = Lattice(L, L, L, TAU1, storage="f32")
+    lat.particles_couple(particle_positions(n, L, 77), particle_velocities(n, kT / M, 77), mass=M,
+                         gamma=6.0 * math.pi * nu * R, kT=kT, radius=R, seed=77, friction=friction)
+    lat.step(5000)
+    lat.vacf_config(lags, 10)
+    temps, done = [], 0
+    while done < steps:
+        lat.step(4000)
+        done += 4000
+        v = lat.v.cpu().numpy()
+        temps.append(float(M * np.mean(np.sum(v ** 2, axis=1)) / (3.0 * kT)))
+    acc, cnt = lat.vacf()
+    C = acc.sum(0).cpu().numpy() / (n * np.maximum(cnt, 1))
+    return np.array(temps), C / C[0]
+
+
+def test_fig2_thermal_suspension_stable_with_cube_spreading():
+    """R30: with the fit on the (2 dx)^3 cube and the reaction force spread on
+    the unit cell, pairs of particles a few dx apart draw energy from the
+    coupling and the paper's thermal Fig. 2 suspension heats up without bound
+    (the particle temperature grows about tenfold within 20,000 steps here);
+    spreading on the same cube keeps it at a steady temperature over 60,000
+    steps.  The stationary C_v then has a power-law tail; with the random force
+    on the particles only (R13) it decays more slowly than the closed form of
+    the response (R26), and M<V^2>/3kT settles below one (R31): both recorded."""
+    from analytic import velocity_relaxation
+
+    t_unit, _ = _thermal_fig2("stokeslet2dx", 32000)
+    announce(f"Fig. 2 thermal, unit-cell spreading: M<V^2>/3kT {np.round(t_unit, 3).tolist()}")
+    assert t_unit[-1] > 5.0 * t_unit[0]
+    temps, C = _thermal_fig2("stokeslet_cube", 60000)
+    nu = (TAU1 - 0.5) / 3.0
+    phi = velocity_relaxation(np.arange(2001), M2, 6.0 * math.pi * nu * R2, R2, nu)
+    ks = [1, 10, 50, 100, 200, 500, 1000, 2000]
+    announce(f"Fig. 2 thermal, cube spreading: M<V^2>/3kT {np.round(temps, 3).tolist()}")
+    announce("  C_v: " + ", ".join(f"{k}: {C[k]:.5f} (closed form {phi[k]:.5f})" for k in ks))
+    assert np.max(temps) < 1.5 * np.min(temps) and 0.3 < np.mean(temps) < 2.0
+    coarse = C[[0, 1, 10, 50, 100, 200, 500, 1000, 2000]]
+    assert np.all(np.diff(coarse) < 0.0) and C[2000] > 0.0
+    slope = math.log(C[2000] / C[500]) / math.log(4.0)
+    announce(f"  local exponent over lags 500..2000: {slope:.3f}")
+    assert -1.8 < slope < -1.0
 
 
 # ---- Fig. 3 ----------------------------------------------------------------------
