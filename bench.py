@@ -55,9 +55,12 @@ def kernel_source_hash() -> str:
 
 
 def pmc_traffic(storage: str):
-    """HBM bytes per stream-collide launch from the committed FETCH_SIZE /
-    WRITE_SIZE profile (scaled by the copy-kernel calibration), or None when
-    the kernel sources changed since the counters were taken."""
+    """HBM bytes per stream-collide launch from the committed counter profile:
+    the L2's read requests to memory counted by size (32 x TCC_EA0_RDREQ_32B +
+    64 x TCC_EA0_RDREQ_64B + 128 x TCC_EA0_RDREQ_128B) plus its write requests
+    (64 x TCC_EA0_WRREQ_64B + 32 x the rest), the rule that gives a plain
+    device copy's bytes exactly; None when the kernel sources changed since
+    the counters were taken."""
     try:
         with open(PMC_PROFILE) as fh:
             line = next(ln for ln in fh if ln.strip().startswith("PMC_TRAFFIC "))
@@ -67,7 +70,7 @@ def pmc_traffic(storage: str):
     if rec.get("source_sha256") != kernel_source_hash() or not rec.get(storage):
         return None
     c = rec[storage]
-    return (c["fetch_kib"] * rec["fetch_scale"] + c["write_kib"] * rec["write_scale"]) * 1024.0
+    return float(c["read_bytes"] + c["write_bytes"])
 
 
 def parse_variant(name: str):
@@ -776,8 +779,9 @@ def main():
             "traffic": traffic,
             "traffic_frac": (round(traffic / (main_res["collide_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
                              if traffic else None),
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, "
-                            "copy-calibrated; null if the kernels changed since)",
+            "traffic_unit": "bytes per launch (rocprofv3: L2 read requests to memory x their size "
+                            "(32/64/128 B) + write requests x their size; a plain copy reads "
+                            "exactly its bytes this way; null if the kernels changed since)",
             "algorithmic_bytes_per_launch": collide_bytes_per_node(args.storage) * ncell,
             "bytes_per_node": collide_bytes_per_node(args.storage),
             "avg_launch_ms": round(main_res["collide_ms"], 5),
