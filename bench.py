@@ -330,8 +330,8 @@ def time_ensemble(steps, warmup):
     VACF on): whole-ensemble MLUPS with graph-replayed steps and with plain
     launches, and the ensemble-averaged VACF.  The graph-replayed run takes
     exactly `steps` steps from the initial state (the autotuner leaves the
-    state untouched), so at 5000 steps its smallest and largest boxes are
-    compared with the oracle's own runs of those boxes
+    state untouched), so at 5000 steps one box of each edge is compared with
+    the oracle's own run of that box alone
     (tests/golden/oracle_ensemble64_edges.json)."""
     import numpy as np
     import torch
@@ -662,7 +662,7 @@ def main():
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=5000,
                     help="0 = skip the ensemble timing (5000: the workload's length, checked against "
-                         "the oracle's runs of its smallest and largest boxes)")
+                         "the oracle's runs of one box of each edge)")
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="0 = skip the reverse-mode leg (2000: the workload's length, with the "
                          "mean-squared-displacement gradient and its finite differences)")
