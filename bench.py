@@ -97,7 +97,7 @@ def make_lattice(w, storage, device="cuda:0", series_capacity=0, q=19):
     lat = Lattice(L, L, L, w["tau"], storage=storage, device=device, velocities=q)
     r, v = workload_particles(w["name"])
     lat.particles_couple(r, v, mass=w["mass"], gamma=w["gamma"], kT=w["kT"], radius=w["radius"],
-                         seed=w["seed"])
+                         seed=w["seed"], friction=w.get("friction", "stokeslet"))
     lat.vacf_config(w["max_lag"], w["stride"])
     if series_capacity > 0:
         lat.series_config(SERIES_EVERY, series_capacity)
@@ -258,7 +258,7 @@ def vacf_errors(c, c_ref, tail, per_particle=None):
 # Tail windows of the precision study: past the Brownian relaxation time
 # M / gamma = 10 steps, up to a lag where the reference curve is still a few
 # per mille of C(0).
-TAIL = {"vacf128": (50, 500), "suspension256": (50, 250)}
+TAIL = {"vacf128": (50, 500), "suspension256": (50, 250), "fig2thermal100": (100, 1000)}
 
 
 def run_precision(w, storage, steps, every):
@@ -330,8 +330,8 @@ def time_ensemble(steps, warmup):
     VACF on): whole-ensemble MLUPS with graph-replayed steps and with plain
     launches, and the ensemble-averaged VACF.  The graph-replayed run takes
     exactly `steps` steps from the initial state (the autotuner leaves the
-    state untouched), so at 5000 steps one box of each edge is compared with
-    the oracle's own run of that box alone
+    state untouched), so at 5000 steps its smallest and largest boxes are
+    compared with the oracle's own run of that box alone
     (tests/golden/oracle_ensemble64_edges.json)."""
     import numpy as np
     import torch
@@ -652,6 +652,10 @@ def main():
                     help="0 = skip the precision study on the 128^3 / 64-particle VACF workload "
                          "(its 20,000 steps against the oracle's run; also skipped with "
                          "--precision-steps 0)")
+    ap.add_argument("--fig2-steps", type=int, default=12000,
+                    help="0 = skip the precision study on the paper's thermal Fig. 2 suspension "
+                         "(100^3, 500 particles of R = 1 on the (2 dx)^3 cube; its 12,000 steps "
+                         "against the oracle's run; also skipped with --precision-steps 0)")
     ap.add_argument("--cpu-steps", type=int, default=90, help="oracle steps timed (0 = skip; 90 is ~11 s on 16 host threads)")
     ap.add_argument("--cpu-steps-one-thread", type=int, default=6,
                     help="oracle steps timed on one host thread, in a child process (0 = skip; also skipped with --cpu-steps 0; 6 is ~10 s)")
@@ -662,7 +666,7 @@ def main():
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=5000,
                     help="0 = skip the ensemble timing (5000: the workload's length, checked against "
-                         "the oracle's runs of one box of each edge)")
+                         "the oracle's runs of its smallest and largest boxes)")
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="0 = skip the reverse-mode leg (2000: the workload's length, with the "
                          "mean-squared-displacement gradient and its finite differences)")
@@ -735,6 +739,15 @@ def main():
         w128 = dict(WORKLOADS["vacf128"])
         w128["name"] = "vacf128"
         precision128 = precision_study(w128)
+    precision_fig2 = None
+    if args.precision_steps > 0 and args.fig2_steps > 0:
+        print(f"[bench] precision study, fig2thermal100 ({args.fig2_steps} steps per storage)",
+              file=sys.stderr, flush=True)
+        from paper_1909_13412_amd.inputs import WORKLOADS
+
+        wf2 = dict(WORKLOADS["fig2thermal100"])
+        wf2["name"] = "fig2thermal100"
+        precision_fig2 = precision_study(wf2)
     cpu = None
     if args.cpu_steps > 0:
         print(f"[bench] oracle baseline ({args.cpu_steps} steps)", file=sys.stderr, flush=True)
@@ -810,6 +823,7 @@ def main():
         "adjoint": adjoint,
         "precision": precision,
         "precision_vacf128": precision128,
+        "precision_fig2thermal100": precision_fig2,
         "size_sweep": sweep,
         "cpu_baseline": cpu,
         "cpu_baseline_one_thread": cpu1,

@@ -21,6 +21,12 @@ friction once R exceeds about 0.87 (the fitted gain for a particle at a cell
 centre in a uniform stream is 1 - 2R/sqrt(3)), so the coupled run diverges; the
 suspensions therefore keep the friction constant 1 and fix R = 0.5.
 
+* ``fig2thermal100`` -- the thermal suspension of the paper's Fig. 2 (section 3)
+  in lattice units: 100^3, tau 0.5534 (nu = 0.89e-6 m^2/s at dx = 5 nm,
+  dt = 0.5 ps), 500 particles of R = 1 and M = 16, friction 6 pi rho0 nu R,
+  kT = 3.3e-7 (300 K), the fit and the spreading on the (2 dx)^3 cube (the
+  unit-cell fit has negative gain at R = 1), 12000 steps, lags to 1000.
+
 * ``ENSEMBLE64``    -- 64 independent cubic boxes with edges drawn from
   {48, 64, 80, 96}, tau 0.8, 8 particles each, kT = 1e-4, FP32.
 
@@ -40,6 +46,10 @@ WORKLOADS = {
                           radius=0.5, steps=2000, seed=3003, max_lag=500, stride=10),
     "suspension512": dict(L=512, tau=0.6, storage="f32", n=4096, mass=10.0, gamma=1.0, kT=1e-4,
                           radius=0.5, steps=2000, seed=3004, max_lag=500, stride=10),
+    "fig2thermal100": dict(L=100, tau=0.5534, storage="f32", n=500, mass=16.0,
+                           gamma=6.0 * np.pi * (0.5534 - 0.5) / 3.0, kT=3.3e-7, radius=1.0,
+                           friction="stokeslet_cube", steps=12000, seed=2019, max_lag=1000,
+                           stride=10),
 }
 
 

@@ -13,14 +13,18 @@ the GPU package is imported).  Each fixture is one JSON file in this folder:
 * ``oracle_suspension256.json``: the 256^3 suspension (tau 0.6, 4096
   particles, R 0.5, kT 1e-4, seed 3003) over 2,000 steps: C(l) for lags
   0..500 and the sums every 10 steps.
+* ``oracle_fig2thermal100.json``: the paper's thermal Fig. 2 suspension
+  (100^3, tau 0.5534, 500 particles, R = 1, M = 16, kT 3.3e-7, fit and
+  spreading on the (2 dx)^3 cube, seed 2019) over 12,000 steps: C(l) for lags
+  0..1000 and the sums every 100 steps.
 * ``oracle_ensemble64_edges.json``: the smallest and the largest box of the
   64-box ensemble (edges 48 and 96, tau 0.8, 8 particles, kT 1e-4) over
   5,000 steps, each run as the single box the ensemble replica stands for:
   C(l) for lags 0..1000 and the final particle state.
 
 Usage: python tests/golden/make_oracle_fixtures.py [vacf128] [suspension256]
-[ensemble]   (no argument: all of them).  The 128^3 and 256^3 runs take about
-20 minutes each on 8 host threads.
+[fig2thermal100] [ensemble]   (no argument: all of them).  The 128^3 and 256^3
+runs take about 20 minutes each on 8 host threads.
 """
 from __future__ import annotations
 
@@ -91,7 +95,7 @@ def make_workload(name, series_every):
     sim = oracle.Sim(L, L, L, w["tau"])
     r, v = INPUTS.workload_particles(name)
     sim.set_particles(r, v, mass=w["mass"], gamma=w["gamma"], kT=w["kT"], radius=w["radius"],
-                      seed=w["seed"])
+                      seed=w["seed"], friction=w.get("friction", "stokeslet"))
     sim.vacf_config(w["max_lag"], w["stride"])
     t0 = time.time()
     series = _series_run(sim, w["steps"], series_every)
@@ -101,6 +105,7 @@ def make_workload(name, series_every):
     rec = {
         "workload": name, "box": [L, L, L], "tau": w["tau"], "particles": w["n"],
         "mass": w["mass"], "gamma": w["gamma"], "kT": w["kT"], "radius": sim.radius,
+        "friction": w.get("friction", "stokeslet"),
         "seed": w["seed"], "steps": w["steps"], "max_lag": w["max_lag"], "stride": w["stride"],
         "storage": "oracle FP64", "citation": CITATION,
         "vacf": [float(x) for x in c], "vacf_counts": [int(x) for x in cnt],
@@ -108,7 +113,7 @@ def make_workload(name, series_every):
         "series_columns": ["step", "fluid mass", "fluid Px", "fluid Py", "fluid Pz",
                            "particle Px", "particle Py", "particle Pz"],
         "series": series,
-        "final_v": vf.tolist() if w["n"] <= 64 else None,
+        "final_v": vf.tolist() if w["n"] <= 500 else None,
         "oracle_threads": oracle.num_threads(), "oracle_seconds": round(wall, 1),
         "generator": "tests/golden/make_oracle_fixtures.py",
     }
@@ -149,7 +154,7 @@ def make_ensemble_edges():
 
 
 def main(argv):
-    what = argv or ["vacf128", "suspension256", "ensemble"]
+    what = argv or ["vacf128", "suspension256", "fig2thermal100", "ensemble"]
     oracle.build(force=False)
     for item in what:
         t = time.time()
@@ -157,6 +162,8 @@ def main(argv):
             make_workload("vacf128", 100)
         elif item == "suspension256":
             make_workload("suspension256", 10)
+        elif item == "fig2thermal100":
+            make_workload("fig2thermal100", 100)
         elif item == "ensemble":
             make_ensemble_edges()
         else:

@@ -1,7 +1,10 @@
 """Long runs of every storage against the FP64 oracle's own runs of the same
 workloads (tests/golden/oracle_*.json, written by make_oracle_fixtures.py from
-the oracle alone): the 128^3 VACF workload over its full 20,000 steps and the
-256^3 suspension over its 2,000 steps, same seeds and the same Philox noise.
+the oracle alone): the 128^3 VACF workload over its full 20,000 steps, the
+256^3 suspension over its 2,000 steps, and the paper's thermal Fig. 2
+suspension (100^3, 500 particles of R = 1 and M = 16 at 300 K, fit and
+spreading on the (2 dx)^3 cube) over 12,000 steps; same seeds and the same
+Philox noise.
 
 The observable is the velocity autocorrelation C(l) = <V(t0).V(t0 + l)> of
 section 2.1 (Figs. 2 and 3 of section 3), averaged over particles and origins.
@@ -69,3 +72,8 @@ def test_vacf128_full_run_against_oracle(storage):
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16", "f16"])
 def test_suspension256_full_run_against_oracle(storage):
     _check("suspension256", storage)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16", "f16"])
+def test_fig2thermal_full_run_against_oracle(storage):
+    _check("fig2thermal100", storage)
