@@ -121,6 +121,7 @@ def time_storage(w, variant, steps, warmup, prof_steps, pair=None, repeats=0):
     torch.cuda.synchronize()
     shape, shape_ms = lat.autotune(20)
     order, cap = lat.sweep_launch
+    rows = lat.layout
     lat.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -164,6 +165,7 @@ def time_storage(w, variant, steps, warmup, prof_steps, pair=None, repeats=0):
         "collide_shape": shape,
         "collide_order": order,
         "collide_waves_per_simd_cap": cap,
+        "layout_rows_per_group": rows,
         "stream_only_ms": ceil_ms,
         "of_stream_only": ceil_ms / coll_ms,
         "autotune_ms": [round(float(x), 5) for x in shape_ms],
@@ -534,6 +536,7 @@ def time_large(steps, warmup):
                         "collide_frac": round(r["collide_frac"], 4), "collide_shape": r["collide_shape"],
                         "collide_order": r["collide_order"],
                         "collide_waves_per_simd_cap": r["collide_waves_per_simd_cap"],
+                        "layout_rows_per_group": r["layout_rows_per_group"],
                         "stream_only_ms": round(r["stream_only_ms"], 5),
                         "of_stream_only": round(r["of_stream_only"], 4)}
         torch.cuda.empty_cache()
@@ -801,6 +804,7 @@ def main():
             "launch_shape": main_res["collide_shape"],
             "launch_order": main_res["collide_order"],
             "launch_waves_per_simd_cap": main_res["collide_waves_per_simd_cap"],
+            "layout_rows_per_group": main_res["layout_rows_per_group"],
             "autotune_ms": main_res["autotune_ms"],
             "pattern_ceiling": {
                 "kernel": "k_stream_only",

@@ -338,14 +338,18 @@ lbm_status lbm_profile_read(lbm_ctx *ctx, double out[4]);
  * launches each, reading the current populations and writing the spare
  * lattice, so the simulation state is not changed) and keep the fastest for
  * later lbm_step calls: first every valid configuration in linear block order
- * without a residency cap, then the two fastest of them with every block
- * order and residency cap (lbm_set_sweep_launch).  Synchronises the stream.
+ * without a residency cap in every storage layout (lbm_set_layout: the state
+ * is permuted between layouts, values unchanged), then in the layout of the
+ * fastest the two fastest configurations with every block order and residency
+ * cap (lbm_set_sweep_launch), and the launch chosen so in every other layout.
+ * Synchronises the stream.
  * ms (host, LBM_NUM_SHAPES entries, may be NULL) receives per configuration
  * the best mean milliseconds per launch over the options timed with it (-1
  * for a configuration that does not apply, or that repeats another's lane
  * mapping exactly: 8 and 9 when 64 | nx and nx divides 256 or 256 divides
  * nx); *chosen (may be NULL) the configuration kept (lbm_get_sweep_launch
- * gives its block order and cap).  The choice is also remembered for
+ * gives its block order and cap, lbm_get_layout the layout).  The choice is
+ * also remembered for
  * contexts created later with the same device, storage, velocity set and box
  * size (process lifetime, thread-safe). */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen);
@@ -388,6 +392,26 @@ lbm_status lbm_get_shape(const lbm_ctx *ctx, int32_t *k);
  * does not fit the new configuration). */
 lbm_status lbm_set_sweep_launch(lbm_ctx *ctx, int32_t order, int32_t waves_per_simd);
 lbm_status lbm_get_sweep_launch(const lbm_ctx *ctx, int32_t *order, int32_t *waves_per_simd);
+
+/* Storage layout of the two lattice buffers (the populations that the pull
+ * streaming of Eq. s2-trans reads): the lattice rows (y, z) are taken
+ * rows_per_group at a time (1, 2, 4, 8, 16, 32 or 64, a divisor of ny), and a group
+ * stores, for each population a in turn, its rows one after another, x
+ * fastest: element (a, x, y, z) at
+ *   ((z*ny + R*(y/R))*Q + y mod R)*nx + a*R*nx + x,   R = rows_per_group.
+ * Longer runs per population can stream faster; the values are the same in
+ * every layout.  lbm_set_layout moves the current populations into the new
+ * layout (a permutation written through the spare lattice, which becomes the
+ * current one; asynchronous); the FP64 field I/O is canonical in every
+ * layout.  A run kept by lbm_record holds lattices in the layout it was
+ * recorded in: lbm_adjoint returns LBM_E_STATE while another layout is in
+ * use (setting the recorded one back makes it usable).  lbm_autotune chooses
+ * the layout
+ * with the launch options; until then a context starts from the last choice
+ * for its key, else 1.  LBM_E_INVAL for a NULL ctx or a rows_per_group that is
+ * not one of these values or does not divide ny. */
+lbm_status lbm_set_layout(lbm_ctx *ctx, int32_t rows_per_group);
+lbm_status lbm_get_layout(const lbm_ctx *ctx, int32_t *rows_per_group);
 
 /* Number of steps taken since lbm_init (the time index n of Eq. s2-lbe). */
 lbm_status lbm_get_step(const lbm_ctx *ctx, int64_t *step);
@@ -444,7 +468,9 @@ lbm_status lbm_adjoint_work_bytes(const lbm_ctx *ctx, size_t *bytes);
  *              only for kT > 0 (0 otherwise: sqrt(kT) has no derivative at 0).
  * Node contributions of particles that share a node are added with FP64
  * atomics, so repeated runs agree to rounding rather than bitwise when two
- * particles touch the same node in a step. */
+ * particles touch the same node in a step.  LBM_E_STATE if tape is not the
+ * last recorded run, or the lattice layout (lbm_set_layout) is not the one
+ * it was recorded in. */
 lbm_status lbm_adjoint(lbm_ctx *ctx, const void *tape, void *work, double *adj_pop,
                        double *adj_r, double *adj_v, double *adj_param);
 

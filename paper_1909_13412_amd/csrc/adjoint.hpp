@@ -359,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(const typename C::T *__r
         const double Gx = 3.0 * Qx + 9.0 * Tx - 3.0 * P * ux;
         const double Gy = 3.0 * Qy + 9.0 * Ty - 3.0 * P * uy;
         const double Gz = 3.0 * Qz + 9.0 * Tz - 3.0 * P * uz;
-        const uint64_t row_base = uint64_t(z * g.ny + y) * Vs::Q * gd.chunk + x;
+        const uint64_t row_base = row_index<Vs>(gd, y, z) + x;
         static_for<0, Vs::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
             constexpr int cx = Vs::ex[a], cy = Vs::ey[a], cz = Vs::ez[a];
@@ -367,9 +367,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(const typename C::T *__r
                          omega * (P + double(cx) * Gx + double(cy) * Gy + double(cz) * Gz);
             if constexpr (FORCED) out += double(cx) * Ux + double(cy) * Uy + double(cz) * Uz;
             if constexpr (NTS)
-                __builtin_nontemporal_store(out, &Bbar[row_base + uint64_t(a) * gd.chunk]);
+                __builtin_nontemporal_store(out, &Bbar[row_base + uint64_t(a) * gd.pstride]);
             else
-                Bbar[row_base + uint64_t(a) * gd.chunk] = out;
+                Bbar[row_base + uint64_t(a) * gd.pstride] = out;
         });
     }
     // dJ/domega of this block, added to its own running slot (fixed order).

@@ -2,12 +2,18 @@
 // (section 2.2: Eqs. s2-lbe, s2-collision, s2-eq, s2-coll, s2-trans and the
 // second Eq. s2-force), and the data layout it streams.
 //
-// Layout: for every lattice row (y, z) the 19 population rows are stored one
-// after another, x fastest: element (a, x, y, z) sits at
-// ((z*ny + y)*Q + a)*chunk + x with chunk = nx (no padding: the rows of a
-// group are back to back).  A block streams whole rows, so each wave reads
-// from nine 19-row groups and writes one contiguous group; this beats one
-// plane per velocity (38 far-apart streams).
+// Layout: the lattice rows (y, z) are taken Y at a time (Y = 1, 2, 4, ..., 64,
+// a divisor of ny: rows y with the same y / Y and z form a group); a group
+// stores, for each population a in turn, its Y rows one after another, x
+// fastest.  Element (a, x, y, z) sits at
+// ((z*ny + Y*(y/Y))*Q + (y mod Y))*chunk + a*Y*chunk + x with chunk = nx (no
+// padding).  A block streams whole rows, so each wave reads from nine row
+// groups and writes into one; with Y > 1 a population's rows of a group are
+// one run of Y*nx elements, so the pulls of consecutive rows continue the same
+// runs (fewer, longer streams).  Y = 1 puts the 19 population rows of each
+// lattice row back to back; one plane per velocity (38 far-apart streams) is
+// slower than either.  Y is a property of the context, chosen by the
+// autotuner (same bits in every layout).
 // Lattice A holds post-collision values at their source node, so the
 // post-streaming population is read by pulling from x - e_a.
 #pragma once
@@ -34,13 +40,29 @@ constexpr uint32_t kErrFixRange = 1u;
 struct Grid {
     uint32_t nx, ny, nz;
     uint32_t ncell;
-    uint32_t chunk;  // elements per population row (nx)
+    uint32_t chunk;    // elements per population row (nx)
+    uint32_t ymask;    // rows per group minus one (Y - 1; Y a power of two dividing ny)
+    uint32_t pstride;  // elements from one population of a node to the next (Y * chunk)
 };
+
+// A Grid with Y rows per group (Y a power of two that divides ny).
+__host__ __device__ inline Grid with_rows_per_group(Grid g, uint32_t Y) {
+    g.ymask = Y - 1u;
+    g.pstride = Y * g.chunk;
+    return g;
+}
+
+// Storage index of population 0 of node (0, y, z): the start of its group
+// plus its row within the group.
+template <class V>
+__device__ inline uint64_t row_index(const Grid &g, uint32_t y, uint32_t z) {
+    return (uint64_t(z * g.ny + (y & ~g.ymask)) * V::Q + (y & g.ymask)) * g.chunk;
+}
 
 // Storage index of population a at node (x, y, z) for velocity set V.
 template <class V>
 __device__ inline uint64_t pop_index(const Grid &g, uint32_t x, uint32_t y, uint32_t z, int a) {
-    return (uint64_t(z * g.ny + y) * V::Q + uint32_t(a)) * g.chunk + x;
+    return row_index<V>(g, y, z) + uint64_t(a) * g.pstride + x;
 }
 
 // Node forces of one step: a dense fixed-point field, written only at the
@@ -189,7 +211,7 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
                 Fz += R(double(ff.f[3 * cell + 2]) * kFixInv);
             }
         }
-        const uint64_t row_base = uint64_t(z * g.ny + y) * V::Q * g.chunk + x;
+        const uint64_t row_base = row_index<V>(g, y, z) + x;
         static_for<0, V::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
             constexpr int cx = V::ex[a], cy = V::ey[a], cz = V::ez[a];
@@ -204,9 +226,9 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
             if constexpr (a != 0) gn += R(3) * w * eF;
             // written once and read only by the next step
             if constexpr (NTS)
-                __builtin_nontemporal_store(C::enc(gn, enc_s), &B[row_base + uint64_t(a) * g.chunk]);
+                __builtin_nontemporal_store(C::enc(gn, enc_s), &B[row_base + uint64_t(a) * g.pstride]);
             else
-                B[row_base + uint64_t(a) * g.chunk] = C::enc(gn, enc_s);
+                B[row_base + uint64_t(a) * g.pstride] = C::enc(gn, enc_s);
         });
     }
 }
@@ -313,13 +335,13 @@ __device__ inline void stream_only_lane(const typename C::T *__restrict__ A,
     }
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-        const uint64_t row_base = uint64_t(z * g.ny + y0 + uint32_t(c) * rows) * V::Q * g.chunk + x;
+        const uint64_t row_base = row_index<V>(g, y0 + uint32_t(c) * rows, z) + x;
         static_for<0, V::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
             if constexpr (NTS)
-                __builtin_nontemporal_store(raw[c][a], &B[row_base + uint64_t(a) * g.chunk]);
+                __builtin_nontemporal_store(raw[c][a], &B[row_base + uint64_t(a) * g.pstride]);
             else
-                B[row_base + uint64_t(a) * g.chunk] = raw[c][a];
+                B[row_base + uint64_t(a) * g.pstride] = raw[c][a];
         });
     }
 }

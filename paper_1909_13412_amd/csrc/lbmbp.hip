@@ -270,6 +270,21 @@ __global__ __launch_bounds__(kBlock) void k_set_equilibrium(const double *__rest
     });
 }
 
+// The same populations in another row-group layout: B[in layout gb] =
+// A[in layout ga], element for element (a permutation; no arithmetic).
+template <class C>
+__global__ __launch_bounds__(kBlock) void k_relayout(const typename C::T *__restrict__ A, Grid ga,
+                                                     typename C::T *__restrict__ B, Grid gb) {
+    using Vs = typename C::V;
+    const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
+    if (cell >= ga.ncell) return;
+    const uint32_t x = cell % ga.nx, t = cell / ga.nx, y = t % ga.ny, z = t / ga.ny;
+    static_for<0, Vs::Q>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        B[pop_index<Vs>(gb, x, y, z, a)] = A[pop_index<Vs>(ga, x, y, z, a)];
+    });
+}
+
 // FP64 sums of (rho - 1, u) over all nodes: fixed grid, fixed tree order, so the
 // result is deterministic.
 template <class C>
@@ -397,6 +412,7 @@ struct lbm_ctx {
     const double *rec_fext;
     int rec_pair_on;
     PairGrid rec_pg;
+    uint32_t rec_rows;  // layout (rows per group) of the recorded lattices
 };
 
 namespace {
@@ -866,6 +882,22 @@ void launch_partials(lbm_ctx *c, double *partials) {
                        typename C::R(c->dec_s), partials);
 }
 
+// Moves the state into the layout with Y rows per group: the current lattice
+// is permuted into the spare one and copied back, so the current populations
+// stay in the same buffer.
+template <class C>
+void launch_relayout(lbm_ctx *c, uint32_t Y, hipError_t *err) {
+    const Grid gn = with_rows_per_group(c->g, Y);
+    hipLaunchKernelGGL(k_relayout<C>, dim3(blocks_for(c->g.ncell)), dim3(kBlock), 0, c->stream,
+                       static_cast<const typename C::T *>(c->pop[c->cur]), c->g,
+                       static_cast<typename C::T *>(c->pop[c->cur ^ 1]), gn);
+    size_t lat = 0;
+    lbm_lattice_bytes(&c->desc, &lat);
+    *err = hipMemcpyAsync(c->pop[c->cur], c->pop[c->cur ^ 1], lat, hipMemcpyDeviceToDevice,
+                          c->stream);
+    c->g = gn;
+}
+
 // The storage codec x velocity set combinations the library instantiates.
 using F64Q19 = Cfg<CodecF64, D3Q19>;
 using F32Q19 = Cfg<CodecF32, D3Q19>;
@@ -999,10 +1031,36 @@ void tune_store(const TuneKey &k, int shape) {
     g_tune[k] = shape;
 }
 
-// A single-box choice is kept as one code: configuration, block order and
-// residency cap (ensembles keep the configuration alone: order 0, no cap).
-int tune_code(int shape, int order, int cap) {
-    return shape + kNumShapes * (order + int(kNumOrders) * cap);
+// A single-box choice is kept as one code: configuration, block order,
+// residency cap and layout (log2 of the rows per group); ensembles keep the
+// configuration alone (order 0, no cap, one row per group).
+int tune_code(int shape, int order, int cap, int rows_log2) {
+    return shape + kNumShapes * (order + int(kNumOrders) * (cap + kNumCaps * rows_log2));
+}
+
+int rows_log2(const Grid &g) {
+    int k = 0;
+    while ((1u << k) < g.ymask + 1u) ++k;
+    return k;
+}
+
+// Layouts of the lattice: 1, 2, 4, ..., 64 rows per group, those that divide ny.
+constexpr int kMaxRowsLog2 = 6;
+
+int layout_candidates(const lbm_ctx *c, uint32_t *ys) {
+    int n = 0;
+    for (int k = 0; k <= kMaxRowsLog2; ++k)
+        if (c->g.ny % (1u << k) == 0) ys[n++] = 1u << k;
+    return n;
+}
+
+// Puts the state into the layout with Y rows per group (no change of value).
+lbm_status set_layout(lbm_ctx *c, uint32_t Y) {
+    if (Y == c->g.ymask + 1u) return LBM_OK;
+    hipError_t err = hipSuccess;
+    LBM_DISPATCH(c, launch_relayout, Y, &err);
+    const lbm_status st = launch_status();
+    return err != hipSuccess ? LBM_E_DEVICE : st;
 }
 
 TuneKey ctx_tune_key(const lbm_ctx *c) {
@@ -1020,12 +1078,14 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
         return LBM_E_INVAL;
     lbm_ctx *c = static_cast<lbm_ctx *>(calloc(1, sizeof(lbm_ctx)));
     if (!c) return LBM_E_DEVICE;
+    uint32_t init_rows = 1;
     c->desc = *grid;
     c->g.nx = uint32_t(grid->nx);
     c->g.ny = uint32_t(grid->ny);
     c->g.nz = uint32_t(grid->nz);
     c->g.ncell = uint32_t(ncell_of(grid));
     c->g.chunk = row_chunk(grid);
+    c->g = with_rows_per_group(c->g, 1);
     c->q = velocity_count(grid);
     c->device = current_device();
     noalloc_setup(c->device);
@@ -1041,7 +1101,10 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
         const int code = tune_lookup(ctx_tune_key(c), fallback);
         c->shape = code % kNumShapes;
         c->order = (code / kNumShapes) % int(kNumOrders);
-        c->cap = code / (kNumShapes * int(kNumOrders));
+        c->cap = (code / (kNumShapes * int(kNumOrders))) % kNumCaps;
+        // the remembered layout, applied once the lattices are at rest below
+        init_rows = uint32_t(1) << (code / (kNumShapes * int(kNumOrders) * kNumCaps));
+        if (grid->ny % int32_t(init_rows) != 0) init_rows = 1;
         // LDS limits of the device, for the residency caps (none if unknown)
         int v = 0;
         c->lds_cu = (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
@@ -1098,6 +1161,8 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
         free(c);
         return LBM_E_DEVICE;
     }
+    // the rest state is all zeros in every layout
+    c->g = with_rows_per_group(c->g, init_rows);
     *out = c;
     return LBM_OK;
 }
@@ -1367,28 +1432,39 @@ lbm_status lbm_profile_read(lbm_ctx *ctx, double out[4]) {
 
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen) {
     if (!ctx || iters < 1 || iters > 10000) return LBM_E_INVAL;
-    // Stage 1: every configuration in linear order without a residency cap.
-    int ks[kNumShapes * kNumOrders * kNumCaps], os[kNumShapes * kNumOrders * kNumCaps],
-        cs[kNumShapes * kNumOrders * kNumCaps];
-    double t[kNumShapes * kNumOrders * kNumCaps];
-    for (int k = 0; k < kNumShapes; ++k) ks[k] = k, os[k] = int(kOrderLinear), cs[k] = 0;
+    uint32_t ys[kMaxRowsLog2 + 1];
+    const int nl = layout_candidates(ctx, ys);
+    constexpr int kMaxTrials = kNumShapes * kNumOrders * kNumCaps;
+    int ks[kMaxTrials], os[kMaxTrials], cs[kMaxTrials];
+    double t[kMaxTrials];
     hipError_t err = hipSuccess;
-    LBM_DISPATCH(ctx, time_launches, iters, kNumShapes, ks, os, cs, t, &err);
-    if (err != hipSuccess || launch_status() != LBM_OK) return LBM_E_DEVICE;
     double best_k[kNumShapes];
-    for (int k = 0; k < kNumShapes; ++k) best_k[k] = t[k];
-    // Stage 2: the two fastest configurations with every block order and cap.
-    int first = -1, second = -1;
-    for (int k = 0; k < kNumShapes; ++k) {
-        if (t[k] <= 0.0) continue;
-        if (first < 0 || t[k] < t[first]) {
-            second = first;
-            first = k;
-        } else if (second < 0 || t[k] < t[second]) {
-            second = k;
+    for (int k = 0; k < kNumShapes; ++k) best_k[k] = -1.0;
+    auto note = [&](int k, double v) {
+        if (v > 0.0 && (best_k[k] <= 0.0 || v < best_k[k])) best_k[k] = v;
+    };
+    // Stage 1: every configuration in linear order without a residency cap,
+    // in every layout; keep the layout of the fastest launch.
+    double t1[kMaxRowsLog2 + 1][kNumShapes];
+    int bl = -1, first = -1;
+    for (int l = 0; l < nl; ++l) {
+        if (set_layout(ctx, ys[l]) != LBM_OK) return LBM_E_DEVICE;
+        for (int k = 0; k < kNumShapes; ++k) ks[k] = k, os[k] = int(kOrderLinear), cs[k] = 0;
+        LBM_DISPATCH(ctx, time_launches, iters, kNumShapes, ks, os, cs, t, &err);
+        if (err != hipSuccess || launch_status() != LBM_OK) return LBM_E_DEVICE;
+        for (int k = 0; k < kNumShapes; ++k) {
+            t1[l][k] = t[k];
+            note(k, t[k]);
+            if (t[k] > 0.0 && (bl < 0 || t[k] < t1[bl][first])) bl = l, first = k;
         }
     }
-    if (first < 0) return LBM_E_DEVICE;
+    if (bl < 0) return LBM_E_DEVICE;
+    // Stage 2: in that layout, its two fastest configurations with every block
+    // order and cap.
+    int second = -1;
+    for (int k = 0; k < kNumShapes; ++k)
+        if (k != first && t1[bl][k] > 0.0 && (second < 0 || t1[bl][k] < t1[bl][second])) second = k;
+    if (set_layout(ctx, ys[bl]) != LBM_OK) return LBM_E_DEVICE;
     int n = 0;
     for (int k : {first, second}) {
         if (k < 0) continue;
@@ -1402,19 +1478,46 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t iters, double *ms, int32_t *chosen
     LBM_DISPATCH(ctx, time_launches, iters, n, ks, os, cs, t, &err);
     if (err != hipSuccess || launch_status() != LBM_OK) return LBM_E_DEVICE;
     int bk = first, bo = int(kOrderLinear), bc = 0;
-    double bt = best_k[first];
+    double bt = t1[bl][first];
     for (int j = 0; j < n; ++j) {
-        if (t[j] <= 0.0) continue;
-        if (t[j] < best_k[ks[j]]) best_k[ks[j]] = t[j];
-        if (t[j] < bt) bt = t[j], bk = ks[j], bo = os[j], bc = cs[j];
+        note(ks[j], t[j]);
+        if (t[j] > 0.0 && t[j] < bt) bt = t[j], bk = ks[j], bo = os[j], bc = cs[j];
     }
+    // Stage 3: the chosen launch in every other layout (a cap or order can
+    // change which layout streams best).
+    if (bo != int(kOrderLinear) || bc != 0) {
+        const int l0 = bl;
+        for (int l = 0; l < nl; ++l) {
+            if (l == l0) continue;
+            if (set_layout(ctx, ys[l]) != LBM_OK) return LBM_E_DEVICE;
+            ks[0] = bk, os[0] = bo, cs[0] = bc;
+            LBM_DISPATCH(ctx, time_launches, iters, 1, ks, os, cs, t, &err);
+            if (err != hipSuccess || launch_status() != LBM_OK) return LBM_E_DEVICE;
+            note(bk, t[0]);
+            if (t[0] > 0.0 && t[0] < bt) bt = t[0], bl = l;
+        }
+    }
+    if (set_layout(ctx, ys[bl]) != LBM_OK) return LBM_E_DEVICE;
     ctx->shape = bk;
     ctx->order = bo;
     ctx->cap = bc;
-    tune_store(ctx_tune_key(ctx), tune_code(bk, bo, bc));
+    tune_store(ctx_tune_key(ctx), tune_code(bk, bo, bc, rows_log2(ctx->g)));
     if (ms)
         for (int k = 0; k < kNumShapes; ++k) ms[k] = best_k[k];
     if (chosen) *chosen = bk;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_layout(lbm_ctx *ctx, int32_t rows_per_group) {
+    if (!ctx || rows_per_group < 1 || rows_per_group > (1 << kMaxRowsLog2) ||
+        (rows_per_group & (rows_per_group - 1)) != 0 || ctx->desc.ny % rows_per_group != 0)
+        return LBM_E_INVAL;
+    return set_layout(ctx, uint32_t(rows_per_group));
+}
+
+lbm_status lbm_get_layout(const lbm_ctx *ctx, int32_t *rows_per_group) {
+    if (!ctx || !rows_per_group) return LBM_E_INVAL;
+    *rows_per_group = int32_t(ctx->g.ymask + 1);
     return LBM_OK;
 }
 
@@ -1894,6 +1997,7 @@ lbm_status lbm_ens_init(const lbm_ensemble_desc *desc, const lbm_replica_desc *r
         t.g.nz = uint32_t(rd.nz);
         t.g.ncell = uint32_t(uint64_t(rd.nx) * rd.ny * rd.nz);
         t.g.chunk = ens_chunk(rd.nx);
+        t.g = with_rows_per_group(t.g, 1);
         t.pop_off = pop_off;
         t.cell_off = cell_off;
         t.mask_off = uint32_t(mask_off);
@@ -2183,11 +2287,12 @@ TapeLayout tape_layout(const lbm_ctx *c, int32_t np) {
     return t;
 }
 
-// The FP64 adjoint lattice: interleaved rows of 128-byte-aligned doubles.
+// The FP64 adjoint lattice: interleaved rows of 128-byte-aligned doubles, one
+// row per group whatever the forward lattice's layout.
 Grid adj_grid(const lbm_ctx *c) {
     Grid gd = c->g;
     gd.chunk = uint32_t(align_up(c->g.nx, 16));
-    return gd;
+    return with_rows_per_group(gd, 1);
 }
 
 size_t adj_lattice_bytes(const lbm_ctx *c) {
@@ -2475,6 +2580,7 @@ lbm_status lbm_record(lbm_ctx *ctx, int32_t nsteps, int32_t every, void *tape) {
     ctx->rec_fext = ctx->fext;
     ctx->rec_pair_on = ctx->pair_on;
     ctx->rec_pg = ctx->pg;
+    ctx->rec_rows = ctx->g.ymask + 1;
     const size_t pbytes = size_t(ctx->np) * 3 * 8;
     char *tp = static_cast<char *>(tape);
     for (int32_t s = 0; s < nsteps; ++s) {
@@ -2512,6 +2618,8 @@ lbm_status lbm_adjoint(lbm_ctx *ctx, const void *tape, void *work, double *adj_p
     if (ctx->rec_np > 0 && ctx->rec_pdesc.friction == LBM_FRICTION_STOKESLET_CUBE)
         return LBM_E_UNSUPPORTED;
     if (!ctx->rec_tape || tape != ctx->rec_tape) return LBM_E_STATE;
+    // the checkpoints hold lattices in the layout they were recorded in
+    if (ctx->g.ymask + 1 != ctx->rec_rows) return LBM_E_STATE;
     if (ctx->rec_np > 0 && (!adj_r || !adj_v)) return LBM_E_INVAL;
     hipError_t e = hipSuccess;
     LBM_DISPATCH(ctx, adjoint_dispatch, static_cast<char *>(const_cast<void *>(tape)),

@@ -351,6 +351,21 @@ class Lattice(_StreamOrder):
                    self.lib.lbm_get_sweep_launch(self.ctx, ctypes.byref(o), ctypes.byref(w)))
         return o.value, w.value
 
+    def set_layout(self, rows_per_group: int):
+        """Storage layout of the lattice buffers: lattice rows grouped
+        rows_per_group at a time (1, 2, 4, ..., 64, dividing ny), each
+        population's rows of a group one run; the current populations move
+        into it unchanged (same results in every layout)."""
+        with self._staging():
+            _abi.check("lbm_set_layout", self.lib.lbm_set_layout(self.ctx, int(rows_per_group)))
+
+    @property
+    def layout(self) -> int:
+        """Rows per group of the lattice buffers' layout."""
+        y = ctypes.c_int32()
+        _abi.check("lbm_get_layout", self.lib.lbm_get_layout(self.ctx, ctypes.byref(y)))
+        return y.value
+
     @property
     def step_count(self) -> int:
         s = ctypes.c_int64()

@@ -72,9 +72,19 @@ E19 = [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0
        (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]
 
 
+def raw_rows(a, nx, ny, nz, rows_per_group=1, q=19):
+    """A raw lattice buffer of the C ABI layout with the given rows per group R
+    (element (a, x, y, z) at ((z ny + R (y / R)) q + y mod R) nx + a R nx + x)
+    as an array [nz, ny, q, nx]."""
+    R = rows_per_group
+    a = np.asarray(a).reshape(nz, ny // R, q, R, nx)
+    return a.transpose(0, 1, 3, 2, 4).reshape(nz, ny, q, nx)
+
+
 def pulled(a, nx, ny, nz):
-    """The stream-collide's pull applied to one raw lattice of the C ABI layout
-    ((z * ny + y) * 19 + a) * nx + x: plane a of node x taken from x - e_a."""
+    """The stream-collide's pull applied to one lattice as [nz, ny, 19, nx]
+    (the layout with one row per group, ((z * ny + y) * 19 + a) * nx + x):
+    plane a of node x taken from x - e_a."""
     a = a.reshape(nz, ny, 19, nx)
     out = np.empty_like(a)
     for k, (ex, ey, ez) in enumerate(E19):

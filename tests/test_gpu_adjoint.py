@@ -143,6 +143,34 @@ def test_adjoint_repeatable_and_leaves_state_alone(oracle_mod):
         assert np.allclose(g1[k], g2[k], rtol=1e-14, atol=1e-300), k
 
 
+def test_adjoint_in_another_layout_and_after_a_layout_change(oracle_mod):
+    # A run recorded with two rows per group gives the gradients of the
+    # default layout (to the rounding of the FP64 atomics at shared nodes);
+    # switching the layout after the recording
+    # makes the adjoint refuse until the recorded layout is set back.
+    from paper_1909_13412_amd import Lattice, _abi
+
+    f0, r0, v0, cf, cr, cv = _case(oracle_mod, 15)
+    theta = (1.0, 0.8, 10.0, 1e-4)
+    _, _, g1 = _gpu_grad("f64", f0, r0, v0, theta, cf, cr, cv, 12, 5, "stokeslet", 0.0, 9)
+    gamma, tau, M, kT = theta
+    lat = Lattice(*BOX, tau, storage="f64")
+    lat.set_layout(2)
+    lat.set_populations(f0)
+    lat.particles_couple(r0, v0, mass=M, gamma=gamma, kT=kT, seed=9)
+    tape = lat.record(12, 5)
+    g2 = {k: t.cpu().numpy() for k, t in lat.adjoint(tape, cf, cr, cv).items()}
+    for k in g1:
+        assert np.allclose(g1[k], g2[k], rtol=1e-14, atol=1e-300), k
+    lat.set_layout(1)
+    with pytest.raises(_abi.LbmError):
+        lat.adjoint(tape, cf, cr, cv)
+    lat.set_layout(2)
+    g3 = {k: t.cpu().numpy() for k, t in lat.adjoint(tape, cf, cr, cv).items()}
+    for k in g1:
+        assert np.allclose(g1[k], g3[k], rtol=1e-14, atol=1e-300), k
+
+
 def test_adjoint_rejects_unsupported_and_stale(oracle_mod):
     from paper_1909_13412_amd import Lattice, _abi
 

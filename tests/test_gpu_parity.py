@@ -8,7 +8,7 @@ positions.
 import numpy as np
 import pytest
 
-from helpers import announce, nmax_err, pulled, rounding_pin, run_pair
+from helpers import announce, nmax_err, pulled, raw_rows, rounding_pin, run_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -817,14 +817,17 @@ def test_fifteen_velocity_shear_wave(oracle_mod, tau):
 def test_every_launch_configuration_is_bit_identical():
     # Four geometric shapes x plain / non-temporal stores, and the row-aligned
     # mapping x plain / non-temporal, with either block order and residency
-    # cap: the same step, the same bits, also with the FP64 sums fused in.  Boxes with 64 | nx (four rows per block), a row
-    # of three wavefronts with 62 idle lanes, and rows longer than a block.
+    # cap, in every storage layout (rows per group), also with the layout
+    # switched between steps: the same step, the same bits, also with the
+    # FP64 sums fused in.  Boxes with 64 | nx (four rows per block), a row
+    # of three wavefronts with 62 idle lanes, rows longer than a block, and
+    # 64 short rows per plane (row groups up to 64 rows).
     import torch
 
     from paper_1909_13412_amd import Lattice, _abi
     from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
 
-    for L in ((40, 24, 16), (130, 6, 8), (300, 6, 5)):
+    for L in ((40, 24, 16), (130, 6, 8), (300, 6, 5), (24, 64, 5)):
         r = particle_positions(9, L, seed=31)
         v = particle_velocities(9, 1e-5, seed=31)
         # every storage x velocity-set instance the library builds and the
@@ -834,11 +837,17 @@ def test_every_launch_configuration_is_bit_identical():
             ref, sums = None, {}
             # every configuration in node order without a residency cap, and
             # three of them with the per-XCD block order and residency caps
-            runs = [(k, 0, 0) for k in range(_abi.LBM_NUM_SHAPES)]
-            runs += [(k, o, w) for k in (1, 5, 8) for o in (0, 1) for w in (0, 6, 4, 2)
+            runs = [(k, 0, 0, 1, 1) for k in range(_abi.LBM_NUM_SHAPES)]
+            runs += [(k, o, w, 1, 1) for k in (1, 5, 8) for o in (0, 1) for w in (0, 6, 4, 2)
                      if (o, w) != (0, 0)]
-            for k, order, cap in runs:
+            # layouts: from the start, and switched after five steps
+            ys = [y for y in (2, 4, 8, 16, 32, 64) if L[1] % y == 0]
+            runs += [(k, 0, 0, y, y) for k in (1, 4, 7, 9) for y in ys]
+            runs += [(5, 1, 4, ys[-1], 1), (5, 0, 0, 1, ys[-1])]
+            for k, order, cap, y0, y1 in runs:
                 lat = Lattice(*L, 0.7, storage=storage, velocities=q)
+                lat.set_layout(y0)
+                assert lat.layout == y0
                 lat.particles_couple(r, v, kT=1e-4, seed=8)
                 lat.series_config(3, 8)
                 lat.set_shape(k)
@@ -848,15 +857,18 @@ def test_every_launch_configuration_is_bit_identical():
                     assert cap == 2  # the device's LDS per block may not allow two blocks
                     continue
                 assert lat.sweep_launch == (order, cap)
-                lat.step(13)
+                lat.step(5)
+                lat.set_layout(y1)
+                assert lat.layout == y1
+                lat.step(8)
                 f = lat.populations()
                 torch.cuda.synchronize()
                 ser = lat.series()
                 if ref is None:
                     ref = (f.clone(), lat.v.clone(), ser)
                 else:
-                    assert torch.equal(f, ref[0]), (L, storage, q, k, order, cap)
-                    assert torch.equal(lat.v, ref[1]), (L, storage, q, k, order, cap)
+                    assert torch.equal(f, ref[0]), (L, storage, q, k, order, cap, y0, y1)
+                    assert torch.equal(lat.v, ref[1]), (L, storage, q, k, order, cap, y0, y1)
                     # FP64 sums: per-block partials follow the lane mapping, so
                     # only the same mapping reproduces them bit for bit (block
                     # order and cap do not change it)
@@ -868,6 +880,10 @@ def test_every_launch_configuration_is_bit_identical():
     lat = Lattice(9, 7, 5, 0.7)
     with pytest.raises(Exception):
         lat.set_shape(2)  # two rows per lane need an even ny
+    for y in (0, 2, 3, 7, 128):  # not a power of two up to 64 dividing ny = 7
+        with pytest.raises(_abi.LbmError):
+            lat.set_layout(y)
+    assert lat.layout == 1
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f64"])
@@ -882,7 +898,7 @@ def test_stream_ceiling_kernel_pulls_every_population(storage):
     from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
 
     dt = {"f32": torch.float32, "bf16": torch.int16, "f64": torch.float64}[storage]
-    for L in ((40, 24, 16), (130, 6, 8)):
+    for L in ((40, 24, 16), (130, 6, 8), (24, 64, 5)):
         nx, ny, nz = L
         lat = Lattice(*L, 0.7, storage=storage)
         lat.particles_couple(particle_positions(9, L, seed=33), particle_velocities(9, 1e-4, seed=33),
@@ -893,7 +909,9 @@ def test_stream_ceiling_kernel_pulls_every_population(storage):
         n = 19 * nx * ny * nz
 
         def raw(buf):
-            return buf[: n * buf.new_empty(0, dtype=dt).element_size()].view(dt).reshape(nz, ny, 19, nx).cpu().numpy()
+            # [nz, ny, 19, nx] whatever the layout's rows per group
+            return raw_rows(buf[: n * buf.new_empty(0, dtype=dt).element_size()].view(dt).cpu().numpy(),
+                            nx, ny, nz, lat.layout)
 
         a0 = raw(lat.pop_a)
         expect = pulled(a0, nx, ny, nz)
@@ -903,6 +921,18 @@ def test_stream_ceiling_kernel_pulls_every_population(storage):
             ms = lat.stream_ceiling(1, config=k)
             assert ms > 0.0
             assert np.array_equal(raw(lat.pop_b), expect), (L, storage, k)
+        # every layout moves the same values (the state is permuted into it
+        # and stays in the first buffer)
+        for y in (2, 4, 8, 16, 32, 64):
+            if ny % y:
+                continue
+            lat.set_layout(y)
+            lat.pop_b.zero_()
+            torch.cuda.synchronize()
+            assert np.array_equal(raw(lat.pop_a), a0), (L, storage, "layout", y)
+            assert lat.stream_ceiling(1, config=5) > 0.0
+            assert np.array_equal(raw(lat.pop_b), expect), (L, storage, "layout", y)
+        lat.set_layout(1)
         # the per-XCD block order with a residency cap moves the same values
         lat.set_shape(1)
         lat.set_sweep_launch(1, 4)
