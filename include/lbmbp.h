@@ -530,11 +530,21 @@ lbm_status lbm_ens_vacf_counts(const lbm_ens *ens, int64_t *cnt);
 /* Advance every replica nsteps steps (asynchronous). */
 lbm_status lbm_ens_step(lbm_ens *ens, int32_t nsteps);
 
-/* Time the stream-collide launch shapes on the ensemble (state unchanged) and
- * keep the fastest; as lbm_autotune.  The choice is remembered for ensembles
- * created later on the same device with the same storage and the same box
- * sizes in the same order, which start from it. */
+/* Time the stream-collide launch shapes on the ensemble in every layout
+ * (lbm_ens_set_layout; state unchanged) and keep the fastest shape and
+ * layout; as lbm_autotune.  The choice is remembered for ensembles created
+ * later on the same device with the same storage and the same box sizes in
+ * the same order, which start from it. */
 lbm_status lbm_ens_autotune(lbm_ens *ens, int32_t iters, double *ms, int32_t *chosen);
+
+/* Storage layout of the ensemble's lattices (as lbm_set_layout, box by box):
+ * rows_per_group (1, 2, 4, ..., 64) is requested of every box, and each box
+ * takes the largest power of two not above it that divides its ny.  The
+ * current populations move into the new layout unchanged (through the spare
+ * lattice; synchronises the stream).  lbm_ens_get_layout gives the rows per
+ * group of one replica.  LBM_E_INVAL for a NULL ens or out-of-range values. */
+lbm_status lbm_ens_set_layout(lbm_ens *ens, int32_t rows_per_group);
+lbm_status lbm_ens_get_layout(const lbm_ens *ens, int32_t replica, int32_t *rows_per_group);
 
 /* Ceiling of the ensemble stream-collide's data movement, as lbm_stream_ceiling:
  * *ms receives the mean milliseconds per launch (iters 1..10000, after two

@@ -1652,6 +1652,7 @@ struct lbm_ens {
     int64_t vacf_t;
     int64_t step;
     int shape;
+    int rows;    // requested rows per group: each box takes the largest power of two <= rows dividing its ny
     int device;  // device current at lbm_ens_init (autotune cache key)
     // two-step graph, captured on a private stream and replayed on `stream`
     int use_graph;
@@ -1820,6 +1821,55 @@ void ens_dispatch_step(lbm_ens *e, int cur, int par) {
     }
 }
 
+// Rows per group of a box with ny rows per plane when `rows` is requested: the
+// largest power of two not above it that divides ny.
+uint32_t ens_box_rows(int rows, int32_t ny) {
+    uint32_t y = uint32_t(rows);
+    while (y > 1 && ny % int32_t(y) != 0) y >>= 1;
+    return y;
+}
+
+// Moves every box into the layout ens_box_rows(rows, ny): each box is permuted
+// into the spare lattice, and the whole spare lattice is copied back, so the
+// state stays in the current buffer; then the device table is updated.
+template <class C>
+void ens_relayout(lbm_ens *e, int rows, hipError_t *err) {
+    using T = typename C::T;
+    const T *A = static_cast<const T *>(e->pop[e->cur]);
+    T *B = static_cast<T *>(e->pop[e->cur ^ 1]);
+    for (int32_t k = 0; k < e->nrep; ++k) {
+        Replica &t = e->host_table[k];
+        const Grid gn = with_rows_per_group(t.g, ens_box_rows(rows, int32_t(t.g.ny)));
+        hipLaunchKernelGGL(k_relayout<C>, dim3(blocks_for(t.g.ncell)), dim3(kBlock), 0, e->stream,
+                           A + t.pop_off, t.g, B + t.pop_off, gn);
+        t.g = gn;
+    }
+    *err = hipGetLastError();
+    if (*err == hipSuccess)
+        *err = hipMemcpyAsync(e->pop[e->cur], e->pop[e->cur ^ 1], e->total_pop * sizeof(T),
+                              hipMemcpyDeviceToDevice, e->stream);
+    if (*err == hipSuccess)
+        *err = hipMemcpyAsync(e->reps, e->host_table, sizeof(Replica) * e->nrep,
+                              hipMemcpyHostToDevice, e->stream);
+    if (*err == hipSuccess) *err = hipStreamSynchronize(e->stream);  // host_table is reused
+    e->rows = rows;
+}
+
+void ens_drop_graph(lbm_ens *e);
+
+lbm_status ens_set_layout(lbm_ens *e, int rows) {
+    if (rows == e->rows) return LBM_OK;
+    ens_drop_graph(e);
+    hipError_t err = hipSuccess;
+    switch (e->desc.storage) {
+        case LBM_STORE_F64: ens_relayout<F64Q19>(e, rows, &err); break;
+        case LBM_STORE_F32: ens_relayout<F32Q19>(e, rows, &err); break;
+        case LBM_STORE_BF16: ens_relayout<BF16Q19>(e, rows, &err); break;
+        case LBM_STORE_F16: ens_relayout<F16Q19>(e, rows, &err); break;
+    }
+    return err == hipSuccess ? LBM_OK : LBM_E_DEVICE;
+}
+
 void ens_drop_graph(lbm_ens *e) {
     if (e->graph_valid) (void)hipGraphExecDestroy(e->graph);
     e->graph_valid = 0;
@@ -1964,7 +2014,11 @@ lbm_status lbm_ens_init(const lbm_ensemble_desc *desc, const lbm_replica_desc *r
     e->total_mask_words = L.total_mask_words;
     e->device = current_device();
     // until lbm_ens_autotune: the last choice for this key, else by lattice size
-    e->shape = tune_lookup(ens_tune_key(e), L.lattice_bytes >= kStreamStoreBytes ? kNumGeomShapes : 0);
+    {
+        const int code = tune_lookup(ens_tune_key(e), L.lattice_bytes >= kStreamStoreBytes ? kNumGeomShapes : 0);
+        e->shape = code % kNumShapes;
+        e->rows = 1 << (code / kNumShapes);  // applied to every box below (the rest state is all zeros)
+    }
     for (int s = 0; s < kNumGeomShapes; ++s) e->total_blocks[s] = L.total_blocks[s];
     e->n = L.n;
     char *base = static_cast<char *>(scratch);
@@ -1997,7 +2051,7 @@ lbm_status lbm_ens_init(const lbm_ensemble_desc *desc, const lbm_replica_desc *r
         t.g.nz = uint32_t(rd.nz);
         t.g.ncell = uint32_t(uint64_t(rd.nx) * rd.ny * rd.nz);
         t.g.chunk = ens_chunk(rd.nx);
-        t.g = with_rows_per_group(t.g, 1);
+        t.g = with_rows_per_group(t.g, ens_box_rows(e->rows, rd.ny));
         t.pop_off = pop_off;
         t.cell_off = cell_off;
         t.mask_off = uint32_t(mask_off);
@@ -2127,37 +2181,62 @@ lbm_status lbm_ens_autotune(lbm_ens *e, int32_t iters, double *ms, int32_t *chos
     EnsClock saved;
     hipError_t err = hipMemcpyAsync(&saved, e->clock, sizeof(saved), hipMemcpyDeviceToHost, e->stream);
     if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
+    // every configuration in every layout (rows per group requested of all
+    // boxes: 1, 2, ..., 64)
     double t[kNumShapes];
-    for (int k = 0; k < kNumShapes && err == hipSuccess; ++k) {
-        t[k] = -1.0;
-        if (config_row(k) || e->total_blocks[k & 3] == 0) continue;  // rows: single boxes only
-        bool all = true;
-        for (int32_t q = 0; q < e->nrep; ++q) all = all && (e->host_reps[q].ny % kShapes[k & 3].cpt == 0);
-        if (!all) continue;
-        for (int w = 0; w < 2; ++w) ens_time_any(e, k);
-        (void)hipEventRecord(e0, e->stream);
-        for (int32_t it = 0; it < iters; ++it) ens_time_any(e, k);
-        (void)hipEventRecord(e1, e->stream);
-        err = hipEventSynchronize(e1);
-        float f = 0.0f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&f, e0, e1);
-        t[k] = double(f) / iters;
+    for (int k = 0; k < kNumShapes; ++k) t[k] = -1.0;
+    int best = -1, best_rows = 1;
+    double best_t = -1.0;
+    for (int lg = 0; lg <= kMaxRowsLog2 && err == hipSuccess; ++lg) {
+        if (ens_set_layout(e, 1 << lg) != LBM_OK) {
+            err = hipErrorUnknown;
+            break;
+        }
+        for (int k = 0; k < kNumShapes && err == hipSuccess; ++k) {
+            if (config_row(k) || e->total_blocks[k & 3] == 0) continue;  // rows: single boxes only
+            bool all = true;
+            for (int32_t q = 0; q < e->nrep; ++q) all = all && (e->host_reps[q].ny % kShapes[k & 3].cpt == 0);
+            if (!all) continue;
+            for (int w = 0; w < 2; ++w) ens_time_any(e, k);
+            (void)hipEventRecord(e0, e->stream);
+            for (int32_t it = 0; it < iters; ++it) ens_time_any(e, k);
+            (void)hipEventRecord(e1, e->stream);
+            err = hipEventSynchronize(e1);
+            float f = 0.0f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&f, e0, e1);
+            const double v = double(f) / iters;
+            if (t[k] <= 0.0 || v < t[k]) t[k] = v;
+            if (best < 0 || v < best_t) best = k, best_t = v, best_rows = 1 << lg;
+        }
     }
+    if (err == hipSuccess && ens_set_layout(e, best_rows) != LBM_OK) err = hipErrorUnknown;
     if (err == hipSuccess)
         err = hipMemcpyAsync(e->clock, &saved, sizeof(saved), hipMemcpyHostToDevice, e->stream);
     if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (err != hipSuccess) return LBM_E_DEVICE;
-    int best = 0;
-    for (int k = 0; k < kNumShapes; ++k)
-        if (t[k] > 0.0 && (t[best] <= 0.0 || t[k] < t[best])) best = k;
+    if (err != hipSuccess || best < 0) return LBM_E_DEVICE;
     if (best != e->shape) ens_drop_graph(e);
     e->shape = best;
-    tune_store(ens_tune_key(e), best);
+    int lg = 0;
+    while ((1 << lg) < best_rows) ++lg;
+    tune_store(ens_tune_key(e), best + kNumShapes * lg);
     if (ms)
         for (int k = 0; k < kNumShapes; ++k) ms[k] = t[k];
     if (chosen) *chosen = best;
+    return LBM_OK;
+}
+
+lbm_status lbm_ens_set_layout(lbm_ens *e, int32_t rows_per_group) {
+    if (!e || rows_per_group < 1 || rows_per_group > (1 << kMaxRowsLog2) ||
+        (rows_per_group & (rows_per_group - 1)) != 0)
+        return LBM_E_INVAL;
+    return ens_set_layout(e, rows_per_group);
+}
+
+lbm_status lbm_ens_get_layout(const lbm_ens *e, int32_t replica, int32_t *rows_per_group) {
+    if (!e || !rows_per_group || replica < 0 || replica >= e->nrep) return LBM_E_INVAL;
+    *rows_per_group = int32_t(e->host_table[replica].g.ymask + 1);
     return LBM_OK;
 }
 

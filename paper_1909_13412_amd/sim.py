@@ -508,6 +508,19 @@ class Ensemble(_StreamOrder):
                    self.lib.lbm_ens_stream_ceiling(self.ctx, int(config), int(iters), ctypes.byref(ms)))
         return ms.value
 
+    def set_layout(self, rows_per_group: int):
+        """Storage layout of every box (see Lattice.set_layout): each box takes
+        the largest power of two not above rows_per_group that divides its ny;
+        the populations move into it unchanged."""
+        self._after_caller()
+        _abi.check("lbm_ens_set_layout", self.lib.lbm_ens_set_layout(self.ctx, int(rows_per_group)))
+
+    def layout(self, k: int) -> int:
+        """Rows per group of replica k's lattice layout."""
+        y = ctypes.c_int32()
+        _abi.check("lbm_ens_get_layout", self.lib.lbm_ens_get_layout(self.ctx, int(k), ctypes.byref(y)))
+        return y.value
+
     @property
     def launch_config(self) -> int:
         """The stream-collide launch configuration later steps use."""

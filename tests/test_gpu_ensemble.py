@@ -4,7 +4,7 @@ against a single-box run with the same inputs."""
 import numpy as np
 import pytest
 
-from helpers import announce, nmax_err, pulled
+from helpers import announce, nmax_err, pulled, raw_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -124,26 +124,63 @@ def test_ensemble_stream_ceiling_pulls_every_population(storage):
     offs = np.concatenate([[0], np.cumsum(sizes)])
 
     def raw(buf):
-        return buf[: int(offs[-1]) * el].view(dt).cpu().numpy()
+        # box after box as [nz, ny, 19, nx], whatever each box's rows per group
+        a = buf[: int(offs[-1]) * el].view(dt).cpu().numpy()
+        return np.concatenate([raw_rows(a[offs[k]:offs[k + 1]], rd["nx"], rd["ny"], rd["nz"],
+                                        e.layout(k)).ravel() for k, rd in enumerate(reps)])
 
     a0 = raw(e.pop_a)
     expect = np.concatenate([pulled(a0[offs[k]:offs[k + 1]], rd["nx"], rd["ny"], rd["nz"]).ravel()
                              for k, rd in enumerate(reps)])
     even_ny = all(rd["ny"] % 2 == 0 for rd in reps)
-    for k in range(8):
-        if (k & 3) >= 2 and not even_ny:
-            with pytest.raises(Exception):
-                e.stream_ceiling(1, config=k)
-            continue
-        e.pop_b.zero_()
-        torch.cuda.synchronize()
-        assert e.stream_ceiling(1, config=k) > 0.0
-        assert np.array_equal(raw(e.pop_b), expect), (storage, k)
+    # in the layouts with one row per group, and with up to two and four
+    # (boxes whose ny the request does not divide take fewer)
+    for rows in (1, 2, 4):
+        e.set_layout(rows)
+        assert [e.layout(k) for k in range(len(reps))] == [
+            max(y for y in (1, 2, 4) if y <= rows and rd["ny"] % y == 0) for rd in reps]
+        assert np.array_equal(raw(e.pop_a), a0), (storage, rows)
+        for k in range(8):
+            if (k & 3) >= 2 and not even_ny:
+                with pytest.raises(Exception):
+                    e.stream_ceiling(1, config=k)
+                continue
+            e.pop_b.zero_()
+            torch.cuda.synchronize()
+            assert e.stream_ceiling(1, config=k) > 0.0
+            assert np.array_equal(raw(e.pop_b), expect), (storage, rows, k)
     with pytest.raises(Exception):
         e.stream_ceiling(1, config=8)  # row-aligned: single boxes only
     assert np.array_equal(raw(e.pop_a), a0)
     for k in range(len(reps)):
         assert torch.equal(e.populations(k), f0[k])
+
+
+def test_ensemble_layouts_are_bit_identical():
+    # The same ensemble run with one row per group, with up to four rows per
+    # group (mixed across the boxes), and with the layout switched between
+    # graph-replayed steps: the same populations, particles and VACF.
+    import torch
+
+    from paper_1909_13412_amd import Ensemble
+
+    reps = _small_replicas()
+    out = []
+    for rows0, rows1 in ((1, 1), (4, 4), (2, 1), (1, 4)):
+        e = Ensemble(reps, storage="f32", kT=1e-4)
+        e.set_layout(rows0)
+        e.vacf_config(6, 3)
+        e.step(8)
+        e.set_layout(rows1)
+        e.step(9)
+        torch.cuda.synchronize()
+        out.append(([e.populations(k).cpu().numpy() for k in range(len(reps))],
+                    e.v.cpu().numpy(), e.vacf()[0].cpu().numpy()))
+        e.close()
+    for o in out[1:]:
+        for a, b in zip(out[0][0], o[0]):
+            assert np.array_equal(a, b)
+        assert np.array_equal(out[0][1], o[1]) and np.array_equal(out[0][2], o[2])
 
 
 def test_graph_replays_match_plain_launches():
