@@ -341,8 +341,10 @@ lbm_status lbm_profile_read(lbm_ctx *ctx, double out[4]);
  * without a residency cap in every storage layout (lbm_set_layout: the state
  * is permuted between layouts, values unchanged), then in the layout of the
  * fastest the two fastest configurations with every block order and residency
- * cap (lbm_set_sweep_launch), and the launch chosen so in every other layout.
- * Synchronises the stream.
+ * cap (lbm_set_sweep_launch), and the fastest of those in every other layout;
+ * finally the three fastest launches of all are timed again in turn, twice
+ * each with 2 x iters launches, and the lowest total is kept.  Synchronises
+ * the stream.
  * ms (host, LBM_NUM_SHAPES entries, may be NULL) receives per configuration
  * the best mean milliseconds per launch over the options timed with it (-1
  * for a configuration that does not apply, or that repeats another's lane
