@@ -308,8 +308,10 @@ class Lattice(_StreamOrder):
                 "particle_ms": out[2], "particle_launches": int(out[3])}
 
     def autotune(self, iters: int = 20):
-        """Time the stream-collide launch shapes on this lattice (state unchanged)
-        and keep the fastest.  Returns (chosen shape, ms per launch of each)."""
+        """Time the stream-collide launch options (configuration, block order,
+        residency cap, storage layout) on this lattice (state values unchanged)
+        and keep the fastest.  Returns (chosen configuration, best ms per launch
+        of each configuration)."""
         self._after_caller()
         ms = np.zeros(_abi.LBM_NUM_SHAPES)
         chosen = ctypes.c_int32()

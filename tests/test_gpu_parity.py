@@ -468,7 +468,11 @@ def test_autotune_choice_is_remembered():
         a = Lattice(*dims, 0.8, storage="f32")
         k, ms = a.autotune(3)
         assert a.launch_config == k and ms[k] > 0.0
-        assert Lattice(*dims, 0.8, storage="f32").launch_config == k
+        b = Lattice(*dims, 0.8, storage="f32")
+        assert b.launch_config == k
+        # the launch options and the storage layout are remembered too
+        assert b.sweep_launch == a.sweep_launch and b.layout == a.layout
+        assert dims[1] % a.layout == 0
         assert Lattice(*dims, 0.8, storage="f32", velocities=15).launch_config == 0
         assert Lattice(dims[0], dims[1], dims[2] + 1, 0.8, storage="f32").launch_config == 0
     # a lattice beyond the last-level cache defaults to non-temporal stores;
