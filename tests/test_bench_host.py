@@ -63,3 +63,25 @@ def test_one_thread_oracle_leg():
     out = bench.cpu_baseline_one_thread(w, 2)
     assert out is not None
     assert out["cores"] == 1 and out["kind"] == "oracle" and out["value"] > 0
+
+
+def test_row_group_layout_formula():
+    # helpers.raw_rows decodes a raw lattice of the documented layout, element
+    # (a, x, y, z) at ((z ny + R (y / R)) Q + y mod R) nx + a R nx + x: a buffer
+    # filled with each element's own (a, x, y, z) code decodes to the
+    # canonical [z][y][a][x] array of codes, for every R dividing ny.
+    import numpy as np
+
+    sys.path.insert(0, os.path.dirname(__file__))
+    from helpers import raw_rows
+
+    nx, ny, nz, q = 5, 12, 3, 19
+    a_, x_, y_, z_ = np.meshgrid(np.arange(q), np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    code = ((z_ * ny + y_) * q + a_) * nx + x_
+    want = np.empty((nz, ny, q, nx), dtype=np.int64)
+    want[z_, y_, a_, x_] = code
+    for R in (1, 2, 3, 4, 6, 12):
+        raw = np.empty(q * nx * ny * nz, dtype=np.int64)
+        idx = ((z_ * ny + R * (y_ // R)) * q + y_ % R) * nx + a_ * R * nx + x_
+        raw[idx] = code
+        assert np.array_equal(raw_rows(raw, nx, ny, nz, R), want), R
