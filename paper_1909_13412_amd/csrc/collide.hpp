@@ -212,23 +212,38 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
             }
         }
         const uint64_t row_base = row_index<V>(g, y, z) + x;
-        static_for<0, V::Q>([&](auto ac) {
-            constexpr int a = decltype(ac)::value;
-            constexpr int cx = V::ex[a], cy = V::ey[a], cz = V::ez[a];
-            const R w = V::template w<R>(a);
-            const R eu = R(cx) * ux + R(cy) * uy + R(cz) * uz;
-            const R geq = w * (drho + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
-            R gn = gv[a] + omega * (geq - gv[a]);
-            R eF = R(0);
-            if constexpr (cx != 0) eF += cx > 0 ? Fx : -Fx;
-            if constexpr (cy != 0) eF += cy > 0 ? Fy : -Fy;
-            if constexpr (cz != 0) eF += cz > 0 ? Fz : -Fz;
-            if constexpr (a != 0) gn += R(3) * w * eF;
-            // written once and read only by the next step
+        // written once and read only by the next step
+        auto put = [&](int a, R gn) {
             if constexpr (NTS)
                 __builtin_nontemporal_store(C::enc(gn, enc_s), &B[row_base + uint64_t(a) * g.pstride]);
             else
                 B[row_base + uint64_t(a) * g.pstride] = C::enc(gn, enc_s);
+        };
+        // BGK relaxation to the equilibrium of Eq. s2-eq plus the forcing term
+        // 3 w e.F, one opposite pair (a, a + 1) at a time: e_{a+1} = -e_a, so
+        // the even part of the equilibrium, w (drho + 4.5 (e.u)^2 - 1.5 u.u),
+        // is shared, and its odd part 3 w e.u and the forcing change sign.
+        const R base = drho - R(1.5) * uu;
+        put(0, gv[0] + omega * (V::template w<R>(0) * base - gv[0]));
+        static_for<0, (V::Q - 1) / 2>([&](auto pc) {
+            constexpr int a = 1 + 2 * decltype(pc)::value;
+            constexpr int cx = V::ex[a], cy = V::ey[a], cz = V::ez[a];
+            static_assert(V::ex[a + 1] == -cx && V::ey[a + 1] == -cy && V::ez[a + 1] == -cz,
+                          "opposite velocities are adjacent");
+            constexpr R w = V::template w<R>(a);
+            constexpr R w3 = R(3) * w;
+            R eu = R(0), eF = R(0);
+            if constexpr (cx != 0) eu += cx > 0 ? ux : -ux;
+            if constexpr (cy != 0) eu += cy > 0 ? uy : -uy;
+            if constexpr (cz != 0) eu += cz > 0 ? uz : -uz;
+            if constexpr (cx != 0) eF += cx > 0 ? Fx : -Fx;
+            if constexpr (cy != 0) eF += cy > 0 ? Fy : -Fy;
+            if constexpr (cz != 0) eF += cz > 0 ? Fz : -Fz;
+            const R sym = w * (base + R(4.5) * eu * eu);
+            const R anti = w3 * eu;
+            const R fa = w3 * eF;
+            put(a, gv[a] + omega * ((sym + anti) - gv[a]) + fa);
+            put(a + 1, gv[a + 1] + omega * ((sym - anti) - gv[a + 1]) - fa);
         });
     }
 }

@@ -21,10 +21,12 @@ the GPU package is imported).  Each fixture is one JSON file in this folder:
   64-box ensemble (edges 48 and 96, tau 0.8, 8 particles, kT 1e-4) over
   5,000 steps, each run as the single box the ensemble replica stands for:
   C(l) for lags 0..1000 and the final particle state.
+* ``oracle_ensemble64_all.json``: the same for every one of the 64 boxes.
 
 Usage: python tests/golden/make_oracle_fixtures.py [vacf128] [suspension256]
-[fig2thermal100] [ensemble]   (no argument: all of them).  The 128^3 and 256^3
-runs take about 20 minutes each on 8 host threads.
+[fig2thermal100] [ensemble] [ensemble_all]   (no argument: all but
+ensemble_all).  The 128^3 and 256^3 runs take about 20 minutes each on 8 host
+threads, ensemble_all about as long.
 """
 from __future__ import annotations
 
@@ -120,12 +122,12 @@ def make_workload(name, series_every):
     _write(f"oracle_{name}.json", rec)
 
 
-def make_ensemble_edges():
+def make_ensemble_edges(every_box=False):
     w = INPUTS.ENSEMBLE64
     reps = INPUTS.ensemble_replicas(w["replicas"], w["sizes"], w["n"], w["tau"], w["kT"],
                                     w["mass"], w["seed"])
     edges = [rp["nx"] for rp in reps]
-    picks = [edges.index(min(edges)), edges.index(max(edges))]
+    picks = list(range(len(reps))) if every_box else [edges.index(min(edges)), edges.index(max(edges))]
     out = {"workload": "ensemble64", "steps": w["steps"], "max_lag": w["max_lag"],
            "stride": w["stride"], "tau": w["tau"], "mass": w["mass"], "gamma": w["gamma"],
            "kT": w["kT"], "storage": "oracle FP64", "citation": CITATION, "replicas": [],
@@ -150,7 +152,7 @@ def make_ensemble_edges():
             "observables": [float(x) for x in sim.observables()],
             "oracle_seconds": round(wall, 1)})
         print(f"ensemble replica {k} (edge {L}) done in {wall:.0f} s", flush=True)
-    _write("oracle_ensemble64_edges.json", out)
+    _write("oracle_ensemble64_all.json" if every_box else "oracle_ensemble64_edges.json", out)
 
 
 def main(argv):
@@ -166,6 +168,8 @@ def main(argv):
             make_workload("fig2thermal100", 100)
         elif item == "ensemble":
             make_ensemble_edges()
+        elif item == "ensemble_all":
+            make_ensemble_edges(every_box=True)
         else:
             raise SystemExit(f"unknown fixture {item!r}")
         print(f"{item}: {time.time() - t:.0f} s", flush=True)
