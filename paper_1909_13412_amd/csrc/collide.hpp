@@ -119,6 +119,20 @@ __device__ inline void static_for(F &&f) {
 // ---------------------------------------------------------------------------
 // Deterministic block sum of N doubles (fixed butterfly and wave order);
 // thread k < N writes out[k].  Every thread of the block must call it.
+// Sum of v over the lanes of one wavefront, in a fixed butterfly order; lane 0
+// of the wavefront writes the N sums to out[0..N-1].  Every lane of the
+// wavefront must call it.
+template <int N>
+__device__ inline void wave_sum(double (&v)[N], double *__restrict__ out) {
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) out[k] = v[k];
+}
+
 template <int N, int BS>
 __device__ inline void block_sum(double (&v)[N], double *__restrict__ out) {
     __shared__ double sh[BS / 64][N];
@@ -319,8 +333,10 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
     if (active)
         collide_lane<C, FORCED, MOMENTS, CPT, NTS>(A, B, g, omega, enc_s, dec_s, ff, Gx, Gy, Gz,
                                                    lane_cell, acc);
-    // partials by node block, so that every block order gives the same sums
-    if constexpr (MOMENTS) block_sum<4, BS>(acc, mom + 4 * uint64_t(blk));
+    // partials by wavefront of the node block (no barrier), so that every
+    // block order gives the same sums
+    if constexpr (MOMENTS)
+        wave_sum<4>(acc, mom + 4 * (uint64_t(blk) * (BS / 64) + threadIdx.x / 64));
 }
 
 // The stream-collide's data movement alone, for the nodes of one lane (as in

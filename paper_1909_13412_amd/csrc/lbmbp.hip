@@ -147,8 +147,9 @@ __global__ __launch_bounds__(kParticleBlock) void k_ens_particle(
 }
 
 // ---------------------------------------------------------------------------
-// Recorded observables: two fixed-order stages over the per-block partials
-// left by the stream-collide (rho~ - 1, u) and the particle kernel (M V).
+// Recorded observables: two fixed-order stages over the per-wavefront partials
+// left by the stream-collide (rho~ - 1, u) and the per-block ones of the
+// particle kernel (M V).
 // ---------------------------------------------------------------------------
 constexpr int kSeriesBlocks = 64;
 
@@ -401,7 +402,7 @@ struct lbm_ctx {
     int32_t series_every;
     double *series;
     int64_t series_cap, series_count, series_t;
-    double *fluid_partials;  // grid scratch: [collide blocks][4]
+    double *fluid_partials;  // grid scratch: [collide wavefronts][4]
     double *series_stage;    // grid scratch: [kSeriesBlocks][7]
     double *part_partials;   // particle scratch: [particle blocks][3]
     // forward run kept for the adjoint (lbm_record)
@@ -470,12 +471,12 @@ uint32_t row_grid_blocks(uint32_t nx, uint32_t ny, uint32_t nz) {
     return nrows * ((lpr + kRowBlock - 1) / kRowBlock);
 }
 
-// Per-block moment partials of the largest stream-collide grid: 256-lane
-// blocks with one node per lane, or the row-aligned grid, whichever is
-// larger.
+// Per-wavefront moment partials of the largest stream-collide grid: one node
+// per lane in whole blocks of up to 512 lanes, or the row-aligned grid,
+// whichever has more wavefronts.
 size_t fluid_partials_bytes(const lbm_grid_desc *g) {
-    const size_t flat = ncell_of(g) / 256 + 1;
-    const size_t row = row_grid_blocks(uint32_t(g->nx), uint32_t(g->ny), uint32_t(g->nz));
+    const size_t flat = (ncell_of(g) / 512 + 1) * 8;
+    const size_t row = row_grid_blocks(uint32_t(g->nx), uint32_t(g->ny), uint32_t(g->nz)) * (kRowBlock / 64);
     return align_up((flat > row ? flat : row) * 4 * 8, kAlign);
 }
 
@@ -762,7 +763,9 @@ void launch_step(lbm_ctx *c) {
     if (sample) {
         const int32_t np_blocks = c->np > 0 ? int32_t(particle_blocks(c->np)) : 0;
         hipLaunchKernelGGL(k_series_stage1, dim3(kSeriesBlocks), dim3(kBlock), 0, c->stream,
-                           c->fluid_partials, int32_t(collide_grid(c, c->shape)), c->part_partials,
+                           c->fluid_partials,
+                           int32_t(collide_grid(c, c->shape) * (config_block(c->shape) / 64)),
+                           c->part_partials,
                            np_blocks, c->series_stage);
         hipLaunchKernelGGL(k_series_stage2, dim3(1), dim3(64), 0, c->stream, c->series_stage,
                            double(c->g.ncell), double(c->step), c->series + 8 * c->series_count);
@@ -1138,9 +1141,10 @@ lbm_status lbm_init(const lbm_grid_desc *grid, void *pop_a, void *pop_b, void *g
     s += force_field_bytes(grid);
     c->fluid_partials = reinterpret_cast<double *>(s);
     s += fluid_partials_bytes(grid);
-    // every configuration's grid must fit the per-block partials
+    // every configuration's grid must fit the per-wavefront partials
     for (int k = 0; k < kNumShapes; ++k)
-        if (shape_ok(c, k) && size_t(collide_grid(c, k)) * 4 * 8 > fluid_partials_bytes(grid)) {
+        if (shape_ok(c, k) &&
+            size_t(collide_grid(c, k)) * (config_block(k) / 64) * 4 * 8 > fluid_partials_bytes(grid)) {
             free(c);
             return LBM_E_UNSUPPORTED;
         }
