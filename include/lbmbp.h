@@ -507,7 +507,8 @@ typedef struct lbm_replica_desc {
 typedef struct lbm_ens lbm_ens;
 
 /* Bytes of ONE ensemble lattice (two are used) and of the ensemble scratch.
- * Total nodes < 2^31, total particles < 2^24. */
+ * Total nodes < 2^31, total particles < 2^24, 19 nx ny nz < 2^32 for every
+ * box (a box is indexed with 32 bits). */
 lbm_status lbm_ens_bytes(const lbm_ensemble_desc *desc, const lbm_replica_desc *reps,
                          size_t *lattice_bytes, size_t *scratch_bytes);
 

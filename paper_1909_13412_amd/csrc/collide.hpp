@@ -53,17 +53,22 @@ __host__ __device__ inline Grid with_rows_per_group(Grid g, uint32_t Y) {
 }
 
 // Storage index of population 0 of node (0, y, z): the start of its group
-// plus its row within the group.
-template <class V>
-__device__ inline uint64_t row_index(const Grid &g, uint32_t y, uint32_t z) {
-    return (uint64_t(z * g.ny + (y & ~g.ymask)) * V::Q + (y & g.ymask)) * g.chunk;
+// plus its row within the group.  I is the index arithmetic's type: 32 bits
+// suffice (and save the sweep its 64-bit multiplies) while Q nx ny nz < 2^32.
+template <class V, class I = uint64_t>
+__device__ inline I row_index(const Grid &g, uint32_t y, uint32_t z) {
+    return (I(z * g.ny + (y & ~g.ymask)) * V::Q + (y & g.ymask)) * g.chunk;
 }
 
 // Storage index of population a at node (x, y, z) for velocity set V.
-template <class V>
-__device__ inline uint64_t pop_index(const Grid &g, uint32_t x, uint32_t y, uint32_t z, int a) {
-    return row_index<V>(g, y, z) + uint64_t(a) * g.pstride + x;
+template <class V, class I = uint64_t>
+__device__ inline I pop_index(const Grid &g, uint32_t x, uint32_t y, uint32_t z, int a) {
+    return row_index<V, I>(g, y, z) + I(a) * g.pstride + x;
 }
+
+// Index type of the sweep: 32-bit unless the lattice has 2^32 or more elements.
+template <bool IDX64>
+using SweepIndex = typename std::conditional<IDX64, uint64_t, uint32_t>::type;
 
 // Node forces of one step: a dense fixed-point field, written only at the
 // (at most 8 per particle) nodes that receive a reaction force and read only
@@ -95,9 +100,9 @@ struct Neighbours {
         return (sz[V::ez[a] + 1] * g.ny + sy[V::ey[a] + 1]) * g.nx + sx[V::ex[a] + 1];
     }
     // storage index of population a at x - e_a
-    template <class V, int a>
-    __device__ inline uint64_t pop(const Grid &g) const {
-        return pop_index<V>(g, sx[V::ex[a] + 1], sy[V::ey[a] + 1], sz[V::ez[a] + 1], a);
+    template <class V, int a, class I = uint64_t>
+    __device__ inline I pop(const Grid &g) const {
+        return pop_index<V, I>(g, sx[V::ex[a] + 1], sy[V::ey[a] + 1], sz[V::ez[a] + 1], a);
     }
 };
 
@@ -158,7 +163,7 @@ __device__ inline void block_sum(double (&v)[N], double *__restrict__ out) {
 // flagged (FORCED), the particles' reaction force.
 // NTS: write the populations with non-temporal stores (streamed past the
 // caches); pays off once the lattice no longer fits in the last-level cache.
-template <class C, bool FORCED, bool MOMENTS, int CPT, bool NTS>
+template <class C, bool FORCED, bool MOMENTS, int CPT, bool NTS, bool IDX64 = false>
 __device__ inline void collide_lane(const typename C::T *__restrict__ A,
                                     typename C::T *__restrict__ B, const Grid &g,
                                     typename C::R omega, typename C::R enc_s, typename C::R dec_s,
@@ -172,6 +177,7 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
     using T = typename C::T;
     using R = typename C::R;
     using V = typename C::V;
+    using I = SweepIndex<IDX64>;
     const uint32_t x = lane_cell % g.nx;
     const uint32_t t = lane_cell / g.nx;
     const uint32_t rows = g.ny / CPT;
@@ -186,7 +192,7 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
         const Neighbours nb(x, y, z, g);
         static_for<0, V::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            raw[c][a] = A[nb.template pop<V, a>(g)];
+            raw[c][a] = A[nb.template pop<V, a, I>(g)];
         });
         if constexpr (FORCED) {
             const uint32_t cell = (z * g.ny + y) * g.nx + x;
@@ -225,13 +231,13 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
                 Fz += R(double(ff.f[3 * cell + 2]) * kFixInv);
             }
         }
-        const uint64_t row_base = row_index<V>(g, y, z) + x;
+        const I row_base = row_index<V, I>(g, y, z) + x;
         // written once and read only by the next step
         auto put = [&](int a, R gn) {
             if constexpr (NTS)
-                __builtin_nontemporal_store(C::enc(gn, enc_s), &B[row_base + uint64_t(a) * g.pstride]);
+                __builtin_nontemporal_store(C::enc(gn, enc_s), &B[row_base + I(a) * g.pstride]);
             else
-                B[row_base + uint64_t(a) * g.pstride] = C::enc(gn, enc_s);
+                B[row_base + I(a) * g.pstride] = C::enc(gn, enc_s);
         };
         // BGK relaxation to the equilibrium of Eq. s2-eq plus the forcing term
         // 3 w e.F, one opposite pair (a, a + 1) at a time: e_{a+1} = -e_a, so
@@ -315,7 +321,7 @@ __device__ inline bool lane_node(const Grid &g, uint32_t blk, uint32_t &lane_cel
     }
 }
 
-template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW>
+template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW, bool IDX64>
 __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__restrict__ A,
                                                        typename C::T *__restrict__ B, Grid g,
                                                        typename C::R omega, typename C::R enc_s,
@@ -331,8 +337,8 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
     }
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (active)
-        collide_lane<C, FORCED, MOMENTS, CPT, NTS>(A, B, g, omega, enc_s, dec_s, ff, Gx, Gy, Gz,
-                                                   lane_cell, acc);
+        collide_lane<C, FORCED, MOMENTS, CPT, NTS, IDX64>(A, B, g, omega, enc_s, dec_s, ff, Gx, Gy,
+                                                          Gz, lane_cell, acc);
     // partials by wavefront of the node block (no barrier), so that every
     // block order gives the same sums
     if constexpr (MOMENTS)
@@ -344,12 +350,13 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
 // unchanged at x (no moments, collision or forcing), with the same layout and
 // store policy.  Its duration bounds what the stream-collide can reach with
 // this access pattern; B does not hold a lattice update.
-template <class C, int CPT, bool NTS>
+template <class C, int CPT, bool NTS, bool IDX64 = false>
 __device__ inline void stream_only_lane(const typename C::T *__restrict__ A,
                                         typename C::T *__restrict__ B, const Grid &g,
                                         uint32_t lane_cell) {
     using T = typename C::T;
     using V = typename C::V;
+    using I = SweepIndex<IDX64>;
     const uint32_t x = lane_cell % g.nx;
     const uint32_t t = lane_cell / g.nx;
     const uint32_t rows = g.ny / CPT;
@@ -361,31 +368,31 @@ __device__ inline void stream_only_lane(const typename C::T *__restrict__ A,
         const Neighbours nb(x, y0 + uint32_t(c) * rows, z, g);
         static_for<0, V::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            raw[c][a] = A[nb.template pop<V, a>(g)];
+            raw[c][a] = A[nb.template pop<V, a, I>(g)];
         });
     }
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-        const uint64_t row_base = row_index<V>(g, y0 + uint32_t(c) * rows, z) + x;
+        const I row_base = row_index<V, I>(g, y0 + uint32_t(c) * rows, z) + x;
         static_for<0, V::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
             if constexpr (NTS)
-                __builtin_nontemporal_store(raw[c][a], &B[row_base + uint64_t(a) * g.pstride]);
+                __builtin_nontemporal_store(raw[c][a], &B[row_base + I(a) * g.pstride]);
             else
-                B[row_base + uint64_t(a) * g.pstride] = raw[c][a];
+                B[row_base + I(a) * g.pstride] = raw[c][a];
         });
     }
 }
 
 // Streaming-only counterpart of k_stream_collide in configuration <CPT, BS,
 // NTS, ROW> (same lanes).
-template <class C, int CPT, int BS, bool NTS, bool ROW>
+template <class C, int CPT, int BS, bool NTS, bool ROW, bool IDX64>
 __global__ __launch_bounds__(BS) void k_stream_only(const typename C::T *__restrict__ A,
                                                     typename C::T *__restrict__ B, Grid g,
                                                     uint32_t order) {
     uint32_t lane_cell;
     if (!lane_node<CPT, BS, ROW>(g, sweep_block(order), lane_cell)) return;
-    stream_only_lane<C, CPT, NTS>(A, B, g, lane_cell);
+    stream_only_lane<C, CPT, NTS, IDX64>(A, B, g, lane_cell);
 }
 
 // Launch configurations of the stream-collide, chosen per context

@@ -612,15 +612,26 @@ long residency_lds(int lds_cu, int lds_block, int cap, int bs) {
 
 long sweep_lds(const lbm_ctx *c, int cap, int bs) { return residency_lds(c->lds_cu, c->lds_block, cap, bs); }
 
+// The sweep computes its indices in 32 bits unless the lattice holds 2^32 or
+// more elements (Q nx ny nz; boxes beyond about 226M nodes).
+bool sweep_idx64(const lbm_ctx *c) { return uint64_t(c->q) * c->g.ncell >= (uint64_t(1) << 32); }
+
 template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW>
 void launch_collide_shape(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff,
                           double *mom, unsigned grid, int order, int cap) {
     using R = typename C::R;
     const long lds = sweep_lds(c, cap, BS);
-    hipLaunchKernelGGL((k_stream_collide<C, FORCED, MOMENTS, CPT, BS, NTS, ROW>), dim3(grid), dim3(BS),
-                       lds > 0 ? size_t(lds) : 0, c->stream, A, B, c->g, R(c->omega), R(c->enc_s),
-                       R(c->dec_s), ff, R(c->body[0]), R(c->body[1]), R(c->body[2]), mom,
-                       uint32_t(order));
+    const size_t dyn = lds > 0 ? size_t(lds) : 0;
+    if (sweep_idx64(c))
+        hipLaunchKernelGGL((k_stream_collide<C, FORCED, MOMENTS, CPT, BS, NTS, ROW, true>), dim3(grid),
+                           dim3(BS), dyn, c->stream, A, B, c->g, R(c->omega), R(c->enc_s),
+                           R(c->dec_s), ff, R(c->body[0]), R(c->body[1]), R(c->body[2]), mom,
+                           uint32_t(order));
+    else
+        hipLaunchKernelGGL((k_stream_collide<C, FORCED, MOMENTS, CPT, BS, NTS, ROW, false>), dim3(grid),
+                           dim3(BS), dyn, c->stream, A, B, c->g, R(c->omega), R(c->enc_s),
+                           R(c->dec_s), ff, R(c->body[0]), R(c->body[1]), R(c->body[2]), mom,
+                           uint32_t(order));
 }
 
 // mom != nullptr: also leave the per-block FP64 moment sums there.  order,
@@ -829,9 +840,15 @@ void time_stream_only(lbm_ctx *c, int k, int32_t iters, double *ms, hipError_t *
     const size_t dyn = lds > 0 ? size_t(lds) : 0;
     const uint32_t order = uint32_t(c->order);
     auto launch = [&]() {
-#define LBM_STREAM_ONLY(CPT, BS, NTS, ROW)                                                          \
-    hipLaunchKernelGGL((k_stream_only<C, CPT, BS, NTS, ROW>), dim3(grid), dim3(BS), dyn, c->stream, \
-                       A, B, c->g, order)
+#define LBM_STREAM_ONLY(CPT, BS, NTS, ROW)                                                           \
+    do {                                                                                             \
+        if (sweep_idx64(c))                                                                          \
+            hipLaunchKernelGGL((k_stream_only<C, CPT, BS, NTS, ROW, true>), dim3(grid), dim3(BS), dyn, \
+                               c->stream, A, B, c->g, order);                                        \
+        else                                                                                         \
+            hipLaunchKernelGGL((k_stream_only<C, CPT, BS, NTS, ROW, false>), dim3(grid), dim3(BS),    \
+                               dyn, c->stream, A, B, c->g, order);                                   \
+    } while (0)
         LBM_CONFIG_SWITCH(k, LBM_STREAM_ONLY)
 #undef LBM_STREAM_ONLY
     };
@@ -1728,6 +1745,8 @@ bool ens_desc_ok(const lbm_ensemble_desc *d, const lbm_replica_desc *reps) {
         if (r.nx < 2 || r.ny < 2 || r.nz < 2 || r.n < 1 || !(r.tau > 0.5) || !isfinite(r.tau))
             return false;
         if (r.reserved != 0) return false;
+        // a box's sweep indexes within the box in 32 bits
+        if (uint64_t(r.nx) * uint64_t(r.ny) * uint64_t(r.nz) * 19 >= (uint64_t(1) << 32)) return false;
         cells += uint64_t(r.nx) * uint64_t(r.ny) * uint64_t(r.nz);
         n += uint64_t(r.n);
     }

@@ -183,6 +183,12 @@ def test_ensemble_sizes_and_validation(lib):
     bad[1].tau = 0.7
     bad[2].n = 0
     assert lib.lbm_ens_bytes(ctypes.byref(d), bad, ctypes.byref(lat), ctypes.byref(scr)) == 1
+    # one box of 19 x 620^3 >= 2^32 population elements: beyond a box's 32-bit index
+    big = (_abi.ReplicaDesc * 1)(_abi.ReplicaDesc(620, 620, 620, 8, 0.8, 1, 0, 0))
+    d1 = _abi.EnsembleDesc(1, 1, 16, 0, 10.0, 1.0, 1e-4, 0.0, 0, 0)
+    assert lib.lbm_ens_bytes(ctypes.byref(d1), big, ctypes.byref(lat), ctypes.byref(scr)) == 1
+    big[0].nx = 580  # 19 x 580 x 620 x 620 < 2^32
+    assert lib.lbm_ens_bytes(ctypes.byref(d1), big, ctypes.byref(lat), ctypes.byref(scr)) == 0
     d.nrep = 0
     assert lib.lbm_ens_bytes(ctypes.byref(d), reps, ctypes.byref(lat), ctypes.byref(scr)) == 1
     out = ctypes.c_void_p()

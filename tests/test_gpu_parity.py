@@ -380,6 +380,74 @@ def test_suspension512_tiled_against_oracle(oracle_mod):
     torch.cuda.empty_cache()
 
 
+def test_beyond_32bit_lattice_index_tiled_against_oracle(oracle_mod):
+    # A lattice of 19 x 1024 x 512 x 448 >= 2^32 population elements, which the
+    # sweep indexes with 64-bit arithmetic (smaller lattices use 32 bits): a
+    # 32^3 state (perturbed fields, one particle, kT = 0) tiled 32 x 16 x 14
+    # times, 7168 particles at the same place in every tile, 3 steps in FP32,
+    # with one and with 16 rows per group.  Every tile must hold the same
+    # moments and tile 0 must match the oracle's 32^3 run.
+    import torch
+
+    from paper_1909_13412_amd import Lattice
+    from paper_1909_13412_amd.inputs import perturbed_fields
+
+    T, steps = 32, 3
+    K = (32, 16, 14)  # tiles along x, y, z
+    dims = (T * K[0], T * K[1], T * K[2])
+    assert 19 * dims[0] * dims[1] * dims[2] >= 2**32
+    tau = 0.6
+    rho_t, u_t = perturbed_fields((T, T, T), seed=53, amp_rho=1e-3, amp_u=1e-3)
+    p0 = np.array([13.25, 7.8125, 21.625])
+    v0 = np.array([[2e-4, -1e-4, 5e-5]])
+    kw = dict(mass=10.0, gamma=1.0, kT=0.0, radius=0.5, seed=77)
+    ref = oracle_mod.Sim(T, T, T, tau)
+    ref.set_equilibrium(rho_t, u_t)
+    ref.set_particles(p0[None, :], v0, **kw)
+    ref.step(steps)
+    rho_r, u_r = ref.moments()
+    v_r = ref.particles()[1][0]
+    idx = np.stack(np.meshgrid(np.arange(K[0]), np.arange(K[1]), np.arange(K[2]), indexing="ij"),
+                   -1).reshape(-1, 3)
+    r = (T * idx + p0).astype(np.float64)
+    v = np.repeat(v0, len(r), axis=0)
+    announce(f"64-bit lattice index: {dims} FP32 of {T}^3 tiles, {len(r)} particles, {steps} steps")
+    dev = torch.device("cuda")
+    rho_d = torch.from_numpy(rho_t).to(dev).repeat(K[2], K[1], K[0])
+    u_d = torch.from_numpy(u_t).to(dev).repeat(1, K[2], K[1], K[0])
+    g = Lattice(*dims, tau, storage="f32")
+    first = None
+    for shape, rows in ((5, 1), (4, 16)):
+        g.set_layout(rows)
+        g.set_shape(shape)
+        g.set_equilibrium(rho_d, u_d)
+        g.particles_couple(r, v, **kw)
+        g.step(steps)
+        rho_g, u_g = g.moments()
+        rv = rho_g.view(K[2], T, K[1], T, K[0], T)
+        uv = u_g.view(3, K[2], T, K[1], T, K[0], T)
+        d_rho = (rv - rv[:1, :, :1, :, :1, :]).abs().max().item()
+        d_u = (uv - uv[:, :1, :, :1, :, :1, :]).abs().max().item()
+        vg = g.v.cpu().numpy()
+        tile_rho = rho_g[:T, :T, :T].cpu().numpy()
+        tile_u = u_g[:, :T, :T, :T].cpu().numpy()
+        e_rho = nmax_err(tile_rho - 1.0, rho_r - 1.0)
+        e_u = nmax_err(tile_u, u_r)
+        e_v = nmax_err(vg[0], v_r)
+        announce(f"  shape {shape}, {rows} rows per group: tiles differ by rho {d_rho:.1e} u {d_u:.1e}; "
+                 f"tile 0 vs oracle rho-1 {e_rho:.2e} u {e_u:.2e} v {e_v:.2e}")
+        assert d_rho <= 1e-9 and d_u <= 1e-9
+        assert np.abs(vg - vg[:1]).max() <= 1e-10 * np.abs(v0).max()
+        assert e_rho < 1e-5 and e_u < 1e-5 and e_v < 1e-5
+        if first is None:
+            first = (tile_rho, tile_u)
+        else:
+            assert np.array_equal(first[0], tile_rho) and np.array_equal(first[1], tile_u)
+        del rho_g, u_g, rv, uv
+    del g, rho_d, u_d
+    torch.cuda.empty_cache()
+
+
 def test_suspension512_tiled_bf16_one_step_pinned_to_rounding(oracle_mod):
     # The BF16 instance at full size (19 x 512^3 elements), every node: a 32^3
     # perturbed state whose shifted populations are rounded to BF16 (so the
