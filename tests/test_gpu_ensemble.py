@@ -242,16 +242,23 @@ def test_ensemble64_workload():
 
 def test_ensemble64_full_run_against_oracle():
     # The 64-replica workload over its full 5000 steps, graph-replayed, FP32:
-    # the smallest and the largest box against the FP64 oracle's own runs of
-    # those boxes (tests/golden/oracle_ensemble64_edges.json): velocity
-    # autocorrelation (lags 0..1000, origins every 10 steps) and the final
-    # particle velocities.
+    # every box against the FP64 oracle's own run of that box alone
+    # (tests/golden/oracle_ensemble64_all.json): velocity autocorrelation
+    # (lags 0..1000, origins every 10 steps) and the final particle velocities.
+    # A box whose FP32 trajectories still follow the oracle's (final velocities
+    # within 1e-3) must match its VACF to 1e-4 of C(0).  In a box where the
+    # rounding differences have grown (the fit is nonlinear in the nodal
+    # velocities, and eight particles give a noisy estimator), C(0) must agree
+    # within four standard errors of the box's own estimate.  The
+    # ensemble-averaged VACF over all 512 particles (the workload's observable)
+    # must match the oracle's average to 1% of C(0), and its tail sum (lags
+    # 50-250) within twice its sampling error.
     import bench
     from paper_1909_13412_amd import Ensemble
     from paper_1909_13412_amd.inputs import ENSEMBLE64, ensemble_replicas
 
     w = ENSEMBLE64
-    ref = bench.oracle_fixture("ensemble64_edges")
+    ref = bench.oracle_fixture("ensemble64_all")
     assert ref is not None and ref["steps"] == w["steps"]
     reps = ensemble_replicas(w["replicas"], w["sizes"], w["n"], w["tau"], w["kT"], w["mass"], w["seed"])
     ens = Ensemble(reps, storage="f32", kT=w["kT"], mass=w["mass"], gamma=w["gamma"])
@@ -259,6 +266,8 @@ def test_ensemble64_full_run_against_oracle():
     ens.step(w["steps"])
     acc, cnt = ens.vacf()
     acc = acc.cpu().numpy() / np.maximum(cnt, 1)
+    assert sorted(rec["index"] for rec in ref["replicas"]) == list(range(len(reps)))
+    following = 0
     for rec in ref["replicas"]:
         k = rec["index"]
         assert reps[k]["nx"] == rec["edge"] and reps[k]["seed"] == rec["seed"]
@@ -266,11 +275,25 @@ def test_ensemble64_full_run_against_oracle():
         rows = acc[w["n"] * k: w["n"] * (k + 1)]
         e = bench.vacf_errors(rows.mean(axis=0), rec["vacf"], (50, 250), rows)
         ev = nmax_err(ens.particles(k)[1].cpu().numpy(), rec["final_v"])
-        announce(f"  replica {k} (edge {rec['edge']}): C(0) {e['c0_rel']:.2e}, VACF "
+        c0 = rows[:, 0]
+        se_c0 = np.std(c0, ddof=1) / np.sqrt(len(c0)) / abs(c0.mean())
+        announce(f"  replica {k} (edge {rec['edge']}): C(0) {e['c0_rel']:.2e} (se {se_c0:.1e}), VACF "
                  f"{e['vacf_abs_err']:.2e}, tail sum {e['tail_integral_rel']:.2e}, final V {ev:.2e}")
-        assert e["c0_rel"] < 1e-4 and e["vacf_abs_err"] < 1e-4
-        assert e["tail_integral_rel"] < 1e-2
-        assert ev < 1e-3
+        if ev < 1e-3:
+            following += 1
+            assert e["c0_rel"] < 1e-4 and e["vacf_abs_err"] < 1e-4, k
+        else:
+            assert e["c0_rel"] < 4.0 * se_c0, k
+    # the ensemble average over every particle of every box
+    c_ref = np.mean([np.asarray(rec["vacf"]) for rec in sorted(ref["replicas"], key=lambda r: r["index"])],
+                    axis=0)
+    e = bench.vacf_errors(acc.mean(axis=0), c_ref, (50, 250), acc)
+    announce(f"  {following} of {len(reps)} boxes follow the oracle's trajectories; ensemble: C(0) "
+             f"{e['c0_rel']:.2e}, VACF {e['vacf_abs_err']:.2e}, tail sum {e['tail_integral_rel']:.2e} "
+             f"(se {e['tail_integral_se_rel']:.2e})")
+    assert following >= len(reps) // 2
+    assert e["c0_rel"] < 1e-2 and e["vacf_abs_err"] < 1e-2
+    assert e["tail_integral_rel"] < 2.0 * e["tail_integral_se_rel"]
 
 
 def test_autotune_choice_is_remembered():
