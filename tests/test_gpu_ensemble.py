@@ -61,17 +61,19 @@ def test_ensemble_replicas_match_oracle(oracle_mod):
         assert nmax_err(o_g[1:], o_r[1:]) < 1e-10
 
 
-def test_ensemble_equals_single_box_runs():
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16", "f64"])
+def test_ensemble_equals_single_box_runs(storage):
     from paper_1909_13412_amd import Ensemble, Lattice
 
     reps = _small_replicas()
-    ens = Ensemble(reps, storage="f32", kT=1e-4)
+    ens = Ensemble(reps, storage=storage, kT=1e-4)
     ens.step(24)
     # The ensemble kernels run the single-box node and particle updates with
     # the same rounding (multiply-adds fuse only within one expression), so
-    # every replica must reproduce its single-box run bit for bit.
+    # every replica must reproduce its single-box run bit for bit, in every
+    # storage.
     for k, rd in enumerate(reps):
-        one = Lattice(rd["nx"], rd["ny"], rd["nz"], rd["tau"], storage="f32")
+        one = Lattice(rd["nx"], rd["ny"], rd["nz"], rd["tau"], storage=storage)
         one.particles_couple(rd["r"], rd["v"], kT=1e-4, seed=rd["seed"], replica=rd["replica"])
         one.step(24)
         fe, fo = ens.populations(k).cpu().numpy(), one.populations().cpu().numpy()
