@@ -481,7 +481,7 @@ lbm_status lbm_adjoint(lbm_ctx *ctx, const void *tape, void *work, double *adj_p
  * e.g. for ensemble-averaged velocity autocorrelation, stepped together.  One
  * particle launch and one stream-collide launch per step cover every replica
  * (a block never straddles two boxes); steps are replayed from a captured
- * two-step HIP graph.  Every replica computes exactly what a single-box
+ * HIP graph of LBM_ENS_GRAPH_STEPS steps.  Every replica computes exactly what a single-box
  * context with the same box, tau, particles, seed and replica word computes.
  * ------------------------------------------------------------------------- */
 typedef struct lbm_ensemble_desc {
@@ -519,9 +519,12 @@ lbm_status lbm_ens_init(const lbm_ensemble_desc *desc, const lbm_replica_desc *r
                         void *pop_b, void *scratch, double *r, double *v, void *stream,
                         lbm_ens **out);
 
-/* 1 (default): lbm_ens_step replays a captured two-step graph (captured on a
- * private stream, replayed on the context's stream; plain launches are used
- * if capture is not possible); 0: plain launches. */
+/* 1 (default): lbm_ens_step replays a captured graph of LBM_ENS_GRAPH_STEPS
+ * steps for every whole group of that many steps from an even step (captured
+ * on a private stream, replayed on the context's stream), and launches the
+ * rest of the steps directly; plain launches throughout if capture is not
+ * possible; 0: plain launches. */
+#define LBM_ENS_GRAPH_STEPS 16
 lbm_status lbm_ens_use_graph(lbm_ens *ens, int32_t use);
 
 /* Per-particle VACF over all replicas (layouts as lbm_vacf_config with n = all
@@ -567,7 +570,8 @@ lbm_status lbm_ens_get_shape(const lbm_ens *ens, int32_t *k);
 lbm_status lbm_ens_observables(lbm_ens *ens, int32_t replica, double out[7]);
 lbm_status lbm_ens_get_populations(lbm_ens *ens, int32_t replica, double *f);
 lbm_status lbm_ens_get_step(const lbm_ens *ens, int64_t *step);
-/* Number of two-step graph launches made so far (0 when stepping eagerly). */
+/* Number of graph launches (of LBM_ENS_GRAPH_STEPS steps each) made so far
+ * (0 when stepping eagerly). */
 lbm_status lbm_ens_graph_replays(const lbm_ens *ens, int64_t *replays);
 lbm_status lbm_ens_destroy(lbm_ens *ens);
 

@@ -28,6 +28,7 @@ EXPORTS = [
     "lbm_status_string",
 ]
 LBM_NUM_SHAPES = 10
+LBM_ENS_GRAPH_STEPS = 16
 # advisory bits of lbm_warnings
 WARNINGS = {
     1: "radius beyond sqrt(3) dx (2 sqrt(3) dx for the (2 dx)^3 fit): the particle covers the fitting nodes",

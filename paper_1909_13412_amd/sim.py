@@ -422,7 +422,7 @@ class Lattice(_StreamOrder):
 
 class Ensemble(_StreamOrder):
     """Many independent periodic boxes stepped together (one launch per kernel
-    per step, replayed from a captured two-step graph).
+    per step, replayed from a captured graph of several steps).
 
     replicas: list of dicts with keys nx, ny, nz, r [n, 3], v [n, 3], tau, seed,
     replica (Philox third counter word).  Shared: storage, mass, gamma, kT,

@@ -202,6 +202,8 @@ def test_launch_configuration_count_matches_header():
     text = open(os.path.join(ROOT, "include", "lbmbp.h")).read()
     m = re.search(r"#define LBM_NUM_SHAPES (\d+)", text)
     assert m and int(m.group(1)) == _abi.LBM_NUM_SHAPES == 10
+    m = re.search(r"#define LBM_ENS_GRAPH_STEPS (\d+)", text)
+    assert m and int(m.group(1)) == _abi.LBM_ENS_GRAPH_STEPS
 
 
 def test_binding_attributes_not_shadowed_by_properties():

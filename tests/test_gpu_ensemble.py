@@ -30,18 +30,20 @@ def _small_replicas(kT=1e-4):
 
 
 def test_ensemble_replicas_match_oracle(oracle_mod):
-    from paper_1909_13412_amd import Ensemble
+    from paper_1909_13412_amd import Ensemble, _abi
 
     reps = _small_replicas()
     ens = Ensemble(reps, storage="f64", kT=1e-4)
     ens.vacf_config(9, 4)
-    ens.step(31)  # odd: fifteen two-step graph replays and one plain step
-    assert ens.graph_replays == 15
+    G = _abi.LBM_ENS_GRAPH_STEPS
+    steps = 2 * G + 5  # two graph replays and five plain steps
+    ens.step(steps)
+    assert ens.graph_replays == 2
     for k, rd in enumerate(reps):
         ref = oracle_mod.Sim(rd["nx"], rd["ny"], rd["nz"], rd["tau"])
         ref.set_particles(rd["r"], rd["v"], kT=1e-4, seed=rd["seed"], replica=rd["replica"])
         ref.vacf_config(9, 4)
-        ref.step(31)
+        ref.step(steps)
         rr, vr = ref.particles()
         rg, vg = ens.particles(k)
         e_v = nmax_err(vg.cpu().numpy(), vr)
@@ -186,23 +188,32 @@ def test_ensemble_layouts_are_bit_identical():
 
 
 def test_graph_replays_match_plain_launches():
-    # Replays of the captured two-step graph, with eager work and
-    # synchronisation between them, against the same ensemble stepped with
-    # plain launches: every replay compared.
+    # Replays of the captured graph, with eager work and synchronisation
+    # between them, against the same ensemble stepped with plain launches:
+    # every replay compared; a call of fewer steps than one graph, and an odd
+    # start, run plainly.
     import torch
 
-    from paper_1909_13412_amd import Ensemble
+    from paper_1909_13412_amd import Ensemble, _abi
 
+    G = _abi.LBM_ENS_GRAPH_STEPS
     reps = _small_replicas()
     g = Ensemble(reps, storage="f32", kT=1e-4)
     e = Ensemble(reps, storage="f32", kT=1e-4)
     e.use_graph(False)
     g.vacf_config(6, 3)
     e.vacf_config(6, 3)
-    for rep in range(6):
-        g.step(2)
-        e.step(2)
-        assert g.graph_replays == rep + 1 and e.graph_replays == 0
+    step, replays = 0, 0
+    for rep, n in enumerate((G, G, 3, G + 1, 2 * G + 1, 5)):
+        g.step(n)
+        e.step(n)
+        # from an odd step one plain step first; then one replay per whole
+        # graph; the rest plain
+        if step % 2 and n > 0:
+            step, n = step + 1, n - 1
+        replays += n // G
+        step += n
+        assert g.graph_replays == replays and e.graph_replays == 0, rep
         torch.cuda.synchronize()
         for k in range(len(reps)):
             assert np.array_equal(g.populations(k).cpu().numpy(), e.populations(k).cpu().numpy()), (rep, k)
