@@ -389,6 +389,23 @@ def time_ensemble(steps, warmup):
                                    **{kk: (float(f"{vv:.4g}") if isinstance(vv, float) else vv)
                                       for kk, vv in e.items()}})
                 out["vs_oracle"] = checks
+            # every box: the ensemble-averaged VACF over all particles against
+            # the average of the oracle's single-box runs, and how many boxes
+            # still follow the oracle's trajectories (final velocities 1e-3)
+            full = oracle_fixture("ensemble64_all")
+            if full is not None and full["steps"] == steps:
+                recs = sorted(full["replicas"], key=lambda r: r["index"])
+                per = acc / np.maximum(cnt, 1)
+                c_ref = np.mean([np.asarray(r["vacf"]) for r in recs], axis=0)
+                e = vacf_errors(per.mean(axis=0), c_ref, (50, 250), per)
+                follow = 0
+                for r in recs:
+                    _, vk = ens.particles(r["index"])
+                    fv = np.asarray(r["final_v"])
+                    follow += int(np.max(np.abs(vk.cpu().numpy() - fv)) / np.max(np.abs(fv)) < 1e-3)
+                out["vs_oracle_all_boxes"] = {
+                    "boxes": len(recs), "boxes_following_oracle_trajectories": follow,
+                    **{kk: (float(f"{vv:.4g}") if isinstance(vv, float) else vv) for kk, vv in e.items()}}
         del ens
         torch.cuda.empty_cache()
     return out
