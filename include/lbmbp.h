@@ -275,8 +275,8 @@ lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps);
  * {step, fluid mass sum rho~, fluid momentum sum u (3), particle momentum
  * sum M V (3)} of the state at the start of that step, for k < capacity
  * (recording stops when full).  The fluid sums are taken inside the
- * stream-collide and the particle sums inside the particle kernel, as
- * per-block FP64 partials finished in a fixed order (deterministic).
+ * stream-collide (FP64 partials per wavefront) and the particle sums inside
+ * the particle kernel (per block), finished in a fixed order (deterministic).
  * series: device FP64 [capacity][8], caller-owned.  every = 0 stops. */
 lbm_status lbm_series_config(lbm_ctx *ctx, int32_t every, double *series, int64_t capacity);
 

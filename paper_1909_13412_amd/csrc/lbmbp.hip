@@ -634,7 +634,7 @@ void launch_collide_shape(lbm_ctx *c, const typename C::T *A, typename C::T *B, 
                            uint32_t(order));
 }
 
-// mom != nullptr: also leave the per-block FP64 moment sums there.  order,
+// mom != nullptr: also leave the per-wavefront FP64 moment sums there.  order,
 // cap: block order and residency cap (-1: the context's).
 template <class C, bool FORCED>
 void launch_collide(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff, int shape,
