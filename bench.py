@@ -369,6 +369,7 @@ def time_ensemble(steps, warmup):
         out[f"mlups_{key}"] = round(nodes * steps / dt / 1e6, 1)
         out[f"ms_per_step_{key}"] = round(dt * 1e3 / steps, 5)
         out["launch_shape"] = shape
+        out["launch_order"], out["launch_waves_per_simd_cap"] = ens.sweep_launch
         if use_graph:
             out["graph_replays"] = ens.graph_replays
             acc, cnt = ens.vacf()

@@ -537,11 +537,23 @@ lbm_status lbm_ens_vacf_counts(const lbm_ens *ens, int64_t *cnt);
 lbm_status lbm_ens_step(lbm_ens *ens, int32_t nsteps);
 
 /* Time the stream-collide launch shapes on the ensemble in every layout
- * (lbm_ens_set_layout; state unchanged) and keep the fastest shape and
- * layout; as lbm_autotune.  The choice is remembered for ensembles created
- * later on the same device with the same storage and the same box sizes in
- * the same order, which start from it. */
+ * (lbm_ens_set_layout; state unchanged), then the block orders and
+ * residency caps (lbm_ens_set_sweep_launch) of the two fastest in the best
+ * layout, and keep the fastest launch in the same four stages as
+ * lbm_autotune.  The choice is remembered for ensembles created later on the
+ * same device with the same storage and the same box sizes in the same
+ * order, which start from it. */
 lbm_status lbm_ens_autotune(lbm_ens *ens, int32_t iters, double *ms, int32_t *chosen);
+
+/* Block order and residency cap of the ensemble's stream-collide, as
+ * lbm_set_sweep_launch: the same node updates whatever the choice (the block
+ * -> box table is read at the renumbered block).  A change drops the
+ * captured graph (the next lbm_ens_step captures again).  LBM_E_INVAL for a
+ * NULL argument, an order or cap outside the values of lbm_set_sweep_launch,
+ * or a cap the device's LDS cannot impose for the current configuration's
+ * block size. */
+lbm_status lbm_ens_set_sweep_launch(lbm_ens *ens, int32_t order, int32_t waves_per_simd);
+lbm_status lbm_ens_get_sweep_launch(const lbm_ens *ens, int32_t *order, int32_t *waves_per_simd);
 
 /* Storage layout of the ensemble's lattices (as lbm_set_layout, box by box):
  * rows_per_group (1, 2, 4, ..., 64) is requested of every box, and each box
@@ -555,14 +567,21 @@ lbm_status lbm_ens_get_layout(const lbm_ens *ens, int32_t replica, int32_t *rows
 /* Ceiling of the ensemble stream-collide's data movement, as lbm_stream_ceiling:
  * *ms receives the mean milliseconds per launch (iters 1..10000, after two
  * warm-up launches) of a kernel that pulls and stores every population of every
- * box unchanged, with the ensemble's block -> box table and launch
- * configuration k (k < 0: the current one; 0..7 only).  Reads the current
+ * box unchanged, with the ensemble's block -> box table, block order and
+ * residency cap (where it fits the block size) and launch configuration k
+ * (k < 0: the current one; 0..7 only).  Reads the current
  * populations and overwrites the spare lattice: the state is unchanged.
  * Synchronises the stream.  LBM_E_INVAL for a NULL ens or ms, iters out of
  * range, or a configuration that does not apply to every box. */
 lbm_status lbm_ens_stream_ceiling(lbm_ens *ens, int32_t k, int32_t iters, double *ms);
 
-/* The launch configuration later lbm_ens_step calls use. */
+/* Use launch configuration k (0..7; two-node configurations need an even ny
+ * in every box) for later lbm_ens_step calls, as lbm_set_shape: the same
+ * results in every configuration; a residency cap that does not fit the new
+ * block size is dropped, and a change drops the captured graph.  LBM_E_INVAL
+ * for a NULL ens or a configuration that does not apply to every box.
+ * lbm_ens_get_shape gives the configuration later steps use. */
+lbm_status lbm_ens_set_shape(lbm_ens *ens, int32_t k);
 lbm_status lbm_ens_get_shape(const lbm_ens *ens, int32_t *k);
 
 /* Per-replica FP64 sums (as lbm_observables) and populations (as

@@ -20,7 +20,7 @@ EXPORTS = [
     "lbm_set_body_force", "lbm_get_populations", "lbm_get_moments", "particles_couple", "lbm_set_particle_force", "lbm_set_pair_force", "lbm_pair_forces", "lbm_particle_radius", "lbm_warnings",
     "lbm_particle_forces", "lbm_vacf_config", "lbm_vacf_counts", "lbm_step", "lbm_series_config",
     "lbm_series_count", "lbm_observables", "lbm_observables_noalloc",
-    "lbm_profile_enable", "lbm_profile_read", "lbm_autotune", "lbm_stream_ceiling", "lbm_set_shape", "lbm_get_shape", "lbm_set_sweep_launch", "lbm_get_sweep_launch", "lbm_set_layout", "lbm_get_layout", "lbm_ens_set_layout", "lbm_ens_get_layout", "lbm_get_step", "lbm_destroy",
+    "lbm_profile_enable", "lbm_profile_read", "lbm_autotune", "lbm_stream_ceiling", "lbm_set_shape", "lbm_get_shape", "lbm_set_sweep_launch", "lbm_get_sweep_launch", "lbm_set_layout", "lbm_get_layout", "lbm_ens_set_layout", "lbm_ens_get_layout", "lbm_ens_set_sweep_launch", "lbm_ens_get_sweep_launch", "lbm_ens_set_shape", "lbm_get_step", "lbm_destroy",
     "lbm_tape_bytes", "lbm_record", "lbm_adjoint_work_bytes", "lbm_adjoint",
     "lbm_ens_bytes", "lbm_ens_init", "lbm_ens_use_graph", "lbm_ens_vacf_config",
     "lbm_ens_vacf_counts", "lbm_ens_step", "lbm_ens_autotune", "lbm_ens_stream_ceiling", "lbm_ens_get_shape", "lbm_ens_observables",
@@ -119,6 +119,9 @@ def load() -> ctypes.CDLL:
         "lbm_get_layout": [vp, ctypes.POINTER(i32)],
         "lbm_ens_set_layout": [vp, i32],
         "lbm_ens_get_layout": [vp, i32, ctypes.POINTER(i32)],
+        "lbm_ens_set_sweep_launch": [vp, i32, i32],
+        "lbm_ens_set_shape": [vp, i32],
+        "lbm_ens_get_sweep_launch": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "lbm_warnings": [vp, ctypes.POINTER(ctypes.c_uint32)],
         "lbm_get_step": [vp, ctypes.POINTER(i64)],
         "lbm_destroy": [vp],

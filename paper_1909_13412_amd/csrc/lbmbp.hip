@@ -78,10 +78,11 @@ __global__ __launch_bounds__(BS) void k_ens_collide(const typename C::T *__restr
                                                     int shape, long long *force,
                                                     uint32_t *mask, typename C::R enc_s,
                                                     typename C::R dec_s, EnsClock *clock,
-                                                    int vacf_on) {
-    const uint32_t rid = blk_rep[blockIdx.x];
+                                                    int vacf_on, uint32_t order) {
+    const uint32_t b = sweep_block(order);
+    const uint32_t rid = blk_rep[b];
     const Replica &rp = reps[rid];
-    const uint32_t lane_cell = (blockIdx.x - rp.first_block[shape]) * BS + threadIdx.x;
+    const uint32_t lane_cell = (b - rp.first_block[shape]) * BS + threadIdx.x;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         // the step's last reader of the clock has finished (previous kernel)
         clock->step += 1;
@@ -95,16 +96,18 @@ __global__ __launch_bounds__(BS) void k_ens_collide(const typename C::T *__restr
                                            enc_s, dec_s, ff, R(0), R(0), R(0), lane_cell, acc);
 }
 
-// Streaming-only counterpart of k_ens_collide (same block -> box table, lanes
-// and store policy): the ceiling the ensemble stream-collide is measured
-// against.
+// Streaming-only counterpart of k_ens_collide (same block -> box table, block
+// order, lanes and store policy): the comparison kernel the ensemble
+// stream-collide is measured against.
 template <class C, int CPT, int BS, bool NTS>
 __global__ __launch_bounds__(BS) void k_ens_stream_only(const typename C::T *__restrict__ A,
                                                         typename C::T *__restrict__ B,
                                                         const Replica *__restrict__ reps,
-                                                        const uint16_t *__restrict__ blk_rep, int shape) {
-    const Replica &rp = reps[blk_rep[blockIdx.x]];
-    const uint32_t lane_cell = (blockIdx.x - rp.first_block[shape]) * BS + threadIdx.x;
+                                                        const uint16_t *__restrict__ blk_rep, int shape,
+                                                        uint32_t order) {
+    const uint32_t b = sweep_block(order);
+    const Replica &rp = reps[blk_rep[b]];
+    const uint32_t lane_cell = (b - rp.first_block[shape]) * BS + threadIdx.x;
     if (lane_cell >= rp.g.ncell / CPT) return;
     stream_only_lane<C, CPT, NTS>(A + rp.pop_off, B + rp.pop_off, rp.g, lane_cell);
 }
@@ -1697,6 +1700,8 @@ struct lbm_ens {
     int64_t vacf_t;
     int64_t step;
     int shape;
+    int order, cap;         // block order and residency cap of the stream-collide
+    int lds_cu, lds_block;  // LDS bytes per compute unit and per block (device limits)
     int rows;    // requested rows per group: each box takes the largest power of two <= rows dividing its ny
     int device;  // device current at lbm_ens_init (autotune cache key)
     // graph of LBM_ENS_GRAPH_STEPS steps, captured on a private stream and
@@ -1834,13 +1839,19 @@ ParticleArgs ens_particle_args(lbm_ens *e) {
     return pa;
 }
 
+// Dynamic LDS that caps the ensemble sweep at kResidencyCaps[cap] waves per
+// SIMD for blocks of bs lanes (0: no cap; -1: not possible on this device).
+long ens_sweep_lds(const lbm_ens *e, int cap, int bs) { return residency_lds(e->lds_cu, e->lds_block, cap, bs); }
+
 template <class C, int CPT, int BS, bool NTS>
 void ens_collide_shape(lbm_ens *e, const typename C::T *A, typename C::T *B, int par) {
     using R = typename C::R;
     const int sh = e->shape & 3;
-    hipLaunchKernelGGL((k_ens_collide<C, CPT, BS, NTS>), dim3(e->total_blocks[sh]), dim3(BS), 0,
-                       e->stream, A, B, e->reps, e->blk_rep[sh], sh, e->force[par], e->mask[par],
-                       R(e->enc_s), R(e->dec_s), e->clock, e->vacf_on);
+    const long lds = ens_sweep_lds(e, e->cap, BS);
+    hipLaunchKernelGGL((k_ens_collide<C, CPT, BS, NTS>), dim3(e->total_blocks[sh]), dim3(BS),
+                       lds > 0 ? size_t(lds) : 0, e->stream, A, B, e->reps, e->blk_rep[sh], sh,
+                       e->force[par], e->mask[par], R(e->enc_s), R(e->dec_s), e->clock, e->vacf_on,
+                       uint32_t(e->order));
 }
 
 // One step of every replica; par = field parity of this step.
@@ -1967,20 +1978,24 @@ bool ens_capture(lbm_ens *e) {
 }
 
 template <class C, int CPT, int BS, bool NTS>
-void ens_time_shape(lbm_ens *e, int k) {
+void ens_time_shape(lbm_ens *e, int k, int o, int c) {
     // A -> B without swapping (the state in A is untouched); the caller
     // restores the device clock the launches advance.
-    const int saved = e->shape;
+    const int saved[3] = {e->shape, e->order, e->cap};
     e->shape = k;
+    e->order = o;
+    e->cap = c;
     ens_collide_shape<C, CPT, BS, NTS>(e, static_cast<const typename C::T *>(e->pop[e->cur]),
                                        static_cast<typename C::T *>(e->pop[e->cur ^ 1]),
                                        int((e->step + 1) & 1));  // last step's node forces
-    e->shape = saved;
+    e->shape = saved[0];
+    e->order = saved[1];
+    e->cap = saved[2];
 }
 
 template <class C>
-void ens_time_dispatch(lbm_ens *e, int k) {
-#define LBM_ENS_TIME(CPT, BS, NTS, ROW) ens_time_shape<C, CPT, BS, NTS>(e, k)
+void ens_time_dispatch(lbm_ens *e, int k, int o, int c) {
+#define LBM_ENS_TIME(CPT, BS, NTS, ROW) ens_time_shape<C, CPT, BS, NTS>(e, k, o, c)
     LBM_CONFIG_SWITCH(k, LBM_ENS_TIME)
 #undef LBM_ENS_TIME
 }
@@ -1991,9 +2006,13 @@ void ens_stream_only(lbm_ens *e, int k) {
     const int sh = k & 3;
     const T *A = static_cast<const T *>(e->pop[e->cur]);
     T *B = static_cast<T *>(e->pop[e->cur ^ 1]);
-#define LBM_ENS_STREAM_ONLY(CPT, BS, NTS, ROW)                                                      \
-    hipLaunchKernelGGL((k_ens_stream_only<C, CPT, BS, NTS>), dim3(e->total_blocks[sh]), dim3(BS), 0, \
-                       e->stream, A, B, e->reps, e->blk_rep[sh], sh)
+#define LBM_ENS_STREAM_ONLY(CPT, BS, NTS, ROW)                                                   \
+    do {                                                                                          \
+        const long lds = ens_sweep_lds(e, e->cap, BS);                                            \
+        hipLaunchKernelGGL((k_ens_stream_only<C, CPT, BS, NTS>), dim3(e->total_blocks[sh]),       \
+                           dim3(BS), lds > 0 ? size_t(lds) : 0, e->stream, A, B, e->reps,         \
+                           e->blk_rep[sh], sh, uint32_t(e->order));                               \
+    } while (0)
     LBM_CONFIG_SWITCH(k, LBM_ENS_STREAM_ONLY)
 #undef LBM_ENS_STREAM_ONLY
 }
@@ -2007,13 +2026,36 @@ void ens_stream_only_any(lbm_ens *e, int k) {
     }
 }
 
-void ens_time_any(lbm_ens *e, int k) {
+void ens_time_any(lbm_ens *e, int k, int o, int c) {
     switch (e->desc.storage) {
-        case LBM_STORE_F64: ens_time_dispatch<F64Q19>(e, k); break;
-        case LBM_STORE_F32: ens_time_dispatch<F32Q19>(e, k); break;
-        case LBM_STORE_BF16: ens_time_dispatch<BF16Q19>(e, k); break;
-        case LBM_STORE_F16: ens_time_dispatch<F16Q19>(e, k); break;
+        case LBM_STORE_F64: ens_time_dispatch<F64Q19>(e, k, o, c); break;
+        case LBM_STORE_F32: ens_time_dispatch<F32Q19>(e, k, o, c); break;
+        case LBM_STORE_BF16: ens_time_dispatch<BF16Q19>(e, k, o, c); break;
+        case LBM_STORE_F16: ens_time_dispatch<F16Q19>(e, k, o, c); break;
     }
+}
+
+// Configuration k applies to every box (two-node shapes need an even ny) and
+// cap c can be imposed on its blocks.
+bool ens_launch_ok(const lbm_ens *e, int k, int c) {
+    if (k < 0 || k >= kNumShapes || config_row(k) || e->total_blocks[k & 3] == 0) return false;
+    for (int32_t q = 0; q < e->nrep; ++q)
+        if (e->host_reps[q].ny % kShapes[k & 3].cpt != 0) return false;
+    return ens_sweep_lds(e, c, config_block(k)) >= 0;
+}
+
+// Mean ms per launch of configuration k with block order o and cap c over
+// iters launches (after two unrecorded ones); < 0 on a device error.
+double ens_time_launch(lbm_ens *e, int k, int o, int c, int32_t iters, hipEvent_t e0, hipEvent_t e1) {
+    for (int w = 0; w < 2; ++w) ens_time_any(e, k, o, c);
+    (void)hipEventRecord(e0, e->stream);
+    for (int32_t it = 0; it < iters; ++it) ens_time_any(e, k, o, c);
+    (void)hipEventRecord(e1, e->stream);
+    float f = 0.0f;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&f, e0, e1) != hipSuccess ||
+        launch_status() != LBM_OK)
+        return -1.0;
+    return double(f) / iters;
 }
 
 }  // namespace
@@ -2075,7 +2117,16 @@ lbm_status lbm_ens_init(const lbm_ensemble_desc *desc, const lbm_replica_desc *r
     {
         const int code = tune_lookup(ens_tune_key(e), L.lattice_bytes >= kStreamStoreBytes ? kNumGeomShapes : 0);
         e->shape = code % kNumShapes;
-        e->rows = 1 << (code / kNumShapes);  // applied to every box below (the rest state is all zeros)
+        e->order = (code / kNumShapes) % int(kNumOrders);
+        e->cap = (code / (kNumShapes * int(kNumOrders))) % kNumCaps;
+        // applied to every box below (the rest state is all zeros)
+        e->rows = 1 << (code / (kNumShapes * int(kNumOrders) * kNumCaps));
+        int v = 0;
+        e->lds_cu = (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                           e->device) == hipSuccess) ? v : 0;
+        e->lds_block = (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                              e->device) == hipSuccess) ? v : 0;
+        if (ens_sweep_lds(e, e->cap, config_block(e->shape)) < 0) e->cap = 0;
     }
     for (int s = 0; s < kNumGeomShapes; ++s) e->total_blocks[s] = L.total_blocks[s];
     e->n = L.n;
@@ -2235,54 +2286,127 @@ lbm_status lbm_ens_autotune(lbm_ens *e, int32_t iters, double *ms, int32_t *chos
     if (!e || iters < 1 || iters > 10000) return LBM_E_INVAL;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return LBM_E_DEVICE;
-    if (hipEventCreate(&e1) != hipSuccess) return LBM_E_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return LBM_E_DEVICE;
+    }
     // the timing launches advance the device clock; restore it afterwards
     EnsClock saved;
     hipError_t err = hipMemcpyAsync(&saved, e->clock, sizeof(saved), hipMemcpyDeviceToHost, e->stream);
     if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
-    // every configuration in every layout (rows per group requested of all
-    // boxes: 1, 2, ..., 64)
-    double t[kNumShapes];
-    for (int k = 0; k < kNumShapes; ++k) t[k] = -1.0;
-    int best = -1, best_rows = 1;
-    double best_t = -1.0;
-    for (int lg = 0; lg <= kMaxRowsLog2 && err == hipSuccess; ++lg) {
-        if (ens_set_layout(e, 1 << lg) != LBM_OK) {
-            err = hipErrorUnknown;
-            break;
+    double best_k[kNumShapes];
+    for (int k = 0; k < kNumShapes; ++k) best_k[k] = -1.0;
+    // every launch timed: configuration, order, cap, layout (log2 of the rows
+    // per group requested of all boxes), ms
+    struct Trial {
+        int k, o, c, l;
+        double t;
+    };
+    std::vector<Trial> trials;
+    bool ok = err == hipSuccess;
+    auto time_in = [&](int l, int k, int o, int c, int32_t n) -> double {
+        if (!ok) return -1.0;
+        if (ens_set_layout(e, 1 << l) != LBM_OK) {
+            ok = false;
+            return -1.0;
         }
-        for (int k = 0; k < kNumShapes && err == hipSuccess; ++k) {
-            if (config_row(k) || e->total_blocks[k & 3] == 0) continue;  // rows: single boxes only
-            bool all = true;
-            for (int32_t q = 0; q < e->nrep; ++q) all = all && (e->host_reps[q].ny % kShapes[k & 3].cpt == 0);
-            if (!all) continue;
-            for (int w = 0; w < 2; ++w) ens_time_any(e, k);
-            (void)hipEventRecord(e0, e->stream);
-            for (int32_t it = 0; it < iters; ++it) ens_time_any(e, k);
-            (void)hipEventRecord(e1, e->stream);
-            err = hipEventSynchronize(e1);
-            float f = 0.0f;
-            if (err == hipSuccess) err = hipEventElapsedTime(&f, e0, e1);
-            const double v = double(f) / iters;
-            if (t[k] <= 0.0 || v < t[k]) t[k] = v;
-            if (best < 0 || v < best_t) best = k, best_t = v, best_rows = 1 << lg;
+        const double v = ens_time_launch(e, k, o, c, n, e0, e1);
+        if (v < 0.0) ok = false;
+        return v;
+    };
+    auto note = [&](int k, int o, int c, int l, double v) {
+        if (v <= 0.0) return;
+        if (best_k[k] <= 0.0 || v < best_k[k]) best_k[k] = v;
+        trials.push_back(Trial{k, o, c, l, v});
+    };
+    // Stage 1: every configuration in linear order without a residency cap,
+    // in every layout; keep the layout of the fastest launch.
+    double t1[kMaxRowsLog2 + 1][kNumShapes];
+    int bl = -1, first = -1;
+    for (int l = 0; l <= kMaxRowsLog2 && ok; ++l)
+        for (int k = 0; k < kNumShapes && ok; ++k) {
+            t1[l][k] = ens_launch_ok(e, k, 0) ? time_in(l, k, int(kOrderLinear), 0, iters) : -1.0;
+            note(k, int(kOrderLinear), 0, l, t1[l][k]);
+            if (t1[l][k] > 0.0 && (bl < 0 || t1[l][k] < t1[bl][first])) bl = l, first = k;
+        }
+    if (bl < 0) ok = false;
+    // Stage 2: in that layout, its two fastest configurations with every block
+    // order and cap.
+    Trial best{first, int(kOrderLinear), 0, bl, ok ? t1[bl][first] : 0.0};
+    if (ok) {
+        int second = -1;
+        for (int k = 0; k < kNumShapes; ++k)
+            if (k != first && t1[bl][k] > 0.0 && (second < 0 || t1[bl][k] < t1[bl][second])) second = k;
+        for (int k : {first, second}) {
+            if (k < 0) continue;
+            for (int o = 0; o < int(kNumOrders) && ok; ++o)
+                for (int c = 0; c < kNumCaps && ok; ++c) {
+                    if ((o == int(kOrderLinear) && c == 0) || !ens_launch_ok(e, k, c)) continue;
+                    const double v = time_in(bl, k, o, c, iters);
+                    note(k, o, c, bl, v);
+                    if (v > 0.0 && v < best.t) best = Trial{k, o, c, bl, v};
+                }
         }
     }
-    if (err == hipSuccess && ens_set_layout(e, best_rows) != LBM_OK) err = hipErrorUnknown;
-    if (err == hipSuccess)
+    // Stage 3: that launch in every other layout (a cap or order can change
+    // which layout streams best).
+    if (ok && (best.o != int(kOrderLinear) || best.c != 0)) {
+        const Trial b0 = best;
+        for (int l = 0; l <= kMaxRowsLog2 && ok; ++l)
+            if (l != b0.l) note(b0.k, b0.o, b0.c, l, time_in(l, b0.k, b0.o, b0.c, iters));
+    }
+    // Stage 4: the three fastest launches timed again, in turn, twice each
+    // with twice the iterations; the lowest total wins.
+    if (ok) {
+        std::sort(trials.begin(), trials.end(), [](const Trial &x, const Trial &y) { return x.t < y.t; });
+        const int m = int(std::min<size_t>(3, trials.size()));
+        double total[3] = {0.0, 0.0, 0.0};
+        for (int round = 0; round < 2 && ok; ++round)
+            for (int j = 0; j < m && ok; ++j) {
+                const double v = time_in(trials[j].l, trials[j].k, trials[j].o, trials[j].c, 2 * iters);
+                total[j] += v > 0.0 ? v : 1e30;
+            }
+        int jb = 0;
+        for (int j = 1; j < m; ++j)
+            if (total[j] < total[jb]) jb = j;
+        if (m > 0) best = trials[jb];
+    }
+    if (ok && ens_set_layout(e, 1 << best.l) != LBM_OK) ok = false;
+    if (ok) {
         err = hipMemcpyAsync(e->clock, &saved, sizeof(saved), hipMemcpyHostToDevice, e->stream);
-    if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
+        if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
+        ok = err == hipSuccess;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (err != hipSuccess || best < 0) return LBM_E_DEVICE;
-    if (best != e->shape) ens_drop_graph(e);
-    e->shape = best;
-    int lg = 0;
-    while ((1 << lg) < best_rows) ++lg;
-    tune_store(ens_tune_key(e), best + kNumShapes * lg);
+    if (!ok) return LBM_E_DEVICE;
+    if (best.k != e->shape || best.o != e->order || best.c != e->cap) ens_drop_graph(e);
+    e->shape = best.k;
+    e->order = best.o;
+    e->cap = best.c;
+    tune_store(ens_tune_key(e), tune_code(best.k, best.o, best.c, best.l));
     if (ms)
-        for (int k = 0; k < kNumShapes; ++k) ms[k] = t[k];
-    if (chosen) *chosen = best;
+        for (int k = 0; k < kNumShapes; ++k) ms[k] = best_k[k];
+    if (chosen) *chosen = best.k;
+    return LBM_OK;
+}
+
+lbm_status lbm_ens_set_sweep_launch(lbm_ens *e, int32_t order, int32_t waves_per_simd) {
+    if (!e || order < 0 || order >= int32_t(kNumOrders)) return LBM_E_INVAL;
+    int cap = -1;
+    for (int j = 0; j < kNumCaps; ++j)
+        if (kResidencyCaps[j] == waves_per_simd) cap = j;
+    if (cap < 0 || ens_sweep_lds(e, cap, config_block(e->shape)) < 0) return LBM_E_INVAL;
+    if (order != e->order || cap != e->cap) ens_drop_graph(e);
+    e->order = order;
+    e->cap = cap;
+    return LBM_OK;
+}
+
+lbm_status lbm_ens_get_sweep_launch(const lbm_ens *e, int32_t *order, int32_t *waves_per_simd) {
+    if (!e || !order || !waves_per_simd) return LBM_E_INVAL;
+    *order = e->order;
+    *waves_per_simd = kResidencyCaps[e->cap];
     return LBM_OK;
 }
 
@@ -2374,6 +2498,15 @@ lbm_status lbm_ens_get_populations(lbm_ens *e, int32_t replica, double *f) {
 #undef LBM_ENS_POPS
     }
     return launch_status();
+}
+
+lbm_status lbm_ens_set_shape(lbm_ens *e, int32_t k) {
+    if (!e || !ens_launch_ok(e, k, 0)) return LBM_E_INVAL;
+    const int cap = ens_sweep_lds(e, e->cap, config_block(k)) < 0 ? 0 : e->cap;  // cap not possible here
+    if (k != e->shape || cap != e->cap) ens_drop_graph(e);
+    e->shape = k;
+    e->cap = cap;
+    return LBM_OK;
 }
 
 lbm_status lbm_ens_get_shape(const lbm_ens *e, int32_t *k) {

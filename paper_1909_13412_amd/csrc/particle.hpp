@@ -171,6 +171,16 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
     const Grid &g = site.g;
     const ForceField &cur = site.cur;
     const ForceField &old = site.old;
+    // Release this lane's node from the field used one step ago (that step's
+    // stream-collide has consumed it).  Issued first, so that its stores are
+    // in flight together with the gather below.
+    const uint32_t pc = valid ? pa.prev_cell[8 * i + p] : kNoNode;
+    if (pc != kNoNode) {
+        old.f[3 * uint64_t(pc) + 0] = 0;
+        old.f[3 * uint64_t(pc) + 1] = 0;
+        old.f[3 * uint64_t(pc) + 2] = 0;
+        atomicAnd(&old.mask[pc >> 5], ~(1u << (pc & 31)));
+    }
     const uint32_t Ln[3] = {g.nx, g.ny, g.nz};
     const int b[3] = {p & 1, (p >> 1) & 1, (p >> 2) & 1};
     double d[3];
@@ -217,9 +227,7 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
         });
     }
 
-    // Loads whose results are needed only at the end: this lane's node of one
-    // step ago, and the given and pair forces.
-    const uint32_t pc = valid ? pa.prev_cell[8 * i + p] : kNoNode;
+    // Loads whose results are needed only at the end: the given and pair forces.
     double fc[3] = {0.0, 0.0, 0.0};
     if (valid && p == 0) {
 #pragma unroll
@@ -303,14 +311,6 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
     friction_lanes(pa.friction, pa.gamma, site.R, W, u, V, dfit, FH, tr);
     if (!valid) return;
 
-    // Release this lane's node from the field used one step ago (it was
-    // consumed by that step's stream-collide).
-    if (pc != kNoNode) {
-        old.f[3 * uint64_t(pc) + 0] = 0;
-        old.f[3 * uint64_t(pc) + 1] = 0;
-        old.f[3 * uint64_t(pc) + 2] = 0;
-        atomicAnd(&old.mask[pc >> 5], ~(1u << (pc & 31)));
-    }
     // First Eq. s2-force: the node receives -F_H W_p (unit cell volume).
     uint32_t my_cell = kNoNode;
     if (coupled) {

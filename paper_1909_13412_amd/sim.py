@@ -530,6 +530,25 @@ class Ensemble(_StreamOrder):
         _abi.check("lbm_ens_get_shape", self.lib.lbm_ens_get_shape(self.ctx, ctypes.byref(k)))
         return k.value
 
+    def set_launch_config(self, k: int):
+        """Stream-collide launch configuration k (0..7) of later steps; same
+        results, drops the captured graph."""
+        _abi.check("lbm_ens_set_shape", self.lib.lbm_ens_set_shape(self.ctx, int(k)))
+
+    def set_sweep_launch(self, order: int = 0, waves_per_simd: int = 0):
+        """Block order and residency cap of the ensemble stream-collide (see
+        Lattice.set_sweep_launch); same results, drops the captured graph."""
+        _abi.check("lbm_ens_set_sweep_launch",
+                   self.lib.lbm_ens_set_sweep_launch(self.ctx, int(order), int(waves_per_simd)))
+
+    @property
+    def sweep_launch(self):
+        """(block order, residency cap in waves per SIMD) of later steps."""
+        o, w = ctypes.c_int32(), ctypes.c_int32()
+        _abi.check("lbm_ens_get_sweep_launch",
+                   self.lib.lbm_ens_get_sweep_launch(self.ctx, ctypes.byref(o), ctypes.byref(w)))
+        return o.value, w.value
+
     def vacf_config(self, max_lag: int, stride: int):
         sz = ctypes.c_size_t()
         _abi.check("lbm_vacf_origin_bytes",

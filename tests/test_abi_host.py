@@ -127,6 +127,8 @@ def test_null_context_rejected(lib):
     assert lib.lbm_get_layout(None, ctypes.byref(k)) == 1
     assert lib.lbm_ens_set_layout(None, 1) == 1
     assert lib.lbm_ens_get_layout(None, 0, ctypes.byref(k)) == 1
+    assert lib.lbm_ens_set_sweep_launch(None, 0, 0) == 1
+    assert lib.lbm_ens_get_sweep_launch(None, ctypes.byref(o), ctypes.byref(k)) == 1
     assert lib.lbm_observables_noalloc(None, out) == 1
     assert lib.lbm_set_pair_force(None, ctypes.c_double(0.1), ctypes.c_double(1.0)) == 1
     assert lib.lbm_pair_forces(None, None) == 1

@@ -187,6 +187,57 @@ def test_ensemble_layouts_are_bit_identical():
         assert np.array_equal(out[0][1], o[1]) and np.array_equal(out[0][2], o[2])
 
 
+def test_ensemble_launch_options_are_bit_identical():
+    # Launch configuration, block order and residency cap change only which
+    # lanes and blocks update which nodes, and when: the same run with each
+    # choice, also switched between graph-replayed steps (the graph is
+    # captured again after a change), gives the same populations, particles
+    # and VACF.
+    import torch
+
+    from paper_1909_13412_amd import Ensemble, _abi
+
+    G = _abi.LBM_ENS_GRAPH_STEPS
+    reps = _small_replicas()  # odd ny in two boxes: one node per lane only
+    runs = [((k, 0, 0), (k, 0, 0)) for k in (0, 1, 4, 5)]
+    # caps that 160 KiB of LDS per compute unit can impose even with only
+    # 64 KiB per block: 6 waves per SIMD for 512-lane blocks, 6 and 4 for
+    # 256-lane ones
+    runs += [((k, o, w), (k, o, w)) for k, ws in ((0, (0, 6)), (5, (0, 6, 4))) for o in (0, 1)
+             for w in ws if (o, w) != (0, 0)]
+    runs += [((1, 1, 4), (4, 0, 0)), ((4, 1, 6), (1, 0, 4)), ((5, 0, 6), (0, 1, 0))]
+    out = []
+    for (k0, o0, w0), (k1, o1, w1) in runs:
+        e = Ensemble(reps, storage="f32", kT=1e-4)
+        e.set_launch_config(k0)
+        e.set_sweep_launch(o0, w0)
+        assert (e.launch_config, e.sweep_launch) == (k0, (o0, w0))
+        e.vacf_config(6, 3)
+        e.step(G + 3)
+        e.set_launch_config(k1)
+        e.set_sweep_launch(o1, w1)
+        assert (e.launch_config, e.sweep_launch) == (k1, (o1, w1))
+        e.step(G + 1)
+        torch.cuda.synchronize()
+        assert e.graph_replays == 2
+        out.append(([e.populations(k).cpu().numpy() for k in range(len(reps))],
+                    e.v.cpu().numpy(), e.vacf()[0].cpu().numpy()))
+        e.close()
+    for (a0, a1), o in zip(runs[1:], out[1:]):
+        for a, b in zip(out[0][0], o[0]):
+            assert np.array_equal(a, b), (a0, a1)
+        assert np.array_equal(out[0][1], o[1]) and np.array_equal(out[0][2], o[2]), (a0, a1)
+    e = Ensemble(reps, storage="f32", kT=1e-4)
+    for k in (2, 3, 6, 7, 8, 9):  # two nodes per lane (odd ny), row-aligned (single boxes)
+        with pytest.raises(_abi.LbmError):
+            e.set_launch_config(k)
+    with pytest.raises(_abi.LbmError):
+        e.set_sweep_launch(2, 0)
+    with pytest.raises(_abi.LbmError):
+        e.set_sweep_launch(0, 7)
+    e.close()
+
+
 def test_graph_replays_match_plain_launches():
     # Replays of the captured graph, with eager work and synchronisation
     # between them, against the same ensemble stepped with plain launches:
