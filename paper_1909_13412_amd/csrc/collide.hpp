@@ -66,9 +66,92 @@ __device__ inline I pop_index(const Grid &g, uint32_t x, uint32_t y, uint32_t z,
     return row_index<V, I>(g, y, z) + I(a) * g.pstride + x;
 }
 
-// Index type of the sweep: 32-bit unless the lattice has 2^32 or more elements.
-template <bool IDX64>
-using SweepIndex = typename std::conditional<IDX64, uint64_t, uint32_t>::type;
+// Addressing of the sweep's loads and stores.
+//   kAddrLane32, kAddrLane64: every lane decodes its own node and computes each
+//     element index itself, in 32 bits (lattices below 2^32 elements) or 64.
+//   kAddrRow: every wavefront lies in one lattice row (nx a multiple of 64, or
+//     the row-aligned mapping), so y and z are the same in all its lanes: the
+//     base addresses of the nine source rows and of the node's own row are
+//     computed once per wavefront in scalar registers, and an access adds only
+//     the lane's 32-bit byte offset (x, x + 1 or x - 1, plus the population's
+//     offset).  Any lattice size.
+constexpr int kAddrLane32 = 0;
+constexpr int kAddrLane64 = 1;
+constexpr int kAddrRow = 2;
+
+// Index type of the per-lane modes.
+template <int ADDR>
+using SweepIndex = typename std::conditional<ADDR == kAddrLane64, uint64_t, uint32_t>::type;
+
+// Lane byte offset plus a population's offset, added in the vector unit: left
+// to itself the compiler folds the (wavefront-uniform) population offset into
+// a 64-bit scalar address per access, two scalar instructions each.
+__device__ inline uint32_t lane_offset(uint32_t xo, uint32_t pop_bytes) {
+    uint32_t r;
+    asm("v_add_u32 %0, %1, %2" : "=v"(r) : "s"(pop_bytes), "v"(xo));
+    return r;
+}
+
+// Rows of one wavefront in the kAddrRow mode: the byte offsets of row y and of
+// its neighbours y -/+ 1 (periodic) within a z-plane, of plane z and its
+// neighbours, and the lane's byte offsets of x - e_x.  Every member but xo is
+// the same in all lanes of the wavefront.
+struct RowOffsets {
+    uint64_t yb[3], zb[3];  // index e + 1: coordinate - e
+    uint32_t xo[3];
+    __device__ inline RowOffsets(uint32_t x, uint32_t y, uint32_t z, const Grid &g, uint32_t q,
+                                 uint32_t elem) {
+        const uint32_t ys[3] = {y + 1 == g.ny ? 0 : y + 1, y, y == 0 ? g.ny - 1 : y - 1};
+        const uint32_t zs[3] = {z + 1 == g.nz ? 0 : z + 1, z, z == 0 ? g.nz - 1 : z - 1};
+        const uint64_t row_bytes = uint64_t(g.chunk) * elem;
+        const uint64_t plane_bytes = uint64_t(g.ny) * q * row_bytes;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            // row_index(y, z) = z ny Q chunk + ((y & ~ymask) Q + (y & ymask)) chunk
+            yb[k] = uint64_t((ys[k] & ~g.ymask) * q + (ys[k] & g.ymask)) * row_bytes;
+            zb[k] = uint64_t(zs[k]) * plane_bytes;
+        }
+        xo[0] = (x + 1 == g.nx ? 0u : x + 1) * elem;
+        xo[1] = x * elem;
+        xo[2] = (x == 0 ? g.nx - 1 : x - 1) * elem;
+    }
+    // population a of the node (x, y, z) - e_a, pulled
+    template <class V, int a, class T>
+    __device__ inline const T *pull(const T *A, uint32_t pop_bytes) const {
+        const char *row = reinterpret_cast<const char *>(A) + (zb[V::ez[a] + 1] + yb[V::ey[a] + 1]);
+        const uint32_t off = a == 0 ? xo[V::ex[a] + 1] : lane_offset(xo[V::ex[a] + 1], uint32_t(a) * pop_bytes);
+        return reinterpret_cast<const T *>(row + off);
+    }
+    // population a of the node (x, y, z) itself
+    template <class T>
+    __device__ inline T *own(T *B, int a, uint32_t pop_bytes) const {
+        char *row = reinterpret_cast<char *>(B) + (zb[1] + yb[1]);
+        const uint32_t off = a == 0 ? xo[1] : lane_offset(xo[1], uint32_t(a) * pop_bytes);
+        return reinterpret_cast<T *>(row + off);
+    }
+};
+
+// The node coordinates of a lane: x, the first band's row y0 and the plane z
+// of lane_cell (< ncell / CPT; rows = ny / CPT rows per band).  In the kAddrRow
+// mode the row is decoded from the wavefront's first node (lane_cell minus the
+// lane index is the same in every lane: blocks and rows start at whole
+// wavefronts), so y0 and z are wavefront-uniform.
+template <int ADDR>
+__device__ inline void lane_coords(const Grid &g, uint32_t lane_cell, uint32_t rows, uint32_t &x,
+                                   uint32_t &y0, uint32_t &z) {
+    if constexpr (ADDR == kAddrRow) {
+        const uint32_t first = __builtin_amdgcn_readfirstlane(lane_cell - (threadIdx.x & 63u));
+        const uint32_t t = first / g.nx;
+        x = lane_cell - t * g.nx;
+        y0 = t % rows;
+        z = t / rows;
+    } else {
+        x = lane_cell % g.nx;
+        const uint32_t t = lane_cell / g.nx;
+        y0 = t % rows;
+        z = t / rows;
+    }
+}
 
 // Node forces of one step: a dense fixed-point field, written only at the
 // (at most 8 per particle) nodes that receive a reaction force and read only
@@ -163,7 +246,7 @@ __device__ inline void block_sum(double (&v)[N], double *__restrict__ out) {
 // flagged (FORCED), the particles' reaction force.
 // NTS: write the populations with non-temporal stores (streamed past the
 // caches); pays off once the lattice no longer fits in the last-level cache.
-template <class C, bool FORCED, bool MOMENTS, int CPT, bool NTS, bool IDX64 = false>
+template <class C, bool FORCED, bool MOMENTS, int CPT, bool NTS, int ADDR = kAddrLane32>
 __device__ inline void collide_lane(const typename C::T *__restrict__ A,
                                     typename C::T *__restrict__ B, const Grid &g,
                                     typename C::R omega, typename C::R enc_s, typename C::R dec_s,
@@ -177,23 +260,30 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
     using T = typename C::T;
     using R = typename C::R;
     using V = typename C::V;
-    using I = SweepIndex<IDX64>;
-    const uint32_t x = lane_cell % g.nx;
-    const uint32_t t = lane_cell / g.nx;
+    using I = SweepIndex<ADDR>;
     const uint32_t rows = g.ny / CPT;
-    const uint32_t y0 = t % rows;
-    const uint32_t z = t / rows;
+    uint32_t x, y0, z;
+    lane_coords<ADDR>(g, lane_cell, rows, x, y0, z);
+    const uint32_t pop_bytes = g.pstride * uint32_t(sizeof(T));
 
     T raw[CPT][V::Q];
     uint32_t flags[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const uint32_t y = y0 + uint32_t(c) * rows;
-        const Neighbours nb(x, y, z, g);
-        static_for<0, V::Q>([&](auto ac) {
-            constexpr int a = decltype(ac)::value;
-            raw[c][a] = A[nb.template pop<V, a, I>(g)];
-        });
+        if constexpr (ADDR == kAddrRow) {
+            const RowOffsets ro(x, y, z, g, V::Q, sizeof(T));
+            static_for<0, V::Q>([&](auto ac) {
+                constexpr int a = decltype(ac)::value;
+                raw[c][a] = *ro.template pull<V, a>(A, pop_bytes);
+            });
+        } else {
+            const Neighbours nb(x, y, z, g);
+            static_for<0, V::Q>([&](auto ac) {
+                constexpr int a = decltype(ac)::value;
+                raw[c][a] = A[nb.template pop<V, a, I>(g)];
+            });
+        }
         if constexpr (FORCED) {
             const uint32_t cell = (z * g.ny + y) * g.nx + x;
             flags[c] = (ff.mask[cell >> 5] >> (cell & 31)) & 1u;
@@ -231,13 +321,18 @@ __device__ inline void collide_lane(const typename C::T *__restrict__ A,
                 Fz += R(double(ff.f[3 * cell + 2]) * kFixInv);
             }
         }
-        const I row_base = row_index<V, I>(g, y, z) + x;
         // written once and read only by the next step
+        [[maybe_unused]] const RowOffsets ro(x, y, z, g, V::Q, sizeof(T));  // kAddrRow only
         auto put = [&](int a, R gn) {
-            if constexpr (NTS)
-                __builtin_nontemporal_store(C::enc(gn, enc_s), &B[row_base + I(a) * g.pstride]);
+            T *p;
+            if constexpr (ADDR == kAddrRow)
+                p = ro.own(B, a, pop_bytes);
             else
-                B[row_base + I(a) * g.pstride] = C::enc(gn, enc_s);
+                p = &B[row_index<V, I>(g, y, z) + x + I(a) * g.pstride];
+            if constexpr (NTS)
+                __builtin_nontemporal_store(C::enc(gn, enc_s), p);
+            else
+                *p = C::enc(gn, enc_s);
         };
         // BGK relaxation to the equilibrium of Eq. s2-eq plus the forcing term
         // 3 w e.F, one opposite pair (a, a + 1) at a time: e_{a+1} = -e_a, so
@@ -321,7 +416,7 @@ __device__ inline bool lane_node(const Grid &g, uint32_t blk, uint32_t &lane_cel
     }
 }
 
-template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW, bool IDX64>
+template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW, int ADDR>
 __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__restrict__ A,
                                                        typename C::T *__restrict__ B, Grid g,
                                                        typename C::R omega, typename C::R enc_s,
@@ -337,8 +432,8 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
     }
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (active)
-        collide_lane<C, FORCED, MOMENTS, CPT, NTS, IDX64>(A, B, g, omega, enc_s, dec_s, ff, Gx, Gy,
-                                                          Gz, lane_cell, acc);
+        collide_lane<C, FORCED, MOMENTS, CPT, NTS, ADDR>(A, B, g, omega, enc_s, dec_s, ff, Gx, Gy,
+                                                         Gz, lane_cell, acc);
     // partials by wavefront of the node block (no barrier), so that every
     // block order gives the same sums
     if constexpr (MOMENTS)
@@ -350,49 +445,63 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
 // unchanged at x (no moments, collision or forcing), with the same layout and
 // store policy.  Its duration bounds what the stream-collide can reach with
 // this access pattern; B does not hold a lattice update.
-template <class C, int CPT, bool NTS, bool IDX64 = false>
+template <class C, int CPT, bool NTS, int ADDR = kAddrLane32>
 __device__ inline void stream_only_lane(const typename C::T *__restrict__ A,
                                         typename C::T *__restrict__ B, const Grid &g,
                                         uint32_t lane_cell) {
     using T = typename C::T;
     using V = typename C::V;
-    using I = SweepIndex<IDX64>;
-    const uint32_t x = lane_cell % g.nx;
-    const uint32_t t = lane_cell / g.nx;
+    using I = SweepIndex<ADDR>;
     const uint32_t rows = g.ny / CPT;
-    const uint32_t y0 = t % rows;
-    const uint32_t z = t / rows;
+    uint32_t x, y0, z;
+    lane_coords<ADDR>(g, lane_cell, rows, x, y0, z);
+    const uint32_t pop_bytes = g.pstride * uint32_t(sizeof(T));
     T raw[CPT][V::Q];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-        const Neighbours nb(x, y0 + uint32_t(c) * rows, z, g);
-        static_for<0, V::Q>([&](auto ac) {
-            constexpr int a = decltype(ac)::value;
-            raw[c][a] = A[nb.template pop<V, a, I>(g)];
-        });
+        const uint32_t y = y0 + uint32_t(c) * rows;
+        if constexpr (ADDR == kAddrRow) {
+            const RowOffsets ro(x, y, z, g, V::Q, sizeof(T));
+            static_for<0, V::Q>([&](auto ac) {
+                constexpr int a = decltype(ac)::value;
+                raw[c][a] = *ro.template pull<V, a>(A, pop_bytes);
+            });
+        } else {
+            const Neighbours nb(x, y, z, g);
+            static_for<0, V::Q>([&](auto ac) {
+                constexpr int a = decltype(ac)::value;
+                raw[c][a] = A[nb.template pop<V, a, I>(g)];
+            });
+        }
     }
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-        const I row_base = row_index<V, I>(g, y0 + uint32_t(c) * rows, z) + x;
+        const uint32_t y = y0 + uint32_t(c) * rows;
+        [[maybe_unused]] const RowOffsets ro(x, y, z, g, V::Q, sizeof(T));  // kAddrRow only
         static_for<0, V::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            if constexpr (NTS)
-                __builtin_nontemporal_store(raw[c][a], &B[row_base + I(a) * g.pstride]);
+            T *p;
+            if constexpr (ADDR == kAddrRow)
+                p = ro.own(B, a, pop_bytes);
             else
-                B[row_base + I(a) * g.pstride] = raw[c][a];
+                p = &B[row_index<V, I>(g, y, z) + x + I(a) * g.pstride];
+            if constexpr (NTS)
+                __builtin_nontemporal_store(raw[c][a], p);
+            else
+                *p = raw[c][a];
         });
     }
 }
 
 // Streaming-only counterpart of k_stream_collide in configuration <CPT, BS,
 // NTS, ROW> (same lanes).
-template <class C, int CPT, int BS, bool NTS, bool ROW, bool IDX64>
+template <class C, int CPT, int BS, bool NTS, bool ROW, int ADDR>
 __global__ __launch_bounds__(BS) void k_stream_only(const typename C::T *__restrict__ A,
                                                     typename C::T *__restrict__ B, Grid g,
                                                     uint32_t order) {
     uint32_t lane_cell;
     if (!lane_node<CPT, BS, ROW>(g, sweep_block(order), lane_cell)) return;
-    stream_only_lane<C, CPT, NTS, IDX64>(A, B, g, lane_cell);
+    stream_only_lane<C, CPT, NTS, ADDR>(A, B, g, lane_cell);
 }
 
 // Launch configurations of the stream-collide, chosen per context

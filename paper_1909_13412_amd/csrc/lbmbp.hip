@@ -615,26 +615,40 @@ long residency_lds(int lds_cu, int lds_block, int cap, int bs) {
 
 long sweep_lds(const lbm_ctx *c, int cap, int bs) { return residency_lds(c->lds_cu, c->lds_block, cap, bs); }
 
-// The sweep computes its indices in 32 bits unless the lattice holds 2^32 or
-// more elements (Q nx ny nz; boxes beyond about 226M nodes).
-bool sweep_idx64(const lbm_ctx *c) { return uint64_t(c->q) * c->g.ncell >= (uint64_t(1) << 32); }
+// Addressing of the sweep (kAddr* in collide.hpp): wavefront-uniform rows
+// whenever every wavefront lies in one row (the row-aligned mapping, or rows of
+// whole wavefronts), else per-lane indices in 32 bits unless the lattice holds
+// 2^32 or more elements (Q nx ny nz; boxes beyond about 226M nodes).
+int sweep_addr(const lbm_ctx *c, bool row_mapping) {
+    if (row_mapping || c->g.nx % 64 == 0) return kAddrRow;
+    return uint64_t(c->q) * c->g.ncell >= (uint64_t(1) << 32) ? kAddrLane64 : kAddrLane32;
+}
+
+template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW, int ADDR>
+void launch_collide_addr(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff,
+                         double *mom, unsigned grid, int order, size_t dyn) {
+    using R = typename C::R;
+    hipLaunchKernelGGL((k_stream_collide<C, FORCED, MOMENTS, CPT, BS, NTS, ROW, ADDR>), dim3(grid),
+                       dim3(BS), dyn, c->stream, A, B, c->g, R(c->omega), R(c->enc_s), R(c->dec_s),
+                       ff, R(c->body[0]), R(c->body[1]), R(c->body[2]), mom, uint32_t(order));
+}
 
 template <class C, bool FORCED, bool MOMENTS, int CPT, int BS, bool NTS, bool ROW>
 void launch_collide_shape(lbm_ctx *c, const typename C::T *A, typename C::T *B, ForceField ff,
                           double *mom, unsigned grid, int order, int cap) {
-    using R = typename C::R;
     const long lds = sweep_lds(c, cap, BS);
     const size_t dyn = lds > 0 ? size_t(lds) : 0;
-    if (sweep_idx64(c))
-        hipLaunchKernelGGL((k_stream_collide<C, FORCED, MOMENTS, CPT, BS, NTS, ROW, true>), dim3(grid),
-                           dim3(BS), dyn, c->stream, A, B, c->g, R(c->omega), R(c->enc_s),
-                           R(c->dec_s), ff, R(c->body[0]), R(c->body[1]), R(c->body[2]), mom,
-                           uint32_t(order));
-    else
-        hipLaunchKernelGGL((k_stream_collide<C, FORCED, MOMENTS, CPT, BS, NTS, ROW, false>), dim3(grid),
-                           dim3(BS), dyn, c->stream, A, B, c->g, R(c->omega), R(c->enc_s),
-                           R(c->dec_s), ff, R(c->body[0]), R(c->body[1]), R(c->body[2]), mom,
-                           uint32_t(order));
+    const int addr = sweep_addr(c, ROW);
+    if constexpr (ROW) {
+        launch_collide_addr<C, FORCED, MOMENTS, CPT, BS, NTS, ROW, kAddrRow>(c, A, B, ff, mom, grid, order, dyn);
+    } else {
+        if (addr == kAddrRow)
+            launch_collide_addr<C, FORCED, MOMENTS, CPT, BS, NTS, ROW, kAddrRow>(c, A, B, ff, mom, grid, order, dyn);
+        else if (addr == kAddrLane64)
+            launch_collide_addr<C, FORCED, MOMENTS, CPT, BS, NTS, ROW, kAddrLane64>(c, A, B, ff, mom, grid, order, dyn);
+        else
+            launch_collide_addr<C, FORCED, MOMENTS, CPT, BS, NTS, ROW, kAddrLane32>(c, A, B, ff, mom, grid, order, dyn);
+    }
 }
 
 // mom != nullptr: also leave the per-wavefront FP64 moment sums there.  order,
@@ -833,6 +847,26 @@ void time_launches(lbm_ctx *c, int32_t iters, int n, const int *ks, const int *o
 // Mean time per launch of the streaming-only kernel in configuration k with
 // the context's block order and residency cap, over iters launches (A -> B,
 // as the autotuner's trial launches).
+template <class C, int CPT, int BS, bool NTS, bool ROW>
+void stream_only_shape(lbm_ctx *c, const typename C::T *A, typename C::T *B, unsigned grid,
+                       uint32_t order, size_t dyn) {
+    const int addr = sweep_addr(c, ROW);
+    if constexpr (ROW) {
+        hipLaunchKernelGGL((k_stream_only<C, CPT, BS, NTS, ROW, kAddrRow>), dim3(grid), dim3(BS), dyn,
+                           c->stream, A, B, c->g, order);
+    } else {
+        if (addr == kAddrRow)
+            hipLaunchKernelGGL((k_stream_only<C, CPT, BS, NTS, ROW, kAddrRow>), dim3(grid), dim3(BS), dyn,
+                               c->stream, A, B, c->g, order);
+        else if (addr == kAddrLane64)
+            hipLaunchKernelGGL((k_stream_only<C, CPT, BS, NTS, ROW, kAddrLane64>), dim3(grid), dim3(BS),
+                               dyn, c->stream, A, B, c->g, order);
+        else
+            hipLaunchKernelGGL((k_stream_only<C, CPT, BS, NTS, ROW, kAddrLane32>), dim3(grid), dim3(BS),
+                               dyn, c->stream, A, B, c->g, order);
+    }
+}
+
 template <class C>
 void time_stream_only(lbm_ctx *c, int k, int32_t iters, double *ms, hipError_t *err) {
     using T = typename C::T;
@@ -843,15 +877,7 @@ void time_stream_only(lbm_ctx *c, int k, int32_t iters, double *ms, hipError_t *
     const size_t dyn = lds > 0 ? size_t(lds) : 0;
     const uint32_t order = uint32_t(c->order);
     auto launch = [&]() {
-#define LBM_STREAM_ONLY(CPT, BS, NTS, ROW)                                                           \
-    do {                                                                                             \
-        if (sweep_idx64(c))                                                                          \
-            hipLaunchKernelGGL((k_stream_only<C, CPT, BS, NTS, ROW, true>), dim3(grid), dim3(BS), dyn, \
-                               c->stream, A, B, c->g, order);                                        \
-        else                                                                                         \
-            hipLaunchKernelGGL((k_stream_only<C, CPT, BS, NTS, ROW, false>), dim3(grid), dim3(BS),    \
-                               dyn, c->stream, A, B, c->g, order);                                   \
-    } while (0)
+#define LBM_STREAM_ONLY(CPT, BS, NTS, ROW) stream_only_shape<C, CPT, BS, NTS, ROW>(c, A, B, grid, order, dyn)
         LBM_CONFIG_SWITCH(k, LBM_STREAM_ONLY)
 #undef LBM_STREAM_ONLY
     };

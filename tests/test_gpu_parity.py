@@ -380,20 +380,23 @@ def test_suspension512_tiled_against_oracle(oracle_mod):
     torch.cuda.empty_cache()
 
 
-def test_beyond_32bit_lattice_index_tiled_against_oracle(oracle_mod):
-    # A lattice of 19 x 1024 x 512 x 448 >= 2^32 population elements, which the
-    # sweep indexes with 64-bit arithmetic (smaller lattices use 32 bits): a
-    # 32^3 state (perturbed fields, one particle, kT = 0) tiled 32 x 16 x 14
-    # times, 7168 particles at the same place in every tile, 3 steps in FP32,
-    # with one and with 16 rows per group.  Every tile must hold the same
-    # moments and tile 0 must match the oracle's 32^3 run.
+@pytest.mark.parametrize("tiles_x", [32, 31])
+def test_beyond_32bit_lattice_index_tiled_against_oracle(oracle_mod, tiles_x):
+    # Lattices of 19 x nx x 512 x 448 >= 2^32 population elements: nx = 1024
+    # (rows of whole wavefronts: 64-bit row offsets per wavefront) and nx =
+    # 992 (per-lane 64-bit indices in the flat configurations; rows again in
+    # the row-aligned one).  A 32^3 state (perturbed fields, one particle,
+    # kT = 0) tiled tiles_x x 16 x 14 times, a particle at the same place in
+    # every tile, 3 steps in FP32, with one and with 16 rows per group.
+    # Every tile must hold the same moments and tile 0 must match the
+    # oracle's 32^3 run.
     import torch
 
     from paper_1909_13412_amd import Lattice
     from paper_1909_13412_amd.inputs import perturbed_fields
 
     T, steps = 32, 3
-    K = (32, 16, 14)  # tiles along x, y, z
+    K = (tiles_x, 16, 14)  # tiles along x, y, z
     dims = (T * K[0], T * K[1], T * K[2])
     assert 19 * dims[0] * dims[1] * dims[2] >= 2**32
     tau = 0.6
@@ -417,7 +420,8 @@ def test_beyond_32bit_lattice_index_tiled_against_oracle(oracle_mod):
     u_d = torch.from_numpy(u_t).to(dev).repeat(1, K[2], K[1], K[0])
     g = Lattice(*dims, tau, storage="f32")
     first = None
-    for shape, rows in ((5, 1), (4, 16)):
+    runs = ((5, 1), (4, 16)) if tiles_x % 2 == 0 else ((5, 1), (4, 16), (9, 1))
+    for shape, rows in runs:
         g.set_layout(rows)
         g.set_shape(shape)
         g.set_equilibrium(rho_d, u_d)
@@ -898,15 +902,18 @@ def test_every_launch_configuration_is_bit_identical():
     # mapping x plain / non-temporal, with either block order and residency
     # cap, in every storage layout (rows per group), also with the layout
     # switched between steps: the same step, the same bits, also with the
-    # FP64 sums fused in.  Boxes with 64 | nx (four rows per block), a row
-    # of three wavefronts with 62 idle lanes, rows longer than a block, and
-    # 64 short rows per plane (row groups up to 64 rows).
+    # FP64 sums fused in.  Boxes whose row-aligned mapping puts four rows in
+    # a block, a row of three wavefronts with 62 idle lanes, rows longer than
+    # a block, 64 short rows per plane (row groups up to 64 rows), and rows of
+    # two whole wavefronts (64 | nx: every configuration addresses by
+    # wavefront rows; per-lane indices otherwise, the row-aligned mapping
+    # always by rows).
     import torch
 
     from paper_1909_13412_amd import Lattice, _abi
     from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
 
-    for L in ((40, 24, 16), (130, 6, 8), (300, 6, 5), (24, 64, 5)):
+    for L in ((40, 24, 16), (130, 6, 8), (300, 6, 5), (24, 64, 5), (128, 10, 6)):
         r = particle_positions(9, L, seed=31)
         v = particle_velocities(9, 1e-5, seed=31)
         # every storage x velocity-set instance the library builds and the
