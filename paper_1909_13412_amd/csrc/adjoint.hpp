@@ -101,8 +101,7 @@ __global__ __launch_bounds__(kParticleBlock) void k_adj_particle(
         const double s = r[k] - L * floor(r[k] / L);
         const double c = floor(s);
         d[k] = (c + double(b[k])) - s;
-        int32_t ci = (int32_t(c) + b[k]) % int32_t(Ln[k]);
-        node[k] = uint32_t(ci < 0 ? ci + int32_t(Ln[k]) : ci);
+        node[k] = wrap_node(int32_t(c), -1, int32_t(Ln[k]), b[k], int32_t(Ln[k]));
         tf[k] = 1.0 - fabs(d[k]);
         W *= tf[k];
     }

@@ -130,6 +130,7 @@ __global__ __launch_bounds__(kParticleBlock) void k_ens_particle(
         pa.t = t;
         pa.k_hi = t / pa.stride;
         pa.k_lo = t > pa.max_lag ? (t - pa.max_lag + pa.stride - 1) / pa.stride : 0;
+        pa.slot_lo = int32_t(pa.k_lo % pa.nslot);
     }
     double r[3], V[3];
 #pragma unroll
@@ -743,6 +744,7 @@ void launch_step(lbm_ctx *c) {
         pa.k_hi = -1;
         pa.nslot = pa.stride = 1;
         pa.max_lag = 0;
+        pa.slot_lo = 0;
         if (c->vacf_on) {
             // active origins k*stride with t - max_lag <= k*stride <= t
             const int64_t t = c->vacf_t;
@@ -752,6 +754,7 @@ void launch_step(lbm_ctx *c) {
             pa.k_hi = t / c->stride;
             pa.k_lo = t > c->max_lag ? (t - c->max_lag + c->stride - 1) / c->stride : 0;
             pa.nslot = c->nslot;
+            pa.slot_lo = int32_t(pa.k_lo % c->nslot);
             pa.stride = c->stride;
             pa.max_lag = c->max_lag;
             c->vacf_t += 1;
@@ -2734,6 +2737,7 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
     pa.fext = c->rec_fext;
     pa.k_hi = -1;
     pa.nslot = pa.stride = 1;
+    pa.slot_lo = 0;
 
     AdjParticleArgs ap{};
     ap.rbar = adj_r;

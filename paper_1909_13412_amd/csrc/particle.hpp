@@ -43,6 +43,7 @@ struct ParticleArgs {
     double *origins;  // [nslot][n][3]
     int64_t t, k_lo, k_hi;
     int32_t nslot, stride, max_lag;
+    int32_t slot_lo;  // slot of origin k_lo (k_lo % nslot)
     // per-block FP64 sums of M V^n (nullptr: off), [blocks][3]
     double *pmom;
     // given force on each particle, [n][3] (nullptr: none)
@@ -129,6 +130,18 @@ __device__ inline void friction_lanes(int32_t mode, double gamma, double R, doub
     }
 }
 
+// Periodic node coordinate c + off for a corner offset off in [0, 2] and c
+// in [lo, hi] (lo >= -1, hi + 2 <= L + 1), as the floor of a wrapped finite
+// position gives it; the clamp keeps a non-finite position (converted to an
+// arbitrary integer) in the box.  One conditional add or subtract of L in
+// place of an integer division (L >= 2).
+__device__ inline uint32_t wrap_node(int32_t c, int32_t lo, int32_t hi, int32_t off, int32_t L) {
+    int32_t ci = min(max(c, lo), hi) + off;
+    ci = ci < 0 ? ci + L : ci;
+    ci = ci >= L ? ci - L : ci;
+    return uint32_t(ci);
+}
+
 // Node p of the (2 dx)^3 fitting cube of the wide Stokeslet fit: per axis the
 // corners c0 and c0 + 2 with c0 = floor(s + 1/2) - 1, s the wrapped position,
 // so that the particle sits in the middle half of the cube.  q: the node
@@ -141,8 +154,8 @@ __device__ inline void wide_corner(const double (&r)[3], const uint32_t (&Ln)[3]
         const double s = r[k] - L * floor(r[k] / L);
         const double c0 = floor(s + 0.5) - 1.0;
         dq[k] = (c0 + 2.0 * double(b[k])) - s;
-        int32_t ci = (int32_t(c0) + 2 * b[k]) % int32_t(Ln[k]);
-        q[k] = uint32_t(ci < 0 ? ci + int32_t(Ln[k]) : ci);
+        // c0 in [-1, L - 1] for s in [-eps, L]
+        q[k] = wrap_node(int32_t(c0), -1, int32_t(Ln[k]) - 1, 2 * b[k], int32_t(Ln[k]));
     }
 }
 
@@ -192,10 +205,8 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
         const double s = r[k] - L * floor(r[k] / L);  // wrapped position, in [-eps, L]
         const double c = floor(s);
         d[k] = (c + double(b[k])) - s;                // node minus particle, unwrapped
-        // Rounding can leave c at -1 or L; the periodic wrap handles both (a
-        // non-finite position converts with saturation and stays in the box).
-        int32_t ci = (int32_t(c) + b[k]) % int32_t(Ln[k]);
-        node[k] = uint32_t(ci < 0 ? ci + int32_t(Ln[k]) : ci);
+        // Rounding can leave c at -1 or L; the periodic wrap handles both.
+        node[k] = wrap_node(int32_t(c), -1, int32_t(Ln[k]), b[k], int32_t(Ln[k]));
         W *= 1.0 - fabs(d[k]);
     }
     const uint32_t cell = (node[2] * g.ny + node[1]) * g.nx + node[0];
@@ -246,15 +257,28 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
         // particles of a wavefront updates eight consecutive doubles
         double *acc_i = pa.acc + i;
         const int64_t n = pa.n;
+        // origin k lives in slot k % nslot; this lane's origins k_lo + p,
+        // k_lo + p + 8, ... step through the slots by 8 (mod nslot)
+        const int32_t ns = pa.nslot;
+        const int32_t d8 = 8 % ns;
+        int32_t slot = pa.slot_lo + p % ns;
+        slot = slot >= ns ? slot - ns : slot;
         for (int64_t k0 = pa.k_lo + p; k0 <= pa.k_hi; k0 += 8 * kVacfBatch) {
             double ov[kVacfBatch][3], av[kVacfBatch];
+            int32_t sl[kVacfBatch];
+#pragma unroll
+            for (int c = 0; c < kVacfBatch; ++c) {
+                sl[c] = slot;
+                slot += d8;
+                slot = slot >= ns ? slot - ns : slot;
+            }
 #pragma unroll
             for (int c = 0; c < kVacfBatch; ++c) {
                 const int64_t k = k0 + 8 * c;
                 const int64_t lag = pa.t - k * pa.stride;
                 ov[c][0] = ov[c][1] = ov[c][2] = av[c] = 0.0;
                 if (k <= pa.k_hi && lag != 0) {
-                    const double *o = pa.origins + (int64_t(k % pa.nslot) * pa.n + i) * 3;
+                    const double *o = pa.origins + (int64_t(sl[c]) * pa.n + i) * 3;
                     ov[c][0] = o[0];
                     ov[c][1] = o[1];
                     ov[c][2] = o[2];
@@ -267,7 +291,7 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
                 if (k > pa.k_hi) break;
                 const int64_t lag = pa.t - k * pa.stride;
                 if (lag == 0) {
-                    double *o = pa.origins + (int64_t(k % pa.nslot) * pa.n + i) * 3;
+                    double *o = pa.origins + (int64_t(sl[c]) * pa.n + i) * 3;
                     o[0] = V[0];
                     o[1] = V[1];
                     o[2] = V[2];
