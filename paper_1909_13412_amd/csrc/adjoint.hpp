@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kParticleBlock) void k_adj_particle(
     }
 }
 
-template <class C, bool FORCED, bool NTS>
+template <class C, bool FORCED, bool NTS, bool ROWS>
 __global__ __launch_bounds__(kBlock) void k_adj_collide(const typename C::T *__restrict__ A, Grid g,
                                                         typename C::R dec_s,
                                                         const double *__restrict__ Abar,
@@ -305,19 +305,29 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(const typename C::T *__r
                                                         double omega, AdjField uf,
                                                         double *__restrict__ wacc) {
     using Vs = typename C::V;
+    using T = typename C::T;
     const uint32_t cell = blockIdx.x * kBlock + threadIdx.x;
     double wsum = 0.0;
     if (cell < g.ncell) {
-        const uint32_t x = cell % g.nx;
-        const uint32_t t = cell / g.nx;
-        const uint32_t y = t % g.ny;
-        const uint32_t z = t / g.ny;
+        // ROWS: every wavefront lies in one row (64 | nx), addresses from the
+        // wavefront's row offsets as in the forward sweep (kAddrRow)
+        uint32_t x, y, z;
+        lane_coords<ROWS ? kAddrRow : kAddrLane64>(g, cell, g.ny, x, y, z);
+        const uint32_t popA = g.pstride * uint32_t(sizeof(T));
+        const uint32_t popD = gd.pstride * uint32_t(sizeof(double));
+        [[maybe_unused]] const RowOffsets roA(x, y, z, g, Vs::Q, sizeof(T));
+        [[maybe_unused]] const RowOffsets roD(x, y, z, gd, Vs::Q, sizeof(double));
         const Neighbours nb(x, y, z, g);
         double gv[Vs::Q], fs[Vs::Q];
         static_for<0, Vs::Q>([&](auto ac) {
             constexpr int a = decltype(ac)::value;
-            gv[a] = double(C::dec(A[nb.template pop<Vs, a>(g)], dec_s));
-            fs[a] = Abar[push_index<Vs, a>(nb, gd)];
+            if constexpr (ROWS) {
+                gv[a] = double(C::dec(*roA.template pull<Vs, a>(A, popA), dec_s));
+                fs[a] = *roD.template push<Vs, a>(Abar, popD);
+            } else {
+                gv[a] = double(C::dec(A[nb.template pop<Vs, a>(g)], dec_s));
+                fs[a] = Abar[push_index<Vs, a>(nb, gd)];
+            }
         });
         bool flagged = false;
         if constexpr (FORCED) flagged = (uf.mask[cell >> 5] >> (cell & 31)) & 1u;
@@ -365,10 +375,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(const typename C::T *__r
             double out = (1.0 - omega) * fs[a] +
                          omega * (P + double(cx) * Gx + double(cy) * Gy + double(cz) * Gz);
             if constexpr (FORCED) out += double(cx) * Ux + double(cy) * Uy + double(cz) * Uz;
+            double *dst = ROWS ? roD.own(Bbar, a, popD) : &Bbar[row_base + uint64_t(a) * gd.pstride];
             if constexpr (NTS)
-                __builtin_nontemporal_store(out, &Bbar[row_base + uint64_t(a) * gd.pstride]);
+                __builtin_nontemporal_store(out, dst);
             else
-                Bbar[row_base + uint64_t(a) * gd.pstride] = out;
+                *dst = out;
         });
     }
     // dJ/domega of this block, added to its own running slot (fixed order).

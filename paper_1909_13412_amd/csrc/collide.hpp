@@ -122,6 +122,13 @@ struct RowOffsets {
         const uint32_t off = a == 0 ? xo[V::ex[a] + 1] : lane_offset(xo[V::ex[a] + 1], uint32_t(a) * pop_bytes);
         return reinterpret_cast<const T *>(row + off);
     }
+    // population a of the node (x, y, z) + e_a, the streaming target
+    template <class V, int a, class T>
+    __device__ inline const T *push(const T *A, uint32_t pop_bytes) const {
+        const char *row = reinterpret_cast<const char *>(A) + (zb[1 - V::ez[a]] + yb[1 - V::ey[a]]);
+        const uint32_t off = a == 0 ? xo[1 - V::ex[a]] : lane_offset(xo[1 - V::ex[a]], uint32_t(a) * pop_bytes);
+        return reinterpret_cast<const T *>(row + off);
+    }
     // population a of the node (x, y, z) itself
     template <class T>
     __device__ inline T *own(T *B, int a, uint32_t pop_bytes) const {

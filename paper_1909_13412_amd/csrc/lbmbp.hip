@@ -2663,6 +2663,21 @@ bool adjoint_storage(const lbm_ctx *c) {
     return c->desc.storage == LBM_STORE_F64 || c->desc.storage == LBM_STORE_F32;
 }
 
+// The adjoint stream-collide, addressing by wavefront rows where every
+// wavefront lies in one lattice row (64 | nx), by per-lane 64-bit indices
+// otherwise.
+template <class C, bool FORCED, bool NTS>
+void launch_adj_collide(hipStream_t st, unsigned cgrid, const typename C::T *A, const Grid &g,
+                        typename C::R dec_s, const double *Abar, double *Bbar, const Grid &gd,
+                        double omega, AdjField uf, double *wacc) {
+    if (g.nx % 64 == 0)
+        hipLaunchKernelGGL((k_adj_collide<C, FORCED, NTS, true>), dim3(cgrid), dim3(kBlock), 0, st, A, g,
+                           dec_s, Abar, Bbar, gd, omega, uf, wacc);
+    else
+        hipLaunchKernelGGL((k_adj_collide<C, FORCED, NTS, false>), dim3(cgrid), dim3(kBlock), 0, st, A, g,
+                           dec_s, Abar, Bbar, gd, omega, uf, wacc);
+}
+
 template <class C>
 hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, double *adj_r,
                        double *adj_v, double *adj_param) {
@@ -2820,19 +2835,17 @@ hipError_t adjoint_run(lbm_ctx *c, char *tape, char *work, double *adj_pop, doub
                     hipLaunchKernelGGL(k_adj_pair, pair_group_blocks(np), dim3(kPairBlock), 0, st,
                                        seg_r(k), np, c->rec_pg, plist, fcbar, adj_r);
                 if (stream_stores)
-                    hipLaunchKernelGGL((k_adj_collide<C, true, true>), dim3(cgrid), dim3(kBlock), 0,
-                                       st, seg(k), c->g, R(c->dec_s), abar[cur], abar[cur ^ 1], gd,
+                    launch_adj_collide<C, true, true>(st, cgrid, seg(k), c->g, R(c->dec_s), abar[cur], abar[cur ^ 1], gd,
                                        1.0 / c->desc.tau, uf[par], wacc);
                 else
-                    hipLaunchKernelGGL((k_adj_collide<C, true, false>), dim3(cgrid), dim3(kBlock), 0,
-                                       st, seg(k), c->g, R(c->dec_s), abar[cur], abar[cur ^ 1], gd,
+                    launch_adj_collide<C, true, false>(st, cgrid, seg(k), c->g, R(c->dec_s), abar[cur], abar[cur ^ 1], gd,
                                        1.0 / c->desc.tau, uf[par], wacc);
             } else if (stream_stores) {
-                hipLaunchKernelGGL((k_adj_collide<C, false, true>), dim3(cgrid), dim3(kBlock), 0, st,
+                launch_adj_collide<C, false, true>(st, cgrid,
                                    seg(k), c->g, R(c->dec_s), abar[cur], abar[cur ^ 1], gd,
                                    1.0 / c->desc.tau, ff_unused, wacc);
             } else {
-                hipLaunchKernelGGL((k_adj_collide<C, false, false>), dim3(cgrid), dim3(kBlock), 0, st,
+                launch_adj_collide<C, false, false>(st, cgrid,
                                    seg(k), c->g, R(c->dec_s), abar[cur], abar[cur ^ 1], gd,
                                    1.0 / c->desc.tau, ff_unused, wacc);
             }
