@@ -697,7 +697,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU path is not built "
+        print("bench.py: the library runs on one GPU; no multi-GPU path is implemented "
               "(see the sharding design).  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 

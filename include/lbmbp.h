@@ -60,7 +60,7 @@ typedef enum lbm_status {
     LBM_E_DEVICE = 2,      /* a HIP call or kernel launch failed */
     LBM_E_STATE = 3,       /* call not valid in the context's current state */
     LBM_E_NONFINITE = 4,   /* a reduction found NaN/Inf, or a node force overflowed */
-    LBM_E_UNSUPPORTED = 5  /* valid request this build does not implement */
+    LBM_E_UNSUPPORTED = 5  /* valid request the library does not implement */
 } lbm_status;
 
 /* Population storage.  Every storage holds the shifted value g = f - w_a rho0
