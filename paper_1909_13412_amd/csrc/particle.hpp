@@ -228,7 +228,9 @@ __device__ inline void particle_lane(const ParticleSite<C> &site, typename C::R 
 
     // Issue the gather of f^n at this lane's fitting node (pull from node -
     // e_a); the values are consumed only after the VACF sample and the
-    // Brownian force, which overlap the load latency.
+    // Brownian force, which overlap the load latency.  Plain loads: the
+    // following sweep reads these lines again, and non-temporal ones, though
+    // 1.2 us faster here, cost the sweep as much or more.
     typename C::T raw[Vs::Q];
     if (coupled) {
         const Neighbours nb(fnode[0], fnode[1], fnode[2], g);
