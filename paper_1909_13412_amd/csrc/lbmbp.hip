@@ -616,12 +616,17 @@ long residency_lds(int lds_cu, int lds_block, int cap, int bs) {
 
 long sweep_lds(const lbm_ctx *c, int cap, int bs) { return residency_lds(c->lds_cu, c->lds_block, cap, bs); }
 
-// Addressing of the sweep (kAddr* in collide.hpp): wavefront-uniform rows
-// whenever every wavefront lies in one row (the row-aligned mapping, or rows of
-// whole wavefronts), else per-lane indices in 32 bits unless the lattice holds
-// 2^32 or more elements (Q nx ny nz; boxes beyond about 226M nodes).
+// Addressing of the sweep (kAddr* in collide.hpp).  The row-aligned mapping
+// always addresses by wavefront rows.  The flat mapping does so for 16-bit
+// storage when rows are whole wavefronts: there the per-lane index arithmetic
+// competes with the collision for the vector unit (FP16 step 1.8%, BF16 0.4%
+// faster by rows, measured A/B on one device).  FP32 and FP64 sweeps are
+// memory-bound, and per-lane indices measured as fast or faster (FP32 step
+// 0.9%: its sum-carrying launches run longer by rows); those are in 32 bits
+// unless the lattice holds 2^32 or more elements (Q nx ny nz; boxes beyond
+// about 226M nodes).
 int sweep_addr(const lbm_ctx *c, bool row_mapping) {
-    if (row_mapping || c->g.nx % 64 == 0) return kAddrRow;
+    if (row_mapping || (c->elem == 2 && c->g.nx % 64 == 0)) return kAddrRow;
     return uint64_t(c->q) * c->g.ncell >= (uint64_t(1) << 32) ? kAddrLane64 : kAddrLane32;
 }
 

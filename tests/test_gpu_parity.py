@@ -382,10 +382,9 @@ def test_suspension512_tiled_against_oracle(oracle_mod):
 
 @pytest.mark.parametrize("tiles_x", [32, 31])
 def test_beyond_32bit_lattice_index_tiled_against_oracle(oracle_mod, tiles_x):
-    # Lattices of 19 x nx x 512 x 448 >= 2^32 population elements: nx = 1024
-    # (rows of whole wavefronts: 64-bit row offsets per wavefront) and nx =
-    # 992 (per-lane 64-bit indices in the flat configurations; rows again in
-    # the row-aligned one).  A 32^3 state (perturbed fields, one particle,
+    # Lattices of 19 x nx x 512 x 448 >= 2^32 population elements, nx = 1024
+    # and 992: per-lane 64-bit indices in the flat configurations (FP32), and
+    # 64-bit row offsets per wavefront in the row-aligned one.  A 32^3 state (perturbed fields, one particle,
     # kT = 0) tiled tiles_x x 16 x 14 times, a particle at the same place in
     # every tile, 3 steps in FP32, with one and with 16 rows per group.
     # Every tile must hold the same moments and tile 0 must match the
@@ -420,7 +419,7 @@ def test_beyond_32bit_lattice_index_tiled_against_oracle(oracle_mod, tiles_x):
     u_d = torch.from_numpy(u_t).to(dev).repeat(1, K[2], K[1], K[0])
     g = Lattice(*dims, tau, storage="f32")
     first = None
-    runs = ((5, 1), (4, 16)) if tiles_x % 2 == 0 else ((5, 1), (4, 16), (9, 1))
+    runs = ((5, 1), (4, 16), (9, 1))
     for shape, rows in runs:
         g.set_layout(rows)
         g.set_shape(shape)
@@ -905,9 +904,9 @@ def test_every_launch_configuration_is_bit_identical():
     # FP64 sums fused in.  Boxes whose row-aligned mapping puts four rows in
     # a block, a row of three wavefronts with 62 idle lanes, rows longer than
     # a block, 64 short rows per plane (row groups up to 64 rows), and rows of
-    # two whole wavefronts (64 | nx: every configuration addresses by
-    # wavefront rows; per-lane indices otherwise, the row-aligned mapping
-    # always by rows).
+    # two whole wavefronts (64 | nx: the 16-bit storages address by wavefront
+    # rows in every configuration, FP32 and FP64 by per-lane indices in the
+    # flat ones; the row-aligned mapping always by rows).
     import torch
 
     from paper_1909_13412_amd import Lattice, _abi
