@@ -1090,8 +1090,9 @@ void tune_store(const TuneKey &k, int shape) {
 }
 
 // A single-box choice is kept as one code: configuration, block order,
-// residency cap and layout (log2 of the rows per group); ensembles keep the
-// configuration alone (order 0, no cap, one row per group).
+// residency cap and layout (log2 of the rows per group); an ensemble's code
+// holds the same four, its layout being the rows per group requested of
+// every box.
 int tune_code(int shape, int order, int cap, int rows_log2) {
     return shape + kNumShapes * (order + int(kNumOrders) * (cap + kNumCaps * rows_log2));
 }
