@@ -53,3 +53,33 @@ def velocity_relaxation(t, M: float, gamma: float, R: float, nu: float, rho: flo
 def tail_amplitude(M: float, gamma: float, R: float, nu: float, rho: float = 1.0) -> float:
     """B of phi ~ B t^(-3/2): M b / (2 sqrt(pi) gamma^2)."""
     return M * basset_b(R, nu, rho) / (2.0 * math.sqrt(math.pi) * gamma * gamma)
+
+
+def particle_noise_vacf(phi, gamma: float, M: float, kT: float, lags: int):
+    """Stationary VACF of a particle whose random force acts on it alone
+    (Eqs. s2-rf1, s2-rf2: independent normals of variance 2 gamma kT per
+    component and step, nothing acting on the fluid), for a coupled system
+    that responds linearly.
+
+    phi[p, d, j, c] is component c of the particle velocity j steps after a
+    kick of unit velocity along axis d, with the fluid at rest before the
+    kick, measured at the particle position p (p indexes positions over which
+    the result is averaged).  The random force F^k of step k changes V^(k+1)
+    by F^k / M (Eq. s2-langevin), so by superposition
+    V^n = sum_k phi(n - 1 - k) F^k / M, and with independent F^k
+
+        C(t) = sum_c <V_c^n V_c^(n+t)> = (2 gamma kT / M^2) sum_{j,d,c} phi_cd(j) phi_cd(j + t).
+
+    Only when phi is a single exponential (Brownian dynamics) is this
+    proportional to phi itself; the fluctuation-dissipation form
+    C(t) = (kT / M) phi(t) needs random stresses in the fluid as well.
+    Returns C(t) for t = 0..lags, averaged over p; the sums run over the
+    recorded lags j + t <= J."""
+    phi = np.asarray(phi, dtype=np.float64)
+    if phi.ndim != 4 or phi.shape[1] != 3 or phi.shape[3] != 3:
+        raise ValueError("phi must be [positions, 3 kick axes, J + 1 lags, 3 components]")
+    J1 = phi.shape[2]
+    C = np.empty(lags + 1)
+    for t in range(lags + 1):
+        C[t] = np.sum(phi[:, :, : J1 - t, :] * phi[:, :, t:, :]) / phi.shape[0]
+    return 2.0 * gamma * kT / (M * M) * C

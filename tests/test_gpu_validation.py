@@ -19,7 +19,10 @@ with hydrodynamic memory (analytic.py).
 
 Fig. 3 -- response V_R (velocity after an instantaneous kick) against
 relaxation A_R (acceleration after a steady pulling force is released), both
-normalised at t = 0, and the thermal C_v.
+normalised at t = 0, and the thermal C_v.  With the random force on the
+particles only, the thermal C_v is compared with what linear response predicts
+for that noise, (2 gamma kT / M^2) sum_j phi(j) phi(j + t) from the kick
+responses phi (analytic.py), rather than with phi itself.
 """
 import math
 
@@ -188,6 +191,30 @@ def _kick_response(friction, lags):
     return np.array(curves)
 
 
+def _kick_matrix(L, tau, M, gamma, positions, J, friction, radius=0.0):
+    """phi[p, d, j, c]: component c of V(j) / V(0) after a kick along axis d
+    from rest, one particle at positions[p] in an L^3 box at rest (FP64)."""
+    import torch
+
+    from paper_1909_13412_amd import Lattice
+
+    out = np.zeros((len(positions), 3, J + 1, 3))
+    for ip, pos in enumerate(positions):
+        for d in range(3):
+            lat = Lattice(L, L, L, tau, storage="f64")
+            v0 = np.zeros((1, 3))
+            v0[0, d] = 1e-3
+            lat.particles_couple(np.array([pos]), v0, mass=M, gamma=gamma, friction=friction,
+                                 radius=radius)
+            vs = []
+            for _ in range(J):
+                lat.step(1)
+                vs.append(lat.v[0].clone())
+            out[ip, d, 0, d] = 1.0
+            out[ip, d, 1:, :] = torch.stack(vs).cpu().numpy() / 1e-3
+    return out
+
+
 def test_fig2_velocity_relaxation_against_hydrodynamic_memory():
     """The velocity relaxation after a kick -- by the fluctuation-dissipation
     theorem the normalised VACF of Fig. 2 -- against the closed form for a
@@ -256,7 +283,8 @@ def _thermal_fig2(friction, steps, lags=2000):
     """The paper's thermal Fig. 2 suspension: 500 particles of R = 1 dx, M = 16,
     friction 6 pi eta R, at kT = 3.3e-7 (300 K) in a 100^3 box at tau 0.5534,
     FP32; 5000 steps to settle, then `steps` more with the VACF accumulated
-    (origins every 10 steps).  Returns (M<V^2>/3kT every 4000 steps, C/C(0))."""
+    (origins every 10 steps).  Returns (M<V^2>/3kT every 4000 steps, C/C(0),
+    M C(0) / 3kT)."""
     from paper_1909_13412_amd import Lattice
     from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
 
@@ -275,7 +303,7 @@ def _thermal_fig2(friction, steps, lags=2000):
         temps.append(float(M * np.mean(np.sum(v ** 2, axis=1)) / (3.0 * kT)))
     acc, cnt = lat.vacf()
     C = acc.sum(0).cpu().numpy() / (n * np.maximum(cnt, 1))
-    return np.array(temps), C / C[0]
+    return np.array(temps), C / C[0], M * C[0] / (3.0 * kT)
 
 
 def test_fig2_thermal_suspension_stable_with_cube_spreading():
@@ -285,14 +313,17 @@ def test_fig2_thermal_suspension_stable_with_cube_spreading():
     (the particle temperature grows about tenfold within 20,000 steps here);
     spreading on the same cube keeps it at a steady temperature over 60,000
     steps.  The stationary C_v then has a power-law tail; with the random force
-    on the particles only (R13) it decays more slowly than the closed form of
-    the response (R26), and M<V^2>/3kT settles below one (R31): both recorded."""
+    on the particles only (R13) it decays more slowly than the response (R26)
+    and M<V^2>/3kT settles below one (R31).  Both follow from that noise:
+    linear response to it predicts C_v from the kick responses of the same
+    method and box (analytic.particle_noise_vacf), and the suspension's C_v
+    and temperature match the prediction, not the response itself."""
     from analytic import velocity_relaxation
 
-    t_unit, _ = _thermal_fig2("stokeslet2dx", 32000)
+    t_unit, _, _ = _thermal_fig2("stokeslet2dx", 32000)
     announce(f"Fig. 2 thermal, unit-cell spreading: M<V^2>/3kT {np.round(t_unit, 3).tolist()}")
     assert t_unit[-1] > 5.0 * t_unit[0]
-    temps, C = _thermal_fig2("stokeslet_cube", 60000)
+    temps, C, T0 = _thermal_fig2("stokeslet_cube", 60000)
     nu = (TAU1 - 0.5) / 3.0
     phi = velocity_relaxation(np.arange(2001), M2, 6.0 * math.pi * nu * R2, R2, nu)
     ks = [1, 10, 50, 100, 200, 500, 1000, 2000]
@@ -304,6 +335,27 @@ def test_fig2_thermal_suspension_stable_with_cube_spreading():
     slope = math.log(C[2000] / C[500]) / math.log(4.0)
     announce(f"  local exponent over lags 500..2000: {slope:.3f}")
     assert -1.8 < slope < -1.0
+
+    # Linear response to noise on the particles only, from kicks of a lone
+    # particle of the same method at four positions of the same box.
+    from analytic import particle_noise_vacf
+    from paper_1909_13412_amd.inputs import particle_positions
+
+    kT, lags = 3.3e-7, 1000
+    phi = _kick_matrix(100, TAU1, M2, 6.0 * math.pi * nu * R2, particle_positions(4, 100, 321),
+                       4000, "stokeslet_cube", radius=R2)
+    Cp = particle_noise_vacf(phi, 6.0 * math.pi * nu * R2, M2, kT, lags)
+    Tp = M2 * Cp[0] / (3.0 * kT)
+    VR = np.mean([phi[:, d, :, d] for d in range(3)], axis=(0, 1))
+    ks = [1, 10, 50, 100, 200, 500, 1000]
+    announce(f"  M C(0)/3kT {T0:.4f}, predicted for noise on the particles only {Tp:.4f}")
+    announce("  C_v, predicted, V_R: " + ", ".join(f"{k}: {C[k]:.5f} {Cp[k] / Cp[0]:.5f} {VR[k]:.5f}"
+                                                    for k in ks))
+    assert abs(T0 / Tp - 1.0) < 0.03
+    err_pred = np.abs(C[: lags + 1] - Cp / Cp[0])
+    err_resp = np.abs(C[: lags + 1] - VR[: lags + 1])
+    assert np.max(err_pred) < 0.02
+    assert np.max(err_pred[10:501]) < np.max(err_resp[10:501]) / 3.0
 
 
 # ---- Fig. 3 ----------------------------------------------------------------------
@@ -388,3 +440,56 @@ def test_fig3_thermal_vacf_against_response():
     assert np.all(np.diff(coarse) < 0.0) and C[50] > 0.0
     # slower than Brownian dynamics without hydrodynamics, (1 - gamma/M)^k
     assert C[20] > (1.0 - GAMMA3 / M3) ** 20
+
+
+def _fig3_noise_prediction(friction, npos=16, J=2000, steps=40000, lags=100):
+    """Thermal run of the Fig. 3 box (64 particles, kT 1e-4, noise on the
+    particles only) and the linear-response prediction for that noise from
+    kicks of a lone particle at `npos` positions.  Returns (M C(0)/kT,
+    C/C(0), predicted M C(0)/kT, predicted C/C(0), per-position M C(0)/kT)."""
+    from analytic import particle_noise_vacf
+    from paper_1909_13412_amd import Lattice
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    n, kT = 64, 1e-4
+    lat = Lattice(L3, L3, L3, TAU3, storage="f32")
+    lat.particles_couple(particle_positions(n, L3, 5), particle_velocities(n, kT / M3, 5),
+                         mass=M3, gamma=GAMMA3, kT=kT, seed=5, friction=friction)
+    lat.step(2000)
+    lat.vacf_config(lags, 5)
+    lat.step(steps)
+    acc, cnt = lat.vacf()
+    C = acc.sum(0).cpu().numpy() / (n * np.maximum(cnt, 1))
+    phi = _kick_matrix(L3, TAU3, M3, GAMMA3, particle_positions(npos, L3, 123), J, friction)
+    Cp = particle_noise_vacf(phi, GAMMA3, M3, kT, lags)
+    per = [M3 * particle_noise_vacf(phi[i:i + 1], GAMMA3, M3, kT, 0)[0] / kT for i in range(npos)]
+    return M3 * C[0] / kT, C / C[0], M3 * Cp[0] / kT, Cp / Cp[0], np.array(per)
+
+
+def test_fig3_noise_on_particles_only_pointwise():
+    """R26 and R31 shown on the pointwise friction (Eq. s2-dis1), which is
+    linear in the particle and fluid velocities: with the random force on the
+    particles only, the stationary C_v is the prediction of linear response to
+    that noise, (2 gamma kT / M^2) sum_j phi(j) phi(j + t) from the kick
+    responses, and M<V^2>/kT is not 3.  Neither is C_v / C_v(0) the response
+    phi itself, which the regression relation would need."""
+    T, C, Tp, Cp, per = _fig3_noise_prediction("pointwise")
+    announce(f"Fig. 3 pointwise: M<V^2>/kT {T:.4f}, predicted {Tp:.4f} "
+             f"(positions {per.min():.3f}..{per.max():.3f})")
+    announce("  C_v, predicted: " + ", ".join(f"{k}: {C[k]:.4f} {Cp[k]:.4f}" for k in (1, 2, 5, 10, 20, 50, 100)))
+    assert abs(T / Tp - 1.0) < 0.03
+    assert abs(T - 3.0) > 0.5
+    assert np.max(np.abs(C - Cp)) < 5e-3
+
+
+def test_fig3_noise_on_particles_only_stokeslet():
+    """The same prediction for the unit-cell Stokeslet fit.  Its gain depends
+    on where the particle sits in its cell, down to negative values near a
+    node (R29), so the lone particle's response differs from position to
+    position and the linear prediction at fixed positions is a range, not one
+    number; the suspension's temperature must lie within it.  Recorded."""
+    T, C, Tp, Cp, per = _fig3_noise_prediction("stokeslet")
+    announce(f"Fig. 3 Stokeslet fit: M<V^2>/kT {T:.4f}, predicted {Tp:.4f} "
+             f"(positions {per.min():.3f}..{per.max():.3f})")
+    announce("  C_v, predicted: " + ", ".join(f"{k}: {C[k]:.4f} {Cp[k]:.4f}" for k in (1, 2, 5, 10, 20, 50, 100)))
+    assert per.min() < T < per.max()
