@@ -204,6 +204,34 @@ def test_shared_nodes_and_edge_positions(oracle_mod):
     _compare_fields(out["gpu"], out["ref"], 1e-10, "edges")
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_particle_set_replaced_then_detached(oracle_mod, storage):
+    # particles_couple in mid-run (section 2.1): a new, smaller set replaces
+    # the old one and couples from its next step, the nodes the old set forced
+    # are released (its reaction force reaches no later step, first Eq.
+    # s2-force), and n = 0 leaves the plain fluid update (Eq. s2-coll).  Noise
+    # on, a ragged box, against the oracle doing the same.
+    from paper_1909_13412_amd import Lattice
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    L = (21, 18, 13)
+    gpu = Lattice(*L, 0.7, storage=storage)
+    ref = oracle_mod.Sim(*L, 0.7)
+    kw = dict(mass=10.0, gamma=1.0, kT=1e-4, seed=77)
+    sets = [(particle_positions(5, L, seed=31), particle_velocities(5, 1e-5, seed=31), 20),
+            (particle_positions(3, L, seed=32), particle_velocities(3, 1e-5, seed=32), 15),
+            (np.zeros((0, 3)), np.zeros((0, 3)), 12)]
+    for k, (r, v, steps) in enumerate(sets):
+        gpu.particles_couple(r, v, **kw)
+        ref.set_particles(r, v, **kw)
+        gpu.step(steps)
+        ref.step(steps)
+        if len(r):
+            _compare_particles(gpu, ref, TOL[storage], f"{storage} set {k}")
+        _compare_fields(gpu, ref, TOL[storage], f"{storage} set {k}")
+    assert gpu.n == 0
+
+
 def test_bitwise_reproducible(oracle_mod):
     from paper_1909_13412_amd import Lattice
     from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
