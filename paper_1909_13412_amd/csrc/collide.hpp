@@ -214,18 +214,30 @@ __device__ inline void static_for(F &&f) {
 // ---------------------------------------------------------------------------
 // Deterministic block sum of N doubles (fixed butterfly and wave order);
 // thread k < N writes out[k].  Every thread of the block must call it.
-// Sum of v over the lanes of one wavefront, in a fixed butterfly order; lane 0
-// of the wavefront writes the N sums to out[0..N-1].  Every lane of the
-// wavefront must call it.
-template <int N>
-__device__ inline void wave_sum(double (&v)[N], double *__restrict__ out) {
+// Sums of four doubles over the lanes of one wavefront, written to out[0..3].
+// Every lane of the wavefront must call it.  A reduce-scatter butterfly: at
+// offset 32 each lane keeps two of the four values (the half its partner
+// does not) and receives the partner's copy of them, at offset 16 it keeps
+// one, and offsets 8..1 sum that one; seven FP64 exchanges instead of 24 for
+// four full butterflies.  Each addition pairs the same two partials as the
+// full butterfly over offsets 32, 16, ..., 1 (a + b = b + a exactly), so the
+// sums are those of that order bit for bit.  Lanes 0, 16, 32, 48 hold sums 0,
+// 1, 2, 3 and write them.
+__device__ inline void wave_sum4(const double (&v)[4], double *__restrict__ out) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const bool h32 = (lane & 32u) != 0;
+    double k0 = h32 ? v[2] : v[0];
+    double k1 = h32 ? v[3] : v[1];
+    const double s0 = h32 ? v[0] : v[2];
+    const double s1 = h32 ? v[1] : v[3];
+    k0 += __shfl_xor(s0, 32);
+    k1 += __shfl_xor(s1, 32);
+    const bool h16 = (lane & 16u) != 0;
+    double k = h16 ? k1 : k0;
+    k += __shfl_xor(h16 ? k0 : k1, 16);
 #pragma unroll
-    for (int k = 0; k < N; ++k)
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-        for (int k = 0; k < N; ++k) out[k] = v[k];
+    for (int off = 8; off > 0; off >>= 1) k += __shfl_xor(k, off);
+    if ((lane & 15u) == 0) out[lane >> 4] = k;
 }
 
 template <int N, int BS>
@@ -444,7 +456,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename C::T *__re
     // partials by wavefront of the node block (no barrier), so that every
     // block order gives the same sums
     if constexpr (MOMENTS)
-        wave_sum<4>(acc, mom + 4 * (uint64_t(blk) * (BS / 64) + threadIdx.x / 64));
+        wave_sum4(acc, mom + 4 * (uint64_t(blk) * (BS / 64) + threadIdx.x / 64));
 }
 
 // The stream-collide's data movement alone, for the nodes of one lane (as in
