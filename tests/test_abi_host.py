@@ -76,6 +76,11 @@ def test_lattice_and_scratch_sizes(lib):
     assert sz.value > 0
     assert lib.lbm_particle_scratch_bytes(ctypes.byref(g), 0, ctypes.byref(sz)) == 0
     assert sz.value == 0
+    # the particle count's documented range is 0..2^24
+    assert lib.lbm_particle_scratch_bytes(ctypes.byref(g), 1 << 24, ctypes.byref(sz)) == 0
+    assert sz.value >= (1 << 24) * 8 * 4  # at least each lane's last node
+    assert lib.lbm_particle_scratch_bytes(ctypes.byref(g), (1 << 24) + 1, ctypes.byref(sz)) == 1
+    assert lib.lbm_particle_scratch_bytes(ctypes.byref(g), -1, ctypes.byref(sz)) == 1
     assert lib.lbm_vacf_origin_bytes(64, 2000, 10, ctypes.byref(sz)) == 0
     assert sz.value == 201 * 64 * 3 * 8
 

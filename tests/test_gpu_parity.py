@@ -232,6 +232,36 @@ def test_particle_set_replaced_then_detached(oracle_mod, storage):
     assert gpu.n == 0
 
 
+@pytest.mark.parametrize("n,L,steps", [(1 << 20, (48, 40, 36), 2), (1 << 24, (128, 128, 96), 1)])
+def test_maximum_particle_count(oracle_mod, n, L, steps):
+    # The particle count's documented maximum, 2^24 (and 2^20), with far more
+    # particles than nodes (11 to 15 per node): up to 134M particle lanes, and
+    # every node's reaction force summed from about a hundred fixed-point
+    # contributions (first Eq. s2-force).  Noise on, FP64, one or two steps
+    # (the oracle takes about 25 s per step at 2^24): every particle and
+    # every node against the oracle.
+    import torch
+
+    from paper_1909_13412_amd import Lattice
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    r = particle_positions(n, L, seed=41)
+    v = particle_velocities(n, 1e-5, seed=41)
+    kw = dict(mass=10.0, gamma=1.0, kT=1e-4, seed=9)
+    gpu = Lattice(*L, 0.8, storage="f64")
+    gpu.particles_couple(r, v, **kw)
+    ref = oracle_mod.Sim(*L, 0.8)
+    ref.set_particles(r, v, **kw)
+    del r, v
+    gpu.step(steps)
+    ref.step(steps)
+    torch.cuda.synchronize()
+    _compare_particles(gpu, ref, TOL["f64"], f"{n} particles")
+    _compare_fields(gpu, ref, TOL["f64"], f"{n} particles")
+    del gpu
+    torch.cuda.empty_cache()
+
+
 def test_bitwise_reproducible(oracle_mod):
     from paper_1909_13412_amd import Lattice
     from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
