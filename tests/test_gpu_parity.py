@@ -262,6 +262,41 @@ def test_maximum_particle_count(oracle_mod, n, L, steps):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("friction", ["stokeslet", "pointwise", "stokeslet_cube"])
+def test_zero_friction_is_ballistic(oracle_mod, storage, friction):
+    # gamma = 0 (Eq. s2-langevin): no friction, no noise (its variance is
+    # 2 gamma kT, Eqs. s2-rf1, s2-rf2) and no reaction force, so each particle
+    # keeps V^0 and moves by V^0 per step while the fluid stays exactly at
+    # rest; the oracle does the same.
+    from paper_1909_13412_amd import Lattice
+    from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
+
+    L, n, steps = (19, 14, 11), 6, 25
+    r0 = particle_positions(n, L, seed=51)
+    v0 = particle_velocities(n, 1e-4, seed=51)
+    kw = dict(mass=10.0, gamma=0.0, kT=1e-4, radius=0.5, seed=3, friction=friction)
+    gpu = Lattice(*L, 0.7, storage=storage)
+    gpu.particles_couple(r0, v0, **kw)
+    ref = oracle_mod.Sim(*L, 0.7)
+    ref.set_particles(r0, v0, **kw)
+    r = r0.copy()
+    for _ in range(steps):
+        r = r + v0
+    gpu.step(steps)
+    ref.step(steps)
+    assert np.array_equal(gpu.v.cpu().numpy(), v0)
+    assert np.array_equal(gpu.r.cpu().numpy(), r)
+    rr, vr = ref.particles()
+    assert np.array_equal(vr, v0) and np.array_equal(rr, r)
+    fh, fr = gpu.particle_forces()
+    assert not fh.cpu().numpy().any() and not fr.cpu().numpy().any()
+    f = gpu.populations().cpu().numpy()
+    assert np.array_equal(f, np.broadcast_to(_w()[:, None, None, None], f.shape))
+    obs = gpu.observables()
+    assert obs[0] == float(np.prod(L)) and not np.any(obs[1:4])
+
+
 def test_bitwise_reproducible(oracle_mod):
     from paper_1909_13412_amd import Lattice
     from paper_1909_13412_amd.inputs import particle_positions, particle_velocities
